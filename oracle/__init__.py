@@ -1,0 +1,286 @@
+"""ctypes shim over the LAMG+ CPU oracle (``oracle/lamg_oracle.c``).
+
+TEST INFRASTRUCTURE: only the tests, the smoke check and the benchmark's CPU
+baseline may import this package. The product (the HIP library and its Python
+binding) never does.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from pathlib import Path
+
+import numpy as np
+
+_DIR = Path(__file__).resolve().parent
+_SRC = _DIR / "lamg_oracle.c"
+_LIB = _DIR / "liblamg_oracle.so"
+_CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+OK, ERR_ARG, ERR_ALLOC, ERR_STALLED, NOT_CONVERGED = 0, 1, 2, 3, 4
+K = 4
+
+
+def build(force: bool = True) -> Path:
+    """Compile the oracle with gcc (contraction off, no fast-math)."""
+    if force or not _LIB.exists() or _LIB.stat().st_mtime < _SRC.stat().st_mtime:
+        tmp = _LIB.with_suffix(f".so.tmp{os.getpid()}")
+        subprocess.run(["gcc", *_CFLAGS, "-o", str(tmp), str(_SRC), "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+_u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = C.CDLL(str(_LIB))
+        L.orc_splitmix64.restype = C.c_uint64
+        L.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+        L.orc_tv_start.restype = C.c_double
+        L.orc_tv_start.argtypes = [C.c_uint64, C.c_int, C.c_int, C.c_int64]
+        L.orc_laplacian.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p]
+        L.orc_color.argtypes = [C.c_int, _i32p, _i32p, _i32p]
+        L.orc_strong.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_double, C.c_int, _u8p]
+        L.orc_gs_sweep_multi.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, C.c_int, C.c_int,
+                                         C.c_void_p, _f64p]
+        L.orc_test_vectors.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, C.c_int, C.c_uint64,
+                                       C.c_int, C.c_int, _f64p]
+        L.orc_affinity.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p]
+        L.orc_moments.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p]
+        L.orc_guard.argtypes = [_f64p, _f64p, C.c_double, _f64p, _f64p]
+        L.orc_aggregate.argtypes = [C.c_int, _i32p, _i32p, _u8p, _f64p, _f64p, _f64p, C.c_double,
+                                    _i32p, _i32p]
+        L.orc_caliber2_weight.restype = C.c_double
+        L.orc_caliber2_weight.argtypes = [_f64p, _f64p, _f64p]
+        L.orc_interp.argtypes = [C.c_int, _i32p, _i32p, _u8p, _f64p, _i32p, _i32p, C.c_int, C.c_int,
+                                 C.c_double, _i32p, _f64p, _i32p, _f64p]
+        L.orc_galerkin.restype = C.c_longlong
+        L.orc_galerkin.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, _i32p, _f64p, _i32p,
+                                   _f64p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_setup.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_uint64, C.c_int, C.c_int, C.c_int,
+                                C.c_int, C.POINTER(C.c_void_p)]
+        L.orc_free.argtypes = [C.c_void_p]
+        L.orc_nlevels.argtypes = [C.c_void_p]
+        L.orc_level_info.argtypes = [C.c_void_p, C.c_int, np.ctypeslib.ndpointer(np.int64),
+                                     _f64p]
+        L.orc_export_level.argtypes = [C.c_void_p, C.c_int] + [C.c_void_p] * 14
+        L.orc_solve.argtypes = [C.c_void_p, _f64p, C.c_double, C.c_int, _f64p, C.c_void_p, _f64p]
+        L.orc_cycle_once.restype = C.c_double
+        L.orc_cycle_once.argtypes = [C.c_void_p, _f64p, _f64p]
+        L.orc_recombine.argtypes = [C.c_int, C.c_int, _f64p, _f64p, C.c_void_p, C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+# ---------------------------------------------------------------------------
+# Individual steps (each mirrors one function of lamg_oracle.c)
+# ---------------------------------------------------------------------------
+
+def splitmix64(seed: int, i: int) -> int:
+    return int(lib().orc_splitmix64(seed, i))
+
+
+def tv_start(seed: int, level: int, k: int, u: int) -> float:
+    return float(lib().orc_tv_start(seed, level, k, u))
+
+
+def laplacian(g):
+    n = g.n
+    nnz = g.nnz + n
+    rp = np.empty(n + 1, np.int32)
+    ci = np.empty(nnz, np.int32)
+    v = np.empty(nnz, np.float64)
+    lib().orc_laplacian(n, g.row_ptr, g.col_idx, np.ascontiguousarray(g.weight, np.float64), rp,
+                        ci, v)
+    return rp, ci, v
+
+
+def color(rp, ci):
+    n = rp.size - 1
+    col = np.empty(n, np.int32)
+    nc = lib().orc_color(n, rp, ci, col)
+    return col, nc
+
+
+def strong(rp, ci, v, tau=0.05, enable_veto=True):
+    s = np.empty(ci.size, np.uint8)
+    lib().orc_strong(rp.size - 1, rp, ci, v, tau, int(enable_veto), s)
+    return s.astype(bool)
+
+
+def gs_sweep(rp, ci, v, col, ncolors, X, f=None):
+    """One multicolour GS sweep in place on X (n x K node-major, any K)."""
+    X = np.ascontiguousarray(X, np.float64)
+    K_ = 1 if X.ndim == 1 else X.shape[1]
+    fp = None if f is None else np.ascontiguousarray(f, np.float64)
+    lib().orc_gs_sweep_multi(rp.size - 1, rp, ci, v, col, ncolors, K_, _p(fp), X)
+    return X
+
+
+def test_vectors(rp, ci, v, col, ncolors, seed, level, sweeps=3):
+    n = rp.size - 1
+    X = np.empty((n, K), np.float64)
+    lib().orc_test_vectors(n, rp, ci, v, col, ncolors, seed, level, sweeps, X)
+    return X
+
+
+def affinity(rp, ci, X):
+    a = np.empty(ci.size, np.float64)
+    lib().orc_affinity(rp.size - 1, rp, ci, np.ascontiguousarray(X, np.float64), a)
+    return a
+
+
+def moments(rp, ci, v, X):
+    n = rp.size - 1
+    m = np.empty((n, 9), np.float64)
+    lib().orc_moments(n, rp, ci, v, np.ascontiguousarray(X, np.float64), m)
+    return m
+
+
+def guard(mom_u, xs, Q=2.5):
+    ef = np.empty(K)
+    em = np.empty(K)
+    ok = lib().orc_guard(np.ascontiguousarray(mom_u, np.float64), np.ascontiguousarray(xs, np.float64),
+                         Q, ef, em)
+    return bool(ok), ef, em
+
+
+def aggregate(rp, ci, strong_mask, aff, X, mom, Q=2.5):
+    n = rp.size - 1
+    seed = np.empty(n, np.int32)
+    agg = np.empty(n, np.int32)
+    nc = lib().orc_aggregate(n, rp, ci, np.ascontiguousarray(strong_mask, np.uint8), aff,
+                             np.ascontiguousarray(X, np.float64), np.ascontiguousarray(mom), Q,
+                             seed, agg)
+    return seed, agg, nc
+
+
+def caliber2_weight(xu, xa, xb) -> float:
+    f = lambda a: np.ascontiguousarray(a, np.float64)
+    return float(lib().orc_caliber2_weight(f(xu), f(xa), f(xb)))
+
+
+def interp(rp, ci, strong_mask, X, seed, agg, nc, enable_caliber2=True, snap=0.01):
+    n = rp.size - 1
+    p0 = np.empty(n, np.int32)
+    p1 = np.empty(n, np.int32)
+    w0 = np.empty(n)
+    w1 = np.empty(n)
+    n2 = lib().orc_interp(n, rp, ci, np.ascontiguousarray(strong_mask, np.uint8),
+                          np.ascontiguousarray(X, np.float64), seed, agg, nc, int(enable_caliber2),
+                          snap, p0, w0, p1, w1)
+    return p0, w0, p1, w1, n2
+
+
+def galerkin(rp, ci, v, nc, p0, w0, p1, w1):
+    n = rp.size - 1
+    args = (n, rp, ci, v, nc, np.ascontiguousarray(p0, np.int32), np.ascontiguousarray(w0),
+            np.ascontiguousarray(p1, np.int32), np.ascontiguousarray(w1))
+    nnz = lib().orc_galerkin(*args, None, None, None)
+    if nnz < 0:
+        raise MemoryError
+    Crp = np.empty(nc + 1, np.int32)
+    Cci = np.empty(nnz, np.int32)
+    Cv = np.empty(nnz)
+    lib().orc_galerkin(*args, _p(Crp), _p(Cci), _p(Cv))
+    return Crp, Cci, Cv
+
+
+def recombine(phi, r, hphi, hr):
+    """One fine-level recombination (in place on phi, r) over saved pairs."""
+    m = len(hphi)
+    hphi = [np.ascontiguousarray(a, np.float64) for a in hphi]
+    hr = [np.ascontiguousarray(a, np.float64) for a in hr]
+    PA = (C.c_void_p * max(m, 1))(*[a.ctypes.data for a in hphi])
+    RA = (C.c_void_p * max(m, 1))(*[a.ctypes.data for a in hr])
+    lib().orc_recombine(phi.size, m, phi, r, C.cast(PA, C.c_void_p), C.cast(RA, C.c_void_p))
+    return phi, r
+
+
+# ---------------------------------------------------------------------------
+# Whole hierarchy and solve
+# ---------------------------------------------------------------------------
+
+class OracleError(RuntimeError):
+    pass
+
+
+class Hierarchy:
+    """The oracle's LAMG+ hierarchy for one graph."""
+
+    def __init__(self, g, seed: int = 1, n_direct: int = 256, enable_veto: bool = True,
+                 enable_caliber2: bool = True, kappa: int = 4):
+        h = C.c_void_p()
+        rc = lib().orc_setup(g.n, g.row_ptr, g.col_idx, np.ascontiguousarray(g.weight, np.float64),
+                             seed, n_direct, int(enable_veto), int(enable_caliber2), kappa,
+                             C.byref(h))
+        if rc != OK:
+            raise OracleError(f"orc_setup failed with code {rc}")
+        self._h = h
+        self.n = g.n
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.orc_free(self._h)
+            self._h = None
+
+    @property
+    def nlevels(self) -> int:
+        return lib().orc_nlevels(self._h)
+
+    def level_info(self, l: int) -> dict:
+        s = np.zeros(7, np.int64)
+        d = np.zeros(2)
+        if lib().orc_level_info(self._h, l, s, d) != OK:
+            raise IndexError(l)
+        return dict(n=int(s[0]), nnz=int(s[1]), ncolors=int(s[2]), nc=int(s[3]),
+                    n_cal2=int(s[4]), coarsest=bool(s[5]), gamma=float(d[0]), tau=float(d[1]))
+
+    def export(self, l: int) -> dict:
+        info = self.level_info(l)
+        n, nnz = info["n"], info["nnz"]
+        out = dict(info)
+        out["row_ptr"] = np.empty(n + 1, np.int32)
+        out["col_idx"] = np.empty(nnz, np.int32)
+        out["val"] = np.empty(nnz)
+        arrs = [out["row_ptr"], out["col_idx"], out["val"]]
+        if not info["coarsest"]:
+            out.update(color=np.empty(n, np.int32), strong=np.empty(nnz, np.uint8),
+                       X=np.empty((n, K)), affinity=np.empty(nnz), moments=np.empty((n, 9)),
+                       seed=np.empty(n, np.int32), agg=np.empty(n, np.int32),
+                       p0=np.empty(n, np.int32), w0=np.empty(n), p1=np.empty(n, np.int32),
+                       w1=np.empty(n))
+            arrs += [out[k] for k in ("color", "strong", "X", "affinity", "moments", "seed", "agg",
+                                      "p0", "w0", "p1", "w1")]
+        else:
+            arrs += [None] * 11
+        lib().orc_export_level(self._h, l, *[_p(a) for a in arrs])
+        return out
+
+    def solve(self, b, tol: float = 1e-8, max_cycles: int = 300):
+        """Solve for one right-hand side; returns (phi, stats, history)."""
+        b = np.ascontiguousarray(b, np.float64)
+        phi = np.empty(self.n)
+        hist = np.zeros(max_cycles + 1)
+        stats = np.zeros(4)
+        rc = lib().orc_solve(self._h, b, tol, max_cycles, phi, _p(hist), stats)
+        cyc = int(stats[0])
+        return phi, dict(rc=rc, cycles=cyc, relres=float(stats[1]), acf=float(stats[2]),
+                         mu=float(stats[3]), converged=(rc == OK)), hist[: cyc + 1].copy()
+
+    def cycle_once(self, phi, f) -> float:
+        phi = np.ascontiguousarray(phi, np.float64)
+        return float(lib().orc_cycle_once(self._h, phi, np.ascontiguousarray(f, np.float64)))
