@@ -1,0 +1,195 @@
+/*
+ * lamg.h -- C ABI of the MI355X (gfx950) LAMG+ Laplacian solver library (liblamg.so).
+ *
+ * Solves the compatible singular system of a connected weighted undirected graph
+ *     L phi = b,   1^T phi = 0,   1^T b = 0                      (paper eq. (1.1))
+ * with L = D - W its graph Laplacian, by the LAMG+ aggregation multigrid method
+ * (Livne, "LAMG+: A Robust Lean Algebraic Multigrid Solver for Graph Laplacians"):
+ * a hierarchy of caliber-1 aggregates chosen by test-vector affinity (eq. (2.2)) under
+ * the energy-ratio guard (eq. (2.3)) and the strength-of-connection veto (eq. (3.1)),
+ * selective caliber-2 interpolation (Sec. 3.2, eq. (A.7)), Galerkin coarse operators,
+ * and a gamma-cycle (eq. (2.4)) with Gauss-Seidel relaxation, energy correction and
+ * iterate recombination (Sec. 2, "Cycle and acceleration").
+ *
+ * Conventions for every call:
+ *  - All integers are signed; n < 2^31 and stored-entry counts < 2^31.
+ *  - "device" pointers are HIP device memory on the current device; "host" pointers are
+ *    ordinary process memory. Nothing passed in is retained after a call returns,
+ *    unless stated. The library never frees caller memory.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream). All device work of a
+ *    call is ordered on that stream. Calls that return results to the host synchronise
+ *    that stream before returning.
+ *  - One handle may be used by one stream/thread at a time; different handles are
+ *    independent.
+ *  - Every call returns a lamg_status; on error nothing is leaked and output handles are
+ *    set to NULL. lamg_status_string() names each code.
+ */
+#ifndef LAMG_H
+#define LAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LAMG_OK = 0,
+    LAMG_INVALID_ARG = 1,        /* NULL pointer, n < 1, bad sizes, unsorted/out-of-range columns */
+    LAMG_NOT_SYMMETRIC = 2,      /* adjacency structure or weights not symmetric */
+    LAMG_SELF_LOOP = 3,          /* a stored diagonal entry in the adjacency */
+    LAMG_BAD_WEIGHT = 4,         /* weight <= 0, NaN or infinite (weights must be positive) */
+    LAMG_DISCONNECTED = 5,       /* the graph is not connected */
+    LAMG_OOM = 6,                /* device (or host) allocation failed; nothing leaked */
+    LAMG_COARSENING_STALLED = 7, /* a level larger than 1024 nodes did not coarsen */
+    LAMG_NOT_CONVERGED = 8,      /* max_cycles reached; phi and residuals are still written */
+    LAMG_HIP_ERROR = 9,          /* a HIP runtime call failed (no device, launch failure, ...) */
+    LAMG_UNAVAILABLE = 10        /* requested data was not kept (see keep_setup_data) */
+} lamg_status;
+
+typedef enum { LAMG_MEM_HOST = 0, LAMG_MEM_DEVICE = 1 } lamg_memory;
+
+typedef enum {
+    LAMG_FP64 = 0,   /* every cycle in FP64 */
+    LAMG_FP32_IR = 1 /* FP32 cycles as the preconditioner of an FP64 iterative refinement:
+                        outer residual, recombination, projection and the coarsest solve
+                        stay in FP64 */
+} lamg_precision;
+
+/* Input graph: the weighted ADJACENCY W (not the Laplacian) in CSR form, both directions
+ * of every undirected edge stored, no diagonal, columns strictly ascending in each row
+ * (unsorted rows are rejected with LAMG_INVALID_ARG). Weights must be positive and
+ * finite, and w_uv == w_vu exactly. Arrays live in `mem`. */
+typedef struct {
+    int64_t n;              /* nodes */
+    int64_t nnz;            /* stored adjacency entries = 2 * edges */
+    const int32_t *row_ptr; /* n + 1 entries, row_ptr[0] = 0, row_ptr[n] = nnz */
+    const int32_t *col_idx; /* nnz entries */
+    const double *weight;   /* nnz entries */
+    int32_t mem;            /* lamg_memory of the three arrays */
+} lamg_graph;
+
+/* Setup options. Fill with lamg_default_options() and override fields. The defaults are
+ * the paper's parameter-free constants: K = 4 test vectors with 3 Gauss-Seidel sweeps
+ * (Sec. 2, Sec. 3.3), guard Q = 2.5 (eq. (2.3)), veto tau = 0.05 (eq. (3.1)), caliber-2
+ * on (Sec. 3.2). */
+typedef struct {
+    uint64_t seed;           /* seed of the counter-based test-vector generator (default 1) */
+    int32_t n_direct;        /* levels with n <= n_direct are solved directly (default 256, max 1024) */
+    int32_t enable_veto;     /* strength-of-connection veto (default 1) */
+    int32_t enable_caliber2; /* selective caliber-2 interpolation (default 1) */
+    int32_t kappa;           /* finest-level recombination history, 0..4 (default 4) */
+    int32_t build_fp32;      /* also build FP32 copies of every level for LAMG_FP32_IR (default 1) */
+    int32_t keep_setup_data; /* keep canonical operators, colours, strong flags, test vectors,
+                                affinities, moments and aggregates for lamg_export_level (default 0) */
+} lamg_options;
+
+/* Per-level description of a hierarchy. */
+#define LAMG_MAX_LEVELS 64
+typedef struct {
+    int32_t levels;                      /* number of levels; the last is solved directly */
+    int64_t n[LAMG_MAX_LEVELS];          /* nodes per level */
+    int64_t nnz[LAMG_MAX_LEVELS];        /* stored Laplacian entries per level (diagonal included) */
+    int32_t ncolors[LAMG_MAX_LEVELS];    /* colours of the level's greedy colouring (0 on the last) */
+    int64_t n_caliber2[LAMG_MAX_LEVELS]; /* interpolation rows with two parents */
+    double gamma[LAMG_MAX_LEVELS];       /* cycle index of the level (eq. (2.4)) */
+    double tau[LAMG_MAX_LEVELS];         /* edge coarsening ratio |E_{l+1}|/|E_l| */
+    int64_t bytes_device;                /* device bytes held by the handle (hierarchy + cached workspace) */
+    double op_complexity;                /* sum_l nnz_l / nnz_0 */
+    double setup_seconds;                /* wall time of lamg_setup */
+} lamg_hier_info;
+
+/* Solve statistics. The caller may point the array fields at host arrays (or leave them
+ * NULL): relres[nrhs], cycles[nrhs], history[max_cycles + 1] (column 0's relative residual
+ * after each cycle, history[0] = 1). */
+typedef struct {
+    int32_t cycles;        /* cycles (outer refinement steps for FP32_IR) run, max over columns */
+    double relres_max;     /* max over columns of the final ||b - L phi|| / ||b|| (true residual) */
+    double acf_max;        /* max over columns of the asymptotic convergence factor (geometric
+                              mean of the last <= 5 per-cycle residual reductions) */
+    double seconds;        /* wall time of the call */
+    double *relres;        /* optional [nrhs] */
+    int32_t *col_cycles;   /* optional [nrhs] */
+    double *history;       /* optional [max_cycles + 1] */
+    int32_t history_len;   /* written: entries of history filled */
+} lamg_solve_info;
+
+/* One level of the hierarchy copied to host buffers (parity dumps). Any pointer may be
+ * NULL to skip it. Sizes: n+1 for row_ptr, nnz for col_idx/val/strong/affinity, n for
+ * color/seed/aggregate/p0/p1/w0/w1, 4n for x (node-major, x[u*4+k]), 9n for moments
+ * (s0, s1[4], s2[4] per node). Everything but row_ptr/col_idx/val is absent on the last
+ * (directly solved) level. */
+typedef struct {
+    int32_t *row_ptr;
+    int32_t *col_idx;
+    double *val;        /* canonical L_l: ascending columns, diagonal in place */
+    int32_t *color;     /* greedy colour per node */
+    uint8_t *strong;    /* 1 if the entry may carry aggregation (veto, eq. (3.1)) */
+    double *x;          /* test vectors after the relaxation sweeps */
+    double *affinity;   /* c_uv per stored entry (eq. (2.2)); 0 on the diagonal */
+    double *moments;    /* guard moments (App. B) */
+    int32_t *seed;      /* seed node of each node's aggregate (itself for seeds) */
+    int32_t *aggregate; /* coarse id A(u) */
+    int32_t *p0;        /* first interpolation parent (coarse id) */
+    int32_t *p1;        /* second parent or -1 */
+    double *w0;         /* weight of p0 */
+    double *w1;         /* weight of p1 (0 if none) */
+} lamg_level_export;
+
+typedef struct lamg_handle lamg_handle;
+
+/* Optional device allocator hook used for every device allocation of the library
+ * (default: hipMalloc/hipFree). alloc returns NULL on failure, which surfaces as
+ * LAMG_OOM. Set before creating handles; a handle frees with the hook it was built with. */
+typedef void *(*lamg_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*lamg_free_fn)(void *ptr, void *stream, void *ctx);
+void lamg_set_allocator(lamg_alloc_fn alloc_fn, lamg_free_fn free_fn, void *ctx);
+
+/* Static, human-readable name of a status code. */
+const char *lamg_status_string(lamg_status s);
+
+/* Library version string. */
+const char *lamg_version(void);
+
+/* Fills *opt with the defaults listed in lamg_options. */
+void lamg_default_options(lamg_options *opt);
+
+/* Builds the LAMG+ hierarchy of graph g (Sec. 2 and Sec. 3): validates the adjacency,
+ * forms L = D - W, and per level computes the greedy colouring, strong flags, test
+ * vectors, affinities, guard moments, greedy aggregates, interpolation (caliber-1 and
+ * caliber-2), the Galerkin operator P^T L P, and finally the cycle indices and the
+ * coarsest-level inverse. The graph arrays are copied; the caller keeps ownership.
+ * opt == NULL selects the defaults. On success *out owns all device memory of the
+ * hierarchy until lamg_destroy. Errors: INVALID_ARG, NOT_SYMMETRIC, SELF_LOOP,
+ * BAD_WEIGHT, DISCONNECTED, OOM, COARSENING_STALLED, HIP_ERROR. */
+lamg_status lamg_setup(const lamg_graph *g, const lamg_options *opt, void *stream,
+                       lamg_handle **out);
+
+/* Solves L phi = b for nrhs right-hand sides to ||b - L phi|| / ||b|| <= tol per column
+ * (Sec. 4: tol = 1e-8 in the paper). b and phi are DEVICE arrays, column-major n x nrhs
+ * (column j starts at b + j*n), not aliased; b is not modified. Each column's mean is
+ * removed first (eq. (1.1) needs 1^T b = 0) and phi is returned with zero mean. Columns
+ * are independent: each stops at its own convergence cycle and is frozen afterwards.
+ * max_cycles <= 0 selects 300. A zero column returns phi = 0. The handle caches a
+ * workspace sized for the largest nrhs seen. Returns OK, NOT_CONVERGED (phi and info are
+ * still written), INVALID_ARG, OOM or HIP_ERROR. */
+lamg_status lamg_solve(lamg_handle *h, const double *b, int32_t nrhs, double tol,
+                       int32_t max_cycles, lamg_precision prec, double *phi,
+                       lamg_solve_info *info, void *stream);
+
+/* Frees everything the handle owns. NULL is accepted. */
+void lamg_destroy(lamg_handle *h);
+
+/* Describes the hierarchy (sizes, colours, cycle indices, memory). */
+lamg_status lamg_hierarchy_info(const lamg_handle *h, lamg_hier_info *info);
+
+/* Copies level `level` to the caller's host buffers (see lamg_level_export). Requires
+ * keep_setup_data = 1 at setup, else LAMG_UNAVAILABLE. Errors: INVALID_ARG (bad level). */
+lamg_status lamg_export_level(const lamg_handle *h, int32_t level, lamg_level_export *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LAMG_H */

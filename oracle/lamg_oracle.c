@@ -736,7 +736,7 @@ int orc_setup(int n, const int *rp, const int *ci, const double *w, uint64_t see
         if (rc) goto fail;
         if (lv->nc >= lv->L.n || l + 1 >= ORC_MAX_LEVELS) {
             /* no coarsening: a small level becomes the coarsest, a large one is an error */
-            if (lv->L.n <= 4096) {
+            if (lv->L.n <= 1024) {
                 lv->coarsest = 1;
                 break;
             }

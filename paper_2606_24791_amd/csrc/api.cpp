@@ -1,0 +1,229 @@
+// C ABI of liblamg (declared in include/lamg.h): argument checks, handle lifecycle,
+// device-memory pool, hierarchy description and level export. Exceptions raised inside
+// the library stop here and become status codes.
+#include <mutex>
+#include <new>
+
+#include "lamg_internal.h"
+
+namespace lamg {
+void run_setup(lamg_handle *h, const lamg_graph *g);
+lamg_status run_solve(lamg_handle *h, const double *b, int nrhs, double tol, int max_cycles,
+                      lamg_precision prec, double *phi, lamg_solve_info *info);
+
+static std::mutex g_alloc_mu;
+static Allocator g_alloc;
+
+Allocator current_allocator() {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    return g_alloc;
+}
+
+void *Pool::get(size_t bytes) {
+    void *p = nullptr;
+    if (a_.alloc) {
+        p = a_.alloc(bytes, (void *)s_, a_.ctx);
+    } else {
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+        }
+    }
+    if (!p) throw Error(LAMG_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    blks_.push_back({p, bytes});
+    bytes_ += (int64_t)bytes;
+    return p;
+}
+
+void Pool::put(void *p) {
+    for (size_t i = blks_.size(); i-- > 0;) {
+        if (blks_[i].p == p) {
+            bytes_ -= (int64_t)blks_[i].bytes;
+            blks_[i] = blks_.back();
+            blks_.pop_back();
+            if (a_.free)
+                a_.free(p, (void *)s_, a_.ctx);
+            else
+                (void)hipFree(p);
+            return;
+        }
+    }
+}
+
+Pool::~Pool() {
+    for (auto &b : blks_) {
+        if (a_.free)
+            a_.free(b.p, (void *)s_, a_.ctx);
+        else
+            (void)hipFree(b.p);
+    }
+}
+
+template <class F>
+static lamg_status guarded(F &&f) {
+    try {
+        return f();
+    } catch (const Error &e) {
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        return LAMG_OOM;
+    } catch (...) {
+        return LAMG_HIP_ERROR;
+    }
+}
+
+}  // namespace lamg
+
+lamg_handle::~lamg_handle() {
+    // pinned host mirrors; device arrays are released by their owners before the pool
+    if (ws.h_rel) (void)hipHostFree(ws.h_rel);
+    if (ws.h_mask) (void)hipHostFree(ws.h_mask);
+    ws.h_rel = nullptr;
+    ws.h_mask = nullptr;
+}
+
+using namespace lamg;
+
+extern "C" {
+
+void lamg_set_allocator(lamg_alloc_fn alloc_fn, lamg_free_fn free_fn, void *ctx) {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    if (alloc_fn && free_fn) {
+        g_alloc.alloc = alloc_fn;
+        g_alloc.free = free_fn;
+        g_alloc.ctx = ctx;
+    } else {
+        g_alloc = Allocator();
+    }
+}
+
+const char *lamg_status_string(lamg_status s) {
+    switch (s) {
+        case LAMG_OK: return "ok";
+        case LAMG_INVALID_ARG: return "invalid argument";
+        case LAMG_NOT_SYMMETRIC: return "adjacency not symmetric";
+        case LAMG_SELF_LOOP: return "self loop in adjacency";
+        case LAMG_BAD_WEIGHT: return "non-positive or non-finite weight";
+        case LAMG_DISCONNECTED: return "graph not connected";
+        case LAMG_OOM: return "out of memory";
+        case LAMG_COARSENING_STALLED: return "coarsening stalled";
+        case LAMG_NOT_CONVERGED: return "not converged";
+        case LAMG_HIP_ERROR: return "HIP runtime error";
+        case LAMG_UNAVAILABLE: return "data not kept";
+    }
+    return "unknown status";
+}
+
+const char *lamg_version(void) { return "lamg-mi355x 0.1 (gfx950)"; }
+
+void lamg_default_options(lamg_options *opt) {
+    if (!opt) return;
+    opt->seed = 1;
+    opt->n_direct = 256;
+    opt->enable_veto = 1;
+    opt->enable_caliber2 = 1;
+    opt->kappa = 4;
+    opt->build_fp32 = 1;
+    opt->keep_setup_data = 0;
+}
+
+lamg_status lamg_setup(const lamg_graph *g, const lamg_options *opt, void *stream,
+                       lamg_handle **out) {
+    if (!out) return LAMG_INVALID_ARG;
+    *out = nullptr;
+    if (!g) return LAMG_INVALID_ARG;
+    lamg_options o;
+    lamg_default_options(&o);
+    if (opt) o = *opt;
+    if (o.n_direct < 1 || o.n_direct > 1024 || o.kappa < 0 || o.kappa > 4) return LAMG_INVALID_ARG;
+    lamg_handle *h = nullptr;
+    lamg_status st = guarded([&]() -> lamg_status {
+        h = new lamg_handle();
+        h->alloc = current_allocator();
+        h->stream = (hipStream_t)stream;
+        h->pool.reset(new Pool(h->alloc, h->stream));
+        h->opt = o;
+        run_setup(h, g);
+        return LAMG_OK;
+    });
+    if (st != LAMG_OK) {
+        if (h) {
+            // input errors are found on the host before any device work; only a failure
+            // after device work began needs the stream drained before memory is returned
+            if (h->pool && h->pool->bytes() > 0) (void)hipStreamSynchronize((hipStream_t)stream);
+            delete h;
+        }
+        return st;
+    }
+    *out = h;
+    return LAMG_OK;
+}
+
+lamg_status lamg_solve(lamg_handle *h, const double *b, int32_t nrhs, double tol,
+                       int32_t max_cycles, lamg_precision prec, double *phi,
+                       lamg_solve_info *info, void *stream) {
+    if (!h || !b || !phi || nrhs < 1 || !(tol >= 0.0) || (prec != LAMG_FP64 && prec != LAMG_FP32_IR))
+        return LAMG_INVALID_ARG;
+    return guarded([&]() -> lamg_status {
+        h->stream = (hipStream_t)stream;
+        h->pool->set_stream(h->stream);
+        return run_solve(h, b, nrhs, tol, max_cycles, prec, phi, info);
+    });
+}
+
+void lamg_destroy(lamg_handle *h) {
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    delete h;
+}
+
+lamg_status lamg_hierarchy_info(const lamg_handle *h, lamg_hier_info *info) {
+    if (!h || !info) return LAMG_INVALID_ARG;
+    std::memset(info, 0, sizeof(*info));
+    info->levels = h->nlev;
+    double nnz0 = (double)h->lev[0].nnz, tot = 0.0;
+    for (int l = 0; l < h->nlev && l < LAMG_MAX_LEVELS; ++l) {
+        const Level &L = h->lev[l];
+        info->n[l] = L.n;
+        info->nnz[l] = L.nnz;
+        info->ncolors[l] = L.coarsest ? 0 : L.ncolors;
+        info->n_caliber2[l] = L.coarsest ? 0 : L.n_cal2;
+        info->gamma[l] = L.coarsest ? 0.0 : L.gamma;
+        info->tau[l] = L.coarsest ? 0.0 : L.tau;
+        tot += (double)L.nnz;
+    }
+    info->bytes_device = h->pool->bytes();
+    info->op_complexity = tot / nnz0;
+    info->setup_seconds = h->setup_seconds;
+    return LAMG_OK;
+}
+
+lamg_status lamg_export_level(const lamg_handle *h, int32_t level, lamg_level_export *out) {
+    if (!h || !out || level < 0 || level >= h->nlev) return LAMG_INVALID_ARG;
+    if (!h->opt.keep_setup_data) return LAMG_UNAVAILABLE;
+    return guarded([&]() -> lamg_status {
+        const Level &L = h->lev[level];
+        hipStream_t s = h->stream;
+        const int64_t n = L.n, nnz = L.nnz;
+        if (out->row_ptr) L.rp.download(out->row_ptr, n + 1, s);
+        if (out->col_idx) L.ci.download(out->col_idx, nnz, s);
+        if (out->val) L.val.download(out->val, nnz, s);
+        if (!L.coarsest) {
+            if (out->color) std::memcpy(out->color, L.h_color.data(), 4 * n);
+            if (out->strong) L.strong.download(out->strong, nnz, s);
+            if (out->x) L.X.download(out->x, n * kTV, s);
+            if (out->affinity) L.aff.download(out->affinity, nnz, s);
+            if (out->moments) L.mom.download(out->moments, n * 9, s);
+            if (out->seed) std::memcpy(out->seed, L.h_seed.data(), 4 * n);
+            if (out->aggregate) std::memcpy(out->aggregate, L.h_agg.data(), 4 * n);
+            if (out->p0) L.p0.download(out->p0, n, s);
+            if (out->p1) L.p1.download(out->p1, n, s);
+            if (out->w0) L.w0.download(out->w0, n, s);
+            if (out->w1) L.w1.download(out->w1, n, s);
+        }
+        LAMG_HIP(hipStreamSynchronize(s));
+        return LAMG_OK;
+    });
+}
+
+}  // extern "C"

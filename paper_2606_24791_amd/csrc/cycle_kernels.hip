@@ -1,0 +1,635 @@
+// Cycle kernels of the LAMG+ solve (Sec. 2, "Relaxation" and "Cycle and acceleration"):
+// multicolour Gauss-Seidel, residual, restriction P^T r, prolongation with the energy
+// correction, coarse and fine iterate recombination, the coarsest dense solve, and the
+// finest-level FP64 vector work of the solve and of the FP32 iterative refinement.
+//
+// Vectors with k right-hand sides are stored row-interleaved: x[i*k + c]. A row is
+// handled by a group of G = kp * lpr lanes (kp = k rounded up to a power of two,
+// lpr = lanes splitting the row's entries); lane g of a group takes column g % kp and
+// every lpr-th entry of the row, and the lpr partial sums are combined by cross-lane
+// shuffles. Matrix indices and values are read once per group and broadcast across
+// the kp column lanes.
+#include "lamg_internal.h"
+
+namespace lamg {
+
+namespace {
+
+inline unsigned blocks_for(int64_t work) {
+    int64_t b = (work + kBlock - 1) / kBlock;
+    return (unsigned)(b > 0 ? b : 1);
+}
+
+inline int ilog2(int x) {
+    int l = 0;
+    while ((1 << l) < x) ++l;
+    return l;
+}
+
+inline int kp_log2(int k) { return ilog2(k); }
+
+// Reduction over the `sub` lanes of a group (xor partners kp, 2kp, ..., G/2).
+template <class T>
+__device__ inline T group_sum(T v, int lkp, int G) {
+    for (int o = 1 << lkp; o < G; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+enum { OP_GS = 0, OP_RESID = 1, OP_SPMV = 2 };
+
+// One kernel body for the three CSR passes. Rows are r0 + (group index) or, with a row
+// list, rows[group index]. `skip_long` > 0 skips rows longer than it (handled by a
+// separate launch over a list).
+template <class T, int OP>
+__global__ void __launch_bounds__(kBlock)
+    k_csr(int64_t r0, int64_t nrows, const int32_t *__restrict__ rows, int skip_long,
+          const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const T *__restrict__ v,
+          const T *__restrict__ dd, const T *__restrict__ f, const T *xin, T *out, int k, int lkp,
+          int llpr) {
+    const int lg = lkp + llpr;
+    const int G = 1 << lg;
+    const int64_t grp = (int64_t)blockIdx.x * (kBlock >> lg) + (threadIdx.x >> lg);
+    const int g = threadIdx.x & (G - 1);
+    const int col = g & ((1 << lkp) - 1);
+    const int sub = g >> lkp;
+    const int lpr = 1 << llpr;
+    bool live = grp < nrows;
+    int64_t row = 0;
+    int32_t b = 0, e = 0;
+    if (live) {
+        row = rows ? (int64_t)rows[grp] : r0 + grp;
+        b = rp[row];
+        e = rp[row + 1];
+        if (skip_long > 0 && e - b > skip_long) live = false;
+    }
+    T acc = T(0);
+    if (live && col < k) {
+        for (int32_t j = b + sub; j < e; j += lpr) acc += v[j] * xin[(int64_t)ci[j] * k + col];
+    }
+    if (G > (1 << lkp)) acc = group_sum(acc, lkp, G);
+    if (!live || col >= k || sub != 0) return;
+    const int64_t o = row * k + col;
+    if (OP == OP_GS) {
+        out[o] = (f[o] - acc) * dd[row];
+    } else if (OP == OP_RESID) {
+        out[o] = f[o] - dd[row] * xin[o] - acc;
+    } else {
+        out[o] = acc;
+    }
+}
+
+template <class T, int OP>
+void launch_csr(int64_t r0, int64_t nrows, const int32_t *rows, int skip_long, const int32_t *rp,
+                const int32_t *ci, const T *v, const T *dd, const T *f, const T *xin, T *out, int k,
+                int lpr, hipStream_t s) {
+    if (nrows <= 0) return;
+    int lkp = kp_log2(k);
+    int llpr = ilog2(lpr);
+    if (lkp + llpr > 6) llpr = 6 - lkp;
+    if (llpr < 0) llpr = 0;
+    int lg = lkp + llpr;
+    int64_t groups_per_block = kBlock >> lg;
+    unsigned grid = (unsigned)((nrows + groups_per_block - 1) / groups_per_block);
+    k_csr<T, OP><<<grid, kBlock, 0, s>>>(r0, nrows, rows, skip_long, rp, ci, v, dd, f, xin, out, k,
+                                         lkp, llpr);
+    LAMG_LAUNCH_CHECK();
+}
+
+// Lanes per row for a row length: enough lanes to cover the row, capped by the group.
+inline int lanes_long(int k) { return 64 >> kp_log2(k); }
+
+// ---------------------------------------------------------------------------
+// Elementwise kernels
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_fill(T *x, int64_t n, T val) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = val;
+}
+
+template <class T>
+__global__ void k_copy(T *__restrict__ d, const T *__restrict__ s, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = s[i];
+}
+
+// x[u] += mu_c * (w0 e[p0] + w1 e[p1])   (energy-corrected prolongation)
+template <class T>
+__global__ void k_prolong(int64_t n, int k, const int32_t *__restrict__ p0,
+                          const int32_t *__restrict__ p1, const T *__restrict__ w0,
+                          const T *__restrict__ w1, const T *__restrict__ ec,
+                          const double *__restrict__ mu, T *__restrict__ x) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * k) return;
+    int64_t u = t / k;
+    int c = (int)(t - u * k);
+    T pe = w0[u] * ec[(int64_t)p0[u] * k + c];
+    int32_t q = p1[u];
+    if (q >= 0) pe += w1[u] * ec[(int64_t)q * k + c];
+    x[t] += (T)mu[c] * pe;
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic two-pass reductions: blocks write partial sums in a fixed order, one
+// block combines them in block order and finishes the per-column scalar.
+// Element mapping: block of 256 threads = (256/kp) rows x kp columns.
+// ---------------------------------------------------------------------------
+enum { R_MU = 0, R_RC2 = 1, R_NORM2 = 2, R_SUM = 3, R_MAXABS = 4, R_RCF = 5 };
+
+template <int R>
+struct RedQ;
+template <> struct RedQ<R_MU> { static constexpr int Q = 2; };
+template <> struct RedQ<R_RC2> { static constexpr int Q = 2; };
+template <> struct RedQ<R_NORM2> { static constexpr int Q = 1; };
+template <> struct RedQ<R_SUM> { static constexpr int Q = 1; };
+template <> struct RedQ<R_MAXABS> { static constexpr int Q = 1; };
+template <> struct RedQ<R_RCF> { static constexpr int Q = 14; };
+
+struct RedIn {
+    const void *a, *b, *c, *d;  // operand vectors (meaning per reduction)
+    int m;                      // RCF: history size
+    int64_t hstride;            // RCF: elements between history slots
+};
+
+template <class T, int R>
+__device__ inline void red_elem(const RedIn &in, int64_t o, double *q) {
+    if (R == R_MU) {  // a = e, b = fc, c = rho: <e,fc>, <e, fc - rho>
+        double e = (double)((const T *)in.a)[o], fc = (double)((const T *)in.b)[o];
+        double rho = (double)((const T *)in.c)[o];
+        q[0] += e * fc;
+        q[1] += e * (fc - rho);
+    } else if (R == R_RC2) {  // a = rho, b = rho1: G = rho - rho1: <G,G>, <G,rho>
+        double r = (double)((const T *)in.a)[o], r1 = (double)((const T *)in.b)[o];
+        double g = r - r1;
+        q[0] += g * g;
+        q[1] += g * r;
+    } else if (R == R_NORM2) {
+        double x = (double)((const T *)in.a)[o];
+        q[0] += x * x;
+    } else if (R == R_SUM) {
+        q[0] += (double)((const T *)in.a)[o];
+    } else if (R == R_MAXABS) {
+        q[0] = fmax(q[0], fabs((double)((const T *)in.a)[o]));
+    } else {  // RCF: a = r, b = history residuals (m slots): G_i = r - r_i
+        const double *r = (const double *)in.a;
+        const double *hr = (const double *)in.b;
+        double rv = r[o], G[4];
+        for (int i = 0; i < 4; ++i) G[i] = (i < in.m) ? rv - hr[i * in.hstride + o] : 0.0;
+        int t = 0;
+        for (int i = 0; i < 4; ++i)
+            for (int j = i; j < 4; ++j) q[t++] += G[i] * G[j];
+        for (int i = 0; i < 4; ++i) q[10 + i] += G[i] * rv;
+    }
+}
+
+template <class T, int R>
+__global__ void __launch_bounds__(kBlock)
+    k_red_partial(int64_t n, int k, int lkp, RedIn in, double *__restrict__ partial) {
+    constexpr int Q = RedQ<R>::Q;
+    __shared__ double sh[Q][kBlock];
+    const int kp = 1 << lkp;
+    const int col = threadIdx.x & (kp - 1);
+    const int rloc = threadIdx.x >> lkp;
+    const int rows_blk = kBlock >> lkp;
+    double q[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) q[i] = 0.0;
+    if (col < k) {
+        for (int64_t row = (int64_t)blockIdx.x * rows_blk + rloc; row < n;
+             row += (int64_t)gridDim.x * rows_blk)
+            red_elem<T, R>(in, row * k + col, q);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) sh[i][threadIdx.x] = q[i];
+    __syncthreads();
+    for (int st = rows_blk >> 1; st > 0; st >>= 1) {
+        if (rloc < st) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                if (R == R_MAXABS)
+                    sh[i][threadIdx.x] = fmax(sh[i][threadIdx.x], sh[i][threadIdx.x + (st << lkp)]);
+                else
+                    sh[i][threadIdx.x] += sh[i][threadIdx.x + (st << lkp)];
+            }
+        }
+        __syncthreads();
+    }
+    if (rloc == 0 && col < k) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) partial[((int64_t)blockIdx.x * Q + i) * k + col] = sh[i][threadIdx.x];
+    }
+}
+
+// Per-column finishers (one thread per column after the block totals are formed).
+struct Fin {
+    double *out;        // per-column result(s)
+    const double *aux;  // per-column auxiliary input (e.g. ||b|| for relres)
+    double scale;
+    int m;
+};
+
+__device__ inline void solve_rcf(const double *q, int m, double *alpha) {
+    // Jacobi-scaled normal equations of min ||r - sum a_i G_i||, Cholesky with pivots
+    // <= 1e-12 dropped (their a_i = 0).
+    double M[4][4], g[4], s[4], R[4][4], y[4], a[4];
+    bool keep[4];
+    int t = 0;
+    for (int i = 0; i < 4; ++i)
+        for (int j = i; j < 4; ++j) {
+            M[i][j] = q[t];
+            M[j][i] = q[t];
+            ++t;
+        }
+    for (int i = 0; i < 4; ++i) g[i] = q[10 + i];
+    for (int i = 0; i < m; ++i) {
+        keep[i] = M[i][i] > 0.0;
+        s[i] = keep[i] ? 1.0 / sqrt(M[i][i]) : 0.0;
+    }
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) R[i][j] = 0.0;
+    for (int j = 0; j < m; ++j) {
+        if (!keep[j]) continue;
+        double d = s[j] * M[j][j] * s[j];
+        for (int kk = 0; kk < j; ++kk)
+            if (keep[kk]) d -= R[j][kk] * R[j][kk];
+        if (!(d > 1e-12)) {
+            keep[j] = false;
+            continue;
+        }
+        R[j][j] = sqrt(d);
+        for (int i = j + 1; i < m; ++i) {
+            double v = s[i] * M[i][j] * s[j];
+            for (int kk = 0; kk < j; ++kk)
+                if (keep[kk]) v -= R[i][kk] * R[j][kk];
+            R[i][j] = v / R[j][j];
+        }
+    }
+    for (int i = 0; i < m; ++i) {
+        y[i] = 0.0;
+        if (!keep[i]) continue;
+        double v = s[i] * g[i];
+        for (int kk = 0; kk < i; ++kk)
+            if (keep[kk]) v -= R[i][kk] * y[kk];
+        y[i] = v / R[i][i];
+    }
+    for (int i = m - 1; i >= 0; --i) {
+        a[i] = 0.0;
+        if (!keep[i]) continue;
+        double v = y[i];
+        for (int kk = i + 1; kk < m; ++kk)
+            if (keep[kk]) v -= R[kk][i] * a[kk];
+        a[i] = v / R[i][i];
+    }
+    for (int i = 0; i < 4; ++i) alpha[i] = (i < m) ? a[i] * s[i] : 0.0;
+}
+
+template <int R>
+__global__ void __launch_bounds__(kBlock)
+    k_red_final(int nblk, int k, const double *__restrict__ partial, Fin fin) {
+    constexpr int Q = RedQ<R>::Q;
+    __shared__ double tot[Q * 32];
+    for (int idx = threadIdx.x; idx < Q * k; idx += blockDim.x) {
+        int i = idx / k, c = idx % k;
+        double s = (R == R_MAXABS) ? 0.0 : 0.0;
+        for (int b = 0; b < nblk; ++b) {
+            double v = partial[((int64_t)b * Q + i) * k + c];
+            if (R == R_MAXABS)
+                s = fmax(s, v);
+            else
+                s += v;
+        }
+        tot[i * 32 + c] = s;
+    }
+    __syncthreads();
+    int c = threadIdx.x;
+    if (c >= k) return;
+    if (R == R_MU) {
+        double num = tot[c], den = tot[32 + c];
+        double mu = num / den;
+        if (!(den > 0.0) || !isfinite(mu)) mu = 1.0;
+        fin.out[c] = mu;
+    } else if (R == R_RC2) {
+        double gg = tot[c], gr = tot[32 + c];
+        fin.out[c] = (gg > 0.0) ? gr / gg : 0.0;
+    } else if (R == R_NORM2) {
+        double v = sqrt(tot[c]);
+        fin.out[c] = fin.aux ? (fin.aux[c] > 0.0 ? v / fin.aux[c] : 0.0) : v;
+    } else if (R == R_SUM) {
+        fin.out[c] = fin.scale * tot[c];
+    } else if (R == R_MAXABS) {
+        fin.out[c] = tot[c];
+    } else {
+        double q[14];
+        for (int i = 0; i < 14; ++i) q[i] = tot[i * 32 + c];
+        solve_rcf(q, fin.m, fin.out + 4 * c);
+    }
+}
+
+inline int red_blocks(int64_t n, int k) {
+    int lkp = kp_log2(k);
+    int64_t rows_blk = kBlock >> lkp;
+    int64_t b = (n + rows_blk * 4 - 1) / (rows_blk * 4);
+    if (b < 1) b = 1;
+    if (b > kRedBlocksMax) b = kRedBlocksMax;
+    return (int)b;
+}
+
+template <class T, int R>
+void reduce(int64_t n, int k, RedIn in, double *partial, Fin fin, hipStream_t s) {
+    int nblk = red_blocks(n, k);
+    k_red_partial<T, R><<<nblk, kBlock, 0, s>>>(n, k, kp_log2(k), in, partial);
+    LAMG_LAUNCH_CHECK();
+    k_red_final<R><<<1, kBlock, 0, s>>>(nblk, k, partial, fin);
+    LAMG_LAUNCH_CHECK();
+}
+
+// e += alpha (e1 - e); rho -= alpha (rho - rho1)
+template <class T>
+__global__ void k_rc2_update(int64_t nk, int k, T *__restrict__ e, T *__restrict__ rho,
+                             const T *__restrict__ e1, const T *__restrict__ rho1,
+                             const double *__restrict__ alpha) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nk) return;
+    int c = (int)(t % k);
+    T a = (T)alpha[c];
+    T ev = e[t], rv = rho[t];
+    e[t] = ev + a * (e1[t] - ev);
+    rho[t] = rv - a * (rv - rho1[t]);
+}
+
+// Coarsest solve y = Z (f - mean f), then y -= mean y; one block per column, FP64.
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+    k_coarsest(int64_t n, const double *__restrict__ Z, const T *__restrict__ f, T *__restrict__ y,
+               int k) {
+    __shared__ double fs[1024];
+    __shared__ double red[kBlock];
+    const int c = blockIdx.x;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        double v = (double)f[i * k + c];
+        fs[i] = v;
+        s += v;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    double mf = red[0] / (double)n;
+    __syncthreads();
+    double ys[4] = {0, 0, 0, 0};
+    double my = 0.0;
+    for (int64_t i = threadIdx.x, r = 0; i < n; i += blockDim.x, ++r) {
+        double acc = 0.0;
+        for (int64_t j = 0; j < n; ++j) acc += Z[j * n + i] * (fs[j] - mf);  // Z symmetric
+        ys[r] = acc;
+        my += acc;
+    }
+    red[threadIdx.x] = my;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    double mean_y = red[0] / (double)n;
+    for (int64_t i = threadIdx.x, r = 0; i < n; i += blockDim.x, ++r) y[i * k + c] = (T)(ys[r] - mean_y);
+}
+
+// ---------------------------------------------------------------------------
+// Finest-level FP64 vector kernels
+// ---------------------------------------------------------------------------
+__global__ void k_gather_cols(int64_t n, int k, const int32_t *__restrict__ perm,
+                              const double *__restrict__ src, double *__restrict__ dst) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * k) return;
+    int64_t i = t / k;
+    int c = (int)(t - i * k);
+    dst[t] = src[(int64_t)c * n + perm[i]];
+}
+
+__global__ void k_scatter_cols(int64_t n, int k, const int32_t *__restrict__ perm,
+                               const double *__restrict__ src, const int32_t *__restrict__ mask,
+                               double *__restrict__ dst) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * k) return;
+    int64_t i = t / k;
+    int c = (int)(t - i * k);
+    if (mask && !mask[c]) return;
+    dst[(int64_t)c * n + perm[i]] = src[t];
+}
+
+__global__ void k_sub_col(int64_t nk, int k, double *__restrict__ x, const double *__restrict__ m) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nk) x[t] -= m[t % k];
+}
+
+// phi += sum_i a_i (phi_i - phi); r -= sum_i a_i (r - r_i)
+__global__ void k_rcf_update(int64_t nk, int k, int m, double *__restrict__ phi, double *__restrict__ r,
+                             const double *__restrict__ hphi, const double *__restrict__ hr,
+                             int64_t hstride, const double *__restrict__ alpha) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nk) return;
+    int c = (int)(t % k);
+    double p = phi[t], rv = r[t], dp = 0.0, dr = 0.0;
+    for (int i = 0; i < m; ++i) {
+        double a = alpha[4 * c + i];
+        dp += a * (hphi[i * hstride + t] - p);
+        dr += a * (rv - hr[i * hstride + t]);
+    }
+    phi[t] = p + dp;
+    r[t] = rv - dr;
+}
+
+__global__ void k_to_f32_scaled(int64_t nk, int k, const double *__restrict__ r,
+                                const double *__restrict__ sc, float *__restrict__ d) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nk) return;
+    double s = sc[t % k];
+    d[t] = (float)(s > 0.0 ? r[t] / s : 0.0);
+}
+
+__global__ void k_add_scaled_f32(int64_t nk, int k, const float *__restrict__ e,
+                                 const double *__restrict__ sc, double *__restrict__ phi) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nk) return;
+    phi[t] += sc[t % k] * (double)e[t];
+}
+
+__global__ void k_zero_cols(int64_t nk, int k, const int32_t *__restrict__ zmask, double *__restrict__ x) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nk) return;
+    if (zmask[t % k]) x[t] = 0.0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Cycle launchers
+// ---------------------------------------------------------------------------
+
+template <class T>
+void run_gs(const SolveOp &op, const T *v, const T *dinv, const T *f, T *x, int k, int sweeps,
+            hipStream_t s) {
+    const int nc = op.ncolors;
+    for (int sw = 0; sw < sweeps; ++sw) {
+        for (int c = 0; c < nc; ++c) {
+            int64_t a = op.blk[c], b = op.blk[c + 1];  // short rows of colour c
+            launch_csr<T, OP_GS>(a, b - a, nullptr, 0, op.rp.p, op.ci.p, v, dinv, f, x, x, k,
+                                 op.lpr_short, s);
+            int64_t la = op.blk[nc + c], lb = op.blk[nc + c + 1];  // long rows of colour c
+            launch_csr<T, OP_GS>(la, lb - la, nullptr, 0, op.rp.p, op.ci.p, v, dinv, f, x, x, k,
+                                 lanes_long(k), s);
+        }
+    }
+}
+
+template <class T>
+void run_residual(const SolveOp &op, const T *v, const T *d, const T *x, const T *f, T *r, int k,
+                  hipStream_t s) {
+    const int nc = op.ncolors;
+    int64_t nshort = op.blk[nc];
+    launch_csr<T, OP_RESID>(0, nshort, nullptr, 0, op.rp.p, op.ci.p, v, d, f, x, r, k, op.lpr_short, s);
+    launch_csr<T, OP_RESID>(nshort, op.n - nshort, nullptr, 0, op.rp.p, op.ci.p, v, d, f, x, r, k,
+                            lanes_long(k), s);
+}
+
+template <class T>
+void run_restrict(const SolveOp &op, const T *rw, const T *r, T *fc, int k, hipStream_t s) {
+    launch_csr<T, OP_SPMV>(0, op.nc, nullptr, op.n_rlong ? kLongRow : 0, op.rrp.p, op.rci.p, rw,
+                           nullptr, nullptr, r, fc, k, op.lpr_r, s);
+    if (op.n_rlong)
+        launch_csr<T, OP_SPMV>(0, op.n_rlong, op.rlong.p, 0, op.rrp.p, op.rci.p, rw, nullptr,
+                               nullptr, r, fc, k, lanes_long(k), s);
+}
+
+template <class T>
+void run_prolong(const SolveOp &op, const T *w0, const T *w1, const T *ec, const double *mu, T *x,
+                 int k, hipStream_t s) {
+    k_prolong<T><<<blocks_for(op.n * k), kBlock, 0, s>>>(op.n, k, op.p0.p, op.p1.p, w0, w1, ec, mu, x);
+    LAMG_LAUNCH_CHECK();
+}
+
+template <class T>
+void run_fill(T *x, int64_t count, T value, hipStream_t s) {
+    if (count <= 0) return;
+    k_fill<T><<<blocks_for(count), kBlock, 0, s>>>(x, count, value);
+    LAMG_LAUNCH_CHECK();
+}
+
+template <class T>
+void run_copy(T *dst, const T *src, int64_t count, hipStream_t s) {
+    if (count <= 0) return;
+    k_copy<T><<<blocks_for(count), kBlock, 0, s>>>(dst, src, count);
+    LAMG_LAUNCH_CHECK();
+}
+
+template <class T>
+void run_mu(int64_t n, const T *e, const T *f, const T *rho, int k, double *partial, double *mu,
+            hipStream_t s) {
+    RedIn in{e, f, rho, nullptr, 0, 0};
+    reduce<T, R_MU>(n, k, in, partial, Fin{mu, nullptr, 1.0, 0}, s);
+}
+
+template <class T>
+void run_rc2(int64_t n, T *e, T *rho, const T *e1, const T *rho1, int k, double *partial,
+             double *alpha, hipStream_t s) {
+    RedIn in{rho, rho1, nullptr, nullptr, 0, 0};
+    reduce<T, R_RC2>(n, k, in, partial, Fin{alpha, nullptr, 1.0, 0}, s);
+    k_rc2_update<T><<<blocks_for(n * k), kBlock, 0, s>>>(n * k, k, e, rho, e1, rho1, alpha);
+    LAMG_LAUNCH_CHECK();
+}
+
+template <class T>
+void run_coarsest(int64_t n, const double *Z, const T *f, T *y, int k, hipStream_t s) {
+    if (n > 1024) throw Error(LAMG_INVALID_ARG, "coarsest level larger than 1024");
+    k_coarsest<T><<<k, kBlock, 0, s>>>(n, Z, f, y, k);
+    LAMG_LAUNCH_CHECK();
+}
+
+void run_gather_cols(int64_t n, int k, const int32_t *perm, const double *src, double *dst,
+                     hipStream_t s) {
+    k_gather_cols<<<blocks_for(n * k), kBlock, 0, s>>>(n, k, perm, src, dst);
+    LAMG_LAUNCH_CHECK();
+}
+
+void run_scatter_cols(int64_t n, int k, const int32_t *perm, const double *src, const int32_t *mask,
+                      double *dst, hipStream_t s) {
+    k_scatter_cols<<<blocks_for(n * k), kBlock, 0, s>>>(n, k, perm, src, mask, dst);
+    LAMG_LAUNCH_CHECK();
+}
+
+void run_colsum(int64_t n, int k, const double *x, double *partial, double *out, double scale,
+                hipStream_t s) {
+    RedIn in{x, nullptr, nullptr, nullptr, 0, 0};
+    reduce<double, R_SUM>(n, k, in, partial, Fin{out, nullptr, scale, 0}, s);
+}
+
+void run_sub_col(int64_t n, int k, double *x, const double *m, hipStream_t s) {
+    k_sub_col<<<blocks_for(n * k), kBlock, 0, s>>>(n * k, k, x, m);
+    LAMG_LAUNCH_CHECK();
+}
+
+void run_norm2(int64_t n, int k, const double *x, double *partial, double *out, hipStream_t s) {
+    RedIn in{x, nullptr, nullptr, nullptr, 0, 0};
+    reduce<double, R_NORM2>(n, k, in, partial, Fin{out, nullptr, 1.0, 0}, s);
+}
+
+void run_maxabs(int64_t n, int k, const double *x, double *partial, double *out, hipStream_t s) {
+    RedIn in{x, nullptr, nullptr, nullptr, 0, 0};
+    reduce<double, R_MAXABS>(n, k, in, partial, Fin{out, nullptr, 1.0, 0}, s);
+}
+
+void run_relres(int64_t n, int k, const double *r, const double *nb, double *partial, double *out,
+                hipStream_t s) {
+    RedIn in{r, nullptr, nullptr, nullptr, 0, 0};
+    reduce<double, R_NORM2>(n, k, in, partial, Fin{out, nb, 1.0, 0}, s);
+}
+
+void run_recombine_fine(int64_t n, int k, int m, double *phi, double *r, const double *hphi,
+                        const double *hr, double *partial, double *alpha, hipStream_t s) {
+    if (m <= 0) return;
+    RedIn in{r, hr, nullptr, nullptr, m, n * k};
+    reduce<double, R_RCF>(n, k, in, partial, Fin{alpha, nullptr, 1.0, m}, s);
+    k_rcf_update<<<blocks_for(n * k), kBlock, 0, s>>>(n * k, k, m, phi, r, hphi, hr, n * k, alpha);
+    LAMG_LAUNCH_CHECK();
+}
+
+void run_to_f32_scaled(int64_t n, int k, const double *r, const double *scale, float *dst,
+                       hipStream_t s) {
+    k_to_f32_scaled<<<blocks_for(n * k), kBlock, 0, s>>>(n * k, k, r, scale, dst);
+    LAMG_LAUNCH_CHECK();
+}
+
+void run_add_scaled_f32(int64_t n, int k, const float *e, const double *scale, double *phi,
+                        hipStream_t s) {
+    k_add_scaled_f32<<<blocks_for(n * k), kBlock, 0, s>>>(n * k, k, e, scale, phi);
+    LAMG_LAUNCH_CHECK();
+}
+
+void run_zero_cols(int64_t n, int k, const int32_t *zero_mask, double *x, hipStream_t s) {
+    k_zero_cols<<<blocks_for(n * k), kBlock, 0, s>>>(n * k, k, zero_mask, x);
+    LAMG_LAUNCH_CHECK();
+}
+
+#define LAMG_INST(T)                                                                              \
+    template void run_gs<T>(const SolveOp &, const T *, const T *, const T *, T *, int, int,      \
+                            hipStream_t);                                                         \
+    template void run_residual<T>(const SolveOp &, const T *, const T *, const T *, const T *,    \
+                                  T *, int, hipStream_t);                                         \
+    template void run_restrict<T>(const SolveOp &, const T *, const T *, T *, int, hipStream_t);  \
+    template void run_prolong<T>(const SolveOp &, const T *, const T *, const T *,                \
+                                 const double *, T *, int, hipStream_t);                          \
+    template void run_fill<T>(T *, int64_t, T, hipStream_t);                                      \
+    template void run_copy<T>(T *, const T *, int64_t, hipStream_t);                              \
+    template void run_mu<T>(int64_t, const T *, const T *, const T *, int, double *, double *,    \
+                            hipStream_t);                                                         \
+    template void run_rc2<T>(int64_t, T *, T *, const T *, const T *, int, double *, double *,    \
+                             hipStream_t);                                                        \
+    template void run_coarsest<T>(int64_t, const double *, const T *, T *, int, hipStream_t);
+
+LAMG_INST(double)
+LAMG_INST(float)
+
+}  // namespace lamg

@@ -1,0 +1,292 @@
+// Internal declarations of liblamg: hierarchy and workspace layout, device-memory
+// ownership, and the kernel launchers shared by the host-side setup and solve code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "lamg.h"
+
+namespace lamg {
+
+constexpr int kTV = 4;              // test vectors per level (fixed K = 4, Sec. 3.3)
+constexpr int kTVSweeps = 3;        // relaxation sweeps per test vector (Sec. 2)
+constexpr double kGuardQ = 2.5;     // energy-ratio guard bound, eq. (2.3)
+constexpr double kTauSoc = 0.05;    // strength-of-connection threshold, eq. (3.1)
+constexpr double kSnap = 0.01;      // caliber-2 snapping band around 0 and 1
+constexpr int kMaxLevels = LAMG_MAX_LEVELS;
+constexpr int kStallDirectMax = 1024;  // a non-coarsening level up to this size is solved directly
+constexpr int kLongRow = 32;        // rows with more off-diagonals go to the wave-per-row bin
+constexpr int kBlock = 256;         // threads per block of every kernel
+constexpr int kRedBlocksMax = 256;  // partial-sum blocks of a reduction
+constexpr int kRedQMax = 14;        // quantities per reduction (4x4 normal equations + rhs)
+
+// Error carried from the point of failure to the C-ABI boundary.
+struct Error : std::runtime_error {
+    lamg_status status;
+    Error(lamg_status s, const std::string &what) : std::runtime_error(what), status(s) {}
+};
+
+#define LAMG_HIP(call)                                                                \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            throw ::lamg::Error(e_ == hipErrorOutOfMemory ? LAMG_OOM : LAMG_HIP_ERROR, \
+                                std::string(#call) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+#define LAMG_LAUNCH_CHECK() LAMG_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// Device memory through the (optional) allocator hook
+// ---------------------------------------------------------------------------
+
+struct Allocator {
+    lamg_alloc_fn alloc = nullptr;  // nullptr: hipMalloc
+    lamg_free_fn free = nullptr;
+    void *ctx = nullptr;
+};
+Allocator current_allocator();
+
+// Every device allocation of a handle goes through its Pool, which counts bytes and
+// releases everything on destruction.
+class Pool {
+  public:
+    explicit Pool(Allocator a, hipStream_t s) : a_(a), s_(s) {}
+    ~Pool();
+    Pool(const Pool &) = delete;
+    Pool &operator=(const Pool &) = delete;
+    void *get(size_t bytes);  // throws Error(LAMG_OOM)
+    void put(void *p);
+    int64_t bytes() const { return bytes_; }
+    hipStream_t stream() const { return s_; }
+    void set_stream(hipStream_t s) { s_ = s; }
+
+  private:
+    struct Blk {
+        void *p;
+        size_t bytes;
+    };
+    Allocator a_;
+    hipStream_t s_;
+    std::vector<Blk> blks_;
+    int64_t bytes_ = 0;
+};
+
+// Typed device array owned by a Pool.
+template <class T>
+struct DArr {
+    T *p = nullptr;
+    int64_t n = 0;
+    Pool *pool = nullptr;
+    DArr() = default;
+    DArr(const DArr &) = delete;
+    DArr &operator=(const DArr &) = delete;
+    DArr(DArr &&o) noexcept { *this = std::move(o); }
+    DArr &operator=(DArr &&o) noexcept {
+        if (this != &o) {
+            release();
+            p = o.p;
+            n = o.n;
+            pool = o.pool;
+            o.p = nullptr;
+            o.n = 0;
+            o.pool = nullptr;
+        }
+        return *this;
+    }
+    ~DArr() { release(); }
+    void alloc(Pool &pl, int64_t count) {
+        release();
+        pool = &pl;
+        n = count;
+        p = static_cast<T *>(pl.get(sizeof(T) * (size_t)(count > 0 ? count : 1)));
+    }
+    void release() {
+        if (p && pool) pool->put(p);
+        p = nullptr;
+        n = 0;
+    }
+    void upload(const T *h, int64_t count, hipStream_t s) {
+        if (count) LAMG_HIP(hipMemcpyAsync(p, h, sizeof(T) * (size_t)count, hipMemcpyHostToDevice, s));
+    }
+    void download(T *h, int64_t count, hipStream_t s) const {
+        if (count) LAMG_HIP(hipMemcpyAsync(h, p, sizeof(T) * (size_t)count, hipMemcpyDeviceToHost, s));
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Hierarchy
+// ---------------------------------------------------------------------------
+
+// Rows of one level in solve order. The solve numbering permutes the canonical nodes
+// by (row class, colour, canonical index): class 0 = rows with <= kLongRow
+// off-diagonals, class 1 = longer rows. Each (class, colour) block is contiguous, so a
+// Gauss-Seidel colour pass reads a contiguous slice of the matrix.
+struct SolveOp {
+    int64_t n = 0, nnz_off = 0;
+    int ncolors = 0;
+    std::vector<int64_t> blk;  // (2*ncolors + 1) offsets: class 0 colours, then class 1 colours
+    int lpr_short = 1;         // lanes per row of the short-row bin (k = 1)
+    DArr<int32_t> perm;        // solve index -> canonical index
+    DArr<int32_t> rp, ci;      // off-diagonal CSR in solve numbering
+    DArr<double> v64, d64, dinv64;
+    DArr<float> v32, d32, dinv32;
+    // interpolation from the next level, in both levels' solve numbering
+    DArr<int32_t> p0, p1;
+    DArr<double> w0_64, w1_64;
+    DArr<float> w0_32, w1_32;
+    // restriction P^T: coarse row -> (fine row, weight)
+    int64_t nc = 0;
+    DArr<int32_t> rrp, rci, rlong;
+    int64_t n_rlong = 0;
+    int lpr_r = 1;
+    DArr<double> rw64;
+    DArr<float> rw32;
+};
+
+struct Level {
+    int64_t n = 0, nnz = 0;  // canonical Laplacian size (diagonal included)
+    bool coarsest = false;
+    std::vector<int32_t> h_rp, h_ci;  // canonical pattern on the host
+    DArr<int32_t> rp, ci;             // canonical CSR on the device
+    DArr<double> val;
+    int ncolors = 0;
+    std::vector<int32_t> h_color;
+    DArr<int32_t> color;
+    DArr<uint8_t> strong;
+    DArr<double> X, aff, mom;
+    std::vector<int32_t> h_seed, h_agg;
+    DArr<int32_t> p0, p1;  // canonical interpolation (coarse ids canonical)
+    DArr<double> w0, w1;
+    int64_t nc = 0, n_cal2 = 0;
+    double gamma = 1.0, tau = 0.0;
+    SolveOp op;
+    DArr<double> Z;  // coarsest: (L + 11^T/n)^{-1}, n x n
+};
+
+// Per-level cycle vectors of one precision (n_l * k elements each).
+template <class T>
+struct LevelVecs {
+    DArr<T> x, f, r, rho, x1, rho1;
+    DArr<double> mu, alpha;  // k per level
+};
+
+// Cached solve workspace (grown on demand, per precision).
+struct Workspace {
+    int kf = 0;  // columns of the finest FP64 state
+    DArr<double> phi, b, r, b0, tmp, hphi, hr;  // n*k each; history holds 4 slots
+    DArr<double> nb, rel, scale, alpha_f, mean;  // per column
+    DArr<double> partial;                        // reduction scratch
+    DArr<int32_t> mask;                          // per column
+    double *h_rel = nullptr;                     // pinned host mirror (k)
+    int32_t *h_mask = nullptr;
+    int k64 = 0, k32 = 0;
+    std::vector<LevelVecs<double>> lv64;
+    std::vector<LevelVecs<float>> lv32;
+};
+
+}  // namespace lamg
+
+struct lamg_handle {
+    lamg::Allocator alloc;
+    std::unique_ptr<lamg::Pool> pool;
+    hipStream_t stream = nullptr;
+    lamg_options opt{};
+    int nlev = 0;
+    std::vector<lamg::Level> lev;
+    lamg::Workspace ws;
+    double setup_seconds = 0.0;
+    ~lamg_handle();
+};
+
+namespace lamg {
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (setup_kernels.hip): canonical arithmetic, bit-reproducible
+// ---------------------------------------------------------------------------
+void launch_laplacian(int64_t n, const int32_t *arp, const int32_t *aci, const double *aw,
+                      const int32_t *lrp, int32_t *lci, double *lv, hipStream_t s);
+void launch_strong(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, double tau,
+                   int enable_veto, uint8_t *strong, hipStream_t s);
+void launch_tv_init(int64_t n, uint64_t seed, int level, double *X, hipStream_t s);
+void launch_tv_sweep_color(int64_t cnt, const int32_t *rows, const int32_t *rp, const int32_t *ci,
+                           const double *v, double *X, hipStream_t s);
+void launch_affinity(int64_t n, const int32_t *rp, const int32_t *ci, const double *X,
+                     double *sigma_tmp, double *aff, hipStream_t s);
+void launch_moments(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                    const double *X, double *mom, hipStream_t s);
+void launch_interp(int64_t n, const int32_t *rp, const int32_t *ci, const uint8_t *strong,
+                   const double *X, const int32_t *seed, const int32_t *agg, const int32_t *aggseed,
+                   int enable_caliber2, double snap, int32_t *p0, double *w0, int32_t *p1,
+                   double *w1, hipStream_t s);
+// Galerkin operator; allocates the coarse CSR in `pool`. Returns coarse nnz.
+int64_t galerkin(Pool &pool, int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
+                 const double *v, int64_t nc, const int32_t *p0, const double *w0,
+                 const int32_t *p1, const double *w1, DArr<int32_t> &crp, DArr<int32_t> &cci,
+                 DArr<double> &cv, hipStream_t s);
+// Z = (L + 11^T/n)^{-1} by Gauss-Jordan elimination (SPD, no pivoting).
+void coarsest_inverse(Pool &pool, int64_t n, const int32_t *rp, const int32_t *ci,
+                      const double *v, double *Z, hipStream_t s);
+
+// Solve-layout builders
+void launch_permute_csr(int64_t n, const int32_t *perm, const int32_t *iperm, const int32_t *crp,
+                        const int32_t *cci, const double *cv, const int32_t *srp, int32_t *sci,
+                        double *sv64, float *sv32, double *d64, double *dinv64, float *d32,
+                        float *dinv32, hipStream_t s);
+void launch_cast_f32(int64_t n, const double *src, float *dst, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Cycle launchers (cycle_kernels.hip), T = double or float
+// ---------------------------------------------------------------------------
+template <class T>
+void run_gs(const SolveOp &op, const T *v, const T *dinv, const T *f, T *x, int k, int sweeps,
+            hipStream_t s);
+template <class T>
+void run_residual(const SolveOp &op, const T *v, const T *d, const T *x, const T *f, T *r, int k,
+                  hipStream_t s);
+template <class T>
+void run_restrict(const SolveOp &op, const T *rw, const T *r, T *fc, int k, hipStream_t s);
+template <class T>
+void run_prolong(const SolveOp &op, const T *w0, const T *w1, const T *ec, const double *mu,
+                 T *x, int k, hipStream_t s);
+template <class T>
+void run_fill(T *x, int64_t count, T value, hipStream_t s);
+template <class T>
+void run_copy(T *dst, const T *src, int64_t count, hipStream_t s);
+template <class T>
+void run_mu(int64_t n, const T *e, const T *f, const T *rho, int k, double *partial, double *mu,
+            hipStream_t s);
+template <class T>
+void run_rc2(int64_t n, T *e, T *rho, const T *e1, const T *rho1, int k, double *partial,
+             double *alpha, hipStream_t s);
+template <class T>
+void run_coarsest(int64_t n, const double *Z, const T *f, T *y, int k, hipStream_t s);
+
+// Finest-level FP64 helpers
+void run_gather_cols(int64_t n, int k, const int32_t *perm, const double *src_colmajor,
+                     double *dst, hipStream_t s);
+void run_scatter_cols(int64_t n, int k, const int32_t *perm, const double *src, const int32_t *mask,
+                      double *dst_colmajor, hipStream_t s);
+void run_colsum(int64_t n, int k, const double *x, double *partial, double *out, double scale,
+                hipStream_t s);  // out[c] = scale * sum_i x[i,c]
+void run_sub_col(int64_t n, int k, double *x, const double *m, hipStream_t s);  // x[:,c] -= m[c]
+void run_norm2(int64_t n, int k, const double *x, double *partial, double *out, hipStream_t s);
+void run_maxabs(int64_t n, int k, const double *x, double *partial, double *out, hipStream_t s);
+void run_relres(int64_t n, int k, const double *r, const double *nb, double *partial, double *out,
+                hipStream_t s);
+void run_recombine_fine(int64_t n, int k, int m, double *phi, double *r, const double *hphi,
+                        const double *hr, double *partial, double *alpha, hipStream_t s);
+void run_to_f32_scaled(int64_t n, int k, const double *r, const double *scale, float *dst,
+                       hipStream_t s);  // dst = r / scale[c]
+void run_add_scaled_f32(int64_t n, int k, const float *e, const double *scale, double *phi,
+                        hipStream_t s);  // phi += scale[c] * e
+void run_zero_cols(int64_t n, int k, const int32_t *zero_mask, double *x, hipStream_t s);
+
+}  // namespace lamg

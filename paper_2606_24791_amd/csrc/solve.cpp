@@ -1,0 +1,329 @@
+// Host orchestration of lamg_solve: the gamma-cycle recursion (Sec. 2, "Cycle and
+// acceleration"; eq. (2.4)), finest-level recombination, convergence tests, column
+// freezing, and the FP32-cycle / FP64-refinement driver. Every arithmetic step is a
+// kernel in cycle_kernels.hip; the host only sequences launches on the handle's stream
+// and reads one residual norm per column per cycle.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "lamg_internal.h"
+
+namespace lamg {
+
+namespace {
+
+template <class T>
+struct Prec;
+template <>
+struct Prec<double> {
+    static const double *v(const SolveOp &o) { return o.v64.p; }
+    static const double *d(const SolveOp &o) { return o.d64.p; }
+    static const double *dinv(const SolveOp &o) { return o.dinv64.p; }
+    static const double *w0(const SolveOp &o) { return o.w0_64.p; }
+    static const double *w1(const SolveOp &o) { return o.w1_64.p; }
+    static const double *rw(const SolveOp &o) { return o.rw64.p; }
+    static std::vector<LevelVecs<double>> &vecs(Workspace &w) { return w.lv64; }
+};
+template <>
+struct Prec<float> {
+    static const float *v(const SolveOp &o) { return o.v32.p; }
+    static const float *d(const SolveOp &o) { return o.d32.p; }
+    static const float *dinv(const SolveOp &o) { return o.dinv32.p; }
+    static const float *w0(const SolveOp &o) { return o.w0_32.p; }
+    static const float *w1(const SolveOp &o) { return o.w1_32.p; }
+    static const float *rw(const SolveOp &o) { return o.rw32.p; }
+    static std::vector<LevelVecs<float>> &vecs(Workspace &w) { return w.lv32; }
+};
+
+template <class T>
+struct Cycle {
+    lamg_handle *h;
+    int k;
+    hipStream_t s;
+    std::vector<LevelVecs<T>> *v;
+    std::vector<int64_t> visits;  // entries into each level's coarse-correction phase
+    double *partial;
+};
+
+// One gamma-cycle at level l on (x, f): (1,2) multicolour Gauss-Seidel, coarse
+// correction by `nvis` visits to level l+1 (Beatty counts of the fractional cycle index)
+// with two-iterate recombination across the visits, energy correction
+// mu = <e, fc> / <e, L_c e>, prolongation.
+template <class T>
+void cycle(Cycle<T> &C, int l, T *x, const T *f) {
+    lamg_handle *h = C.h;
+    const int k = C.k;
+    hipStream_t s = C.s;
+    Level &L = h->lev[l];
+    using P = Prec<T>;
+    if (L.coarsest) {
+        run_coarsest<T>(L.n, L.Z.p, f, x, k, s);
+        return;
+    }
+    const SolveOp &op = L.op;
+    Level &Lc = h->lev[l + 1];
+    const SolveOp &cop = Lc.op;
+    LevelVecs<T> &me = (*C.v)[l];
+    LevelVecs<T> &cv = (*C.v)[l + 1];
+    run_gs<T>(op, P::v(op), P::dinv(op), f, x, k, 1, s);
+    run_residual<T>(op, P::v(op), P::d(op), x, f, me.r.p, k, s);
+    run_restrict<T>(op, P::rw(op), me.r.p, cv.f.p, k, s);
+    int64_t i = C.visits[l]++;
+    int nvis = (int)(std::floor((double)(i + 1) * L.gamma) - std::floor((double)i * L.gamma));
+    run_fill<T>(cv.x.p, Lc.n * k, T(0), s);
+    for (int j = 1; j <= nvis; ++j) {
+        cycle<T>(C, l + 1, cv.x.p, cv.f.p);
+        run_residual<T>(cop, P::v(cop), P::d(cop), cv.x.p, cv.f.p, cv.rho.p, k, s);
+        if (j >= 2)
+            run_rc2<T>(Lc.n, cv.x.p, cv.rho.p, cv.x1.p, cv.rho1.p, k, C.partial, cv.alpha.p, s);
+        if (j < nvis) {
+            run_copy<T>(cv.x1.p, cv.x.p, Lc.n * k, s);
+            run_copy<T>(cv.rho1.p, cv.rho.p, Lc.n * k, s);
+        }
+    }
+    run_mu<T>(Lc.n, cv.x.p, cv.f.p, cv.rho.p, k, C.partial, me.mu.p, s);
+    run_prolong<T>(op, P::w0(op), P::w1(op), cv.x.p, me.mu.p, x, k, s);
+    run_gs<T>(op, P::v(op), P::dinv(op), f, x, k, 2, s);
+}
+
+template <class T>
+void ensure_level_vecs(lamg_handle *h, int k, std::vector<LevelVecs<T>> &lv, int &have_k) {
+    if (have_k >= k && (int)lv.size() == h->nlev) return;
+    Pool &pool = *h->pool;
+    lv.clear();
+    lv.resize(h->nlev);
+    for (int l = 0; l < h->nlev; ++l) {
+        int64_t m = h->lev[l].n * k;
+        lv[l].x.alloc(pool, m);
+        lv[l].f.alloc(pool, m);
+        lv[l].r.alloc(pool, m);
+        lv[l].rho.alloc(pool, m);
+        lv[l].x1.alloc(pool, m);
+        lv[l].rho1.alloc(pool, m);
+        lv[l].mu.alloc(pool, k);
+        lv[l].alpha.alloc(pool, k);
+    }
+    have_k = k;
+}
+
+void ensure_fine(lamg_handle *h, int k) {
+    Workspace &w = h->ws;
+    if (w.kf >= k) return;
+    Pool &pool = *h->pool;
+    int64_t m = h->lev[0].n * k;
+    w.phi.alloc(pool, m);
+    w.b.alloc(pool, m);
+    w.r.alloc(pool, m);
+    w.b0.alloc(pool, m);
+    w.tmp.alloc(pool, m);
+    w.hphi.alloc(pool, 4 * m);
+    w.hr.alloc(pool, 4 * m);
+    w.nb.alloc(pool, k);
+    w.rel.alloc(pool, k);
+    w.scale.alloc(pool, k);
+    w.alpha_f.alloc(pool, 4 * k);
+    w.mean.alloc(pool, k);
+    w.partial.alloc(pool, (int64_t)kRedBlocksMax * kRedQMax * k);
+    w.mask.alloc(pool, k);
+    if (w.h_rel) (void)hipHostFree(w.h_rel);
+    if (w.h_mask) (void)hipHostFree(w.h_mask);
+    w.h_rel = nullptr;
+    w.h_mask = nullptr;
+    LAMG_HIP(hipHostMalloc((void **)&w.h_rel, sizeof(double) * k));
+    LAMG_HIP(hipHostMalloc((void **)&w.h_mask, sizeof(int32_t) * k));
+    w.kf = k;
+}
+
+double acf_of(const std::vector<double> &hist) {
+    int last = (int)hist.size() - 1;
+    int cnt = std::min(last, 5);
+    if (cnt <= 0 || !(hist[last - cnt] > 0.0) || !(hist[last] > 0.0)) return 0.0;
+    return std::pow(hist[last] / hist[last - cnt], 1.0 / cnt);
+}
+
+// Projects (mean removal) the listed columns of phi and writes them to the caller's
+// column-major output.
+void emit_columns(lamg_handle *h, int k, const int32_t *d_mask, double *phi_out) {
+    Workspace &w = h->ws;
+    hipStream_t s = h->stream;
+    const int64_t n = h->lev[0].n;
+    run_copy<double>(w.tmp.p, w.phi.p, n * k, s);
+    run_colsum(n, k, w.tmp.p, w.partial.p, w.mean.p, 1.0 / (double)n, s);
+    run_sub_col(n, k, w.tmp.p, w.mean.p, s);
+    run_scatter_cols(n, k, h->lev[0].op.perm.p, w.tmp.p, d_mask, phi_out, s);
+}
+
+// One chunk of at most 32 columns.
+lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol, int max_cycles,
+                        bool fp32, double *phi_out, std::vector<double> &relres,
+                        std::vector<int32_t> &cycles, std::vector<double> &acf,
+                        std::vector<double> &hist0) {
+    hipStream_t s = h->stream;
+    Workspace &w = h->ws;
+    Level &L0 = h->lev[0];
+    const SolveOp &op0 = L0.op;
+    const int64_t n = L0.n;
+    const int64_t nk = n * k;
+    ensure_fine(h, k);
+    if (fp32)
+        ensure_level_vecs<float>(h, k, w.lv32, w.k32);
+    else
+        ensure_level_vecs<double>(h, k, w.lv64, w.k64);
+
+    // b <- P b, projected to mean zero (eq. (1.1)); ||b|| per column
+    run_gather_cols(n, k, op0.perm.p, b_user, w.b.p, s);
+    run_colsum(n, k, w.b.p, w.partial.p, w.mean.p, 1.0 / (double)n, s);
+    run_sub_col(n, k, w.b.p, w.mean.p, s);
+    run_copy<double>(w.b0.p, w.b.p, nk, s);
+    run_norm2(n, k, w.b.p, w.partial.p, w.nb.p, s);
+    std::vector<double> nb(k);
+    w.nb.download(nb.data(), k, s);
+    LAMG_HIP(hipStreamSynchronize(s));
+
+    std::vector<int32_t> active(k);
+    std::vector<std::vector<double>> hist(k);
+    int n_active = 0;
+    for (int c = 0; c < k; ++c) {
+        active[c] = nb[c] > 0.0 ? 1 : 0;
+        n_active += active[c];
+        hist[c].push_back(1.0);
+        cycles[c] = 0;
+    }
+    // zero columns: phi = 0; everything else starts from phi = 0, r = b
+    run_fill<double>(w.phi.p, nk, 0.0, s);
+    run_copy<double>(w.r.p, w.b.p, nk, s);
+    const bool direct = L0.coarsest;
+    const int kappa = std::max(0, std::min(4, (int)h->opt.kappa));
+    int hm = 0, hnext = 0;
+    if (!direct && kappa > 0) {  // history starts with (0, b)
+        run_fill<double>(w.hphi.p, nk, 0.0, s);
+        run_copy<double>(w.hr.p, w.b.p, nk, s);
+        hm = 1;
+        hnext = 1;
+    }
+    if (n_active < k) {  // columns with b = 0 finish immediately with phi = 0
+        for (int c = 0; c < k; ++c) w.h_mask[c] = active[c] ? 0 : 1;
+        w.mask.upload(w.h_mask, k, s);
+        run_scatter_cols(n, k, op0.perm.p, w.phi.p, w.mask.p, phi_out, s);
+    }
+
+    Cycle<double> c64{h, k, s, &w.lv64, std::vector<int64_t>(h->nlev, 0), w.partial.p};
+    Cycle<float> c32{h, k, s, &w.lv32, std::vector<int64_t>(h->nlev, 0), w.partial.p};
+    int cyc = 0;
+    while (n_active > 0 && cyc < max_cycles) {
+        if (!fp32) {
+            cycle<double>(c64, 0, w.phi.p, w.b.p);
+        } else {
+            // FP32 cycle on the scaled residual equation, FP64 update
+            run_maxabs(n, k, w.r.p, w.partial.p, w.scale.p, s);
+            LevelVecs<float> &v0 = w.lv32[0];
+            run_to_f32_scaled(n, k, w.r.p, w.scale.p, v0.f.p, s);
+            run_fill<float>(v0.x.p, nk, 0.0f, s);
+            cycle<float>(c32, 0, v0.x.p, v0.f.p);
+            run_add_scaled_f32(n, k, v0.x.p, w.scale.p, w.phi.p, s);
+        }
+        run_residual<double>(op0, op0.v64.p, op0.d64.p, w.phi.p, w.b.p, w.r.p, k, s);
+        if (!direct && kappa > 0) {
+            run_recombine_fine(n, k, hm, w.phi.p, w.r.p, w.hphi.p, w.hr.p, w.partial.p, w.alpha_f.p, s);
+            int slot = hnext % kappa;
+            run_copy<double>(w.hphi.p + slot * nk, w.phi.p, nk, s);
+            run_copy<double>(w.hr.p + slot * nk, w.r.p, nk, s);
+            ++hnext;
+            if (hm < kappa) ++hm;
+        }
+        ++cyc;
+        run_relres(n, k, w.r.p, w.nb.p, w.partial.p, w.rel.p, s);
+        w.rel.download(w.h_rel, k, s);
+        LAMG_HIP(hipStreamSynchronize(s));
+        bool any_new = false;
+        for (int c = 0; c < k; ++c) {
+            w.h_mask[c] = 0;
+            if (!active[c]) continue;
+            double rel = w.h_rel[c];
+            hist[c].push_back(rel);
+            cycles[c] = cyc;
+            if (rel <= tol || !std::isfinite(rel)) {
+                active[c] = 0;
+                --n_active;
+                w.h_mask[c] = 1;
+                any_new = true;
+            }
+        }
+        if (any_new) {
+            // freeze: emit the converged columns, then zero their state so later cycles
+            // leave them untouched
+            w.mask.upload(w.h_mask, k, s);
+            emit_columns(h, k, w.mask.p, phi_out);
+            run_zero_cols(n, k, w.mask.p, w.phi.p, s);
+            run_zero_cols(n, k, w.mask.p, w.b.p, s);
+            run_zero_cols(n, k, w.mask.p, w.r.p, s);
+            for (int i = 0; i < hm; ++i) {
+                run_zero_cols(n, k, w.mask.p, w.hphi.p + i * nk, s);
+                run_zero_cols(n, k, w.mask.p, w.hr.p + i * nk, s);
+            }
+        }
+    }
+    lamg_status st = LAMG_OK;
+    if (n_active > 0) {
+        for (int c = 0; c < k; ++c) w.h_mask[c] = active[c];
+        w.mask.upload(w.h_mask, k, s);
+        emit_columns(h, k, w.mask.p, phi_out);
+        st = LAMG_NOT_CONVERGED;
+    }
+    // true residual of the returned phi
+    run_gather_cols(n, k, op0.perm.p, phi_out, w.phi.p, s);
+    run_residual<double>(op0, op0.v64.p, op0.d64.p, w.phi.p, w.b0.p, w.r.p, k, s);
+    run_relres(n, k, w.r.p, w.nb.p, w.partial.p, w.rel.p, s);
+    w.rel.download(w.h_rel, k, s);
+    LAMG_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < k; ++c) {
+        relres[c] = nb[c] > 0.0 ? w.h_rel[c] : 0.0;
+        acf[c] = acf_of(hist[c]);
+    }
+    hist0 = hist[0];
+    return st;
+}
+
+}  // namespace
+
+lamg_status run_solve(lamg_handle *h, const double *b, int nrhs, double tol, int max_cycles,
+                      lamg_precision prec, double *phi, lamg_solve_info *info) {
+    auto t0 = std::chrono::steady_clock::now();
+    const bool fp32 = prec == LAMG_FP32_IR;
+    if (fp32 && !h->opt.build_fp32) throw Error(LAMG_INVALID_ARG, "FP32 copies were not built");
+    if (max_cycles <= 0) max_cycles = 300;
+    const int64_t n = h->lev[0].n;
+    lamg_status st = LAMG_OK;
+    int32_t cyc_max = 0;
+    double rel_max = 0.0, acf_max = 0.0;
+    std::vector<double> hist0;
+    for (int c0 = 0; c0 < nrhs; c0 += 32) {
+        int k = std::min(32, nrhs - c0);
+        std::vector<double> rel(k), acf(k), hist;
+        std::vector<int32_t> cyc(k);
+        lamg_status s2 = solve_chunk(h, b + (int64_t)c0 * n, k, tol, max_cycles, fp32,
+                                     phi + (int64_t)c0 * n, rel, cyc, acf, hist);
+        if (s2 != LAMG_OK) st = s2;
+        if (c0 == 0) hist0 = hist;
+        for (int c = 0; c < k; ++c) {
+            cyc_max = std::max(cyc_max, cyc[c]);
+            rel_max = std::max(rel_max, rel[c]);
+            acf_max = std::max(acf_max, acf[c]);
+            if (info && info->relres) info->relres[c0 + c] = rel[c];
+            if (info && info->col_cycles) info->col_cycles[c0 + c] = cyc[c];
+        }
+    }
+    if (info) {
+        info->cycles = cyc_max;
+        info->relres_max = rel_max;
+        info->acf_max = acf_max;
+        info->history_len = (int32_t)std::min<size_t>(hist0.size(), (size_t)max_cycles + 1);
+        if (info->history)
+            for (int i = 0; i < info->history_len; ++i) info->history[i] = hist0[i];
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return st;
+}
+
+}  // namespace lamg

@@ -1,0 +1,284 @@
+"""Python binding of liblamg (include/lamg.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls. Device memory and
+streams come from PyTorch (ROCm); every step of setup and solve runs inside the HIP
+library. If liblamg.so has not been built, importing this module raises ImportError:
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from pathlib import Path
+
+import numpy as np
+
+_LIB_PATH = Path(__file__).resolve().parent / "liblamg.so"
+if not _LIB_PATH.exists():
+    raise ImportError(f"{_LIB_PATH} is not built (run __graft_entry__.build())")
+_lib = C.CDLL(str(_LIB_PATH))
+
+MAX_LEVELS = 64
+
+(OK, INVALID_ARG, NOT_SYMMETRIC, SELF_LOOP, BAD_WEIGHT, DISCONNECTED, OOM, COARSENING_STALLED,
+ NOT_CONVERGED, HIP_ERROR, UNAVAILABLE) = range(11)
+MEM_HOST, MEM_DEVICE = 0, 1
+FP64, FP32_IR = 0, 1
+
+
+class lamg_graph(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("row_ptr", C.c_void_p),
+                ("col_idx", C.c_void_p), ("weight", C.c_void_p), ("mem", C.c_int32)]
+
+
+class lamg_options(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("n_direct", C.c_int32), ("enable_veto", C.c_int32),
+                ("enable_caliber2", C.c_int32), ("kappa", C.c_int32), ("build_fp32", C.c_int32),
+                ("keep_setup_data", C.c_int32)]
+
+
+class lamg_hier_info(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("n", C.c_int64 * MAX_LEVELS),
+                ("nnz", C.c_int64 * MAX_LEVELS), ("ncolors", C.c_int32 * MAX_LEVELS),
+                ("n_caliber2", C.c_int64 * MAX_LEVELS), ("gamma", C.c_double * MAX_LEVELS),
+                ("tau", C.c_double * MAX_LEVELS), ("bytes_device", C.c_int64),
+                ("op_complexity", C.c_double), ("setup_seconds", C.c_double)]
+
+
+class lamg_solve_info(C.Structure):
+    _fields_ = [("cycles", C.c_int32), ("relres_max", C.c_double), ("acf_max", C.c_double),
+                ("seconds", C.c_double), ("relres", C.c_void_p), ("col_cycles", C.c_void_p),
+                ("history", C.c_void_p), ("history_len", C.c_int32)]
+
+
+class lamg_level_export(C.Structure):
+    _fields_ = [(name, C.c_void_p) for name in (
+        "row_ptr", "col_idx", "val", "color", "strong", "x", "affinity", "moments", "seed",
+        "aggregate", "p0", "p1", "w0", "w1")]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+_lib.lamg_set_allocator.argtypes = [ALLOC_FN, FREE_FN, C.c_void_p]
+_lib.lamg_set_allocator.restype = None
+_lib.lamg_status_string.argtypes = [C.c_int]
+_lib.lamg_status_string.restype = C.c_char_p
+_lib.lamg_version.argtypes = []
+_lib.lamg_version.restype = C.c_char_p
+_lib.lamg_default_options.argtypes = [C.POINTER(lamg_options)]
+_lib.lamg_default_options.restype = None
+_lib.lamg_setup.argtypes = [C.POINTER(lamg_graph), C.POINTER(lamg_options), C.c_void_p,
+                            C.POINTER(C.c_void_p)]
+_lib.lamg_setup.restype = C.c_int
+_lib.lamg_solve.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_int32, C.c_int,
+                            C.c_void_p, C.POINTER(lamg_solve_info), C.c_void_p]
+_lib.lamg_solve.restype = C.c_int
+_lib.lamg_destroy.argtypes = [C.c_void_p]
+_lib.lamg_destroy.restype = None
+_lib.lamg_hierarchy_info.argtypes = [C.c_void_p, C.POINTER(lamg_hier_info)]
+_lib.lamg_hierarchy_info.restype = C.c_int
+_lib.lamg_export_level.argtypes = [C.c_void_p, C.c_int32, C.POINTER(lamg_level_export)]
+_lib.lamg_export_level.restype = C.c_int
+
+
+class LamgError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {lamg_status_string(status)} ({status})")
+        self.status = status
+
+
+def library_path() -> str:
+    return str(_LIB_PATH)
+
+
+def lamg_status_string(status: int) -> str:
+    return _lib.lamg_status_string(int(status)).decode()
+
+
+def lamg_version() -> str:
+    return _lib.lamg_version().decode()
+
+
+def lamg_default_options(**overrides) -> lamg_options:
+    o = lamg_options()
+    _lib.lamg_default_options(C.byref(o))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, int(v))
+    return o
+
+
+_alloc_keepalive = []
+
+
+def lamg_set_allocator(alloc=None, free=None, ctx=None) -> None:
+    """Routes the library's device allocations through alloc(bytes, stream, ctx) /
+    free(ptr, stream, ctx) (ctypes-callable), or back to hipMalloc with no arguments."""
+    if alloc is None:
+        _lib.lamg_set_allocator(ALLOC_FN(0), FREE_FN(0), None)
+        _alloc_keepalive.clear()
+        return
+    a, f = ALLOC_FN(alloc), FREE_FN(free)
+    _alloc_keepalive[:] = [a, f]
+    _lib.lamg_set_allocator(a, f, ctx)
+
+
+def _stream_ptr(stream) -> int | None:
+    if stream is None:
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Handle:
+    """Owns a lamg_handle*; lamg_destroy runs when it is closed or collected."""
+
+    def __init__(self, ptr: C.c_void_p, n: int):
+        self._ptr = ptr
+        self.n = n
+
+    @property
+    def ptr(self):
+        if not self._ptr:
+            raise ValueError("handle is closed")
+        return self._ptr
+
+    def close(self):
+        if self._ptr:
+            _lib.lamg_destroy(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _graph_struct(graph, device: bool, keep: list) -> lamg_graph:
+    g = lamg_graph()
+    g.n = int(graph.n)
+    g.nnz = int(graph.row_ptr[-1])
+    if device:
+        import torch
+
+        rp = torch.as_tensor(np.ascontiguousarray(graph.row_ptr, np.int32), device="cuda")
+        ci = torch.as_tensor(np.ascontiguousarray(graph.col_idx, np.int32), device="cuda")
+        w = torch.as_tensor(np.ascontiguousarray(graph.weight, np.float64), device="cuda")
+        keep += [rp, ci, w]
+        g.row_ptr, g.col_idx, g.weight = rp.data_ptr(), ci.data_ptr(), w.data_ptr()
+        g.mem = MEM_DEVICE
+    else:
+        rp = np.ascontiguousarray(graph.row_ptr, np.int32)
+        ci = np.ascontiguousarray(graph.col_idx, np.int32)
+        w = np.ascontiguousarray(graph.weight, np.float64)
+        keep += [rp, ci, w]
+        g.row_ptr, g.col_idx, g.weight = rp.ctypes.data, ci.ctypes.data, w.ctypes.data
+        g.mem = MEM_HOST
+    return g
+
+
+def lamg_setup(graph, options: lamg_options | None = None, stream=None, device_input=False,
+               raw_stream: int | None = None) -> Handle:
+    """Builds the hierarchy of `graph` (an inputs.Graph or any object with n, row_ptr,
+    col_idx, weight). Raises LamgError on a non-OK status."""
+    keep: list = []
+    g = _graph_struct(graph, device_input, keep)
+    out = C.c_void_p()
+    s = raw_stream if raw_stream is not None else _stream_ptr(stream)
+    st = _lib.lamg_setup(C.byref(g), C.byref(options) if options is not None else None, s,
+                         C.byref(out))
+    if st != OK:
+        raise LamgError(st, "lamg_setup")
+    return Handle(out, int(graph.n))
+
+
+def lamg_setup_status(graph, options: lamg_options | None = None) -> int:
+    """Status of lamg_setup on a host-memory graph, without raising (input checks)."""
+    keep: list = []
+    g = _graph_struct(graph, False, keep)
+    out = C.c_void_p()
+    st = _lib.lamg_setup(C.byref(g), C.byref(options) if options is not None else None, None,
+                         C.byref(out))
+    if st == OK:
+        _lib.lamg_destroy(out)
+    return st
+
+
+def lamg_solve(h: Handle, b, phi, tol: float = 1e-8, max_cycles: int = 300,
+               precision: int = FP64, stream=None, history: bool = False, check: bool = True):
+    """Solves for the columns of b: torch float64 device tensors of shape (k, n) (row j is
+    right-hand side j) or (n,). phi receives the solutions. Returns a dict of statistics."""
+    import torch
+
+    if b.dtype != torch.float64 or phi.dtype != torch.float64 or not b.is_cuda or not phi.is_cuda:
+        raise TypeError("b and phi must be float64 CUDA tensors")
+    if not b.is_contiguous() or not phi.is_contiguous() or b.shape != phi.shape:
+        raise ValueError("b and phi must be contiguous and of equal shape")
+    k = 1 if b.dim() == 1 else int(b.shape[0])
+    n = int(b.shape[-1])
+    if n != h.n:
+        raise ValueError(f"right-hand side length {n} != graph size {h.n}")
+    rel = np.zeros(k)
+    cyc = np.zeros(k, np.int32)
+    hist = np.zeros(max(max_cycles, 300) + 1) if history else None
+    info = lamg_solve_info()
+    info.relres = rel.ctypes.data
+    info.col_cycles = cyc.ctypes.data
+    info.history = hist.ctypes.data if hist is not None else None
+    st = _lib.lamg_solve(h.ptr, b.data_ptr(), k, float(tol), int(max_cycles), int(precision),
+                         phi.data_ptr(), C.byref(info), _stream_ptr(stream))
+    if check and st not in (OK, NOT_CONVERGED):
+        raise LamgError(st, "lamg_solve")
+    out = dict(status=st, converged=(st == OK), cycles=int(info.cycles),
+               relres_max=float(info.relres_max), acf_max=float(info.acf_max),
+               seconds=float(info.seconds), relres=rel, col_cycles=cyc)
+    if hist is not None:
+        out["history"] = hist[: info.history_len].copy()
+    return out
+
+
+def lamg_destroy(h: Handle) -> None:
+    h.close()
+
+
+def lamg_hierarchy_info(h: Handle) -> dict:
+    info = lamg_hier_info()
+    st = _lib.lamg_hierarchy_info(h.ptr, C.byref(info))
+    if st != OK:
+        raise LamgError(st, "lamg_hierarchy_info")
+    L = info.levels
+    return dict(levels=L, n=list(info.n[:L]), nnz=list(info.nnz[:L]),
+                ncolors=list(info.ncolors[:L]), n_caliber2=list(info.n_caliber2[:L]),
+                gamma=list(info.gamma[:L]), tau=list(info.tau[:L]),
+                bytes_device=int(info.bytes_device), op_complexity=float(info.op_complexity),
+                setup_seconds=float(info.setup_seconds))
+
+
+def lamg_export_level(h: Handle, level: int) -> dict:
+    """Copies one level (canonical operator and every setup artefact) to numpy arrays.
+    Needs keep_setup_data=1 at setup."""
+    hi = lamg_hierarchy_info(h)
+    if not 0 <= level < hi["levels"]:
+        raise IndexError(level)
+    n, nnz = hi["n"][level], hi["nnz"][level]
+    last = level == hi["levels"] - 1
+    arrs = dict(row_ptr=np.empty(n + 1, np.int32), col_idx=np.empty(nnz, np.int32),
+                val=np.empty(nnz))
+    if not last:
+        arrs.update(color=np.empty(n, np.int32), strong=np.empty(nnz, np.uint8),
+                    x=np.empty((n, 4)), affinity=np.empty(nnz), moments=np.empty((n, 9)),
+                    seed=np.empty(n, np.int32), aggregate=np.empty(n, np.int32),
+                    p0=np.empty(n, np.int32), p1=np.empty(n, np.int32), w0=np.empty(n),
+                    w1=np.empty(n))
+    ex = lamg_level_export()
+    for name, a in arrs.items():
+        setattr(ex, name, a.ctypes.data)
+    st = _lib.lamg_export_level(h.ptr, int(level), C.byref(ex))
+    if st != OK:
+        raise LamgError(st, "lamg_export_level")
+    return arrs
