@@ -83,6 +83,10 @@ typedef struct {
     int32_t build_fp32;      /* also build FP32 copies of every level for LAMG_FP32_IR (default 1) */
     int32_t keep_setup_data; /* keep canonical operators, colours, strong flags, test vectors,
                                 affinities, moments and aggregates for lamg_export_level (default 0) */
+    int32_t tail_rows;       /* levels below the finest with at most this many nodes run their
+                                whole cycle in one single-workgroup launch per visit
+                                (default 2500; 0 = every step is its own kernel). Changes only
+                                how the cycle is executed, not what it computes. */
 } lamg_options;
 
 /* Per-level description of a hierarchy. */
@@ -187,6 +191,28 @@ lamg_status lamg_hierarchy_info(const lamg_handle *h, lamg_hier_info *info);
 /* Copies level `level` to the caller's host buffers (see lamg_level_export). Requires
  * keep_setup_data = 1 at setup, else LAMG_UNAVAILABLE. Errors: INVALID_ARG (bad level). */
 lamg_status lamg_export_level(const lamg_handle *h, int32_t level, lamg_level_export *out);
+
+/* Cycle kernels that lamg_profile_kernel can time. */
+typedef enum {
+    LAMG_KERNEL_GS_COLOR = 0, /* one Gauss-Seidel colour pass (colour 0) of the level */
+    LAMG_KERNEL_RESIDUAL = 1, /* r = f - L x over the whole level */
+    LAMG_KERNEL_RESTRICT = 2, /* f_c = P^T r from the level to the next */
+    LAMG_KERNEL_PROLONG = 3   /* x += mu P e_c from the next level */
+} lamg_kernel;
+
+/* Measurement aid for roofline reporting: launches one cycle kernel of level `level`
+ * `reps` times back to back on `stream` between two HIP events, with nrhs columns in the
+ * arithmetic of `prec` (FP64, or FP32 for LAMG_FP32_IR), and writes the mean launch
+ * duration in seconds and the kernel's algorithmic bytes per launch: compulsory traffic
+ * only (every matrix index and value, row pointer and diagonal once, every vector element
+ * the launch reads or writes once). Uses the handle's cached workspace, whose contents it
+ * overwrites; the hierarchy is unchanged. Errors: INVALID_ARG (level out of range, the
+ * directly solved level for GS/RESTRICT/PROLONG, nrhs outside 1..32, reps < 1), OOM,
+ * HIP_ERROR. */
+lamg_status lamg_profile_kernel(lamg_handle *h, int32_t level, lamg_kernel kernel,
+                                lamg_precision prec, int32_t nrhs, int32_t reps,
+                                double *seconds_per_launch, double *bytes_per_launch,
+                                void *stream);
 
 #ifdef __cplusplus
 }

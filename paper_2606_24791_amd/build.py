@@ -28,6 +28,7 @@ SOURCES = {
     "setup_kernels.hip": ["-ffp-contract=off"],
     "setup.cpp": ["-ffp-contract=off", "-x", "hip"],
     "cycle_kernels.hip": [],
+    "tail_kernel.hip": [],
     "solve.cpp": ["-x", "hip"],
     "api.cpp": ["-x", "hip"],
 }

@@ -10,6 +10,8 @@ namespace lamg {
 void run_setup(lamg_handle *h, const lamg_graph *g);
 lamg_status run_solve(lamg_handle *h, const double *b, int nrhs, double tol, int max_cycles,
                       lamg_precision prec, double *phi, lamg_solve_info *info);
+lamg_status run_profile(lamg_handle *h, int level, int kernel, lamg_precision prec, int k,
+                        int reps, double *sec, double *bytes);
 
 static std::mutex g_alloc_mu;
 static Allocator g_alloc;
@@ -125,6 +127,7 @@ void lamg_default_options(lamg_options *opt) {
     opt->kappa = 4;
     opt->build_fp32 = 1;
     opt->keep_setup_data = 0;
+    opt->tail_rows = 2500;
 }
 
 lamg_status lamg_setup(const lamg_graph *g, const lamg_options *opt, void *stream,
@@ -135,7 +138,8 @@ lamg_status lamg_setup(const lamg_graph *g, const lamg_options *opt, void *strea
     lamg_options o;
     lamg_default_options(&o);
     if (opt) o = *opt;
-    if (o.n_direct < 1 || o.n_direct > 1024 || o.kappa < 0 || o.kappa > 4) return LAMG_INVALID_ARG;
+    if (o.n_direct < 1 || o.n_direct > 1024 || o.kappa < 0 || o.kappa > 4 || o.tail_rows < 0)
+        return LAMG_INVALID_ARG;
     lamg_handle *h = nullptr;
     lamg_status st = guarded([&]() -> lamg_status {
         h = new lamg_handle();
@@ -168,6 +172,19 @@ lamg_status lamg_solve(lamg_handle *h, const double *b, int32_t nrhs, double tol
         h->stream = (hipStream_t)stream;
         h->pool->set_stream(h->stream);
         return run_solve(h, b, nrhs, tol, max_cycles, prec, phi, info);
+    });
+}
+
+lamg_status lamg_profile_kernel(lamg_handle *h, int32_t level, lamg_kernel kernel,
+                                lamg_precision prec, int32_t nrhs, int32_t reps,
+                                double *seconds_per_launch, double *bytes_per_launch,
+                                void *stream) {
+    if (!h || !seconds_per_launch || !bytes_per_launch) return LAMG_INVALID_ARG;
+    return guarded([&]() -> lamg_status {
+        h->stream = (hipStream_t)stream;
+        h->pool->set_stream(h->stream);
+        return run_profile(h, level, (int)kernel, prec, nrhs, reps, seconds_per_launch,
+                           bytes_per_launch);
     });
 }
 

@@ -40,7 +40,7 @@ enum { OP_GS = 0, OP_RESID = 1, OP_SPMV = 2 };
 // One kernel body for the three CSR passes. Rows are r0 + (group index) or, with a row
 // list, rows[group index]. `skip_long` > 0 skips rows longer than it (handled by a
 // separate launch over a list).
-template <class T, int OP>
+template <class T, int OP, int FINE>
 __global__ void __launch_bounds__(kBlock)
     k_csr(int64_t r0, int64_t nrows, const int32_t *__restrict__ rows, int skip_long,
           const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const T *__restrict__ v,
@@ -78,7 +78,9 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
-template <class T, int OP>
+// FINE = 1 marks launches on the finest level: the code is identical, the separate
+// symbol lets a kernel trace attribute finest-level time on its own.
+template <class T, int OP, int FINE = 0>
 void launch_csr(int64_t r0, int64_t nrows, const int32_t *rows, int skip_long, const int32_t *rp,
                 const int32_t *ci, const T *v, const T *dd, const T *f, const T *xin, T *out, int k,
                 int lpr, hipStream_t s) {
@@ -90,8 +92,8 @@ void launch_csr(int64_t r0, int64_t nrows, const int32_t *rows, int skip_long, c
     int lg = lkp + llpr;
     int64_t groups_per_block = kBlock >> lg;
     unsigned grid = (unsigned)((nrows + groups_per_block - 1) / groups_per_block);
-    k_csr<T, OP><<<grid, kBlock, 0, s>>>(r0, nrows, rows, skip_long, rp, ci, v, dd, f, xin, out, k,
-                                         lkp, llpr);
+    k_csr<T, OP, FINE><<<grid, kBlock, 0, s>>>(r0, nrows, rows, skip_long, rp, ci, v, dd, f, xin,
+                                               out, k, lkp, llpr);
     LAMG_LAUNCH_CHECK();
 }
 
@@ -469,30 +471,57 @@ __global__ void k_zero_cols(int64_t nk, int k, const int32_t *__restrict__ zmask
 // Cycle launchers
 // ---------------------------------------------------------------------------
 
+template <class T, int FINE>
+static void gs_color(const SolveOp &op, int c, const T *v, const T *dinv, const T *f, T *x, int k,
+                     hipStream_t s) {
+    const int nc = op.ncolors;
+    int64_t a = op.blk[c], b = op.blk[c + 1];  // short rows of colour c
+    launch_csr<T, OP_GS, FINE>(a, b - a, nullptr, 0, op.rp.p, op.ci.p, v, dinv, f, x, x, k,
+                               op.lpr_short, s);
+    int64_t la = op.blk[nc + c], lb = op.blk[nc + c + 1];  // long rows of colour c
+    launch_csr<T, OP_GS, FINE>(la, lb - la, nullptr, 0, op.rp.p, op.ci.p, v, dinv, f, x, x, k,
+                               lanes_long(k), s);
+}
+
 template <class T>
 void run_gs(const SolveOp &op, const T *v, const T *dinv, const T *f, T *x, int k, int sweeps,
-            hipStream_t s) {
-    const int nc = op.ncolors;
-    for (int sw = 0; sw < sweeps; ++sw) {
-        for (int c = 0; c < nc; ++c) {
-            int64_t a = op.blk[c], b = op.blk[c + 1];  // short rows of colour c
-            launch_csr<T, OP_GS>(a, b - a, nullptr, 0, op.rp.p, op.ci.p, v, dinv, f, x, x, k,
-                                 op.lpr_short, s);
-            int64_t la = op.blk[nc + c], lb = op.blk[nc + c + 1];  // long rows of colour c
-            launch_csr<T, OP_GS>(la, lb - la, nullptr, 0, op.rp.p, op.ci.p, v, dinv, f, x, x, k,
-                                 lanes_long(k), s);
+            hipStream_t s, bool fine) {
+    for (int sw = 0; sw < sweeps; ++sw)
+        for (int c = 0; c < op.ncolors; ++c) {
+            if (fine)
+                gs_color<T, 1>(op, c, v, dinv, f, x, k, s);
+            else
+                gs_color<T, 0>(op, c, v, dinv, f, x, k, s);
         }
-    }
+}
+
+template <class T>
+void run_gs_color(const SolveOp &op, int c, const T *v, const T *dinv, const T *f, T *x, int k,
+                  hipStream_t s, bool fine) {
+    if (fine)
+        gs_color<T, 1>(op, c, v, dinv, f, x, k, s);
+    else
+        gs_color<T, 0>(op, c, v, dinv, f, x, k, s);
+}
+
+template <class T, int FINE>
+static void residual_impl(const SolveOp &op, const T *v, const T *d, const T *x, const T *f, T *r,
+                          int k, hipStream_t s) {
+    const int nc = op.ncolors;
+    int64_t nshort = op.blk[nc];
+    launch_csr<T, OP_RESID, FINE>(0, nshort, nullptr, 0, op.rp.p, op.ci.p, v, d, f, x, r, k,
+                                  op.lpr_short, s);
+    launch_csr<T, OP_RESID, FINE>(nshort, op.n - nshort, nullptr, 0, op.rp.p, op.ci.p, v, d, f, x,
+                                  r, k, lanes_long(k), s);
 }
 
 template <class T>
 void run_residual(const SolveOp &op, const T *v, const T *d, const T *x, const T *f, T *r, int k,
-                  hipStream_t s) {
-    const int nc = op.ncolors;
-    int64_t nshort = op.blk[nc];
-    launch_csr<T, OP_RESID>(0, nshort, nullptr, 0, op.rp.p, op.ci.p, v, d, f, x, r, k, op.lpr_short, s);
-    launch_csr<T, OP_RESID>(nshort, op.n - nshort, nullptr, 0, op.rp.p, op.ci.p, v, d, f, x, r, k,
-                            lanes_long(k), s);
+                  hipStream_t s, bool fine) {
+    if (fine)
+        residual_impl<T, 1>(op, v, d, x, f, r, k, s);
+    else
+        residual_impl<T, 0>(op, v, d, x, f, r, k, s);
 }
 
 template <class T>
@@ -615,9 +644,11 @@ void run_zero_cols(int64_t n, int k, const int32_t *zero_mask, double *x, hipStr
 
 #define LAMG_INST(T)                                                                              \
     template void run_gs<T>(const SolveOp &, const T *, const T *, const T *, T *, int, int,      \
-                            hipStream_t);                                                         \
+                            hipStream_t, bool);                                                   \
     template void run_residual<T>(const SolveOp &, const T *, const T *, const T *, const T *,    \
-                                  T *, int, hipStream_t);                                         \
+                                  T *, int, hipStream_t, bool);                                   \
+    template void run_gs_color<T>(const SolveOp &, int, const T *, const T *, const T *, T *,     \
+                                  int, hipStream_t, bool);                                        \
     template void run_restrict<T>(const SolveOp &, const T *, const T *, T *, int, hipStream_t);  \
     template void run_prolong<T>(const SolveOp &, const T *, const T *, const T *,                \
                                  const double *, T *, int, hipStream_t);                          \

@@ -132,7 +132,9 @@ struct DArr {
 struct SolveOp {
     int64_t n = 0, nnz_off = 0;
     int ncolors = 0;
-    std::vector<int64_t> blk;  // (2*ncolors + 1) offsets: class 0 colours, then class 1 colours
+    std::vector<int64_t> blk;      // (2*ncolors + 1) offsets: class 0 colours, then class 1 colours
+    std::vector<int64_t> blk_nnz;  // off-diagonal entries before each blk offset
+    DArr<int64_t> dblk;            // device copy of blk
     int lpr_short = 1;         // lanes per row of the short-row bin (k = 1)
     DArr<int32_t> perm;        // solve index -> canonical index
     DArr<int32_t> rp, ci;      // off-diagonal CSR in solve numbering
@@ -143,7 +145,7 @@ struct SolveOp {
     DArr<double> w0_64, w1_64;
     DArr<float> w0_32, w1_32;
     // restriction P^T: coarse row -> (fine row, weight)
-    int64_t nc = 0;
+    int64_t nc = 0, nnz_r = 0;
     DArr<int32_t> rrp, rci, rlong;
     int64_t n_rlong = 0;
     int lpr_r = 1;
@@ -190,6 +192,8 @@ struct Workspace {
     int k64 = 0, k32 = 0;
     std::vector<LevelVecs<double>> lv64;
     std::vector<LevelVecs<float>> lv32;
+    DArr<char> tail64, tail32;  // coarse-tail level descriptors per precision
+    DArr<int64_t> visits;       // coarse-tail visit counters (per level)
 };
 
 }  // namespace lamg
@@ -247,10 +251,13 @@ void launch_cast_f32(int64_t n, const double *src, float *dst, hipStream_t s);
 // ---------------------------------------------------------------------------
 template <class T>
 void run_gs(const SolveOp &op, const T *v, const T *dinv, const T *f, T *x, int k, int sweeps,
-            hipStream_t s);
+            hipStream_t s, bool fine);
+template <class T>
+void run_gs_color(const SolveOp &op, int c, const T *v, const T *dinv, const T *f, T *x, int k,
+                  hipStream_t s, bool fine);
 template <class T>
 void run_residual(const SolveOp &op, const T *v, const T *d, const T *x, const T *f, T *r, int k,
-                  hipStream_t s);
+                  hipStream_t s, bool fine);
 template <class T>
 void run_restrict(const SolveOp &op, const T *rw, const T *r, T *fc, int k, hipStream_t s);
 template <class T>
@@ -268,6 +275,17 @@ void run_rc2(int64_t n, T *e, T *rho, const T *e1, const T *rho1, int k, double 
              double *alpha, hipStream_t s);
 template <class T>
 void run_coarsest(int64_t n, const double *Z, const T *f, T *y, int k, hipStream_t s);
+
+// Coarse tail (tail_kernel.hip)
+template <class T>
+size_t tail_desc_bytes();
+template <class T>
+void tail_fill_desc(void *host_buf, int l, const Level &L, const SolveOp &op, const int64_t *d_blk,
+                    const T *v, const T *d, const T *dinv, const T *w0, const T *w1, const T *rw,
+                    T *x, T *f, T *r, T *rho, T *x1, T *rho1);
+template <class T>
+void run_tail(const void *d_desc, int l0, int nlev, int k, int64_t *d_visits, hipStream_t s);
+void run_zero_i64(int64_t *p, int64_t n, hipStream_t s);
 
 // Finest-level FP64 helpers
 void run_gather_cols(int64_t n, int k, const int32_t *perm, const double *src_colmajor,

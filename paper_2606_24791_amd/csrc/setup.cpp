@@ -301,6 +301,10 @@ static void build_solve_op(lamg_handle *h, int l, const std::vector<int32_t> &pe
     }
     op.nnz_off = srp[n];
     op.lpr_short = pick_lpr(nshort ? short_len / nshort : 1.0);
+    op.blk_nnz.resize(op.blk.size());
+    for (size_t b = 0; b < op.blk.size(); ++b) op.blk_nnz[b] = srp[op.blk[b]];
+    op.dblk.alloc(pool, (int64_t)op.blk.size());
+    op.dblk.upload(op.blk.data(), (int64_t)op.blk.size(), s);
     DArr<int32_t> d_iperm;
     op.perm.alloc(pool, n);
     d_iperm.alloc(pool, n);
@@ -395,6 +399,7 @@ static void build_solve_op(lamg_handle *h, int l, const std::vector<int32_t> &pe
     }
     op.lpr_r = pick_lpr(rshort ? rlen / rshort : 1.0);
     op.n_rlong = (int64_t)rlong.size();
+    op.nnz_r = rrp[nc];
     op.rrp.alloc(pool, nc + 1);
     op.rci.alloc(pool, rrp[nc]);
     op.rw64.alloc(pool, rrp[nc]);

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <type_traits>
 
 #include "lamg_internal.h"
 
@@ -44,7 +45,18 @@ struct Cycle {
     std::vector<LevelVecs<T>> *v;
     std::vector<int64_t> visits;  // entries into each level's coarse-correction phase
     double *partial;
+    int l0;                 // first level run by the coarse-tail kernel (-1: none)
+    const void *tail_desc;  // its level descriptors
+    int64_t *d_visits;      // its visit counters
 };
+
+// First level (below the finest) whose cycle runs in the coarse-tail kernel.
+int tail_level(const lamg_handle *h) {
+    if (h->opt.tail_rows <= 0) return -1;
+    for (int l = 1; l < h->nlev; ++l)
+        if (h->lev[l].n <= h->opt.tail_rows) return l;
+    return -1;
+}
 
 // One gamma-cycle at level l on (x, f): (1,2) multicolour Gauss-Seidel, coarse
 // correction by `nvis` visits to level l+1 (Beatty counts of the fractional cycle index)
@@ -57,6 +69,10 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
     hipStream_t s = C.s;
     Level &L = h->lev[l];
     using P = Prec<T>;
+    if (l == C.l0) {
+        run_tail<T>(C.tail_desc, l, h->nlev, k, C.d_visits, s);
+        return;
+    }
     if (L.coarsest) {
         run_coarsest<T>(L.n, L.Z.p, f, x, k, s);
         return;
@@ -66,15 +82,15 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
     const SolveOp &cop = Lc.op;
     LevelVecs<T> &me = (*C.v)[l];
     LevelVecs<T> &cv = (*C.v)[l + 1];
-    run_gs<T>(op, P::v(op), P::dinv(op), f, x, k, 1, s);
-    run_residual<T>(op, P::v(op), P::d(op), x, f, me.r.p, k, s);
+    run_gs<T>(op, P::v(op), P::dinv(op), f, x, k, 1, s, l == 0);
+    run_residual<T>(op, P::v(op), P::d(op), x, f, me.r.p, k, s, l == 0);
     run_restrict<T>(op, P::rw(op), me.r.p, cv.f.p, k, s);
     int64_t i = C.visits[l]++;
     int nvis = (int)(std::floor((double)(i + 1) * L.gamma) - std::floor((double)i * L.gamma));
     run_fill<T>(cv.x.p, Lc.n * k, T(0), s);
     for (int j = 1; j <= nvis; ++j) {
         cycle<T>(C, l + 1, cv.x.p, cv.f.p);
-        run_residual<T>(cop, P::v(cop), P::d(cop), cv.x.p, cv.f.p, cv.rho.p, k, s);
+        run_residual<T>(cop, P::v(cop), P::d(cop), cv.x.p, cv.f.p, cv.rho.p, k, s, false);
         if (j >= 2)
             run_rc2<T>(Lc.n, cv.x.p, cv.rho.p, cv.x1.p, cv.rho1.p, k, C.partial, cv.alpha.p, s);
         if (j < nvis) {
@@ -84,12 +100,14 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
     }
     run_mu<T>(Lc.n, cv.x.p, cv.f.p, cv.rho.p, k, C.partial, me.mu.p, s);
     run_prolong<T>(op, P::w0(op), P::w1(op), cv.x.p, me.mu.p, x, k, s);
-    run_gs<T>(op, P::v(op), P::dinv(op), f, x, k, 2, s);
+    run_gs<T>(op, P::v(op), P::dinv(op), f, x, k, 2, s, l == 0);
 }
 
 template <class T>
-void ensure_level_vecs(lamg_handle *h, int k, std::vector<LevelVecs<T>> &lv, int &have_k) {
+void ensure_level_vecs(lamg_handle *h, int k, std::vector<LevelVecs<T>> &lv, int &have_k,
+                       DArr<char> &tail) {
     if (have_k >= k && (int)lv.size() == h->nlev) return;
+    using P = Prec<T>;
     Pool &pool = *h->pool;
     lv.clear();
     lv.resize(h->nlev);
@@ -104,6 +122,19 @@ void ensure_level_vecs(lamg_handle *h, int k, std::vector<LevelVecs<T>> &lv, int
         lv[l].mu.alloc(pool, k);
         lv[l].alpha.alloc(pool, k);
     }
+    // coarse-tail descriptors (pointers to this precision's operators and vectors)
+    size_t db = tail_desc_bytes<T>();
+    std::vector<char> host(db * h->nlev);
+    for (int l = 0; l < h->nlev; ++l) {
+        const Level &L = h->lev[l];
+        const SolveOp &op = L.op;
+        tail_fill_desc<T>(host.data(), l, L, op, op.dblk.p, P::v(op), P::d(op), P::dinv(op),
+                          P::w0(op), P::w1(op), P::rw(op), lv[l].x.p, lv[l].f.p, lv[l].r.p,
+                          lv[l].rho.p, lv[l].x1.p, lv[l].rho1.p);
+    }
+    tail.alloc(pool, (int64_t)host.size());
+    tail.upload(host.data(), (int64_t)host.size(), h->stream);
+    LAMG_HIP(hipStreamSynchronize(h->stream));
     have_k = k;
 }
 
@@ -126,6 +157,7 @@ void ensure_fine(lamg_handle *h, int k) {
     w.mean.alloc(pool, k);
     w.partial.alloc(pool, (int64_t)kRedBlocksMax * kRedQMax * k);
     w.mask.alloc(pool, k);
+    w.visits.alloc(pool, h->nlev);
     if (w.h_rel) (void)hipHostFree(w.h_rel);
     if (w.h_mask) (void)hipHostFree(w.h_mask);
     w.h_rel = nullptr;
@@ -167,9 +199,10 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
     const int64_t nk = n * k;
     ensure_fine(h, k);
     if (fp32)
-        ensure_level_vecs<float>(h, k, w.lv32, w.k32);
+        ensure_level_vecs<float>(h, k, w.lv32, w.k32, w.tail32);
     else
-        ensure_level_vecs<double>(h, k, w.lv64, w.k64);
+        ensure_level_vecs<double>(h, k, w.lv64, w.k64, w.tail64);
+    run_zero_i64(w.visits.p, h->nlev, s);
 
     // b <- P b, projected to mean zero (eq. (1.1)); ||b|| per column
     run_gather_cols(n, k, op0.perm.p, b_user, w.b.p, s);
@@ -208,8 +241,11 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
         run_scatter_cols(n, k, op0.perm.p, w.phi.p, w.mask.p, phi_out, s);
     }
 
-    Cycle<double> c64{h, k, s, &w.lv64, std::vector<int64_t>(h->nlev, 0), w.partial.p};
-    Cycle<float> c32{h, k, s, &w.lv32, std::vector<int64_t>(h->nlev, 0), w.partial.p};
+    const int l0 = tail_level(h);
+    Cycle<double> c64{h, k, s, &w.lv64, std::vector<int64_t>(h->nlev, 0), w.partial.p, l0,
+                      w.tail64.p, w.visits.p};
+    Cycle<float> c32{h, k, s, &w.lv32, std::vector<int64_t>(h->nlev, 0), w.partial.p, l0,
+                     w.tail32.p, w.visits.p};
     int cyc = 0;
     while (n_active > 0 && cyc < max_cycles) {
         if (!fp32) {
@@ -223,7 +259,7 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
             cycle<float>(c32, 0, v0.x.p, v0.f.p);
             run_add_scaled_f32(n, k, v0.x.p, w.scale.p, w.phi.p, s);
         }
-        run_residual<double>(op0, op0.v64.p, op0.d64.p, w.phi.p, w.b.p, w.r.p, k, s);
+        run_residual<double>(op0, op0.v64.p, op0.d64.p, w.phi.p, w.b.p, w.r.p, k, s, true);
         if (!direct && kappa > 0) {
             run_recombine_fine(n, k, hm, w.phi.p, w.r.p, w.hphi.p, w.hr.p, w.partial.p, w.alpha_f.p, s);
             int slot = hnext % kappa;
@@ -273,7 +309,7 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
     }
     // true residual of the returned phi
     run_gather_cols(n, k, op0.perm.p, phi_out, w.phi.p, s);
-    run_residual<double>(op0, op0.v64.p, op0.d64.p, w.phi.p, w.b0.p, w.r.p, k, s);
+    run_residual<double>(op0, op0.v64.p, op0.d64.p, w.phi.p, w.b0.p, w.r.p, k, s, true);
     run_relres(n, k, w.r.p, w.nb.p, w.partial.p, w.rel.p, s);
     w.rel.download(w.h_rel, k, s);
     LAMG_HIP(hipStreamSynchronize(s));
@@ -285,7 +321,93 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
     return st;
 }
 
+template <class T>
+void profile_impl(lamg_handle *h, int level, int kernel, int k, int reps, double *sec,
+                  double *bytes) {
+    using P = Prec<T>;
+    hipStream_t s = h->stream;
+    Workspace &w = h->ws;
+    std::vector<LevelVecs<T>> &lv = P::vecs(w);
+    int &have = std::is_same<T, float>::value ? w.k32 : w.k64;
+    DArr<char> &tail = std::is_same<T, float>::value ? w.tail32 : w.tail64;
+    ensure_level_vecs<T>(h, k, lv, have, tail);
+    Level &L = h->lev[level];
+    const SolveOp &op = L.op;
+    const bool fine = level == 0;
+    const double sv = sizeof(T), sa = sizeof(T), si = 4.0;
+    const int64_t n = L.n;
+    LevelVecs<T> &me = lv[level];
+    run_fill<T>(me.x.p, n * k, T(1), s);
+    run_fill<T>(me.f.p, n * k, T(1), s);
+    LevelVecs<T> *cv = level + 1 < h->nlev ? &lv[level + 1] : nullptr;
+    if (cv) {
+        run_fill<T>(cv->x.p, h->lev[level + 1].n * k, T(1), s);
+        run_fill<double>(me.mu.p, k, 1.0, s);
+    }
+    auto launch = [&]() {
+        switch (kernel) {
+            case LAMG_KERNEL_GS_COLOR:
+                run_gs_color<T>(op, 0, P::v(op), P::dinv(op), me.f.p, me.x.p, k, s, fine);
+                break;
+            case LAMG_KERNEL_RESIDUAL:
+                run_residual<T>(op, P::v(op), P::d(op), me.x.p, me.f.p, me.r.p, k, s, fine);
+                break;
+            case LAMG_KERNEL_RESTRICT:
+                run_restrict<T>(op, P::rw(op), me.r.p, cv->f.p, k, s);
+                break;
+            default:
+                run_prolong<T>(op, P::w0(op), P::w1(op), cv->x.p, me.mu.p, me.x.p, k, s);
+                break;
+        }
+    };
+    launch();  // warm-up
+    hipEvent_t e0, e1;
+    LAMG_HIP(hipEventCreate(&e0));
+    LAMG_HIP(hipEventCreate(&e1));
+    LAMG_HIP(hipEventRecord(e0, s));
+    for (int i = 0; i < reps; ++i) launch();
+    LAMG_HIP(hipEventRecord(e1, s));
+    LAMG_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    LAMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *sec = (double)ms * 1e-3 / reps;
+    const int nc = op.ncolors;
+    double b = 0.0;
+    if (kernel == LAMG_KERNEL_GS_COLOR) {
+        // rows of colour 0 (both bins): CSR entries, row pointers, inverse diagonal,
+        // f read, x written, neighbours' x read once
+        double r = (double)(op.blk[1] - op.blk[0] + op.blk[nc + 1] - op.blk[nc]);
+        double e = (double)(op.blk_nnz[1] - op.blk_nnz[0] + op.blk_nnz[nc + 1] - op.blk_nnz[nc]);
+        b = e * (si + sa) + 4.0 * (r + 1.0) + r * sa + 3.0 * k * r * sv;
+    } else if (kernel == LAMG_KERNEL_RESIDUAL) {
+        b = (double)op.nnz_off * (si + sa) + 4.0 * (n + 1) + n * sa + 3.0 * k * n * sv;
+    } else if (kernel == LAMG_KERNEL_RESTRICT) {
+        b = 4.0 * (op.nc + 1) + (double)op.nnz_r * (si + sa) + (double)k * n * sv +
+            (double)k * op.nc * sv;
+    } else {
+        b = (double)n * (8.0 + 2.0 * sa) + (double)k * op.nc * sv + 2.0 * k * n * sv;
+    }
+    *bytes = b;
+}
+
 }  // namespace
+
+lamg_status run_profile(lamg_handle *h, int level, int kernel, lamg_precision prec, int k,
+                        int reps, double *sec, double *bytes) {
+    if (level < 0 || level >= h->nlev || k < 1 || k > 32 || reps < 1 || kernel < 0 || kernel > 3)
+        throw Error(LAMG_INVALID_ARG, "profile arguments");
+    if (h->lev[level].coarsest && kernel != LAMG_KERNEL_RESIDUAL)
+        throw Error(LAMG_INVALID_ARG, "kernel not run on the directly solved level");
+    if (prec == LAMG_FP32_IR) {
+        if (!h->opt.build_fp32) throw Error(LAMG_INVALID_ARG, "FP32 copies were not built");
+        profile_impl<float>(h, level, kernel, k, reps, sec, bytes);
+    } else {
+        profile_impl<double>(h, level, kernel, k, reps, sec, bytes);
+    }
+    return LAMG_OK;
+}
 
 lamg_status run_solve(lamg_handle *h, const double *b, int nrhs, double tol, int max_cycles,
                       lamg_precision prec, double *phi, lamg_solve_info *info) {

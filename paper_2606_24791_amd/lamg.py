@@ -33,7 +33,7 @@ class lamg_graph(C.Structure):
 class lamg_options(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("n_direct", C.c_int32), ("enable_veto", C.c_int32),
                 ("enable_caliber2", C.c_int32), ("kappa", C.c_int32), ("build_fp32", C.c_int32),
-                ("keep_setup_data", C.c_int32)]
+                ("keep_setup_data", C.c_int32), ("tail_rows", C.c_int32)]
 
 
 class lamg_hier_info(C.Structure):
@@ -79,6 +79,11 @@ _lib.lamg_hierarchy_info.argtypes = [C.c_void_p, C.POINTER(lamg_hier_info)]
 _lib.lamg_hierarchy_info.restype = C.c_int
 _lib.lamg_export_level.argtypes = [C.c_void_p, C.c_int32, C.POINTER(lamg_level_export)]
 _lib.lamg_export_level.restype = C.c_int
+_lib.lamg_profile_kernel.argtypes = [C.c_void_p, C.c_int32, C.c_int, C.c_int, C.c_int32, C.c_int32,
+                                     C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]
+_lib.lamg_profile_kernel.restype = C.c_int
+
+KERNEL_GS_COLOR, KERNEL_RESIDUAL, KERNEL_RESTRICT, KERNEL_PROLONG = range(4)
 
 
 class LamgError(RuntimeError):
@@ -282,3 +287,15 @@ def lamg_export_level(h: Handle, level: int) -> dict:
     if st != OK:
         raise LamgError(st, "lamg_export_level")
     return arrs
+
+
+def lamg_profile_kernel(h: Handle, level: int, kernel: int, precision: int = FP64, nrhs: int = 1,
+                        reps: int = 50, stream=None) -> tuple[float, float]:
+    """(mean seconds per launch, algorithmic bytes per launch) of one cycle kernel."""
+    sec = C.c_double()
+    byt = C.c_double()
+    st = _lib.lamg_profile_kernel(h.ptr, int(level), int(kernel), int(precision), int(nrhs),
+                                  int(reps), C.byref(sec), C.byref(byt), _stream_ptr(stream))
+    if st != OK:
+        raise LamgError(st, "lamg_profile_kernel")
+    return float(sec.value), float(byt.value)
