@@ -9,6 +9,7 @@
 // every lpr-th entry of the row, and the lpr partial sums are combined by cross-lane
 // shuffles. Matrix indices and values are read once per group and broadcast across
 // the kp column lanes.
+#include "csr_device.h"
 #include "lamg_internal.h"
 
 namespace lamg {
@@ -63,9 +64,7 @@ __global__ void __launch_bounds__(kBlock)
         if (skip_long > 0 && e - b > skip_long) live = false;
     }
     T acc = T(0);
-    if (live && col < k) {
-        for (int32_t j = b + sub; j < e; j += lpr) acc += v[j] * xin[(int64_t)ci[j] * k + col];
-    }
+    if (live && col < k) acc = row_dot<T, 8>(ci, v, xin, b + sub, e, lpr, k, col);
     if (G > (1 << lkp)) acc = group_sum(acc, lkp, G);
     if (!live || col >= k || sub != 0) return;
     const int64_t o = row * k + col;
@@ -116,15 +115,28 @@ __global__ void k_copy(T *__restrict__ d, const T *__restrict__ s, int64_t n) {
 }
 
 // x[u] += mu_c * (w0 e[p0] + w1 e[p1])   (energy-corrected prolongation)
+// Elementwise kernels over n rows x k columns use a (row, column) thread mapping with the
+// column count rounded up to kp = 2^lkp, so that no integer division is needed.
+#define ROWCOL(n, lkp)                                                         \
+    const int64_t tt_ = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;        \
+    const int64_t u = tt_ >> (lkp);                                            \
+    const int c = (int)(tt_ & ((1 << (lkp)) - 1));                             \
+    if (u >= (n) || c >= k) return;                                            \
+    const int64_t t = u * k + c;
+
+inline unsigned rc_blocks(int64_t n, int k) {
+    int lkp = 0;
+    while ((1 << lkp) < k) ++lkp;
+    int64_t work = n << lkp;
+    return (unsigned)((work + kBlock - 1) / kBlock > 0 ? (work + kBlock - 1) / kBlock : 1);
+}
+
 template <class T>
-__global__ void k_prolong(int64_t n, int k, const int32_t *__restrict__ p0,
+__global__ void k_prolong(int64_t n, int k, int lkp, const int32_t *__restrict__ p0,
                           const int32_t *__restrict__ p1, const T *__restrict__ w0,
                           const T *__restrict__ w1, const T *__restrict__ ec,
                           const double *__restrict__ mu, T *__restrict__ x) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * k) return;
-    int64_t u = t / k;
-    int c = (int)(t - u * k);
+    ROWCOL(n, lkp)
     T pe = w0[u] * ec[(int64_t)p0[u] * k + c];
     int32_t q = p1[u];
     if (q >= 0) pe += w1[u] * ec[(int64_t)q * k + c];
@@ -347,56 +359,33 @@ void reduce(int64_t n, int k, RedIn in, double *partial, Fin fin, hipStream_t s)
 
 // e += alpha (e1 - e); rho -= alpha (rho - rho1)
 template <class T>
-__global__ void k_rc2_update(int64_t nk, int k, T *__restrict__ e, T *__restrict__ rho,
+__global__ void k_rc2_update(int64_t n, int k, int lkp, T *__restrict__ e, T *__restrict__ rho,
                              const T *__restrict__ e1, const T *__restrict__ rho1,
                              const double *__restrict__ alpha) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nk) return;
-    int c = (int)(t % k);
+    ROWCOL(n, lkp)
     T a = (T)alpha[c];
     T ev = e[t], rv = rho[t];
     e[t] = ev + a * (e1[t] - ev);
     rho[t] = rv - a * (rv - rho1[t]);
 }
 
-// Coarsest solve y = Z (f - mean f), then y -= mean y; one block per column, FP64.
+// Coarsest solve y = L^+ f (Z holds the pseudo-inverse, so y has zero mean), FP64. One
+// wave per (row, column); its lanes split the row of the symmetric Z and add by shuffles.
 template <class T>
 __global__ void __launch_bounds__(kBlock)
     k_coarsest(int64_t n, const double *__restrict__ Z, const T *__restrict__ f, T *__restrict__ y,
                int k) {
-    __shared__ double fs[1024];
-    __shared__ double red[kBlock];
-    const int c = blockIdx.x;
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        double v = (double)f[i * k + c];
-        fs[i] = v;
-        s += v;
+    const int64_t unit = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t u = unit / k;
+    const int c = (int)(unit - u * k);
+    double acc = 0.0;
+    if (u < n) {
+        const double *zr = Z + u * n;
+        for (int64_t j = lane; j < n; j += 64) acc += zr[j] * (double)f[j * k + c];
     }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int st = kBlock / 2; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-        __syncthreads();
-    }
-    double mf = red[0] / (double)n;
-    __syncthreads();
-    double ys[4] = {0, 0, 0, 0};
-    double my = 0.0;
-    for (int64_t i = threadIdx.x, r = 0; i < n; i += blockDim.x, ++r) {
-        double acc = 0.0;
-        for (int64_t j = 0; j < n; ++j) acc += Z[j * n + i] * (fs[j] - mf);  // Z symmetric
-        ys[r] = acc;
-        my += acc;
-    }
-    red[threadIdx.x] = my;
-    __syncthreads();
-    for (int st = kBlock / 2; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-        __syncthreads();
-    }
-    double mean_y = red[0] / (double)n;
-    for (int64_t i = threadIdx.x, r = 0; i < n; i += blockDim.x, ++r) y[i * k + c] = (T)(ys[r] - mean_y);
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (u < n && lane == 0) y[u * k + c] = (T)acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -422,18 +411,18 @@ __global__ void k_scatter_cols(int64_t n, int k, const int32_t *__restrict__ per
     dst[(int64_t)c * n + perm[i]] = src[t];
 }
 
-__global__ void k_sub_col(int64_t nk, int k, double *__restrict__ x, const double *__restrict__ m) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < nk) x[t] -= m[t % k];
+__global__ void k_sub_col(int64_t n, int k, int lkp, double *__restrict__ x,
+                          const double *__restrict__ m) {
+    ROWCOL(n, lkp)
+    x[t] -= m[c];
 }
 
 // phi += sum_i a_i (phi_i - phi); r -= sum_i a_i (r - r_i)
-__global__ void k_rcf_update(int64_t nk, int k, int m, double *__restrict__ phi, double *__restrict__ r,
-                             const double *__restrict__ hphi, const double *__restrict__ hr,
-                             int64_t hstride, const double *__restrict__ alpha) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nk) return;
-    int c = (int)(t % k);
+__global__ void k_rcf_update(int64_t n, int k, int lkp, int m, double *__restrict__ phi,
+                             double *__restrict__ r, const double *__restrict__ hphi,
+                             const double *__restrict__ hr, int64_t hstride,
+                             const double *__restrict__ alpha) {
+    ROWCOL(n, lkp)
     double p = phi[t], rv = r[t], dp = 0.0, dr = 0.0;
     for (int i = 0; i < m; ++i) {
         double a = alpha[4 * c + i];
@@ -444,25 +433,23 @@ __global__ void k_rcf_update(int64_t nk, int k, int m, double *__restrict__ phi,
     r[t] = rv - dr;
 }
 
-__global__ void k_to_f32_scaled(int64_t nk, int k, const double *__restrict__ r,
+__global__ void k_to_f32_scaled(int64_t n, int k, int lkp, const double *__restrict__ r,
                                 const double *__restrict__ sc, float *__restrict__ d) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nk) return;
-    double s = sc[t % k];
+    ROWCOL(n, lkp)
+    double s = sc[c];
     d[t] = (float)(s > 0.0 ? r[t] / s : 0.0);
 }
 
-__global__ void k_add_scaled_f32(int64_t nk, int k, const float *__restrict__ e,
+__global__ void k_add_scaled_f32(int64_t n, int k, int lkp, const float *__restrict__ e,
                                  const double *__restrict__ sc, double *__restrict__ phi) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nk) return;
-    phi[t] += sc[t % k] * (double)e[t];
+    ROWCOL(n, lkp)
+    phi[t] += sc[c] * (double)e[t];
 }
 
-__global__ void k_zero_cols(int64_t nk, int k, const int32_t *__restrict__ zmask, double *__restrict__ x) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nk) return;
-    if (zmask[t % k]) x[t] = 0.0;
+__global__ void k_zero_cols(int64_t n, int k, int lkp, const int32_t *__restrict__ zmask,
+                            double *__restrict__ x) {
+    ROWCOL(n, lkp)
+    if (zmask[c]) x[t] = 0.0;
 }
 
 }  // namespace
@@ -536,7 +523,8 @@ void run_restrict(const SolveOp &op, const T *rw, const T *r, T *fc, int k, hipS
 template <class T>
 void run_prolong(const SolveOp &op, const T *w0, const T *w1, const T *ec, const double *mu, T *x,
                  int k, hipStream_t s) {
-    k_prolong<T><<<blocks_for(op.n * k), kBlock, 0, s>>>(op.n, k, op.p0.p, op.p1.p, w0, w1, ec, mu, x);
+    k_prolong<T><<<rc_blocks(op.n, k), kBlock, 0, s>>>(op.n, k, kp_log2(k), op.p0.p, op.p1.p, w0, w1,
+                                                        ec, mu, x);
     LAMG_LAUNCH_CHECK();
 }
 
@@ -566,14 +554,14 @@ void run_rc2(int64_t n, T *e, T *rho, const T *e1, const T *rho1, int k, double 
              double *alpha, hipStream_t s) {
     RedIn in{rho, rho1, nullptr, nullptr, 0, 0};
     reduce<T, R_RC2>(n, k, in, partial, Fin{alpha, nullptr, 1.0, 0}, s);
-    k_rc2_update<T><<<blocks_for(n * k), kBlock, 0, s>>>(n * k, k, e, rho, e1, rho1, alpha);
+    k_rc2_update<T><<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), e, rho, e1, rho1, alpha);
     LAMG_LAUNCH_CHECK();
 }
 
 template <class T>
 void run_coarsest(int64_t n, const double *Z, const T *f, T *y, int k, hipStream_t s) {
     if (n > 1024) throw Error(LAMG_INVALID_ARG, "coarsest level larger than 1024");
-    k_coarsest<T><<<k, kBlock, 0, s>>>(n, Z, f, y, k);
+    k_coarsest<T><<<(unsigned)((n * k + 3) / 4), kBlock, 0, s>>>(n, Z, f, y, k);
     LAMG_LAUNCH_CHECK();
 }
 
@@ -596,7 +584,7 @@ void run_colsum(int64_t n, int k, const double *x, double *partial, double *out,
 }
 
 void run_sub_col(int64_t n, int k, double *x, const double *m, hipStream_t s) {
-    k_sub_col<<<blocks_for(n * k), kBlock, 0, s>>>(n * k, k, x, m);
+    k_sub_col<<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), x, m);
     LAMG_LAUNCH_CHECK();
 }
 
@@ -621,24 +609,25 @@ void run_recombine_fine(int64_t n, int k, int m, double *phi, double *r, const d
     if (m <= 0) return;
     RedIn in{r, hr, nullptr, nullptr, m, n * k};
     reduce<double, R_RCF>(n, k, in, partial, Fin{alpha, nullptr, 1.0, m}, s);
-    k_rcf_update<<<blocks_for(n * k), kBlock, 0, s>>>(n * k, k, m, phi, r, hphi, hr, n * k, alpha);
+    k_rcf_update<<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), m, phi, r, hphi, hr, n * k,
+                                                     alpha);
     LAMG_LAUNCH_CHECK();
 }
 
 void run_to_f32_scaled(int64_t n, int k, const double *r, const double *scale, float *dst,
                        hipStream_t s) {
-    k_to_f32_scaled<<<blocks_for(n * k), kBlock, 0, s>>>(n * k, k, r, scale, dst);
+    k_to_f32_scaled<<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), r, scale, dst);
     LAMG_LAUNCH_CHECK();
 }
 
 void run_add_scaled_f32(int64_t n, int k, const float *e, const double *scale, double *phi,
                         hipStream_t s) {
-    k_add_scaled_f32<<<blocks_for(n * k), kBlock, 0, s>>>(n * k, k, e, scale, phi);
+    k_add_scaled_f32<<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), e, scale, phi);
     LAMG_LAUNCH_CHECK();
 }
 
 void run_zero_cols(int64_t n, int k, const int32_t *zero_mask, double *x, hipStream_t s) {
-    k_zero_cols<<<blocks_for(n * k), kBlock, 0, s>>>(n * k, k, zero_mask, x);
+    k_zero_cols<<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), zero_mask, x);
     LAMG_LAUNCH_CHECK();
 }
 

@@ -26,6 +26,7 @@ constexpr int kLongRow = 32;        // rows with more off-diagonals go to the wa
 constexpr int kBlock = 256;         // threads per block of every kernel
 constexpr int kRedBlocksMax = 256;  // partial-sum blocks of a reduction
 constexpr int kRedQMax = 14;        // quantities per reduction (4x4 normal equations + rhs)
+constexpr int kTailMaxLevels = 16;  // levels one coarse-tail launch may span
 
 // Error carried from the point of failure to the C-ABI boundary.
 struct Error : std::runtime_error {
@@ -136,6 +137,7 @@ struct SolveOp {
     std::vector<int64_t> blk_nnz;  // off-diagonal entries before each blk offset
     DArr<int64_t> dblk;            // device copy of blk
     int lpr_short = 1;         // lanes per row of the short-row bin (k = 1)
+    int max_short_len = 0;     // longest off-diagonal row; 0 if any row is in the long bin
     DArr<int32_t> perm;        // solve index -> canonical index
     DArr<int32_t> rp, ci;      // off-diagonal CSR in solve numbering
     DArr<double> v64, d64, dinv64;
@@ -170,7 +172,7 @@ struct Level {
     int64_t nc = 0, n_cal2 = 0;
     double gamma = 1.0, tau = 0.0;
     SolveOp op;
-    DArr<double> Z;  // coarsest: (L + 11^T/n)^{-1}, n x n
+    DArr<double> Z;  // coarsest: the pseudo-inverse L^+ = (L + 11^T/n)^{-1} - 11^T/n, n x n
 };
 
 // Per-level cycle vectors of one precision (n_l * k elements each).
@@ -180,6 +182,15 @@ struct LevelVecs {
     DArr<double> mu, alpha;  // k per level
 };
 
+// Device-side plan of a coarse tail for one precision and column count.
+struct TailPlan {
+    const void *desc = nullptr;      // level descriptors (global arrays)
+    const void *lds_desc = nullptr;  // descriptors of LDS-resident levels (offsets)
+    const void *jobs = nullptr;      // global -> LDS copy jobs
+    int njobs = 0;
+    int l_lds = 0;         // first LDS-resident level (nlev: none)
+    size_t lds_bytes = 0;  // dynamic LDS of the launch
+};
 // Cached solve workspace (grown on demand, per precision).
 struct Workspace {
     int kf = 0;  // columns of the finest FP64 state
@@ -193,6 +204,8 @@ struct Workspace {
     std::vector<LevelVecs<double>> lv64;
     std::vector<LevelVecs<float>> lv32;
     DArr<char> tail64, tail32;  // coarse-tail level descriptors per precision
+    DArr<char> tlds64, tlds32, tjobs64, tjobs32;  // LDS-resident tail levels
+    TailPlan plan64, plan32;
     DArr<int64_t> visits;       // coarse-tail visit counters (per level)
 };
 
@@ -235,7 +248,7 @@ int64_t galerkin(Pool &pool, int64_t n, int64_t nnz, const int32_t *rp, const in
                  const double *v, int64_t nc, const int32_t *p0, const double *w0,
                  const int32_t *p1, const double *w1, DArr<int32_t> &crp, DArr<int32_t> &cci,
                  DArr<double> &cv, hipStream_t s);
-// Z = (L + 11^T/n)^{-1} by Gauss-Jordan elimination (SPD, no pivoting).
+// Z = L^+ = (L + 11^T/n)^{-1} - 11^T/n (Gauss-Jordan on the SPD matrix, no pivoting).
 void coarsest_inverse(Pool &pool, int64_t n, const int32_t *rp, const int32_t *ci,
                       const double *v, double *Z, hipStream_t s);
 
@@ -284,7 +297,11 @@ void tail_fill_desc(void *host_buf, int l, const Level &L, const SolveOp &op, co
                     const T *v, const T *d, const T *dinv, const T *w0, const T *w1, const T *rw,
                     T *x, T *f, T *r, T *rho, T *x1, T *rho1);
 template <class T>
-void run_tail(const void *d_desc, int l0, int nlev, int k, int64_t *d_visits, hipStream_t s);
+int tail_lds_plan(const std::vector<Level> &lev, int l0, int k, const void *host_desc,
+                  std::vector<char> &lds_desc, std::vector<char> &jobs, size_t &lds_bytes);
+size_t tail_copy_job_bytes();
+template <class T>
+void run_tail(const TailPlan &tp, int l0, int nlev, int k, int64_t *d_visits, hipStream_t s);
 void run_zero_i64(int64_t *p, int64_t n, hipStream_t s);
 
 // Finest-level FP64 helpers

@@ -404,8 +404,8 @@ __global__ void k_row_fill(int64_t nc, const int32_t *__restrict__ crp, const in
 }
 
 // ---------------------------------------------------------------------------
-// Coarsest level: Z = (L + 11^T/n)^{-1} (SPD for a connected graph) by in-place
-// Gauss-Jordan elimination without pivoting.
+// Coarsest level: (L + 11^T/n)^{-1} (SPD for a connected graph) by in-place Gauss-Jordan
+// elimination without pivoting, then L^+ = that inverse - 11^T/n.
 // ---------------------------------------------------------------------------
 __global__ void k_dense_fill(int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                              const double *__restrict__ v, double *__restrict__ A) {
@@ -436,6 +436,13 @@ __global__ void __launch_bounds__(kBlock) k_gauss_jordan_1blk(int64_t n, double 
         }
         __syncthreads();
     }
+}
+
+// (L + 11^T/n)^{-1} = L^+ + 11^T/n for a connected graph: subtracting 1/n from every
+// entry leaves the pseudo-inverse, whose product with any f is the mean-zero solution.
+__global__ void k_minus_one_over_n(int64_t n, double *__restrict__ Z) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n * n) Z[t] = Z[t] - 1.0 / (double)n;
 }
 
 __global__ void k_gj_pivot(int64_t n, int64_t p, double *__restrict__ A, double *__restrict__ col) {
@@ -672,6 +679,8 @@ void coarsest_inverse(Pool &pool, int64_t n, const int32_t *rp, const int32_t *c
         }
         LAMG_LAUNCH_CHECK();
     }
+    k_minus_one_over_n<<<grid_for(n * n), kBlock, 0, s>>>(n, Z);
+    LAMG_LAUNCH_CHECK();
     LAMG_HIP(hipStreamSynchronize(s));
 }
 

@@ -38,6 +38,27 @@ struct Prec<float> {
 };
 
 template <class T>
+struct WsSel;
+template <>
+struct WsSel<double> {
+    static std::vector<LevelVecs<double>> &lv(Workspace &w) { return w.lv64; }
+    static int &k(Workspace &w) { return w.k64; }
+    static DArr<char> &desc(Workspace &w) { return w.tail64; }
+    static DArr<char> &lds(Workspace &w) { return w.tlds64; }
+    static DArr<char> &jobs(Workspace &w) { return w.tjobs64; }
+    static TailPlan &plan(Workspace &w) { return w.plan64; }
+};
+template <>
+struct WsSel<float> {
+    static std::vector<LevelVecs<float>> &lv(Workspace &w) { return w.lv32; }
+    static int &k(Workspace &w) { return w.k32; }
+    static DArr<char> &desc(Workspace &w) { return w.tail32; }
+    static DArr<char> &lds(Workspace &w) { return w.tlds32; }
+    static DArr<char> &jobs(Workspace &w) { return w.tjobs32; }
+    static TailPlan &plan(Workspace &w) { return w.plan32; }
+};
+
+template <class T>
 struct Cycle {
     lamg_handle *h;
     int k;
@@ -46,7 +67,7 @@ struct Cycle {
     std::vector<int64_t> visits;  // entries into each level's coarse-correction phase
     double *partial;
     int l0;                 // first level run by the coarse-tail kernel (-1: none)
-    const void *tail_desc;  // its level descriptors
+    const TailPlan *plan;   // its descriptors and LDS layout
     int64_t *d_visits;      // its visit counters
 };
 
@@ -54,7 +75,7 @@ struct Cycle {
 int tail_level(const lamg_handle *h) {
     if (h->opt.tail_rows <= 0) return -1;
     for (int l = 1; l < h->nlev; ++l)
-        if (h->lev[l].n <= h->opt.tail_rows) return l;
+        if (h->lev[l].n <= h->opt.tail_rows) return std::max(l, h->nlev - kTailMaxLevels);
     return -1;
 }
 
@@ -70,7 +91,7 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
     Level &L = h->lev[l];
     using P = Prec<T>;
     if (l == C.l0) {
-        run_tail<T>(C.tail_desc, l, h->nlev, k, C.d_visits, s);
+        run_tail<T>(*C.plan, l, h->nlev, k, C.d_visits, s);
         return;
     }
     if (L.coarsest) {
@@ -104,10 +125,12 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
 }
 
 template <class T>
-void ensure_level_vecs(lamg_handle *h, int k, std::vector<LevelVecs<T>> &lv, int &have_k,
-                       DArr<char> &tail) {
-    if (have_k >= k && (int)lv.size() == h->nlev) return;
+void ensure_level_vecs(lamg_handle *h, int k) {
     using P = Prec<T>;
+    using W = WsSel<T>;
+    Workspace &w = h->ws;
+    std::vector<LevelVecs<T>> &lv = W::lv(w);
+    if (W::k(w) >= k && (int)lv.size() == h->nlev) return;
     Pool &pool = *h->pool;
     lv.clear();
     lv.resize(h->nlev);
@@ -122,7 +145,8 @@ void ensure_level_vecs(lamg_handle *h, int k, std::vector<LevelVecs<T>> &lv, int
         lv[l].mu.alloc(pool, k);
         lv[l].alpha.alloc(pool, k);
     }
-    // coarse-tail descriptors (pointers to this precision's operators and vectors)
+    // coarse-tail descriptors (pointers to this precision's operators and vectors) and the
+    // layout of its LDS-resident levels
     size_t db = tail_desc_bytes<T>();
     std::vector<char> host(db * h->nlev);
     for (int l = 0; l < h->nlev; ++l) {
@@ -132,10 +156,31 @@ void ensure_level_vecs(lamg_handle *h, int k, std::vector<LevelVecs<T>> &lv, int
                           P::w0(op), P::w1(op), P::rw(op), lv[l].x.p, lv[l].f.p, lv[l].r.p,
                           lv[l].rho.p, lv[l].x1.p, lv[l].rho1.p);
     }
-    tail.alloc(pool, (int64_t)host.size());
-    tail.upload(host.data(), (int64_t)host.size(), h->stream);
+    DArr<char> &desc = W::desc(w);
+    desc.alloc(pool, (int64_t)host.size());
+    desc.upload(host.data(), (int64_t)host.size(), h->stream);
+    TailPlan &tp = W::plan(w);
+    tp = TailPlan();
+    tp.desc = desc.p;
+    tp.l_lds = h->nlev;
+    std::vector<char> lds_desc, jobs;
+    size_t lds_bytes = 0;
+    int l_lds = tail_lds_plan<T>(h->lev, tail_level(h), k, host.data(), lds_desc, jobs, lds_bytes);
+    if (l_lds < h->nlev) {
+        DArr<char> &dl = W::lds(w);
+        DArr<char> &dj = W::jobs(w);
+        dl.alloc(pool, (int64_t)lds_desc.size());
+        dl.upload(lds_desc.data(), (int64_t)lds_desc.size(), h->stream);
+        dj.alloc(pool, (int64_t)std::max<size_t>(jobs.size(), 1));
+        if (!jobs.empty()) dj.upload(jobs.data(), (int64_t)jobs.size(), h->stream);
+        tp.lds_desc = dl.p;
+        tp.jobs = dj.p;
+        tp.njobs = (int)(jobs.size() / tail_copy_job_bytes());
+        tp.l_lds = l_lds;
+        tp.lds_bytes = lds_bytes;
+    }
     LAMG_HIP(hipStreamSynchronize(h->stream));
-    have_k = k;
+    W::k(w) = k;
 }
 
 void ensure_fine(lamg_handle *h, int k) {
@@ -199,9 +244,9 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
     const int64_t nk = n * k;
     ensure_fine(h, k);
     if (fp32)
-        ensure_level_vecs<float>(h, k, w.lv32, w.k32, w.tail32);
+        ensure_level_vecs<float>(h, k);
     else
-        ensure_level_vecs<double>(h, k, w.lv64, w.k64, w.tail64);
+        ensure_level_vecs<double>(h, k);
     run_zero_i64(w.visits.p, h->nlev, s);
 
     // b <- P b, projected to mean zero (eq. (1.1)); ||b|| per column
@@ -243,9 +288,9 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
 
     const int l0 = tail_level(h);
     Cycle<double> c64{h, k, s, &w.lv64, std::vector<int64_t>(h->nlev, 0), w.partial.p, l0,
-                      w.tail64.p, w.visits.p};
+                      &w.plan64, w.visits.p};
     Cycle<float> c32{h, k, s, &w.lv32, std::vector<int64_t>(h->nlev, 0), w.partial.p, l0,
-                     w.tail32.p, w.visits.p};
+                     &w.plan32, w.visits.p};
     int cyc = 0;
     while (n_active > 0 && cyc < max_cycles) {
         if (!fp32) {
@@ -328,9 +373,7 @@ void profile_impl(lamg_handle *h, int level, int kernel, int k, int reps, double
     hipStream_t s = h->stream;
     Workspace &w = h->ws;
     std::vector<LevelVecs<T>> &lv = P::vecs(w);
-    int &have = std::is_same<T, float>::value ? w.k32 : w.k64;
-    DArr<char> &tail = std::is_same<T, float>::value ? w.tail32 : w.tail64;
-    ensure_level_vecs<T>(h, k, lv, have, tail);
+    ensure_level_vecs<T>(h, k);
     Level &L = h->lev[level];
     const SolveOp &op = L.op;
     const bool fine = level == 0;

@@ -11,6 +11,7 @@ import ctypes as C
 from pathlib import Path
 
 import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime the library then shares with PyTorch)
 
 _LIB_PATH = Path(__file__).resolve().parent / "liblamg.so"
 if not _LIB_PATH.exists():

@@ -225,3 +225,25 @@ def test_full_size_anisotropic_1024(B):
     for prec in (B.FP64, B.FP32_IR):
         st, ph, bh, refs = solve_both(B, g, 1, prec, seed=0)
         check_solution(g, st, ph, bh, refs)
+
+
+@pytest.mark.parametrize("tail_rows", [0, 400, 2500, 100000])
+def test_cycle_execution_modes_agree(B, tail_rows):
+    """Every split between per-step kernels and the single-workgroup coarse tail (with its
+    LDS-resident levels) computes the same cycle: each reaches the tolerance and the
+    oracle's solution, in both precisions, for 1 and 3 right-hand sides."""
+    import torch
+
+    g = GRAPHS["aniso_ragged"]()
+    note(f"execution mode tail_rows={tail_rows}")
+    oh = O.Hierarchy(g, seed=1)
+    h = B.lamg_setup(g, B.lamg_default_options(tail_rows=tail_rows))
+    bh = I.rhs(g.n, 3, seed=21)
+    refs = [oh.solve(bh[c], TOL, 100) for c in range(3)]
+    for prec in (B.FP64, B.FP32_IR):
+        for k in (1, 3):
+            b = torch.tensor(bh[:k], device="cuda")
+            phi = torch.empty_like(b)
+            st = B.lamg_solve(h, b, phi, precision=prec)
+            check_solution(g, st, phi.cpu().numpy(), bh[:k], refs[:k])
+    h.close()
