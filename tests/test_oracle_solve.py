@@ -118,7 +118,7 @@ def test_zero_rhs_returns_zero():
     assert np.all(phi == 0) and st["cycles"] == 0
 
 
-# --- soft targets (Table A.1, Table 3.2): bands, not parity ---------------------
+# --- soft targets (anisotropy table of App. A.1; Sec. 4.8): bands, not parity -----
 
 def test_soft_target_anisotropic_grids():
     """64^2 grid-aligned anisotropy: the paper's full solver reaches ACF 0.007 / 0.051 /
