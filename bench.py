@@ -11,9 +11,12 @@ y-weight 1e-3; n = 1,048,576, nnz(L) = 2m + n = 5,238,784), b ~ N(0,1) (mean rem
 the solver), one right-hand side.
 
 The JSON line also carries
-  roofline: the finest-level FP32 Gauss-Seidel colour pass (the dominant kernel): its
-            algorithmic bytes per launch over its mean launch time (HIP events, on the
-            library's stream), against 8 TB/s HBM;
+  roofline: the finest-level FP32 Gauss-Seidel colour pass (the dominant bandwidth kernel):
+            its algorithmic bytes per launch over its mean launch time, both summed over
+            every launch in the timed FP32+IR region (HIP events around each launch on the
+            solve stream), against 8 TB/s HBM;
+  coarse_tail: the same timing of the single-workgroup coarse-level kernel, which takes the
+            largest share of the solve and is bound by dependent steps, not bytes;
   cpu_baseline: the CPU oracle (single-threaded, FP64) solving the same system once.
 """
 from __future__ import annotations
@@ -53,7 +56,8 @@ def main() -> int:
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile-reps", type=int, default=200)
+    ap.add_argument("--profile-reps", type=int, default=0,
+                    help="also time the finest GS colour pass in isolation (back-to-back launches)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the solver has no multi-GPU path); got --gpus "
@@ -83,12 +87,12 @@ def main() -> int:
     b = torch.tensor(bh, device=dev)
     stream = torch.cuda.current_stream()
 
-    results = {}
-    for name, prec in (("fp32ir", B.FP32_IR), ("fp64", B.FP64)):
-        phi = torch.empty_like(b)
-        for _ in range(args.warmup):
-            B.lamg_solve(h, b, phi, tol=args.tol, precision=prec, stream=stream)
+    def run_steps(prec, phi, timed):
+        """K solves between synchronisations; with `timed`, the library brackets every launch
+        of the finest-level kernels and of the coarse tail with HIP events on `stream`."""
         torch.cuda.synchronize()
+        if timed:
+            B.lamg_timing_start(h, 65536)
         lat, stats = [], None
         t0 = time.perf_counter()
         for _ in range(args.steps):
@@ -97,27 +101,56 @@ def main() -> int:
             lat.append(time.perf_counter() - ts)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        kt = B.lamg_timing_stop(h) if timed else None
+        return wall, lat, stats, kt
+
+    results = {}
+    for name, prec in (("fp32ir", B.FP32_IR), ("fp64", B.FP64)):
+        phi = torch.empty_like(b)
+        for _ in range(args.warmup):
+            B.lamg_solve(h, b, phi, tol=args.tol, precision=prec, stream=stream)
+        wall, lat, stats, kt = run_steps(prec, phi, True)
+        wall_plain, _, _, _ = run_steps(prec, phi, False)
         ms = 1e3 * wall / args.steps
         results[name] = dict(ms=ms, value=g.nnz_laplacian * k / (wall / args.steps),
                              p50_ms=1e3 * percentile(lat, 50), p99_ms=1e3 * percentile(lat, 99),
                              cycles=stats["cycles"], relres=stats["relres_max"],
-                             converged=bool(stats["converged"]), phi=phi.cpu().numpy())
-        log(f"{name}: {ms:.3f} ms/solve, {results[name]['value']:.3e} nnz*RHS/s, "
-            f"cycles={stats['cycles']} relres={stats['relres_max']:.2e}")
+                             converged=bool(stats["converged"]), phi=phi.cpu().numpy(),
+                             kt=kt, ms_no_events=1e3 * wall_plain / args.steps, wall=wall)
+        log(f"{name}: {ms:.3f} ms/solve ({results[name]['ms_no_events']:.3f} without events), "
+            f"{results[name]['value']:.3e} nnz*RHS/s, cycles={stats['cycles']} "
+            f"relres={stats['relres_max']:.2e}")
 
-    # dominant kernel: finest-level FP32 Gauss-Seidel colour pass
-    sec, byt = B.lamg_profile_kernel(h, 0, B.KERNEL_GS_COLOR, B.FP32_IR, k, args.profile_reps,
-                                     stream=stream)
+    # in-situ kernel times of the FP32+IR timed region
+    r32 = results["fp32ir"]
+    kt = r32["kt"]
+
+    def kstat(kern, prec):
+        t = kt.get((kern, prec))
+        if not t:
+            return None
+        return dict(launches=t["launches"], us_per_launch=round(1e6 * t["seconds"] / t["launches"], 3),
+                    GBs=round(t["bytes"] / t["seconds"] / 1e9, 1) if t["bytes"] else None,
+                    share=round(t["seconds"] / r32["wall"], 4))
+
+    gs = kt[(B.KERNEL_GS_COLOR, B.FP32_IR)]
+    sec = gs["seconds"] / gs["launches"]
+    byt = gs["bytes"] / gs["launches"]
     achieved = byt / sec / 1e9
-    log(f"gs colour pass (finest, fp32): {sec * 1e6:.2f} us, {byt / 1e6:.2f} MB -> {achieved:.0f} GB/s")
-    other = {}
-    for kname, kid in (("residual", B.KERNEL_RESIDUAL), ("restrict", B.KERNEL_RESTRICT),
-                       ("prolong", B.KERNEL_PROLONG)):
-        s2, b2 = B.lamg_profile_kernel(h, 0, kid, B.FP32_IR, k, args.profile_reps, stream=stream)
-        other[kname] = dict(us=round(s2 * 1e6, 3), GBs=round(b2 / s2 / 1e9, 1))
-    s2, b2 = B.lamg_profile_kernel(h, 0, B.KERNEL_RESIDUAL, B.FP64, k, args.profile_reps,
-                                   stream=stream)
-    other["residual_fp64"] = dict(us=round(s2 * 1e6, 3), GBs=round(b2 / s2 / 1e9, 1))
+    log(f"gs colour pass (finest, fp32, in situ): {gs['launches']} launches, {sec * 1e6:.2f} us, "
+        f"{byt / 1e6:.2f} MB -> {achieved:.0f} GB/s")
+    other = {"residual": kstat(B.KERNEL_RESIDUAL, B.FP32_IR),
+             "restrict": kstat(B.KERNEL_RESTRICT, B.FP32_IR),
+             "prolong": kstat(B.KERNEL_PROLONG, B.FP32_IR),
+             "residual_fp64_outer": kstat(B.KERNEL_RESIDUAL, B.FP64),
+             "gs_color": kstat(B.KERNEL_GS_COLOR, B.FP32_IR)}
+    tail = kstat(B.KERNEL_TAIL, B.FP32_IR)
+    log(f"coarse tail (fp32, in situ): {tail}")
+    isolated = None
+    if args.profile_reps > 0:
+        s2, b2 = B.lamg_profile_kernel(h, 0, B.KERNEL_GS_COLOR, B.FP32_IR, k, args.profile_reps,
+                                       stream=stream)
+        isolated = dict(us_per_launch=s2 * 1e6, GBs=b2 / s2 / 1e9, reps=args.profile_reps)
 
     # the FP64 oracle: error of every result against it, and the CPU baseline
     cpu = None
@@ -173,8 +206,15 @@ def main() -> int:
         "roofline": {"bound": "hbm", "kernel": "k_csr<float, GS, finest> (one colour pass)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": byt, "us_per_launch": sec * 1e6},
+                     "bytes_per_launch": byt, "us_per_launch": sec * 1e6,
+                     "launches": gs["launches"], "timing": "HIP events attached to every launch "
+                     "(dispatch timestamps) in the timed FP32+IR region, on the solve stream"},
         "kernels_finest": other,
+        "coarse_tail": dict(tail or {}, bound="latency (dependent steps of one workgroup)",
+                            kernel="k_tail<float>"),
+        "events_overhead": {"fp32ir_ms_no_events": r32["ms_no_events"],
+                            "fp64_ms_no_events": results["fp64"]["ms_no_events"]},
+        "gs_color_isolated": isolated,
         "cpu_baseline": cpu,
         "paper_context": "0.19 us/edge median solve, 1 CPU thread Apple M5 Pro (Julia), "
                          "SuiteSparse corpus; not this workload",

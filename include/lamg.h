@@ -102,6 +102,8 @@ typedef struct {
     int64_t bytes_device;                /* device bytes held by the handle (hierarchy + cached workspace) */
     double op_complexity;                /* sum_l nnz_l / nnz_0 */
     double setup_seconds;                /* wall time of lamg_setup */
+    int64_t bytes_peak;                  /* most device bytes the handle has held at once
+                                            (setup temporaries included) */
 } lamg_hier_info;
 
 /* Solve statistics. The caller may point the array fields at host arrays (or leave them
@@ -192,12 +194,14 @@ lamg_status lamg_hierarchy_info(const lamg_handle *h, lamg_hier_info *info);
  * keep_setup_data = 1 at setup, else LAMG_UNAVAILABLE. Errors: INVALID_ARG (bad level). */
 lamg_status lamg_export_level(const lamg_handle *h, int32_t level, lamg_level_export *out);
 
-/* Cycle kernels that lamg_profile_kernel can time. */
+/* Cycle kernels that lamg_profile_kernel and the in-situ timer can time. */
 typedef enum {
     LAMG_KERNEL_GS_COLOR = 0, /* one Gauss-Seidel colour pass (colour 0) of the level */
     LAMG_KERNEL_RESIDUAL = 1, /* r = f - L x over the whole level */
     LAMG_KERNEL_RESTRICT = 2, /* f_c = P^T r from the level to the next */
-    LAMG_KERNEL_PROLONG = 3   /* x += mu P e_c from the next level */
+    LAMG_KERNEL_PROLONG = 3,  /* x += mu P e_c from the next level */
+    LAMG_KERNEL_TAIL = 4      /* one launch of the single-workgroup coarse-level cycle
+                                 (in-situ timer only) */
 } lamg_kernel;
 
 /* Measurement aid for roofline reporting: launches one cycle kernel of level `level`
@@ -213,6 +217,32 @@ lamg_status lamg_profile_kernel(lamg_handle *h, int32_t level, lamg_kernel kerne
                                 lamg_precision prec, int32_t nrhs, int32_t reps,
                                 double *seconds_per_launch, double *bytes_per_launch,
                                 void *stream);
+
+/* In-situ kernel timing (measurement aid). Between lamg_timing_start and lamg_timing_stop,
+ * every lamg_solve on the handle attaches a pair of HIP events to each launch of the finest
+ * level's cycle kernels (every Gauss-Seidel colour pass, residual, restriction,
+ * prolongation, in the precision they run in; the FP64 outer residual of an FP32+IR solve
+ * counts as an FP64 residual) and of the coarse-tail kernel, on the solve's stream. The
+ * events take the dispatch's own start and end times (hipExtLaunchKernel), so a pair spans
+ * the kernel's execution alone; they add no synchronisation and no stream markers. Timing
+ * stops recording after `max_launches` launches (the events are created by
+ * lamg_timing_start).
+ * lamg_timing_stop waits for the last recorded event, converts every pair to a duration
+ * and frees the events; lamg_timing_get then returns, per kernel and precision, the number
+ * of timed launches, their summed duration and their summed algorithmic bytes (the figures
+ * of lamg_profile_kernel for the launch's rows; 0 for the coarse tail, which is bound by
+ * dependent steps, not by bytes). Errors: INVALID_ARG (max_launches < 1, kernel out of
+ * range, timing still running for lamg_timing_get), HIP_ERROR. */
+typedef struct {
+    int64_t launches;
+    double seconds;
+    double bytes;
+} lamg_kernel_time;
+
+lamg_status lamg_timing_start(lamg_handle *h, int32_t max_launches);
+lamg_status lamg_timing_stop(lamg_handle *h);
+lamg_status lamg_timing_get(const lamg_handle *h, lamg_kernel kernel, lamg_precision prec,
+                            lamg_kernel_time *out);
 
 #ifdef __cplusplus
 }

@@ -1,6 +1,7 @@
 // C ABI of liblamg (declared in include/lamg.h): argument checks, handle lifecycle,
 // device-memory pool, hierarchy description and level export. Exceptions raised inside
 // the library stop here and become status codes.
+#include <algorithm>
 #include <mutex>
 #include <new>
 
@@ -34,6 +35,7 @@ void *Pool::get(size_t bytes) {
     if (!p) throw Error(LAMG_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
     blks_.push_back({p, bytes});
     bytes_ += (int64_t)bytes;
+    peak_ = std::max(peak_, bytes_);
     return p;
 }
 
@@ -77,6 +79,7 @@ static lamg_status guarded(F &&f) {
 }  // namespace lamg
 
 lamg_handle::~lamg_handle() {
+    timer.release();
     // pinned host mirrors; device arrays are released by their owners before the pool
     if (ws.h_rel) (void)hipHostFree(ws.h_rel);
     if (ws.h_mask) (void)hipHostFree(ws.h_mask);
@@ -188,6 +191,34 @@ lamg_status lamg_profile_kernel(lamg_handle *h, int32_t level, lamg_kernel kerne
     });
 }
 
+lamg_status lamg_timing_start(lamg_handle *h, int32_t max_launches) {
+    if (!h || max_launches < 1) return LAMG_INVALID_ARG;
+    return guarded([&]() -> lamg_status {
+        h->timer.start(max_launches);
+        return LAMG_OK;
+    });
+}
+
+lamg_status lamg_timing_stop(lamg_handle *h) {
+    if (!h) return LAMG_INVALID_ARG;
+    return guarded([&]() -> lamg_status {
+        h->timer.stop();
+        return LAMG_OK;
+    });
+}
+
+lamg_status lamg_timing_get(const lamg_handle *h, lamg_kernel kernel, lamg_precision prec,
+                            lamg_kernel_time *out) {
+    if (!h || !out || (int)kernel < 0 || (int)kernel >= KTimer::kKinds || h->timer.on ||
+        (prec != LAMG_FP64 && prec != LAMG_FP32_IR))
+        return LAMG_INVALID_ARG;
+    const int p = prec == LAMG_FP32_IR ? 1 : 0;
+    out->launches = h->timer.cnt[kernel][p];
+    out->seconds = h->timer.sec[kernel][p];
+    out->bytes = h->timer.bytes[kernel][p];
+    return LAMG_OK;
+}
+
 void lamg_destroy(lamg_handle *h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
@@ -212,6 +243,7 @@ lamg_status lamg_hierarchy_info(const lamg_handle *h, lamg_hier_info *info) {
     info->bytes_device = h->pool->bytes();
     info->op_complexity = tot / nnz0;
     info->setup_seconds = h->setup_seconds;
+    info->bytes_peak = h->pool->peak();
     return LAMG_OK;
 }
 

@@ -91,8 +91,8 @@ void launch_csr(int64_t r0, int64_t nrows, const int32_t *rows, int skip_long, c
     int lg = lkp + llpr;
     int64_t groups_per_block = kBlock >> lg;
     unsigned grid = (unsigned)((nrows + groups_per_block - 1) / groups_per_block);
-    k_csr<T, OP, FINE><<<grid, kBlock, 0, s>>>(r0, nrows, rows, skip_long, rp, ci, v, dd, f, xin,
-                                               out, k, lkp, llpr);
+    launch_kernel(k_csr<T, OP, FINE>, dim3(grid), dim3(kBlock), 0, s, r0, nrows, rows, skip_long,
+                  rp, ci, v, dd, f, xin, out, k, lkp, llpr);
     LAMG_LAUNCH_CHECK();
 }
 
@@ -523,8 +523,8 @@ void run_restrict(const SolveOp &op, const T *rw, const T *r, T *fc, int k, hipS
 template <class T>
 void run_prolong(const SolveOp &op, const T *w0, const T *w1, const T *ec, const double *mu, T *x,
                  int k, hipStream_t s) {
-    k_prolong<T><<<rc_blocks(op.n, k), kBlock, 0, s>>>(op.n, k, kp_log2(k), op.p0.p, op.p1.p, w0, w1,
-                                                        ec, mu, x);
+    launch_kernel(k_prolong<T>, dim3(rc_blocks(op.n, k)), dim3(kBlock), 0, s, op.n, k, kp_log2(k),
+                  op.p0.p, op.p1.p, w0, w1, ec, mu, x);
     LAMG_LAUNCH_CHECK();
 }
 

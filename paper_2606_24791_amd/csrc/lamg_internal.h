@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdint>
 #include <cstring>
@@ -66,6 +67,7 @@ class Pool {
     void *get(size_t bytes);  // throws Error(LAMG_OOM)
     void put(void *p);
     int64_t bytes() const { return bytes_; }
+    int64_t peak() const { return peak_; }  // high-water mark of bytes()
     hipStream_t stream() const { return s_; }
     void set_stream(hipStream_t s) { s_ = s; }
 
@@ -78,6 +80,7 @@ class Pool {
     hipStream_t s_;
     std::vector<Blk> blks_;
     int64_t bytes_ = 0;
+    int64_t peak_ = 0;
 };
 
 // Typed device array owned by a Pool.
@@ -209,6 +212,48 @@ struct Workspace {
     DArr<int64_t> visits;       // coarse-tail visit counters (per level)
 };
 
+// In-situ launch timer: a pair of HIP events per timed launch, recorded by the launch
+// itself (hipExtLaunchKernel takes the dispatch's own start and end timestamps), so the
+// elapsed time is the kernel's execution time without stream-marker overhead.
+struct KTimer {
+    static constexpr int kKinds = 5;
+    bool on = false;
+    std::vector<hipEvent_t> ev;  // 2 per launch
+    struct Rec {
+        int kind, prec;  // prec 0: FP64, 1: FP32; kind -1: nothing was launched
+        double bytes;
+    };
+    std::vector<Rec> recs;
+    int64_t cnt[kKinds][2] = {};
+    double sec[kKinds][2] = {}, bytes[kKinds][2] = {};
+    // Reserves an event pair; returns its index or -1 (timer off or full).
+    int open(int kind, int prec, double b);
+    void start(int max_launches);
+    void stop();
+    void release();
+};
+
+// Events that the launch helpers attach to the kernels they launch while set (the first
+// launch records `start`, every launch records `stop`). Set by the solve on its own thread.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool started = false;
+};
+extern thread_local LaunchEvents *t_launch_events;
+
+template <class... KArgs, class... Args>
+inline void launch_kernel(void (*kern)(KArgs...), dim3 grid, dim3 block, uint32_t shmem,
+                          hipStream_t s, Args... args) {
+    LaunchEvents *le = t_launch_events;
+    if (!le) {
+        hipLaunchKernelGGL(kern, grid, block, shmem, s, args...);
+        return;
+    }
+    hipEvent_t e0 = le->started ? nullptr : le->start;
+    le->started = true;
+    hipExtLaunchKernelGGL(kern, grid, block, shmem, s, e0, le->stop, 0u, args...);
+}
+
 }  // namespace lamg
 
 struct lamg_handle {
@@ -219,6 +264,7 @@ struct lamg_handle {
     int nlev = 0;
     std::vector<lamg::Level> lev;
     lamg::Workspace ws;
+    lamg::KTimer timer;
     double setup_seconds = 0.0;
     ~lamg_handle();
 };

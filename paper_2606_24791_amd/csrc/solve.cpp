@@ -58,6 +58,55 @@ struct WsSel<float> {
     static TailPlan &plan(Workspace &w) { return w.plan32; }
 };
 
+// Algorithmic (compulsory) bytes of one launch of the finest-level cycle kernels, s = value
+// and vector element size: every matrix index and value, row pointer and diagonal once,
+// every vector element the launch reads or writes once.
+double bytes_gs_color(const SolveOp &op, int c, int k, double s) {
+    const int nc = op.ncolors;
+    double r = (double)(op.blk[c + 1] - op.blk[c] + op.blk[nc + c + 1] - op.blk[nc + c]);
+    double e = (double)(op.blk_nnz[c + 1] - op.blk_nnz[c] + op.blk_nnz[nc + c + 1] -
+                        op.blk_nnz[nc + c]);
+    return e * (4.0 + s) + 4.0 * (r + 1.0) + r * s + 3.0 * k * r * s;
+}
+double bytes_residual(const SolveOp &op, int k, double s) {
+    const double n = (double)op.n;
+    return (double)op.nnz_off * (4.0 + s) + 4.0 * (n + 1) + n * s + 3.0 * k * n * s;
+}
+double bytes_restrict(const SolveOp &op, int k, double s) {
+    return 4.0 * (op.nc + 1) + (double)op.nnz_r * (4.0 + s) + (double)k * op.n * s +
+           (double)k * op.nc * s;
+}
+double bytes_prolong(const SolveOp &op, int k, double s) {
+    const double n = (double)op.n;
+    return n * (8.0 + 2.0 * s) + (double)k * op.nc * s + 2.0 * k * n * s;
+}
+
+// Attaches a pair of the handle's timer events to the kernels launched during its lifetime.
+struct Timed {
+    KTimer &t;
+    int idx;
+    LaunchEvents le;
+    LaunchEvents *prev = nullptr;
+    Timed(lamg_handle *h, int kind, int prec, double bytes)
+        : t(h->timer), idx(h->timer.on ? h->timer.open(kind, prec, bytes) : -1) {
+        if (idx < 0) return;
+        le.start = t.ev[2 * idx];
+        le.stop = t.ev[2 * idx + 1];
+        prev = t_launch_events;
+        t_launch_events = &le;
+    }
+    ~Timed() {
+        if (idx < 0) return;
+        t_launch_events = prev;
+        if (!le.started) t.recs[idx].kind = -1;
+    }
+};
+
+template <class T>
+constexpr int prec_id() {
+    return sizeof(T) == 4 ? 1 : 0;
+}
+
 template <class T>
 struct Cycle {
     lamg_handle *h;
@@ -91,6 +140,7 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
     Level &L = h->lev[l];
     using P = Prec<T>;
     if (l == C.l0) {
+        Timed tm(h, LAMG_KERNEL_TAIL, prec_id<T>(), 0.0);
         run_tail<T>(*C.plan, l, h->nlev, k, C.d_visits, s);
         return;
     }
@@ -103,9 +153,28 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
     const SolveOp &cop = Lc.op;
     LevelVecs<T> &me = (*C.v)[l];
     LevelVecs<T> &cv = (*C.v)[l + 1];
-    run_gs<T>(op, P::v(op), P::dinv(op), f, x, k, 1, s, l == 0);
-    run_residual<T>(op, P::v(op), P::d(op), x, f, me.r.p, k, s, l == 0);
-    run_restrict<T>(op, P::rw(op), me.r.p, cv.f.p, k, s);
+    const bool timed = l == 0 && h->timer.on;
+    const double sz = sizeof(T);
+    auto smooth = [&](int sweeps) {
+        if (!timed) {
+            run_gs<T>(op, P::v(op), P::dinv(op), f, x, k, sweeps, s, l == 0);
+            return;
+        }
+        for (int sw = 0; sw < sweeps; ++sw)
+            for (int c = 0; c < op.ncolors; ++c) {
+                Timed tm(h, LAMG_KERNEL_GS_COLOR, prec_id<T>(), bytes_gs_color(op, c, k, sz));
+                run_gs_color<T>(op, c, P::v(op), P::dinv(op), f, x, k, s, true);
+            }
+    };
+    smooth(1);
+    {
+        Timed tm(h, timed ? LAMG_KERNEL_RESIDUAL : -1, prec_id<T>(), bytes_residual(op, k, sz));
+        run_residual<T>(op, P::v(op), P::d(op), x, f, me.r.p, k, s, l == 0);
+    }
+    {
+        Timed tm(h, timed ? LAMG_KERNEL_RESTRICT : -1, prec_id<T>(), bytes_restrict(op, k, sz));
+        run_restrict<T>(op, P::rw(op), me.r.p, cv.f.p, k, s);
+    }
     int64_t i = C.visits[l]++;
     int nvis = (int)(std::floor((double)(i + 1) * L.gamma) - std::floor((double)i * L.gamma));
     run_fill<T>(cv.x.p, Lc.n * k, T(0), s);
@@ -120,8 +189,11 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
         }
     }
     run_mu<T>(Lc.n, cv.x.p, cv.f.p, cv.rho.p, k, C.partial, me.mu.p, s);
-    run_prolong<T>(op, P::w0(op), P::w1(op), cv.x.p, me.mu.p, x, k, s);
-    run_gs<T>(op, P::v(op), P::dinv(op), f, x, k, 2, s, l == 0);
+    {
+        Timed tm(h, timed ? LAMG_KERNEL_PROLONG : -1, prec_id<T>(), bytes_prolong(op, k, sz));
+        run_prolong<T>(op, P::w0(op), P::w1(op), cv.x.p, me.mu.p, x, k, s);
+    }
+    smooth(2);
 }
 
 template <class T>
@@ -304,7 +376,10 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
             cycle<float>(c32, 0, v0.x.p, v0.f.p);
             run_add_scaled_f32(n, k, v0.x.p, w.scale.p, w.phi.p, s);
         }
-        run_residual<double>(op0, op0.v64.p, op0.d64.p, w.phi.p, w.b.p, w.r.p, k, s, true);
+        {
+            Timed tm(h, LAMG_KERNEL_RESIDUAL, 0, bytes_residual(op0, k, 8.0));
+            run_residual<double>(op0, op0.v64.p, op0.d64.p, w.phi.p, w.b.p, w.r.p, k, s, true);
+        }
         if (!direct && kappa > 0) {
             run_recombine_fine(n, k, hm, w.phi.p, w.r.p, w.hphi.p, w.hr.p, w.partial.p, w.alpha_f.p, s);
             int slot = hnext % kappa;
@@ -377,7 +452,6 @@ void profile_impl(lamg_handle *h, int level, int kernel, int k, int reps, double
     Level &L = h->lev[level];
     const SolveOp &op = L.op;
     const bool fine = level == 0;
-    const double sv = sizeof(T), sa = sizeof(T), si = 4.0;
     const int64_t n = L.n;
     LevelVecs<T> &me = lv[level];
     run_fill<T>(me.x.p, n * k, T(1), s);
@@ -416,26 +490,64 @@ void profile_impl(lamg_handle *h, int level, int kernel, int k, int reps, double
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     *sec = (double)ms * 1e-3 / reps;
-    const int nc = op.ncolors;
-    double b = 0.0;
-    if (kernel == LAMG_KERNEL_GS_COLOR) {
-        // rows of colour 0 (both bins): CSR entries, row pointers, inverse diagonal,
-        // f read, x written, neighbours' x read once
-        double r = (double)(op.blk[1] - op.blk[0] + op.blk[nc + 1] - op.blk[nc]);
-        double e = (double)(op.blk_nnz[1] - op.blk_nnz[0] + op.blk_nnz[nc + 1] - op.blk_nnz[nc]);
-        b = e * (si + sa) + 4.0 * (r + 1.0) + r * sa + 3.0 * k * r * sv;
-    } else if (kernel == LAMG_KERNEL_RESIDUAL) {
-        b = (double)op.nnz_off * (si + sa) + 4.0 * (n + 1) + n * sa + 3.0 * k * n * sv;
-    } else if (kernel == LAMG_KERNEL_RESTRICT) {
-        b = 4.0 * (op.nc + 1) + (double)op.nnz_r * (si + sa) + (double)k * n * sv +
-            (double)k * op.nc * sv;
-    } else {
-        b = (double)n * (8.0 + 2.0 * sa) + (double)k * op.nc * sv + 2.0 * k * n * sv;
-    }
-    *bytes = b;
+    const double sz = sizeof(T);
+    if (kernel == LAMG_KERNEL_GS_COLOR)
+        *bytes = bytes_gs_color(op, 0, k, sz);
+    else if (kernel == LAMG_KERNEL_RESIDUAL)
+        *bytes = bytes_residual(op, k, sz);
+    else if (kernel == LAMG_KERNEL_RESTRICT)
+        *bytes = bytes_restrict(op, k, sz);
+    else
+        *bytes = bytes_prolong(op, k, sz);
 }
 
 }  // namespace
+
+thread_local LaunchEvents *t_launch_events = nullptr;
+
+int KTimer::open(int kind, int prec, double b) {
+    if (!on || kind < 0 || 2 * (recs.size() + 1) > ev.size()) return -1;
+    recs.push_back(Rec{kind, prec, b});
+    return (int)recs.size() - 1;
+}
+
+void KTimer::start(int max_launches) {
+    release();
+    for (auto &c : cnt) c[0] = c[1] = 0;
+    for (auto &c : sec) c[0] = c[1] = 0.0;
+    for (auto &c : bytes) c[0] = c[1] = 0.0;
+    ev.assign(2 * (size_t)max_launches, nullptr);
+    for (auto &e : ev) LAMG_HIP(hipEventCreate(&e));
+    recs.clear();
+    recs.reserve(max_launches);
+    on = true;
+}
+
+void KTimer::stop() {
+    on = false;
+    for (size_t i = recs.size(); i-- > 0;)
+        if (recs[i].kind >= 0) {
+            LAMG_HIP(hipEventSynchronize(ev[2 * i + 1]));
+            break;
+        }
+    for (size_t i = 0; i < recs.size(); ++i) {
+        const Rec &r = recs[i];
+        if (r.kind < 0) continue;
+        float ms = 0.f;
+        LAMG_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+        cnt[r.kind][r.prec] += 1;
+        sec[r.kind][r.prec] += 1e-3 * (double)ms;
+        bytes[r.kind][r.prec] += r.bytes;
+    }
+    release();
+}
+
+void KTimer::release() {
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    ev.clear();
+    recs.clear();
+}
 
 lamg_status run_profile(lamg_handle *h, int level, int kernel, lamg_precision prec, int k,
                         int reps, double *sec, double *bytes) {

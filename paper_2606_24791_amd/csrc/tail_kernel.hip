@@ -593,7 +593,7 @@ void run_tail(const TailPlan &tp, int l0, int nlev, int k, int64_t *d_visits, hi
     while ((1 << lkp) < k) ++lkp;
     A.lkp = lkp;
     A.visits = d_visits;
-    k_tail<T><<<1, TB, tp.lds_bytes, s>>>(A);
+    launch_kernel(k_tail<T>, dim3(1), dim3(TB), (uint32_t)tp.lds_bytes, s, A);
     LAMG_LAUNCH_CHECK();
 }
 

@@ -42,7 +42,8 @@ class lamg_hier_info(C.Structure):
                 ("nnz", C.c_int64 * MAX_LEVELS), ("ncolors", C.c_int32 * MAX_LEVELS),
                 ("n_caliber2", C.c_int64 * MAX_LEVELS), ("gamma", C.c_double * MAX_LEVELS),
                 ("tau", C.c_double * MAX_LEVELS), ("bytes_device", C.c_int64),
-                ("op_complexity", C.c_double), ("setup_seconds", C.c_double)]
+                ("op_complexity", C.c_double), ("setup_seconds", C.c_double),
+                ("bytes_peak", C.c_int64)]
 
 
 class lamg_solve_info(C.Structure):
@@ -84,7 +85,19 @@ _lib.lamg_profile_kernel.argtypes = [C.c_void_p, C.c_int32, C.c_int, C.c_int, C.
                                      C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]
 _lib.lamg_profile_kernel.restype = C.c_int
 
-KERNEL_GS_COLOR, KERNEL_RESIDUAL, KERNEL_RESTRICT, KERNEL_PROLONG = range(4)
+KERNEL_GS_COLOR, KERNEL_RESIDUAL, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_TAIL = range(5)
+
+
+class lamg_kernel_time(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("seconds", C.c_double), ("bytes", C.c_double)]
+
+
+_lib.lamg_timing_start.argtypes = [C.c_void_p, C.c_int32]
+_lib.lamg_timing_start.restype = C.c_int
+_lib.lamg_timing_stop.argtypes = [C.c_void_p]
+_lib.lamg_timing_stop.restype = C.c_int
+_lib.lamg_timing_get.argtypes = [C.c_void_p, C.c_int, C.c_int, C.POINTER(lamg_kernel_time)]
+_lib.lamg_timing_get.restype = C.c_int
 
 
 class LamgError(RuntimeError):
@@ -123,10 +136,10 @@ def lamg_set_allocator(alloc=None, free=None, ctx=None) -> None:
     free(ptr, stream, ctx) (ctypes-callable), or back to hipMalloc with no arguments."""
     if alloc is None:
         _lib.lamg_set_allocator(ALLOC_FN(0), FREE_FN(0), None)
-        _alloc_keepalive.clear()
         return
     a, f = ALLOC_FN(alloc), FREE_FN(free)
-    _alloc_keepalive[:] = [a, f]
+    # handles keep the hook they were built with, so every hook ever installed stays alive
+    _alloc_keepalive.extend([a, f])
     _lib.lamg_set_allocator(a, f, ctx)
 
 
@@ -262,7 +275,7 @@ def lamg_hierarchy_info(h: Handle) -> dict:
                 ncolors=list(info.ncolors[:L]), n_caliber2=list(info.n_caliber2[:L]),
                 gamma=list(info.gamma[:L]), tau=list(info.tau[:L]),
                 bytes_device=int(info.bytes_device), op_complexity=float(info.op_complexity),
-                setup_seconds=float(info.setup_seconds))
+                setup_seconds=float(info.setup_seconds), bytes_peak=int(info.bytes_peak))
 
 
 def lamg_export_level(h: Handle, level: int) -> dict:
@@ -300,3 +313,29 @@ def lamg_profile_kernel(h: Handle, level: int, kernel: int, precision: int = FP6
     if st != OK:
         raise LamgError(st, "lamg_profile_kernel")
     return float(sec.value), float(byt.value)
+
+
+def lamg_timing_start(h: Handle, max_launches: int = 16384) -> None:
+    """Starts in-situ event timing of the finest-level cycle kernels and the coarse tail."""
+    st = _lib.lamg_timing_start(h.ptr, int(max_launches))
+    if st != OK:
+        raise LamgError(st, "lamg_timing_start")
+
+
+def lamg_timing_stop(h: Handle) -> dict:
+    """Stops timing; returns {(kernel, precision): dict(launches, seconds, bytes)} for every
+    kernel and precision with at least one timed launch."""
+    st = _lib.lamg_timing_stop(h.ptr)
+    if st != OK:
+        raise LamgError(st, "lamg_timing_stop")
+    out = {}
+    for kern in range(5):
+        for prec in (FP64, FP32_IR):
+            t = lamg_kernel_time()
+            st = _lib.lamg_timing_get(h.ptr, kern, prec, C.byref(t))
+            if st != OK:
+                raise LamgError(st, "lamg_timing_get")
+            if t.launches:
+                out[(kern, prec)] = dict(launches=int(t.launches), seconds=float(t.seconds),
+                                         bytes=float(t.bytes))
+    return out

@@ -247,3 +247,49 @@ def test_cycle_execution_modes_agree(B, tail_rows):
             st = B.lamg_solve(h, b, phi, precision=prec)
             check_solution(g, st, phi.cpu().numpy(), bh[:k], refs[:k])
     h.close()
+
+
+def test_in_situ_timing_counts_launches_and_leaves_results_unchanged(B):
+    """The event timer brackets launches only: a timed solve returns the untimed solve's
+    bits; every finest-level kernel and the coarse tail are counted, with positive
+    durations and the algorithmic bytes of their rows; after stop, solves are untimed."""
+    import torch
+
+    g = GRAPHS["aniso_ragged"]()
+    note("in-situ timing")
+    h = B.lamg_setup(g)
+    info = B.lamg_hierarchy_info(h)
+    b = torch.tensor(I.rhs(g.n, 2, seed=5), device="cuda")
+    for prec in (B.FP32_IR, B.FP64):
+        ref = torch.empty_like(b)
+        st0 = B.lamg_solve(h, b, ref, precision=prec)
+        B.lamg_timing_start(h, 4096)
+        phi = torch.empty_like(b)
+        st = B.lamg_solve(h, b, phi, precision=prec)
+        kt = B.lamg_timing_stop(h)
+        assert torch.equal(phi, ref) and st["cycles"] == st0["cycles"]
+        cyc = st["cycles"]
+        ncol = info["ncolors"][0]
+        gs = kt[(B.KERNEL_GS_COLOR, prec)]
+        assert gs["launches"] == 3 * ncol * cyc and gs["seconds"] > 0 and gs["bytes"] > 0
+        for kern in (B.KERNEL_RESTRICT, B.KERNEL_PROLONG):
+            assert kt[(kern, prec)]["launches"] == cyc
+        # the cycle's residual in its precision plus the FP64 outer residual per cycle
+        if prec == B.FP64:
+            assert kt[(B.KERNEL_RESIDUAL, B.FP64)]["launches"] == 2 * cyc
+        else:
+            assert kt[(B.KERNEL_RESIDUAL, B.FP32_IR)]["launches"] == cyc
+            assert kt[(B.KERNEL_RESIDUAL, B.FP64)]["launches"] == cyc
+        assert kt[(B.KERNEL_TAIL, prec)]["launches"] >= cyc
+        assert kt[(B.KERNEL_TAIL, prec)]["bytes"] == 0.0
+        # bytes per GS launch: whole-level sum over colours equals one residual's matrix part
+        n, e = info["n"][0], info["nnz"][0] - info["n"][0]
+        s = 4 if prec == B.FP32_IR else 8
+        per_sweep = gs["bytes"] / (3 * cyc)
+        assert per_sweep == pytest.approx(e * (4 + s) + 4 * (n + ncol) + n * s + 3 * 2 * n * s)
+        B.lamg_timing_start(h, 16)  # a full timer stops recording without error
+        B.lamg_solve(h, b, phi, precision=prec)
+        kt = B.lamg_timing_stop(h)
+        assert sum(t["launches"] for t in kt.values()) == 16
+        assert torch.equal(phi, ref)
+    h.close()
