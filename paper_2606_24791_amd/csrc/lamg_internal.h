@@ -188,8 +188,9 @@ struct LevelVecs {
 // Device-side plan of a coarse tail for one precision and column count.
 struct TailPlan {
     const void *desc = nullptr;      // level descriptors (global arrays)
-    const void *lds_desc = nullptr;  // descriptors of LDS-resident levels (offsets)
+    const void *lds_desc = nullptr;  // the launch's descriptors (LDS-resident levels: offsets)
     const void *jobs = nullptr;      // global -> LDS copy jobs
+    void *top_x = nullptr;           // global iterate of the tail's top level
     int njobs = 0;
     int l_lds = 0;         // first LDS-resident level (nlev: none)
     size_t lds_bytes = 0;  // dynamic LDS of the launch

@@ -237,8 +237,9 @@ void ensure_level_vecs(lamg_handle *h, int k) {
     tp.l_lds = h->nlev;
     std::vector<char> lds_desc, jobs;
     size_t lds_bytes = 0;
-    int l_lds = tail_lds_plan<T>(h->lev, tail_level(h), k, host.data(), lds_desc, jobs, lds_bytes);
-    if (l_lds < h->nlev) {
+    const int l0 = tail_level(h);
+    int l_lds = tail_lds_plan<T>(h->lev, l0, k, host.data(), lds_desc, jobs, lds_bytes);
+    if (l0 >= 0) {
         DArr<char> &dl = W::lds(w);
         DArr<char> &dj = W::jobs(w);
         dl.alloc(pool, (int64_t)lds_desc.size());
@@ -250,6 +251,7 @@ void ensure_level_vecs(lamg_handle *h, int k) {
         tp.njobs = (int)(jobs.size() / tail_copy_job_bytes());
         tp.l_lds = l_lds;
         tp.lds_bytes = lds_bytes;
+        tp.top_x = lv[l0].x.p;
     }
     LAMG_HIP(hipStreamSynchronize(h->stream));
     W::k(w) = k;

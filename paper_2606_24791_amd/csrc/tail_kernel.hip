@@ -6,15 +6,28 @@
 // towards 2 where coarsening is aggressive), and every visit is a chain of dependent
 // steps: Gauss-Seidel colour passes, residual, restriction, coarse recombination,
 // energy correction, prolongation. As separate kernels each step costs a dispatch of a
-// few microseconds; here each step is a loop over the level's rows followed by a
-// workgroup barrier, with the level data resident in L2. The recursion over levels is an
-// explicit state machine; the per-level visit counters live in device memory so that the
-// Beatty visit counts continue across launches within one solve.
+// few microseconds; here each step is a loop over the level's rows followed by one
+// workgroup barrier, so the cost of a step is the latency of its few dependent memory
+// accesses. Everything is arranged to keep that latency short:
+//  - the smallest levels (operators and vectors) are copied into LDS at the start of a
+//    launch and addressed through LDS pointers (ds_* instructions), the others stay in
+//    global memory (L2-resident);
+//  - level descriptors are read with scalar loads, all control flow is wave-uniform, and
+//    the recursion over levels is a state machine whose per-level state (phase, visit
+//    index, visit count, Beatty counter) lives in one VGPR lane per level of every wave,
+//    so no LDS traffic or barrier is spent on bookkeeping;
+//  - on levels whose (row, column) pairs fit one per thread and whose rows are short, a
+//    thread holds its row (column offsets, values, diagonal, right-hand side) in
+//    registers for a whole smoothing call, so a colour pass is one gather, one store and
+//    one barrier, and the residual after pre-smoothing reuses the same registers;
+//  - a workgroup reduction is one barrier: waves write partial sums, and after the
+//    barrier every thread forms its column's totals itself (in wave order, so all
+//    threads agree bit for bit), so the dependent update needs no second pass;
+//  - 32-bit indexing throughout (a tail level has at most a few thousand rows).
 //
 // The arithmetic per step is that of the multi-kernel path (cycle_kernels.hip).
 #include <type_traits>
 
-#include "csr_device.h"
 #include "lamg_internal.h"
 
 namespace lamg {
@@ -23,74 +36,120 @@ namespace {
 
 constexpr int TB = 1024;  // threads of the tail workgroup
 constexpr int TW = TB / 64;
+constexpr int kFast = 16;  // longest row held in registers
+template <class T>
+constexpr int kGather = sizeof(T) == 4 ? 8 : 4;  // gathers in flight per group
+constexpr int kRedQ = 2;   // quantities per tail reduction
 
+// Level descriptor. Array fields hold device pointers for levels in global memory and
+// byte offsets into the launch's dynamic LDS for LDS-resident levels (Z always global).
 template <class T>
 struct TailLvl {
-    int64_t n;
-    int ncolors, coarsest;
+    int32_t n, ncolors, coarsest, nc;  // nc: rows of the next level
+    int32_t n_rlong, maxlen, pad0, pad1;
+    double gamma;
     const int64_t *blk;  // 2*ncolors + 1 offsets (class 0 colours, class 1 colours)
     const int32_t *rp, *ci;
     const T *v, *d, *dinv;
     const int32_t *p0, *p1;  // P to the next level
     const T *w0, *w1;
-    int64_t nc;
     const int32_t *rrp, *rci, *rlong;  // P^T
-    int64_t n_rlong;
     const T *rw;
-    const double *Z;  // coarsest
+    const double *Z;  // coarsest: pseudo-inverse
     T *x, *f, *r, *rho, *x1, *rho1;
-    double gamma;
-    int maxlen;  // longest off-diagonal row; 0 if the level has long-class rows
 };
 
-constexpr int kTailMax = kTailMaxLevels;
-
-// Global -> LDS copy performed at the start of every tail launch (4-byte words).
+// Global -> LDS copy performed at the start of every tail launch.
 struct CopyJob {
     const void *src;
-    uint32_t dst;    // byte offset in the dynamic LDS buffer
+    uint32_t dst;    // byte offset in the dynamic LDS buffer (multiple of 16)
     uint32_t bytes;  // multiple of 4
 };
 
-template <class T>
 struct TailArgs {
-    const TailLvl<T> *lv;      // device descriptors of all levels (global-memory arrays)
-    const TailLvl<T> *lds_lv;  // levels >= l_lds: pointer fields are LDS byte offsets (Z stays global)
     const CopyJob *jobs;
-    int njobs;
-    int l0, nlev, l_lds, k, lkp;
     int64_t *visits;  // per level, persistent within a solve
+    void *top_x;      // global iterate of the top level (written back if it lives in LDS)
+    int32_t njobs, l0, nlev, l_lds, k, lkp;
+    uint32_t red_off;  // byte offset of the two reduction buffers in the dynamic LDS
+    uint32_t pad;
 };
 
 __device__ inline void bar() { __syncthreads(); }
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Sum over the sub-lanes of a group of G lanes (xor partners of stride kp).
-template <class V>
-__device__ inline V wave_sum_sub(V v, int kp, int G) {
-    for (int o = kp; o < G; o <<= 1) v += __shfl_xor(v, o, 64);
-    return v;
+template <bool LDS, class P>
+__device__ inline P *at(char *smem, P *p) {
+    if constexpr (LDS)
+        return reinterpret_cast<P *>(smem + static_cast<uint32_t>(reinterpret_cast<uintptr_t>(p)));
+    else
+        return p;
 }
 
-// CSR pass over rows [a, b) (short rows) and [la, lb) (long rows):
-//   OP 0: x[r] = (f[r] - sum_off) * dinv[r]      (Gauss-Seidel colour pass, in place)
-//   OP 1: out[r] = f[r] - d[r] x[r] - sum_off     (residual)
-//   OP 2: out[r] = sum_off                        (P^T r)
-// Short rows: one thread per (row, column). Long rows: one wave per row, the 64 lanes
-// split as kp columns x (64/kp) entry lanes.
+// The arrays of one level, rebased into LDS where the level lives there.
+template <class T, bool LDS>
+struct Lv {
+    int n, nc, ncol, nrl, maxlen;
+    const int64_t *blk;
+    const int32_t *rp, *ci;
+    const T *v, *d, *dinv;
+    const int32_t *p0, *p1;
+    const T *w0, *w1;
+    const int32_t *rrp, *rci, *rlong;
+    const T *rw;
+    T *x, *f, *r, *rho, *x1, *rho1;
+    __device__ Lv(const TailLvl<T> &D, char *s)
+        : n(D.n), nc(D.nc), ncol(D.ncolors), nrl(D.n_rlong), maxlen(D.maxlen),
+          blk(at<LDS>(s, D.blk)), rp(at<LDS>(s, D.rp)), ci(at<LDS>(s, D.ci)), v(at<LDS>(s, D.v)),
+          d(at<LDS>(s, D.d)), dinv(at<LDS>(s, D.dinv)), p0(at<LDS>(s, D.p0)),
+          p1(at<LDS>(s, D.p1)), w0(at<LDS>(s, D.w0)), w1(at<LDS>(s, D.w1)),
+          rrp(at<LDS>(s, D.rrp)), rci(at<LDS>(s, D.rci)), rlong(at<LDS>(s, D.rlong)),
+          rw(at<LDS>(s, D.rw)), x(at<LDS>(s, D.x)), f(at<LDS>(s, D.f)), r(at<LDS>(s, D.r)),
+          rho(at<LDS>(s, D.rho)), x1(at<LDS>(s, D.x1)), rho1(at<LDS>(s, D.rho1)) {}
+};
+
+// sum over [j0, e) step `stride` of v[j] * x[ci[j] * k + col], U entries in flight.
+template <class T, int U>
+__device__ inline T row_sum(const int32_t *ci, const T *v, const T *x, int j0, int e, int stride,
+                            int k, int col) {
+    T acc = T(0);
+    for (int j = j0; j < e; j += U * stride) {
+        int cc[U];
+        T vv[U], xx[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int jj = j + u * stride;
+            const bool ok = jj < e;
+            cc[u] = ok ? ci[jj] : -1;
+            vv[u] = ok ? v[jj] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) xx[u] = cc[u] >= 0 ? x[cc[u] * k + col] : T(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += vv[u] * xx[u];
+    }
+    return acc;
+}
+
+// CSR pass over rows [a, b) (short rows) and [la, lb) (long rows, through `rows` if given):
+//   OP 0: x[r] = (f[r] - sum_off) * dd[r]      (Gauss-Seidel colour pass, in place)
+//   OP 1: out[r] = f[r] - dd[r] x[r] - sum_off  (residual)
+//   OP 2: out[r] = sum_off                      (P^T r)
+// Short rows: one thread per (row, column); rows longer than skip_long (> 0) are left to
+// the long list. Long rows: one wave per row, the 64 lanes split as kp columns x (64/kp).
 template <class T, int OP>
-__device__ void csr_pass(int64_t a, int64_t b, int64_t la, int64_t lb, const int32_t *rows,
-                         int skip_long, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                         const T *__restrict__ v, const T *__restrict__ dd, const T *f, const T *xin,
-                         T *out, int k, int lkp) {
+__device__ __forceinline__ void csr_rows(int a, int b, int la, int lb, const int32_t *rows, int skip_long,
+                         const int32_t *rp, const int32_t *ci, const T *v, const T *dd, const T *f,
+                         const T *xin, T *out, int k, int lkp) {
     const int tid = threadIdx.x;
     const int kp = 1 << lkp;
     const int c = tid & (kp - 1);
     if (c < k) {
-        for (int64_t row = a + (tid >> lkp); row < b; row += (TB >> lkp)) {
-            int32_t e0 = rp[row], e1 = rp[row + 1];
+        for (int row = a + (tid >> lkp); row < b; row += (TB >> lkp)) {
+            const int e0 = rp[row], e1 = rp[row + 1];
             if (skip_long > 0 && e1 - e0 > skip_long) continue;
-            T acc = row_dot<T, 8>(ci, v, xin, e0, e1, 1, k, c);
-            int64_t o = row * k + c;
+            const T acc = row_sum<T, 8>(ci, v, xin, e0, e1, 1, k, c);
+            const int o = row * k + c;
             if (OP == 0)
                 out[o] = (f[o] - acc) * dd[row];
             else if (OP == 1)
@@ -101,14 +160,14 @@ __device__ void csr_pass(int64_t a, int64_t b, int64_t la, int64_t lb, const int
     }
     const int wave = tid >> 6, lane = tid & 63;
     const int sub = lane >> lkp, col = lane & (kp - 1), nsub = 64 >> lkp;
-    for (int64_t i = la + wave; i < lb; i += TW) {
-        int64_t row = rows ? (int64_t)rows[i] : i;
-        int32_t e0 = rp[row], e1 = rp[row + 1];
+    for (int i = la + wave; i < lb; i += TW) {
+        const int row = rows ? rows[i] : i;
+        const int e0 = rp[row], e1 = rp[row + 1];
         T acc = T(0);
-        if (col < k) acc = row_dot<T, 4>(ci, v, xin, e0 + sub, e1, nsub, k, col);
-        acc = wave_sum_sub(acc, kp, 64);
+        if (col < k) acc = row_sum<T, 4>(ci, v, xin, e0 + sub, e1, nsub, k, col);
+        for (int o = kp; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
         if (sub == 0 && col < k) {
-            int64_t o = row * k + col;
+            const int o = row * k + col;
             if (OP == 0)
                 out[o] = (f[o] - acc) * dd[row];
             else if (OP == 1)
@@ -119,148 +178,147 @@ __device__ void csr_pass(int64_t a, int64_t b, int64_t la, int64_t lb, const int
     }
 }
 
-// Loop helper over (row, column) pairs of an n x k block with the kp mapping.
-#define TAIL_ROWS(n, ...)                                                         \
-    {                                                                              \
-        const int c_ = tid & (kp - 1);                                             \
-        if (c_ < k)                                                                \
-            for (int64_t u_ = tid >> lkp; u_ < (n); u_ += (TB >> lkp)) {           \
-                const int64_t t = u_ * k + c_;                                     \
-                const int64_t u = u_;                                              \
-                const int c = c_;                                                  \
-                (void)u;                                                           \
-                (void)c;                                                           \
-                __VA_ARGS__                                                        \
-            }                                                                      \
-    }
-
-// register-resident rows: at most this many off-diagonals (fewer in FP64 to stay in registers)
-template <class T>
-struct FastRow {
-    static constexpr int N = sizeof(T) == 4 ? 16 : 12;
-};
-
-// `sweeps` Gauss-Seidel sweeps. On a level whose (row, column) pairs fit one per thread and
-// whose rows are short, each thread loads its row (indices, values, inverse diagonal,
-// right-hand side) into registers once per call; a colour pass is then one gather, one
-// store and one barrier. Otherwise every colour pass is a full CSR pass.
-template <class T>
-__device__ void gs_sweeps(const TailLvl<T> &L, int k, int lkp, int sweeps) {
-    const int nc = L.ncolors;
+// `sweeps` Gauss-Seidel sweeps over the colours of level L, then (if `resid`) the residual
+// r = f - L x. On a level whose (row, column) pairs fit one per thread and whose rows have
+// at most kFast off-diagonals, each thread loads its row into registers once (column
+// offsets, values, inverse diagonal, diagonal, right-hand side; padding entries point at
+// the row's own value with weight 0, so every gather is unconditional), and every colour
+// pass is one gather, one store and one barrier.
+template <class T, bool LDS>
+__device__ __forceinline__ void smooth(const Lv<T, LDS> &L, int k, int lkp, int sweeps, bool resid) {
     const int tid = threadIdx.x;
-    constexpr int kFastRow = FastRow<T>::N;
-    if (L.maxlen > 0 && L.maxlen <= kFastRow && (L.n << lkp) <= TB) {
-        const int64_t row = tid >> lkp;
-        const int c = tid & ((1 << lkp) - 1);
+    const int kp = 1 << lkp;
+    const int nc = L.ncol;
+    const bool fast = L.maxlen > 0 && L.maxlen <= kFast && (L.n << lkp) <= TB;
+    constexpr int kGroup = kGather<T>;
+    if (fast) {
+        const int row = tid >> lkp;
+        const int c = tid & (kp - 1);
         const bool live = row < L.n && c < k;
-        int32_t cc[kFastRow];
-        T vv[kFastRow];
-        T dinv = T(0), fv = T(0);
+        const int o = row * k + c;
+        int cc[kFast];
+        T vv[kFast];
+        T dinv = T(0), dg = T(0), fv = T(0);
         int mycol = -1;
         if (live) {
-            const int32_t e0 = L.rp[row], len = L.rp[row + 1] - e0;
+            const int e0 = L.rp[row], len = L.rp[row + 1] - e0;
 #pragma unroll
-            for (int u = 0; u < kFastRow; ++u) {
+            for (int u = 0; u < kFast; ++u) {
                 const bool ok = u < len;
-                cc[u] = ok ? L.ci[e0 + u] : -1;
+                cc[u] = ok ? L.ci[e0 + u] * k + c : o;
                 vv[u] = ok ? L.v[e0 + u] : T(0);
             }
             dinv = L.dinv[row];
-            fv = L.f[row * k + c];
-            for (int cl = 0; cl < nc; ++cl)
-                if (row >= L.blk[cl] && row < L.blk[cl + 1]) mycol = cl;
+            dg = L.d[row];
+            fv = L.f[o];
+            int lo = 0, hi = nc;  // colour: blk[lo] <= row < blk[lo + 1]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if ((int)L.blk[mid] <= row)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            mycol = lo;
         }
         T *x = L.x;
-        for (int sw = 0; sw < sweeps; ++sw) {
+        auto gather = [&]() {  // loads in groups of kGroup, summed in entry order
+            T acc = T(0);
+#pragma unroll
+            for (int u0 = 0; u0 < kFast; u0 += kGroup) {
+                T xx[kGroup];
+#pragma unroll
+                for (int u = 0; u < kGroup; ++u) xx[u] = x[cc[u0 + u]];
+#pragma unroll
+                for (int u = 0; u < kGroup; ++u) acc += vv[u0 + u] * xx[u];
+            }
+            return acc;
+        };
+        for (int sw = 0; sw < sweeps; ++sw)
             for (int cl = 0; cl < nc; ++cl) {
-                if (live && mycol == cl) {
-                    T acc = T(0);
-#pragma unroll
-                    for (int u0 = 0; u0 < kFastRow; u0 += 4) {  // gathers in groups of four
-                        T xx[4];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u)
-                            xx[u] = (u0 + u < kFastRow && cc[u0 + u] >= 0)
-                                        ? x[(int64_t)cc[u0 + u] * k + c]
-                                        : T(0);
-#pragma unroll
-                        for (int u = 0; u < 4; ++u)
-                            if (u0 + u < kFastRow) acc += vv[u0 + u] * xx[u];
-                    }
-                    x[row * k + c] = (fv - acc) * dinv;
-                }
+                if (live && mycol == cl) x[o] = (fv - gather()) * dinv;
                 bar();
             }
+        if (resid) {
+            if (live) L.r[o] = fv - dg * x[o] - gather();
+            bar();
         }
         return;
     }
     for (int sw = 0; sw < sweeps; ++sw)
-        for (int c = 0; c < nc; ++c) {
-            csr_pass<T, 0>(L.blk[c], L.blk[c + 1], L.blk[nc + c], L.blk[nc + c + 1], nullptr, 0,
-                           L.rp, L.ci, L.v, L.dinv, L.f, L.x, L.x, k, lkp);
+        for (int cl = 0; cl < nc; ++cl) {
+            csr_rows<T, 0>((int)L.blk[cl], (int)L.blk[cl + 1], (int)L.blk[nc + cl],
+                           (int)L.blk[nc + cl + 1], nullptr, 0, L.rp, L.ci, L.v, L.dinv, L.f, L.x,
+                           L.x, k, lkp);
             bar();
         }
+    if (resid) {
+        csr_rows<T, 1>(0, (int)L.blk[nc], (int)L.blk[nc], L.n, nullptr, 0, L.rp, L.ci, L.v, L.d,
+                       L.f, L.x, L.r, k, lkp);
+        bar();
+    }
 }
 
-template <class T>
-__device__ void residual(const TailLvl<T> &L, const T *x, const T *f, T *r, int k, int lkp) {
-    const int nc = L.ncolors;
-    csr_pass<T, 1>(0, L.blk[nc], L.blk[nc], L.n, nullptr, 0, L.rp, L.ci, L.v, L.d, f, x, r, k, lkp);
-    bar();
-}
-
-// Deterministic workgroup reduction of Q per-column sums. Thread (rloc, col), col = tid
-// mod kp, holds partial sums over rows rloc, rloc + TB/kp, ...; a fixed xor-shuffle tree
-// combines the lanes of one column inside each wave, then the first kp threads add the
-// waves' totals in wave order. out[i*32 + col] receives sum i of column col.
+// Partial sums of Q quantities per column: xor-shuffle inside each wave over the lanes of
+// one column, then one write per (wave, column). The caller's barrier follows.
 template <int Q>
-__device__ void block_sums(double (&q)[Q], double *sh, int kp, double *out /* Q*32 */) {
+__device__ inline void wave_partials(double (&q)[Q], double *red, int kp) {
     const int tid = threadIdx.x;
-    const int wave = tid >> 6;
+    const int wave = tid >> 6, lane = tid & 63;
+#pragma unroll
     for (int i = 0; i < Q; ++i)
         for (int o = kp; o < 64; o <<= 1) q[i] += __shfl_xor(q[i], o, 64);
-    if ((tid & 63) < kp)
-        for (int i = 0; i < Q; ++i) sh[(wave * Q + i) * 32 + (tid & 63)] = q[i];
-    bar();
-    if (tid < kp)
-        for (int i = 0; i < Q; ++i) {
-            double acc = 0.0;
-            for (int w = 0; w < TW; ++w) acc += sh[(w * Q + i) * 32 + tid];
-            out[i * 32 + tid] = acc;
-        }
-    bar();
+    if (lane < kp)
+#pragma unroll
+        for (int i = 0; i < Q; ++i) red[(i * TW + wave) * kp + lane] = q[i];
 }
 
-template <class T>
-__device__ void coarsest_solve(const TailLvl<T> &L, const T *f, T *y, int k, int lkp) {
+// Column totals from the wave partials, added in wave order (same bits in every thread).
+template <int Q>
+__device__ inline void column_totals(const double *red, int kp, int c, double (&t)[Q]) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        double a = 0.0;
+        for (int w = 0; w < TW; ++w) a += red[(i * TW + w) * kp + c];
+        t[i] = a;
+    }
+}
+
+// y = Z f on the directly solved level (FP64 pseudo-inverse, global memory), G lanes per
+// (row, column) with kZ loads of Z in flight.
+template <class T, bool LDS>
+__device__ __forceinline__ void coarsest(const double *Z, const Lv<T, LDS> &L, int k, int lkp) {
+    constexpr int kZ = 8;
     const int tid = threadIdx.x;
     const int kp = 1 << lkp;
-    const int64_t n = L.n;
-    const int64_t units = n << lkp;
+    const int n = L.n;
+    const int units = n << lkp;
     int lg = 0;
     while (lg < 6 && (units << (lg + 1)) <= TB) ++lg;
     const int G = 1 << lg;
-    for (int64_t base = 0; base < (units << lg); base += TB) {
-        const int64_t t = base + tid;
-        const int64_t unit = t >> lg;
-        const int p = (int)(t & (G - 1));
-        const int64_t u = unit >> lkp;
-        const int c = (int)(unit & (kp - 1));
+    const T *f = L.f;
+    T *y = L.x;
+    for (int base = 0; base < (units << lg); base += TB) {
+        const int t = base + tid;
+        const int unit = t >> lg;
+        const int p = t & (G - 1);
+        const int u = unit >> lkp;
+        const int c = unit & (kp - 1);
         const bool live = unit < units && c < k;
         double acc = 0.0;
         if (live) {
-            const double *zr = L.Z + u * n;
-            for (int64_t j = p; j < n; j += 16 * G) {
-                double zz[16], ff[16];
+            const double *zr = Z + (int64_t)u * n;
+            for (int j = p; j < n; j += kZ * G) {
+                double zz[kZ], ff[kZ];
 #pragma unroll
-                for (int w = 0; w < 16; ++w) {
-                    const int64_t jj = j + (int64_t)w * G;
+                for (int w = 0; w < kZ; ++w) {
+                    const int jj = j + w * G;
                     const bool ok = jj < n;
                     zz[w] = ok ? zr[jj] : 0.0;
                     ff[w] = ok ? (double)f[jj * k + c] : 0.0;
                 }
 #pragma unroll
-                for (int w = 0; w < 16; ++w) acc += zz[w] * ff[w];
+                for (int w = 0; w < kZ; ++w) acc += zz[w] * ff[w];
             }
         }
         for (int o = 1; o < G; o <<= 1) acc += __shfl_xor(acc, o, 64);
@@ -269,158 +327,173 @@ __device__ void coarsest_solve(const TailLvl<T> &L, const T *f, T *y, int k, int
     bar();
 }
 
-template <class P>
-__device__ inline P lds_ptr(char *base, P off) {
-    return off ? reinterpret_cast<P>(base + reinterpret_cast<uintptr_t>(off)) : off;
+// Per-wave level state, one level per lane (the same values in every wave).
+struct WaveState {
+    int st;   // phase | j << 1 | nvis << 9
+    int cnt;  // Beatty visit counter
+    __device__ int get_st(int l) const { return __builtin_amdgcn_readlane(st, l); }
+    __device__ int get_cnt(int l) const { return __builtin_amdgcn_readlane(cnt, l); }
+    __device__ void set_st(int l, int val) { st = ((int)(threadIdx.x & 63) == l) ? val : st; }
+    __device__ void set_cnt(int l, int val) { cnt = ((int)(threadIdx.x & 63) == l) ? val : cnt; }
+};
+
+// One phase of level l (not the coarsest) with child level l+1; returns the next level.
+//  phase 0: pre-smoothing, residual, restriction, zero coarse iterate; descend.
+//  phase 1: back from visit j of the child: child residual, recombination of the last two
+//           child iterates (j >= 2); then descend again, or energy correction,
+//           prolongation and post-smoothing, and ascend.
+template <class T, bool LL, bool LC>
+__device__ __forceinline__ int visit(const TailArgs &A, const TailLvl<T> &DL, const TailLvl<T> &DC, int l,
+                     char *smem, WaveState &ws, int &rbuf) {
+    const int tid = threadIdx.x;
+    const int k = A.k, lkp = A.lkp, kp = 1 << lkp;
+    const Lv<T, LL> L(DL, smem);
+    const Lv<T, LC> C(DC, smem);
+    const int s = ws.get_st(l);
+    if ((s & 1) == 0) {
+        smooth<T, LL>(L, k, lkp, 1, true);
+        csr_rows<T, 2>(0, L.nc, 0, L.nrl, L.rlong, L.nrl ? kLongRow : 0, L.rrp, L.rci, L.rw,
+                       nullptr, nullptr, L.r, C.f, k, lkp);
+        for (int t = tid; t < C.n * k; t += TB) C.x[t] = T(0);
+        bar();
+        const int i = ws.get_cnt(l);
+        ws.set_cnt(l, i + 1);
+        const double g = DL.gamma;
+        const int nvis = (int)(floor((double)(i + 1) * g) - floor((double)i * g));
+        ws.set_st(l, 1 | (0 << 1) | (nvis << 9));
+        ws.set_st(l + 1, 0);
+        return l + 1;
+    }
+    const int j = ((s >> 1) & 255) + 1;
+    const int nvis = s >> 9;
+    const int c = tid & (kp - 1);
+    // rho = f_c - L_c x_c
+    csr_rows<T, 1>(0, (int)C.blk[C.ncol], (int)C.blk[C.ncol], C.n, nullptr, 0, C.rp, C.ci, C.v,
+                   C.d, C.f, C.x, C.rho, k, lkp);
+    bar();
+    const bool again = j < nvis;
+    if (j >= 2) {  // two-iterate recombination across the visits
+        double *red = reinterpret_cast<double *>(smem + A.red_off) + rbuf * (kRedQ * TW * kp);
+        rbuf ^= 1;
+        double q[2] = {0.0, 0.0};
+        if (c < k)
+            for (int i = tid >> lkp; i < C.n; i += TB >> lkp) {
+                const double rv = (double)C.rho[i * k + c];
+                const double g = rv - (double)C.rho1[i * k + c];
+                q[0] += g * g;
+                q[1] += g * rv;
+            }
+        wave_partials<2>(q, red, kp);
+        bar();
+        double t[2];
+        column_totals<2>(red, kp, c, t);
+        const T a = (T)(t[0] > 0.0 ? t[1] / t[0] : 0.0);
+        if (c < k)
+            for (int i = tid >> lkp; i < C.n; i += TB >> lkp) {
+                const int o = i * k + c;
+                const T ev = C.x[o], rv = C.rho[o];
+                const T xn = ev + a * (C.x1[o] - ev);
+                const T rn = rv - a * (rv - C.rho1[o]);
+                C.x[o] = xn;
+                C.rho[o] = rn;
+                if (again) {
+                    C.x1[o] = xn;
+                    C.rho1[o] = rn;
+                }
+            }
+        bar();
+    } else if (again) {
+        if (c < k)
+            for (int i = tid >> lkp; i < C.n; i += TB >> lkp) {
+                const int o = i * k + c;
+                C.x1[o] = C.x[o];
+                C.rho1[o] = C.rho[o];
+            }
+        bar();
+    }
+    if (again) {
+        ws.set_st(l, 1 | (j << 1) | (nvis << 9));
+        ws.set_st(l + 1, 0);
+        return l + 1;
+    }
+    // energy correction mu = <e, f_c> / <e, f_c - rho>, prolongation, post-smoothing
+    {
+        double *red = reinterpret_cast<double *>(smem + A.red_off) + rbuf * (kRedQ * TW * kp);
+        rbuf ^= 1;
+        double q[2] = {0.0, 0.0};
+        if (c < k)
+            for (int i = tid >> lkp; i < C.n; i += TB >> lkp) {
+                const double e = (double)C.x[i * k + c], fc = (double)C.f[i * k + c];
+                q[0] += e * fc;
+                q[1] += e * (fc - (double)C.rho[i * k + c]);
+            }
+        wave_partials<2>(q, red, kp);
+        bar();
+        double t[2];
+        column_totals<2>(red, kp, c, t);
+        double mu = t[0] / t[1];
+        if (!(t[1] > 0.0) || !isfinite(mu)) mu = 1.0;
+        if (c < k)
+            for (int i = tid >> lkp; i < L.n; i += TB >> lkp) {
+                T pe = L.w0[i] * C.x[L.p0[i] * k + c];
+                const int q1 = L.p1[i];
+                if (q1 >= 0) pe += L.w1[i] * C.x[q1 * k + c];
+                L.x[i * k + c] += (T)mu * pe;
+            }
+        bar();
+    }
+    smooth<T, LL>(L, k, lkp, 2, false);
+    return l - 1;
 }
 
 template <class T>
-__global__ void __launch_bounds__(TB) k_tail(TailArgs<T> A) {
+__global__ void __launch_bounds__(TB) k_tail(TailArgs A, const TailLvl<T> *__restrict__ G) {
     extern __shared__ __align__(16) char smem[];
-    __shared__ double sh[TW * 2 * 32];
-    __shared__ double tot[2 * 32];
-    __shared__ double coef[32];
-    __shared__ int s_phase[kMaxLevels], s_j[kMaxLevels], s_nvis[kMaxLevels];
-    __shared__ TailLvl<T> dl[kTailMax];
     const int tid = threadIdx.x;
-    const int k = A.k, lkp = A.lkp, kp = 1 << lkp;
-    const int l0 = A.l0;
-    // stage the descriptors of this tail's levels; LDS-resident levels point into smem
-    if (tid < A.nlev - l0) {
-        const int lv = l0 + tid;
-        if (lv >= A.l_lds) {
-            TailLvl<T> D = A.lds_lv[lv];
-            D.blk = lds_ptr(smem, D.blk);
-            D.rp = lds_ptr(smem, D.rp);
-            D.ci = lds_ptr(smem, D.ci);
-            D.v = lds_ptr(smem, D.v);
-            D.d = lds_ptr(smem, D.d);
-            D.dinv = lds_ptr(smem, D.dinv);
-            D.p0 = lds_ptr(smem, D.p0);
-            D.p1 = lds_ptr(smem, D.p1);
-            D.w0 = lds_ptr(smem, D.w0);
-            D.w1 = lds_ptr(smem, D.w1);
-            D.rrp = lds_ptr(smem, D.rrp);
-            D.rci = lds_ptr(smem, D.rci);
-            D.rlong = lds_ptr(smem, D.rlong);
-            D.rw = lds_ptr(smem, D.rw);
-            D.x = lds_ptr(smem, D.x);
-            D.f = lds_ptr(smem, D.f);
-            D.r = lds_ptr(smem, D.r);
-            D.rho = lds_ptr(smem, D.rho);
-            D.x1 = lds_ptr(smem, D.x1);
-            D.rho1 = lds_ptr(smem, D.rho1);
-            dl[tid] = D;
-        } else {
-            dl[tid] = A.lv[lv];
-        }
-    }
-    // bring the LDS-resident operators (and the top level's iterate and right-hand side)
+    const int lane = tid & 63;
+    const int l0 = A.l0, nlev = A.nlev, l_lds = A.l_lds;
+    // bring the LDS-resident levels (and the top level's iterate and right-hand side)
     for (int jb = 0; jb < A.njobs; ++jb) {
-        const uint32_t *src = static_cast<const uint32_t *>(A.jobs[jb].src);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(smem + A.jobs[jb].dst);
-        const uint32_t words = A.jobs[jb].bytes >> 2;
-        for (uint32_t w = tid; w < words; w += TB) dst[w] = src[w];
+        const CopyJob J = A.jobs[jb];
+        const uint32_t n16 = J.bytes >> 4;
+        const uint4 *s16 = static_cast<const uint4 *>(J.src);
+        uint4 *d16 = reinterpret_cast<uint4 *>(smem + J.dst);
+        for (uint32_t w = tid; w < n16; w += TB) d16[w] = s16[w];
+        const uint32_t *s4 = static_cast<const uint32_t *>(J.src);
+        uint32_t *d4 = reinterpret_cast<uint32_t *>(smem + J.dst);
+        for (uint32_t w = 4 * n16 + tid; w < (J.bytes >> 2); w += TB) d4[w] = s4[w];
     }
-    int l = l0;
-    if (tid == 0) s_phase[l] = 0;
+    WaveState ws;
+    ws.st = 0;
+    ws.cnt = (lane >= l0 && lane < nlev) ? (int)A.visits[lane] : 0;
+    int rbuf = 0;
     bar();
+    int l = l0;
     while (l >= l0) {
-        const TailLvl<T> &L = dl[l - l0];
-        if (L.coarsest) {
-            coarsest_solve<T>(L, L.f, L.x, k, lkp);
+        l = uni(l);
+        const TailLvl<T> &D = G[l];
+        if (D.coarsest) {
+            if (l >= l_lds)
+                coarsest<T, true>(D.Z, Lv<T, true>(D, smem), A.k, A.lkp);
+            else
+                coarsest<T, false>(D.Z, Lv<T, false>(D, smem), A.k, A.lkp);
             --l;
             continue;
         }
-        const TailLvl<T> &C = dl[l + 1 - l0];
-        if (s_phase[l] == 0) {
-            // pre-relaxation, residual, restriction, zero coarse iterate
-            gs_sweeps<T>(L, k, lkp, 1);
-            residual<T>(L, L.x, L.f, L.r, k, lkp);
-            csr_pass<T, 2>(0, L.nc, 0, L.n_rlong, L.rlong, L.n_rlong ? kLongRow : 0, L.rrp, L.rci,
-                           L.rw, nullptr, nullptr, L.r, C.f, k, lkp);
-            TAIL_ROWS(C.n, { C.x[t] = T(0); })
-            if (tid == 0) {
-                int64_t i = A.visits[l]++;
-                s_nvis[l] = (int)(floor((double)(i + 1) * L.gamma) - floor((double)i * L.gamma));
-                s_j[l] = 0;
-                s_phase[l] = 1;
-                s_phase[l + 1] = 0;
-            }
-            bar();
-            ++l;
-            continue;
-        }
-        // returned from one visit to level l+1
-        residual<T>(C, C.x, C.f, C.rho, k, lkp);
-        const int j = s_j[l] + 1;
-        const int nvis = s_nvis[l];
-        const int col = tid & (kp - 1);
-        bar();  // every thread has read the level's loop state before thread 0 updates it
-        if (j >= 2) {  // two-iterate recombination across the visits
-            double q[2] = {0.0, 0.0};
-            if (col < k)
-                for (int64_t i = tid >> lkp; i < C.n; i += TB >> lkp) {
-                    double rv = (double)C.rho[i * k + col], g = rv - (double)C.rho1[i * k + col];
-                    q[0] += g * g;
-                    q[1] += g * rv;
-                }
-            block_sums<2>(q, sh, kp, tot);
-            if (tid < k) coef[tid] = tot[tid] > 0.0 ? tot[32 + tid] / tot[tid] : 0.0;
-            bar();
-            TAIL_ROWS(C.n, {
-                T a = (T)coef[c];
-                T ev = C.x[t], rv = C.rho[t];
-                C.x[t] = ev + a * (C.x1[t] - ev);
-                C.rho[t] = rv - a * (rv - C.rho1[t]);
-            })
-            bar();
-        }
-        if (j < nvis) {
-            TAIL_ROWS(C.n, {
-                C.x1[t] = C.x[t];
-                C.rho1[t] = C.rho[t];
-            })
-            if (tid == 0) {
-                s_j[l] = j;
-                s_phase[l + 1] = 0;
-            }
-            bar();
-            ++l;
-            continue;
-        }
-        // energy correction mu = <e, fc> / <e, fc - rho>, prolongation, post-relaxation
-        {
-            double q[2] = {0.0, 0.0};
-            if (col < k)
-                for (int64_t i = tid >> lkp; i < C.n; i += TB >> lkp) {
-                    double e = (double)C.x[i * k + col], fc = (double)C.f[i * k + col];
-                    q[0] += e * fc;
-                    q[1] += e * (fc - (double)C.rho[i * k + col]);
-                }
-            block_sums<2>(q, sh, kp, tot);
-            if (tid < k) {
-                double num = tot[tid], den = tot[32 + tid], mu = num / den;
-                if (!(den > 0.0) || !isfinite(mu)) mu = 1.0;
-                coef[tid] = mu;
-            }
-            bar();
-            TAIL_ROWS(L.n, {
-                T pe = L.w0[u] * C.x[(int64_t)L.p0[u] * k + c];
-                int32_t q1 = L.p1[u];
-                if (q1 >= 0) pe += L.w1[u] * C.x[(int64_t)q1 * k + c];
-                L.x[t] += (T)coef[c] * pe;
-            })
-            bar();
-        }
-        gs_sweeps<T>(L, k, lkp, 2);
-        --l;
+        if (l >= l_lds)
+            l = visit<T, true, true>(A, D, G[l + 1], l, smem, ws, rbuf);
+        else if (l + 1 >= l_lds)
+            l = visit<T, false, true>(A, D, G[l + 1], l, smem, ws, rbuf);
+        else
+            l = visit<T, false, false>(A, D, G[l + 1], l, smem, ws, rbuf);
     }
-    if (l0 >= A.l_lds) {  // the top level's iterate lives in LDS: write it back
-        T *gx = A.lv[l0].x;
-        const T *lx = dl[0].x;
-        TAIL_ROWS(dl[0].n, { gx[t] = lx[t]; })
+    if (l0 >= l_lds) {  // the top level's iterate lives in LDS: write it back
+        const TailLvl<T> &D = G[l0];
+        const T *lx = at<true>(smem, D.x);
+        T *gx = static_cast<T *>(A.top_x);
+        for (int t = tid; t < D.n * A.k; t += TB) gx[t] = lx[t];
     }
+    if (tid < 64 && lane >= l0 && lane < nlev) A.visits[lane] = ws.cnt;
 }
 
 __global__ void k_fill_i64(int64_t *p, int64_t n) {
@@ -443,9 +516,13 @@ void tail_fill_desc(void *host_buf, int l, const Level &L, const SolveOp &op, co
                     T *x, T *f, T *r, T *rho, T *x1, T *rho1) {
     TailLvl<T> &D = static_cast<TailLvl<T> *>(host_buf)[l];
     std::memset(&D, 0, sizeof(D));
-    D.n = L.n;
+    D.n = (int32_t)L.n;
     D.ncolors = op.ncolors;
     D.coarsest = L.coarsest ? 1 : 0;
+    D.nc = (int32_t)op.nc;
+    D.n_rlong = (int32_t)op.n_rlong;
+    D.maxlen = op.max_short_len;
+    D.gamma = L.gamma;
     D.blk = d_blk;
     D.rp = op.rp.p;
     D.ci = op.ci.p;
@@ -456,11 +533,9 @@ void tail_fill_desc(void *host_buf, int l, const Level &L, const SolveOp &op, co
     D.p1 = op.p1.p;
     D.w0 = w0;
     D.w1 = w1;
-    D.nc = op.nc;
     D.rrp = op.rrp.p;
     D.rci = op.rci.p;
     D.rlong = op.rlong.p;
-    D.n_rlong = op.n_rlong;
     D.rw = rw;
     D.Z = L.Z.p;
     D.x = x;
@@ -469,31 +544,33 @@ void tail_fill_desc(void *host_buf, int l, const Level &L, const SolveOp &op, co
     D.rho = rho;
     D.x1 = x1;
     D.rho1 = rho1;
-    D.gamma = L.gamma;
-    D.maxlen = op.max_short_len;
 }
 
-// Chooses the LDS-resident levels of a tail starting at l0 (the coarsest ones whose
-// operators and vectors fit together in the LDS left beside the kernel's static use),
-// and writes their offset descriptors and copy jobs. Returns l_lds (nlev: none) and the
-// dynamic LDS bytes.
+// Lays out the launch's dynamic LDS: the two reduction buffers, then the coarsest levels
+// of the tail starting at l0 whose operators and vectors fit together in what is left.
+// Writes the launch's descriptor array (levels in LDS carry offsets) and the copy jobs.
+// Returns l_lds (nlev: no level in LDS) and the dynamic LDS bytes.
 template <class T>
 int tail_lds_plan(const std::vector<Level> &lev, int l0, int k, const void *host_desc,
                   std::vector<char> &lds_desc, std::vector<char> &jobs, size_t &lds_bytes) {
     const int nlev = (int)lev.size();
-    lds_bytes = 0;
+    const TailLvl<T> *G = static_cast<const TailLvl<T> *>(host_desc);
     lds_desc.assign(sizeof(TailLvl<T>) * nlev, 0);
+    std::memcpy(lds_desc.data(), host_desc, sizeof(TailLvl<T>) * nlev);
     jobs.clear();
-    if (l0 < 0 || nlev - l0 > kTailMax) return nlev;
+    lds_bytes = 0;
+    if (l0 < 0 || l0 >= nlev) return nlev;
+    int kp = 1;
+    while (kp < k) kp <<= 1;
+    auto al = [](int64_t b) { return (b + 15) & ~(int64_t)15; };
+    const int64_t red_bytes = 2 * (int64_t)kRedQ * TW * kp * 8;
     int dev = 0;
     LAMG_HIP(hipGetDevice(&dev));
     int max_lds = 0;
     LAMG_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     hipFuncAttributes fa;
     LAMG_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_tail<T>)));
-    const int64_t budget = (int64_t)max_lds - (int64_t)fa.sharedSizeBytes - 512;
-    const TailLvl<T> *G = static_cast<const TailLvl<T> *>(host_desc);
-    auto al = [](int64_t b) { return (b + 15) & ~(int64_t)15; };
+    const int64_t budget = (int64_t)max_lds - (int64_t)fa.sharedSizeBytes - 256;
     auto level_bytes = [&](int l) {
         const Level &L = lev[l];
         const SolveOp &op = L.op;
@@ -508,15 +585,14 @@ int tail_lds_plan(const std::vector<Level> &lev, int l0, int k, const void *host
         return b;
     };
     int l_lds = nlev;
-    int64_t total = 16;  // offset 0 means "no array"
+    int64_t total = 16 + al(red_bytes);  // offset 0 means "no array"
     for (int l = nlev - 1; l >= l0; --l) {
         int64_t b = level_bytes(l);
         if (total + b > budget) break;
         total += b;
         l_lds = l;
     }
-    if (l_lds == nlev) return nlev;
-    int64_t off = 16;
+    int64_t off = 16 + al(red_bytes);
     std::vector<CopyJob> jv;
     TailLvl<T> *D = reinterpret_cast<TailLvl<T> *>(lds_desc.data());
     for (int l = l_lds; l < nlev; ++l) {
@@ -580,11 +656,12 @@ int tail_lds_plan(const std::vector<Level> &lev, int l0, int k, const void *host
 
 template <class T>
 void run_tail(const TailPlan &tp, int l0, int nlev, int k, int64_t *d_visits, hipStream_t s) {
-    TailArgs<T> A;
-    A.lv = static_cast<const TailLvl<T> *>(tp.desc);
-    A.lds_lv = static_cast<const TailLvl<T> *>(tp.lds_desc);
+    TailArgs A;
+    std::memset(&A, 0, sizeof(A));
     A.jobs = static_cast<const CopyJob *>(tp.jobs);
     A.njobs = tp.njobs;
+    A.visits = d_visits;
+    A.top_x = tp.top_x;
     A.l0 = l0;
     A.nlev = nlev;
     A.l_lds = tp.l_lds;
@@ -592,8 +669,9 @@ void run_tail(const TailPlan &tp, int l0, int nlev, int k, int64_t *d_visits, hi
     int lkp = 0;
     while ((1 << lkp) < k) ++lkp;
     A.lkp = lkp;
-    A.visits = d_visits;
-    launch_kernel(k_tail<T>, dim3(1), dim3(TB), (uint32_t)tp.lds_bytes, s, A);
+    A.red_off = 16;
+    const TailLvl<T> *G = static_cast<const TailLvl<T> *>(tp.lds_desc);
+    launch_kernel(k_tail<T>, dim3(1), dim3(TB), (uint32_t)tp.lds_bytes, s, A, G);
     LAMG_LAUNCH_CHECK();
 }
 
