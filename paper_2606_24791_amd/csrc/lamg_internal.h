@@ -156,6 +156,13 @@ struct SolveOp {
     int lpr_r = 1;
     DArr<double> rw64;
     DArr<float> rw32;
+    // ELL copy of the off-diagonals (entry u of row i at u * n + i, padding: own index and
+    // weight 0) for levels below 65536 rows with short rows, read coalesced by the
+    // single-workgroup coarse-level kernel
+    int ell_w = 0;
+    DArr<int32_t> ell_ci;
+    DArr<double> ell_v64;
+    DArr<float> ell_v32;
 };
 
 struct Level {
@@ -193,6 +200,7 @@ struct TailPlan {
     void *top_x = nullptr;           // global iterate of the tail's top level
     int njobs = 0;
     int l_lds = 0;         // first LDS-resident level (nlev: none)
+    int l_x = -1;          // level whose iterate alone is LDS-resident (-1: none)
     size_t lds_bytes = 0;  // dynamic LDS of the launch
 };
 // Cached solve workspace (grown on demand, per precision).
@@ -305,6 +313,8 @@ void launch_permute_csr(int64_t n, const int32_t *perm, const int32_t *iperm, co
                         double *sv64, float *sv32, double *d64, double *dinv64, float *d32,
                         float *dinv32, hipStream_t s);
 void launch_cast_f32(int64_t n, const double *src, float *dst, hipStream_t s);
+void launch_build_ell(int64_t n, int w, const int32_t *rp, const int32_t *ci, const double *v64,
+                      const float *v32, int32_t *eci, double *ev64, float *ev32, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Cycle launchers (cycle_kernels.hip), T = double or float
@@ -342,10 +352,11 @@ size_t tail_desc_bytes();
 template <class T>
 void tail_fill_desc(void *host_buf, int l, const Level &L, const SolveOp &op, const int64_t *d_blk,
                     const T *v, const T *d, const T *dinv, const T *w0, const T *w1, const T *rw,
-                    T *x, T *f, T *r, T *rho, T *x1, T *rho1);
+                    const T *ev, T *x, T *f, T *r, T *rho, T *x1, T *rho1);
 template <class T>
 int tail_lds_plan(const std::vector<Level> &lev, int l0, int k, const void *host_desc,
-                  std::vector<char> &lds_desc, std::vector<char> &jobs, size_t &lds_bytes);
+                  std::vector<char> &lds_desc, std::vector<char> &jobs, size_t &lds_bytes,
+                  int &l_x);
 size_t tail_copy_job_bytes();
 template <class T>
 void run_tail(const TailPlan &tp, int l0, int nlev, int k, int64_t *d_visits, hipStream_t s);

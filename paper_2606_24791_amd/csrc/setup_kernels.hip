@@ -499,6 +499,23 @@ __global__ void k_permute_csr(int64_t n, const int32_t *__restrict__ perm,
     }
 }
 
+// ELL copy (entry u of row i at u * n + i) of an off-diagonal CSR whose rows have at most w
+// entries; padding entries hold the row's own index and weight 0.
+__global__ void k_build_ell(int64_t n, int w, const int32_t *__restrict__ rp,
+                            const int32_t *__restrict__ ci, const double *__restrict__ v64,
+                            const float *__restrict__ v32, int32_t *__restrict__ eci,
+                            double *__restrict__ ev64, float *__restrict__ ev32) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t e0 = rp[i], len = rp[i + 1] - e0;
+    for (int u = 0; u < w; ++u) {
+        const bool ok = u < len;
+        eci[(int64_t)u * n + i] = ok ? ci[e0 + u] : (int32_t)i;
+        ev64[(int64_t)u * n + i] = ok ? v64[e0 + u] : 0.0;
+        if (ev32) ev32[(int64_t)u * n + i] = ok ? v32[e0 + u] : 0.0f;
+    }
+}
+
 __global__ void k_cast_f32(int64_t n, const double *__restrict__ s, float *__restrict__ d) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) d[i] = (float)s[i];
@@ -690,6 +707,13 @@ void launch_permute_csr(int64_t n, const int32_t *perm, const int32_t *iperm, co
                         float *dinv32, hipStream_t s) {
     k_permute_csr<<<grid_for(n), kBlock, 0, s>>>(n, perm, iperm, crp, cci, cv, srp, sci, sv64, sv32,
                                                   d64, dinv64, d32, dinv32);
+    LAMG_LAUNCH_CHECK();
+}
+
+void launch_build_ell(int64_t n, int w, const int32_t *rp, const int32_t *ci, const double *v64,
+                      const float *v32, int32_t *eci, double *ev64, float *ev32, hipStream_t s) {
+    if (n <= 0 || w <= 0) return;
+    k_build_ell<<<grid_for(n), kBlock, 0, s>>>(n, w, rp, ci, v64, v32, eci, ev64, ev32);
     LAMG_LAUNCH_CHECK();
 }
 

@@ -24,6 +24,7 @@ struct Prec<double> {
     static const double *w0(const SolveOp &o) { return o.w0_64.p; }
     static const double *w1(const SolveOp &o) { return o.w1_64.p; }
     static const double *rw(const SolveOp &o) { return o.rw64.p; }
+    static const double *ev(const SolveOp &o) { return o.ell_w ? o.ell_v64.p : nullptr; }
     static std::vector<LevelVecs<double>> &vecs(Workspace &w) { return w.lv64; }
 };
 template <>
@@ -34,6 +35,7 @@ struct Prec<float> {
     static const float *w0(const SolveOp &o) { return o.w0_32.p; }
     static const float *w1(const SolveOp &o) { return o.w1_32.p; }
     static const float *rw(const SolveOp &o) { return o.rw32.p; }
+    static const float *ev(const SolveOp &o) { return o.ell_w ? o.ell_v32.p : nullptr; }
     static std::vector<LevelVecs<float>> &vecs(Workspace &w) { return w.lv32; }
 };
 
@@ -225,7 +227,7 @@ void ensure_level_vecs(lamg_handle *h, int k) {
         const Level &L = h->lev[l];
         const SolveOp &op = L.op;
         tail_fill_desc<T>(host.data(), l, L, op, op.dblk.p, P::v(op), P::d(op), P::dinv(op),
-                          P::w0(op), P::w1(op), P::rw(op), lv[l].x.p, lv[l].f.p, lv[l].r.p,
+                          P::w0(op), P::w1(op), P::rw(op), P::ev(op), lv[l].x.p, lv[l].f.p, lv[l].r.p,
                           lv[l].rho.p, lv[l].x1.p, lv[l].rho1.p);
     }
     DArr<char> &desc = W::desc(w);
@@ -238,7 +240,8 @@ void ensure_level_vecs(lamg_handle *h, int k) {
     std::vector<char> lds_desc, jobs;
     size_t lds_bytes = 0;
     const int l0 = tail_level(h);
-    int l_lds = tail_lds_plan<T>(h->lev, l0, k, host.data(), lds_desc, jobs, lds_bytes);
+    int l_x = -1;
+    int l_lds = tail_lds_plan<T>(h->lev, l0, k, host.data(), lds_desc, jobs, lds_bytes, l_x);
     if (l0 >= 0) {
         DArr<char> &dl = W::lds(w);
         DArr<char> &dj = W::jobs(w);
@@ -250,6 +253,7 @@ void ensure_level_vecs(lamg_handle *h, int k) {
         tp.jobs = dj.p;
         tp.njobs = (int)(jobs.size() / tail_copy_job_bytes());
         tp.l_lds = l_lds;
+        tp.l_x = l_x;
         tp.lds_bytes = lds_bytes;
         tp.top_x = lv[l0].x.p;
     }

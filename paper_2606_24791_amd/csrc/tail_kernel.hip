@@ -26,6 +26,7 @@
 //  - 32-bit indexing throughout (a tail level has at most a few thousand rows).
 //
 // The arithmetic per step is that of the multi-kernel path (cycle_kernels.hip).
+#include <algorithm>
 #include <type_traits>
 
 #include "lamg_internal.h"
@@ -46,7 +47,7 @@ constexpr int kRedQ = 2;   // quantities per tail reduction
 template <class T>
 struct TailLvl {
     int32_t n, ncolors, coarsest, nc;  // nc: rows of the next level
-    int32_t n_rlong, maxlen, pad0, pad1;
+    int32_t n_rlong, maxlen, maxcol, ew;  // maxcol: rows of the largest colour; ew: ELL width
     double gamma;
     const int64_t *blk;  // 2*ncolors + 1 offsets (class 0 colours, class 1 colours)
     const int32_t *rp, *ci;
@@ -57,6 +58,8 @@ struct TailLvl {
     const T *rw;
     const double *Z;  // coarsest: pseudo-inverse
     T *x, *f, *r, *rho, *x1, *rho1;
+    const int32_t *eci;  // ELL copy of the off-diagonals (0 if absent; always global)
+    const T *ev;
 };
 
 // Global -> LDS copy performed at the start of every tail launch.
@@ -72,7 +75,7 @@ struct TailArgs {
     void *top_x;      // global iterate of the top level (written back if it lives in LDS)
     int32_t njobs, l0, nlev, l_lds, k, lkp;
     uint32_t red_off;  // byte offset of the two reduction buffers in the dynamic LDS
-    uint32_t pad;
+    int32_t l_x;       // level whose iterate alone lives in LDS (-1: none)
 };
 
 __device__ inline void bar() { __syncthreads(); }
@@ -86,10 +89,19 @@ __device__ inline P *at(char *smem, P *p) {
         return p;
 }
 
-// The arrays of one level, rebased into LDS where the level lives there.
-template <class T, bool LDS>
+// Residency of a level's arrays: everything in global memory; only the iterate x in LDS
+// (the level right above the LDS-resident ones, whose operator does not fit but whose
+// randomly gathered iterate does); everything in LDS.
+constexpr int kGlobal = 0, kXLds = 1, kAllLds = 2;
+
+// The arrays of one level, rebased into LDS where they live there.
+template <class T, int M>
 struct Lv {
-    int n, nc, ncol, nrl, maxlen;
+    static constexpr bool OL = M == kAllLds;  // operator, transfer and other vectors
+    static constexpr bool XL = M != kGlobal;  // iterate
+    int n, nc, ncol, nrl, maxlen, maxcol, ew;
+    const int32_t *eci;
+    const T *ev;
     const int64_t *blk;
     const int32_t *rp, *ci;
     const T *v, *d, *dinv;
@@ -99,13 +111,14 @@ struct Lv {
     const T *rw;
     T *x, *f, *r, *rho, *x1, *rho1;
     __device__ Lv(const TailLvl<T> &D, char *s)
-        : n(D.n), nc(D.nc), ncol(D.ncolors), nrl(D.n_rlong), maxlen(D.maxlen),
-          blk(at<LDS>(s, D.blk)), rp(at<LDS>(s, D.rp)), ci(at<LDS>(s, D.ci)), v(at<LDS>(s, D.v)),
-          d(at<LDS>(s, D.d)), dinv(at<LDS>(s, D.dinv)), p0(at<LDS>(s, D.p0)),
-          p1(at<LDS>(s, D.p1)), w0(at<LDS>(s, D.w0)), w1(at<LDS>(s, D.w1)),
-          rrp(at<LDS>(s, D.rrp)), rci(at<LDS>(s, D.rci)), rlong(at<LDS>(s, D.rlong)),
-          rw(at<LDS>(s, D.rw)), x(at<LDS>(s, D.x)), f(at<LDS>(s, D.f)), r(at<LDS>(s, D.r)),
-          rho(at<LDS>(s, D.rho)), x1(at<LDS>(s, D.x1)), rho1(at<LDS>(s, D.rho1)) {}
+        : n(D.n), nc(D.nc), ncol(D.ncolors), nrl(D.n_rlong), maxlen(D.maxlen), maxcol(D.maxcol),
+          ew(D.ew), eci(D.eci), ev(D.ev),
+          blk(at<OL>(s, D.blk)), rp(at<OL>(s, D.rp)), ci(at<OL>(s, D.ci)), v(at<OL>(s, D.v)),
+          d(at<OL>(s, D.d)), dinv(at<OL>(s, D.dinv)), p0(at<OL>(s, D.p0)), p1(at<OL>(s, D.p1)),
+          w0(at<OL>(s, D.w0)), w1(at<OL>(s, D.w1)), rrp(at<OL>(s, D.rrp)), rci(at<OL>(s, D.rci)),
+          rlong(at<OL>(s, D.rlong)), rw(at<OL>(s, D.rw)), x(at<XL>(s, D.x)), f(at<OL>(s, D.f)),
+          r(at<OL>(s, D.r)), rho(at<OL>(s, D.rho)), x1(at<OL>(s, D.x1)),
+          rho1(at<OL>(s, D.rho1)) {}
 };
 
 // sum over [j0, e) step `stride` of v[j] * x[ci[j] * k + col], U entries in flight.
@@ -178,14 +191,120 @@ __device__ __forceinline__ void csr_rows(int a, int b, int la, int lb, const int
     }
 }
 
+// out = f - L x over all rows of level L (the caller's barrier follows). Levels in global
+// memory with an ELL copy read it coalesced: one thread per (row, column), entry u of all
+// rows at consecutive addresses; the sum runs in entry order as in the CSR pass.
+template <class T, int M>
+__device__ __forceinline__ void residual(const Lv<T, M> &L, T *out, int k, int lkp) {
+    if (M != kAllLds && L.ew > 0) {
+        const int tid = threadIdx.x;
+        const int kp = 1 << lkp;
+        const int c = tid & (kp - 1);
+        const int n = L.n, ew = L.ew;
+        constexpr int G = kGather<T>;
+        if (c < k)
+            for (int row = tid >> lkp; row < n; row += TB >> lkp) {
+                T acc = T(0);
+                for (int u0 = 0; u0 < ew; u0 += G) {
+                    int jj[G];
+                    T vv[G], xx[G];
+#pragma unroll
+                    for (int u = 0; u < G; ++u) {
+                        const bool ok = u0 + u < ew;
+                        jj[u] = ok ? L.eci[(u0 + u) * n + row] : row;
+                        vv[u] = ok ? L.ev[(u0 + u) * n + row] : T(0);
+                    }
+#pragma unroll
+                    for (int u = 0; u < G; ++u) xx[u] = L.x[jj[u] * k + c];
+#pragma unroll
+                    for (int u = 0; u < G; ++u) acc += vv[u] * xx[u];
+                }
+                const int o = row * k + c;
+                out[o] = L.f[o] - L.d[row] * L.x[o] - acc;
+            }
+        return;
+    }
+    const int nc = L.ncol;
+    csr_rows<T, 1>(0, (int)L.blk[nc], (int)L.blk[nc], L.n, nullptr, 0, L.rp, L.ci, L.v, L.d, L.f,
+                   L.x, out, k, lkp);
+}
+
+template <class T>
+constexpr int kPipe = sizeof(T) == 4 ? 16 : 14;  // longest row of the pipelined path (even)
+
+// One thread's row of one colour pass, loaded ahead of its update (stage 1: inverse
+// diagonal and right-hand side; stage 2: column indices, packed two per register, and
+// values from the level's ELL copy). Padding entries point at the row itself with weight 0.
+template <class T, int W>
+struct PipeRow {
+    uint32_t cp[W / 2];
+    T vv[W];
+    T dinv, fv;
+    int row;
+    bool live;
+    template <int M>
+    __device__ __forceinline__ void stage1(const Lv<T, M> &L, int cl, int k, int lkp) {
+        const int tid = threadIdx.x;
+        const int c = tid & ((1 << lkp) - 1);
+        row = (int)L.blk[cl] + (tid >> lkp);
+        live = row < (int)L.blk[cl + 1] && c < k;
+        if (live) {
+            dinv = L.dinv[row];
+            fv = L.f[row * k + c];
+        }
+    }
+    // the row's entries from the ELL copy: lane-consecutive rows are address-consecutive
+    template <int M>
+    __device__ __forceinline__ void stage2(const Lv<T, M> &L) {
+        if (!live) return;
+        const int n = L.n, ew = L.ew;
+#pragma unroll
+        for (int u = 0; u < W; u += 2) {
+            uint32_t a = (uint32_t)row, b = (uint32_t)row;
+            T va = T(0), vb = T(0);
+            if (u < ew) {
+                a = (uint32_t)L.eci[u * n + row];
+                va = L.ev[u * n + row];
+            }
+            if (u + 1 < ew) {
+                b = (uint32_t)L.eci[(u + 1) * n + row];
+                vb = L.ev[(u + 1) * n + row];
+            }
+            cp[u / 2] = a | (b << 16);
+            vv[u] = va;
+            vv[u + 1] = vb;
+        }
+    }
+    __device__ __forceinline__ void relax(T *x, int k, int c) const {
+        if (!live) return;
+        constexpr int G = kGather<T>;
+        T acc = T(0);
+#pragma unroll
+        for (int u0 = 0; u0 < W; u0 += G) {
+            T xx[G];
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                if (u0 + u < W) {
+                    const uint32_t j = (cp[(u0 + u) / 2] >> (16 * ((u0 + u) & 1))) & 0xffffu;
+                    xx[u] = x[(int)j * k + c];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < G; ++u)
+                if (u0 + u < W) acc += vv[u0 + u] * xx[u];
+        }
+        x[row * k + c] = (fv - acc) * dinv;
+    }
+};
+
 // `sweeps` Gauss-Seidel sweeps over the colours of level L, then (if `resid`) the residual
 // r = f - L x. On a level whose (row, column) pairs fit one per thread and whose rows have
 // at most kFast off-diagonals, each thread loads its row into registers once (column
 // offsets, values, inverse diagonal, diagonal, right-hand side; padding entries point at
 // the row's own value with weight 0, so every gather is unconditional), and every colour
 // pass is one gather, one store and one barrier.
-template <class T, bool LDS>
-__device__ __forceinline__ void smooth(const Lv<T, LDS> &L, int k, int lkp, int sweeps, bool resid) {
+template <class T, int M>
+__device__ __forceinline__ void smooth(const Lv<T, M> &L, int k, int lkp, int sweeps, bool resid) {
     const int tid = threadIdx.x;
     const int kp = 1 << lkp;
     const int nc = L.ncol;
@@ -245,16 +364,42 @@ __device__ __forceinline__ void smooth(const Lv<T, LDS> &L, int k, int lkp, int 
         }
         return;
     }
-    for (int sw = 0; sw < sweeps; ++sw)
-        for (int cl = 0; cl < nc; ++cl) {
-            csr_rows<T, 0>((int)L.blk[cl], (int)L.blk[cl + 1], (int)L.blk[nc + cl],
-                           (int)L.blk[nc + cl + 1], nullptr, 0, L.rp, L.ci, L.v, L.dinv, L.f, L.x,
-                           L.x, k, lkp);
+    constexpr int W = kPipe<T>;
+    if (L.ew > 0 && L.ew <= W && (L.maxcol << lkp) <= TB && L.n < 65536) {
+        // every colour has at most one (row, column) pair per thread: the row of the next
+        // colour pass (column offsets, values, inverse diagonal, right-hand side) is loaded
+        // while the current pass computes and waits at its barrier, so a pass costs one
+        // gather, one store and one barrier
+        // pass q relaxes with the row data of stage 2 issued during pass q-1, whose
+        // bounds came from stage 1 issued during pass q-2 (right after that pass's update)
+        PipeRow<T, W> A, Bn;
+        const int q_end = sweeps * nc;
+        const int c = tid & (kp - 1);
+        A.stage1(L, 0, k, lkp);
+        if (1 < q_end) Bn.stage1(L, 1 % nc, k, lkp);
+        A.stage2(L);
+        for (int q = 0; q < q_end; q += 2) {
+            A.relax(L.x, k, c);
+            if (q + 2 < q_end) A.stage1(L, (q + 2) % nc, k, lkp);
+            if (q + 1 < q_end) Bn.stage2(L);
+            bar();
+            if (q + 1 >= q_end) break;
+            Bn.relax(L.x, k, c);
+            if (q + 3 < q_end) Bn.stage1(L, (q + 3) % nc, k, lkp);
+            if (q + 2 < q_end) A.stage2(L);
             bar();
         }
+    } else {
+        for (int sw = 0; sw < sweeps; ++sw)
+            for (int cl = 0; cl < nc; ++cl) {
+                csr_rows<T, 0>((int)L.blk[cl], (int)L.blk[cl + 1], (int)L.blk[nc + cl],
+                               (int)L.blk[nc + cl + 1], nullptr, 0, L.rp, L.ci, L.v, L.dinv, L.f,
+                               L.x, L.x, k, lkp);
+                bar();
+            }
+    }
     if (resid) {
-        csr_rows<T, 1>(0, (int)L.blk[nc], (int)L.blk[nc], L.n, nullptr, 0, L.rp, L.ci, L.v, L.d,
-                       L.f, L.x, L.r, k, lkp);
+        residual<T, M>(L, L.r, k, lkp);
         bar();
     }
 }
@@ -286,9 +431,9 @@ __device__ inline void column_totals(const double *red, int kp, int c, double (&
 
 // y = Z f on the directly solved level (FP64 pseudo-inverse, global memory), G lanes per
 // (row, column) with kZ loads of Z in flight.
-template <class T, bool LDS>
-__device__ __forceinline__ void coarsest(const double *Z, const Lv<T, LDS> &L, int k, int lkp) {
-    constexpr int kZ = 8;
+template <class T, int M>
+__device__ __forceinline__ void coarsest(const double *Z, const Lv<T, M> &L, int k, int lkp) {
+    constexpr int kZ = 16;
     const int tid = threadIdx.x;
     const int kp = 1 << lkp;
     const int n = L.n;
@@ -342,16 +487,16 @@ struct WaveState {
 //  phase 1: back from visit j of the child: child residual, recombination of the last two
 //           child iterates (j >= 2); then descend again, or energy correction,
 //           prolongation and post-smoothing, and ascend.
-template <class T, bool LL, bool LC>
+template <class T, int ML, int MC>
 __device__ __forceinline__ int visit(const TailArgs &A, const TailLvl<T> &DL, const TailLvl<T> &DC, int l,
                      char *smem, WaveState &ws, int &rbuf) {
     const int tid = threadIdx.x;
     const int k = A.k, lkp = A.lkp, kp = 1 << lkp;
-    const Lv<T, LL> L(DL, smem);
-    const Lv<T, LC> C(DC, smem);
+    const Lv<T, ML> L(DL, smem);
+    const Lv<T, MC> C(DC, smem);
     const int s = ws.get_st(l);
     if ((s & 1) == 0) {
-        smooth<T, LL>(L, k, lkp, 1, true);
+        smooth<T, ML>(L, k, lkp, 1, true);
         csr_rows<T, 2>(0, L.nc, 0, L.nrl, L.rlong, L.nrl ? kLongRow : 0, L.rrp, L.rci, L.rw,
                        nullptr, nullptr, L.r, C.f, k, lkp);
         for (int t = tid; t < C.n * k; t += TB) C.x[t] = T(0);
@@ -368,8 +513,7 @@ __device__ __forceinline__ int visit(const TailArgs &A, const TailLvl<T> &DL, co
     const int nvis = s >> 9;
     const int c = tid & (kp - 1);
     // rho = f_c - L_c x_c
-    csr_rows<T, 1>(0, (int)C.blk[C.ncol], (int)C.blk[C.ncol], C.n, nullptr, 0, C.rp, C.ci, C.v,
-                   C.d, C.f, C.x, C.rho, k, lkp);
+    residual<T, MC>(C, C.rho, k, lkp);
     bar();
     const bool again = j < nvis;
     if (j >= 2) {  // two-iterate recombination across the visits
@@ -442,7 +586,7 @@ __device__ __forceinline__ int visit(const TailArgs &A, const TailLvl<T> &DL, co
             }
         bar();
     }
-    smooth<T, LL>(L, k, lkp, 2, false);
+    smooth<T, ML>(L, k, lkp, 2, false);
     return l - 1;
 }
 
@@ -451,7 +595,7 @@ __global__ void __launch_bounds__(TB) k_tail(TailArgs A, const TailLvl<T> *__res
     extern __shared__ __align__(16) char smem[];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int l0 = A.l0, nlev = A.nlev, l_lds = A.l_lds;
+    const int l0 = A.l0, nlev = A.nlev, l_lds = A.l_lds, l_x = A.l_x;
     // bring the LDS-resident levels (and the top level's iterate and right-hand side)
     for (int jb = 0; jb < A.njobs; ++jb) {
         const CopyJob J = A.jobs[jb];
@@ -474,20 +618,24 @@ __global__ void __launch_bounds__(TB) k_tail(TailArgs A, const TailLvl<T> *__res
         const TailLvl<T> &D = G[l];
         if (D.coarsest) {
             if (l >= l_lds)
-                coarsest<T, true>(D.Z, Lv<T, true>(D, smem), A.k, A.lkp);
+                coarsest<T, kAllLds>(D.Z, Lv<T, kAllLds>(D, smem), A.k, A.lkp);
             else
-                coarsest<T, false>(D.Z, Lv<T, false>(D, smem), A.k, A.lkp);
+                coarsest<T, kGlobal>(D.Z, Lv<T, kGlobal>(D, smem), A.k, A.lkp);
             --l;
             continue;
         }
         if (l >= l_lds)
-            l = visit<T, true, true>(A, D, G[l + 1], l, smem, ws, rbuf);
+            l = visit<T, kAllLds, kAllLds>(A, D, G[l + 1], l, smem, ws, rbuf);
+        else if (l == l_x)
+            l = visit<T, kXLds, kAllLds>(A, D, G[l + 1], l, smem, ws, rbuf);
+        else if (l + 1 == l_x)
+            l = visit<T, kGlobal, kXLds>(A, D, G[l + 1], l, smem, ws, rbuf);
         else if (l + 1 >= l_lds)
-            l = visit<T, false, true>(A, D, G[l + 1], l, smem, ws, rbuf);
+            l = visit<T, kGlobal, kAllLds>(A, D, G[l + 1], l, smem, ws, rbuf);
         else
-            l = visit<T, false, false>(A, D, G[l + 1], l, smem, ws, rbuf);
+            l = visit<T, kGlobal, kGlobal>(A, D, G[l + 1], l, smem, ws, rbuf);
     }
-    if (l0 >= l_lds) {  // the top level's iterate lives in LDS: write it back
+    if (l0 >= l_lds || l0 == l_x) {  // the top level's iterate lives in LDS: write it back
         const TailLvl<T> &D = G[l0];
         const T *lx = at<true>(smem, D.x);
         T *gx = static_cast<T *>(A.top_x);
@@ -513,7 +661,7 @@ size_t tail_desc_bytes() {
 template <class T>
 void tail_fill_desc(void *host_buf, int l, const Level &L, const SolveOp &op, const int64_t *d_blk,
                     const T *v, const T *d, const T *dinv, const T *w0, const T *w1, const T *rw,
-                    T *x, T *f, T *r, T *rho, T *x1, T *rho1) {
+                    const T *ev, T *x, T *f, T *r, T *rho, T *x1, T *rho1) {
     TailLvl<T> &D = static_cast<TailLvl<T> *>(host_buf)[l];
     std::memset(&D, 0, sizeof(D));
     D.n = (int32_t)L.n;
@@ -522,6 +670,8 @@ void tail_fill_desc(void *host_buf, int l, const Level &L, const SolveOp &op, co
     D.nc = (int32_t)op.nc;
     D.n_rlong = (int32_t)op.n_rlong;
     D.maxlen = op.max_short_len;
+    for (int c = 0; c < op.ncolors; ++c)
+        D.maxcol = std::max(D.maxcol, (int32_t)(op.blk[c + 1] - op.blk[c]));
     D.gamma = L.gamma;
     D.blk = d_blk;
     D.rp = op.rp.p;
@@ -544,16 +694,22 @@ void tail_fill_desc(void *host_buf, int l, const Level &L, const SolveOp &op, co
     D.rho = rho;
     D.x1 = x1;
     D.rho1 = rho1;
+    D.ew = ev ? op.ell_w : 0;
+    D.eci = ev ? op.ell_ci.p : nullptr;
+    D.ev = ev;
 }
 
 // Lays out the launch's dynamic LDS: the two reduction buffers, then the coarsest levels
-// of the tail starting at l0 whose operators and vectors fit together in what is left.
-// Writes the launch's descriptor array (levels in LDS carry offsets) and the copy jobs.
+// of the tail starting at l0 whose operators and vectors fit together in what is left,
+// then, if it still fits, the iterate of the level right above them (l_x, else -1).
+// Writes the launch's descriptor array (arrays in LDS carry offsets) and the copy jobs.
 // Returns l_lds (nlev: no level in LDS) and the dynamic LDS bytes.
 template <class T>
 int tail_lds_plan(const std::vector<Level> &lev, int l0, int k, const void *host_desc,
-                  std::vector<char> &lds_desc, std::vector<char> &jobs, size_t &lds_bytes) {
+                  std::vector<char> &lds_desc, std::vector<char> &jobs, size_t &lds_bytes,
+                  int &l_x) {
     const int nlev = (int)lev.size();
+    l_x = -1;
     const TailLvl<T> *G = static_cast<const TailLvl<T> *>(host_desc);
     lds_desc.assign(sizeof(TailLvl<T>) * nlev, 0);
     std::memcpy(lds_desc.data(), host_desc, sizeof(TailLvl<T>) * nlev);
@@ -645,6 +801,20 @@ int tail_lds_plan(const std::vector<Level> &lev, int l0, int k, const void *host
             E.x1 = E.rho1 = nullptr;
         }
     }
+    // the level right above: its iterate alone, if it fits
+    l_x = -1;
+    if (l_lds > l0 && l_lds < nlev) {
+        const int l = l_lds - 1;
+        const int64_t xb = (int64_t)sizeof(T) * lev[l].n * k;
+        if (off + al(xb) <= budget) {
+            TailLvl<T> &E = D[l];
+            const void *src = (const void *)E.x;
+            E.x = reinterpret_cast<T *>((uintptr_t)off);
+            if (l == l0) jv.push_back(CopyJob{src, (uint32_t)off, (uint32_t)xb});
+            off += al(xb);
+            l_x = l;
+        }
+    }
     lds_bytes = (size_t)off;
     jobs.resize(jv.size() * sizeof(CopyJob));
     if (!jv.empty()) std::memcpy(jobs.data(), jv.data(), jobs.size());
@@ -670,6 +840,7 @@ void run_tail(const TailPlan &tp, int l0, int nlev, int k, int64_t *d_visits, hi
     while ((1 << lkp) < k) ++lkp;
     A.lkp = lkp;
     A.red_off = 16;
+    A.l_x = tp.l_x;
     const TailLvl<T> *G = static_cast<const TailLvl<T> *>(tp.lds_desc);
     launch_kernel(k_tail<T>, dim3(1), dim3(TB), (uint32_t)tp.lds_bytes, s, A, G);
     LAMG_LAUNCH_CHECK();
@@ -687,17 +858,18 @@ template size_t tail_desc_bytes<double>();
 template size_t tail_desc_bytes<float>();
 template void tail_fill_desc<double>(void *, int, const Level &, const SolveOp &, const int64_t *,
                                      const double *, const double *, const double *,
-                                     const double *, const double *, const double *, double *,
-                                     double *, double *, double *, double *, double *);
+                                     const double *, const double *, const double *,
+                                     const double *, double *, double *, double *, double *,
+                                     double *, double *);
 template void tail_fill_desc<float>(void *, int, const Level &, const SolveOp &, const int64_t *,
                                     const float *, const float *, const float *, const float *,
-                                    const float *, const float *, float *, float *, float *,
-                                    float *, float *, float *);
+                                    const float *, const float *, const float *, float *, float *,
+                                    float *, float *, float *, float *);
 template void run_tail<double>(const TailPlan &, int, int, int, int64_t *, hipStream_t);
 template void run_tail<float>(const TailPlan &, int, int, int, int64_t *, hipStream_t);
 template int tail_lds_plan<double>(const std::vector<Level> &, int, int, const void *,
-                                   std::vector<char> &, std::vector<char> &, size_t &);
+                                   std::vector<char> &, std::vector<char> &, size_t &, int &);
 template int tail_lds_plan<float>(const std::vector<Level> &, int, int, const void *,
-                                  std::vector<char> &, std::vector<char> &, size_t &);
+                                  std::vector<char> &, std::vector<char> &, size_t &, int &);
 
 }  // namespace lamg
