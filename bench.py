@@ -41,6 +41,33 @@ WORKLOADS = {
 }
 
 
+def kernel_source_hash() -> str:
+    """Hash of the sources the finest-level cycle kernels are built from."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("cycle_kernels.hip", "csr_device.h"):
+        with open(os.path.join(ROOT, "paper_2606_24791_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, k: int):
+    """HBM bytes per launch of the finest FP32 Gauss-Seidel colour pass from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on a copy kernel), or None
+    when it does not cover this workload or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_gs_color_finest.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("workload") != workload or t.get("nrhs") != k or \
+            t.get("source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
 def percentile(xs, q):
     import numpy as np
 
@@ -56,6 +83,9 @@ def main() -> int:
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="after the timed region, one device copy of this many MB (calibrates "
+                         "the HBM byte counters of a profiler run)")
     ap.add_argument("--profile-reps", type=int, default=0,
                     help="also time the finest GS colour pass in isolation (back-to-back launches)")
     args = ap.parse_args()
@@ -152,6 +182,16 @@ def main() -> int:
                                        stream=stream)
         isolated = dict(us_per_launch=s2 * 1e6, GBs=b2 / s2 / 1e9, reps=args.profile_reps)
 
+    if args.copy_probe_mb > 0:
+        nel = args.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {nel * 4} bytes read, {nel * 4} bytes written")
+        del src, dst
+
     # the FP64 oracle: error of every result against it, and the CPU baseline
     cpu = None
     errs = {}
@@ -174,6 +214,7 @@ def main() -> int:
         log(f"oracle: setup {t_setup:.2f}s solve {t_solve:.2f}s cycles {so['cycles']}; "
             f"err fp32ir {errs.get('fp32ir'):.2e} fp64 {errs.get('fp64'):.2e}")
 
+    traffic = measured_traffic(args.workload, k)
     r = results["fp32ir"]
     line = {
         "metric": "nnz*RHS solved/s to 1e-8 rel resid (FP32 cycles + FP64 refinement)",
@@ -205,7 +246,7 @@ def main() -> int:
                  "err_vs_oracle": errs.get("fp64")},
         "roofline": {"bound": "hbm", "kernel": "k_csr<float, GS, finest> (one colour pass)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": byt, "us_per_launch": sec * 1e6,
                      "launches": gs["launches"], "timing": "HIP events attached to every launch "
                      "(dispatch timestamps) in the timed FP32+IR region, on the solve stream"},

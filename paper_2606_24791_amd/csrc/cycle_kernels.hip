@@ -8,7 +8,7 @@
 // lpr = lanes splitting the row's entries); lane g of a group takes column g % kp and
 // every lpr-th entry of the row, and the lpr partial sums are combined by cross-lane
 // shuffles. Matrix indices and values are read once per group and broadcast across
-// the kp column lanes.
+// the kp column lanes. Rows of the long class get a whole block each (k_csr_long).
 #include "csr_device.h"
 #include "lamg_internal.h"
 
@@ -96,8 +96,52 @@ void launch_csr(int64_t r0, int64_t nrows, const int32_t *rows, int skip_long, c
     LAMG_LAUNCH_CHECK();
 }
 
-// Lanes per row for a row length: enough lanes to cover the row, capped by the group.
-inline int lanes_long(int k) { return 64 >> kp_log2(k); }
+// Long rows (more than kLongRow off-diagonals: the hubs of power-law graphs and of their
+// dense coarse levels): one block of kBlock threads per row, kp column lanes times
+// kBlock/kp entry lanes, each with 8 loads in flight; the entry lanes' partial sums are
+// combined by a wave shuffle tree and then across the waves in wave order.
+constexpr int kWavesLong = kBlock / 64;
+
+template <class T, int OP, int FINE>
+__global__ void __launch_bounds__(kBlock)
+    k_csr_long(int64_t r0, const int32_t *__restrict__ rows, const int32_t *__restrict__ rp,
+               const int32_t *__restrict__ ci, const T *__restrict__ v, const T *__restrict__ dd,
+               const T *__restrict__ f, const T *xin, T *out, int k, int lkp) {
+    __shared__ T part[kWavesLong][32];
+    const int64_t row = rows ? (int64_t)rows[blockIdx.x] : r0 + (int64_t)blockIdx.x;
+    const int tid = threadIdx.x;
+    const int kp = 1 << lkp;
+    const int col = tid & (kp - 1);
+    const int sub = tid >> lkp;
+    const int32_t b = rp[row], e = rp[row + 1];
+    T acc = T(0);
+    if (col < k) acc = row_dot<T, 8>(ci, v, xin, b + sub, e, kBlock >> lkp, k, col);
+    for (int o = kp; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
+    const int wave = tid >> 6, lane = tid & 63;
+    if (lane < kp) part[wave][lane] = acc;
+    __syncthreads();
+    if (tid >= k) return;
+    T sum = T(0);
+    for (int w = 0; w < kWavesLong; ++w) sum += part[w][tid];
+    const int64_t o = row * k + tid;
+    if (OP == OP_GS) {
+        out[o] = (f[o] - sum) * dd[row];
+    } else if (OP == OP_RESID) {
+        out[o] = f[o] - dd[row] * xin[o] - sum;
+    } else {
+        out[o] = sum;
+    }
+}
+
+template <class T, int OP, int FINE = 0>
+void launch_csr_long(int64_t r0, int64_t nrows, const int32_t *rows, const int32_t *rp,
+                     const int32_t *ci, const T *v, const T *dd, const T *f, const T *xin, T *out,
+                     int k, hipStream_t s) {
+    if (nrows <= 0) return;
+    launch_kernel(k_csr_long<T, OP, FINE>, dim3((unsigned)nrows), dim3(kBlock), 0, s, r0, rows,
+                  rp, ci, v, dd, f, xin, out, k, kp_log2(k));
+    LAMG_LAUNCH_CHECK();
+}
 
 // ---------------------------------------------------------------------------
 // Elementwise kernels
@@ -466,8 +510,8 @@ static void gs_color(const SolveOp &op, int c, const T *v, const T *dinv, const 
     launch_csr<T, OP_GS, FINE>(a, b - a, nullptr, 0, op.rp.p, op.ci.p, v, dinv, f, x, x, k,
                                op.lpr_short, s);
     int64_t la = op.blk[nc + c], lb = op.blk[nc + c + 1];  // long rows of colour c
-    launch_csr<T, OP_GS, FINE>(la, lb - la, nullptr, 0, op.rp.p, op.ci.p, v, dinv, f, x, x, k,
-                               lanes_long(k), s);
+    launch_csr_long<T, OP_GS, FINE>(la, lb - la, nullptr, op.rp.p, op.ci.p, v, dinv, f, x, x, k,
+                                    s);
 }
 
 template <class T>
@@ -498,8 +542,8 @@ static void residual_impl(const SolveOp &op, const T *v, const T *d, const T *x,
     int64_t nshort = op.blk[nc];
     launch_csr<T, OP_RESID, FINE>(0, nshort, nullptr, 0, op.rp.p, op.ci.p, v, d, f, x, r, k,
                                   op.lpr_short, s);
-    launch_csr<T, OP_RESID, FINE>(nshort, op.n - nshort, nullptr, 0, op.rp.p, op.ci.p, v, d, f, x,
-                                  r, k, lanes_long(k), s);
+    launch_csr_long<T, OP_RESID, FINE>(nshort, op.n - nshort, nullptr, op.rp.p, op.ci.p, v, d, f,
+                                       x, r, k, s);
 }
 
 template <class T>
@@ -516,8 +560,8 @@ void run_restrict(const SolveOp &op, const T *rw, const T *r, T *fc, int k, hipS
     launch_csr<T, OP_SPMV>(0, op.nc, nullptr, op.n_rlong ? kLongRow : 0, op.rrp.p, op.rci.p, rw,
                            nullptr, nullptr, r, fc, k, op.lpr_r, s);
     if (op.n_rlong)
-        launch_csr<T, OP_SPMV>(0, op.n_rlong, op.rlong.p, 0, op.rrp.p, op.rci.p, rw, nullptr,
-                               nullptr, r, fc, k, lanes_long(k), s);
+        launch_csr_long<T, OP_SPMV>(0, op.n_rlong, op.rlong.p, op.rrp.p, op.rci.p, rw, nullptr,
+                                    nullptr, r, fc, k, s);
 }
 
 template <class T>

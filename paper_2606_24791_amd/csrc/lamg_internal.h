@@ -28,6 +28,7 @@ constexpr int kBlock = 256;         // threads per block of every kernel
 constexpr int kRedBlocksMax = 256;  // partial-sum blocks of a reduction
 constexpr int kRedQMax = 14;        // quantities per reduction (4x4 normal equations + rhs)
 constexpr int kTailMaxLevels = 16;  // levels one coarse-tail launch may span
+constexpr int kTVShortRow = 64;     // test-vector rows longer than this get a wave each
 
 // Error carried from the point of failure to the C-ABI boundary.
 struct Error : std::runtime_error {
@@ -290,6 +291,9 @@ void launch_strong(int64_t n, const int32_t *rp, const int32_t *ci, const double
 void launch_tv_init(int64_t n, uint64_t seed, int level, double *X, hipStream_t s);
 void launch_tv_sweep_color(int64_t cnt, const int32_t *rows, const int32_t *rp, const int32_t *ci,
                            const double *v, double *X, hipStream_t s);
+// the same relaxation for rows with more than kTVShortRow stored entries (one wave per row)
+void launch_tv_sweep_long(int64_t cnt, const int32_t *rows, const int32_t *rp, const int32_t *ci,
+                          const double *v, double *X, hipStream_t s);
 void launch_affinity(int64_t n, const int32_t *rp, const int32_t *ci, const double *X,
                      double *sigma_tmp, double *aff, hipStream_t s);
 void launch_moments(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,

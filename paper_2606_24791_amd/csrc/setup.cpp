@@ -182,14 +182,25 @@ static void setup_level(lamg_handle *h, int l) {
     const int64_t n = L.n, nnz = L.nnz;
 
     L.ncolors = greedy_color(n, L.h_rp, L.h_ci, L.h_color);
-    // rows of each colour, ascending
-    std::vector<int64_t> coff(L.ncolors + 1, 0);
-    for (int64_t u = 0; u < n; ++u) coff[L.h_color[u] + 1]++;
+    // rows of each colour: those with at most kTVShortRow stored entries ascending, then the
+    // longer ones ascending (rows of one colour are independent, so the order only decides
+    // which kernel relaxes them)
+    std::vector<int64_t> coff(L.ncolors + 1, 0), clong(L.ncolors, 0);
+    auto is_long = [&](int64_t u) { return L.h_rp[u + 1] - L.h_rp[u] > kTVShortRow; };
+    for (int64_t u = 0; u < n; ++u) {
+        coff[L.h_color[u] + 1]++;
+        if (!is_long(u)) clong[L.h_color[u]]++;
+    }
     for (int c = 0; c < L.ncolors; ++c) coff[c + 1] += coff[c];
     std::vector<int32_t> crow(n);
     {
-        std::vector<int64_t> pos(coff.begin(), coff.end() - 1);
-        for (int64_t u = 0; u < n; ++u) crow[pos[L.h_color[u]]++] = (int32_t)u;
+        std::vector<int64_t> pos_s(coff.begin(), coff.end() - 1), pos_l(L.ncolors);
+        for (int c = 0; c < L.ncolors; ++c) pos_l[c] = coff[c] + clong[c];
+        for (int64_t u = 0; u < n; ++u) {
+            const int c = L.h_color[u];
+            crow[is_long(u) ? pos_l[c]++ : pos_s[c]++] = (int32_t)u;
+        }
+        for (int c = 0; c < L.ncolors; ++c) clong[c] += coff[c];  // start of the long rows
     }
     DArr<int32_t> d_crow;
     d_crow.alloc(pool, n);
@@ -200,9 +211,12 @@ static void setup_level(lamg_handle *h, int l) {
     L.X.alloc(pool, n * kTV);
     launch_tv_init(n, h->opt.seed, l, L.X.p, s);
     for (int sw = 0; sw < kTVSweeps; ++sw)
-        for (int c = 0; c < L.ncolors; ++c)
-            launch_tv_sweep_color(coff[c + 1] - coff[c], d_crow.p + coff[c], L.rp.p, L.ci.p, L.val.p,
+        for (int c = 0; c < L.ncolors; ++c) {
+            launch_tv_sweep_color(clong[c] - coff[c], d_crow.p + coff[c], L.rp.p, L.ci.p, L.val.p,
                                   L.X.p, s);
+            launch_tv_sweep_long(coff[c + 1] - clong[c], d_crow.p + clong[c], L.rp.p, L.ci.p,
+                                 L.val.p, L.X.p, s);
+        }
     L.aff.alloc(pool, nnz);
     {
         DArr<double> sig;

@@ -125,6 +125,71 @@ __global__ void k_tv_sweep_color(int64_t cnt, const int32_t *__restrict__ rows,
     xu[3] = (0.0 - a3) / d;
 }
 
+// The same update for long rows, one wave per row: the lanes load 64 entries at a time
+// and form their products (each product is rounded on its own, as in the per-row loop),
+// then lane 0 adds them to the four running sums in CSR order. The diagonal and the
+// lanes past the row's end contribute +0.0, which leaves a sum that started at +0.0
+// unchanged, so every sum is the left-to-right sum of the per-row loop bit for bit.
+constexpr int kTVLongRowsPerBlock = kBlock / 64;
+
+__global__ void __launch_bounds__(kBlock)
+    k_tv_sweep_long(int64_t cnt, const int32_t *__restrict__ rows, const int32_t *__restrict__ rp,
+                    const int32_t *__restrict__ ci, const double *__restrict__ v,
+                    double *__restrict__ X) {
+    __shared__ double prod[kTVLongRowsPerBlock][64][kTV];
+    __shared__ double diag[kTVLongRowsPerBlock];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t t = (int64_t)blockIdx.x * kTVLongRowsPerBlock + wave;
+    if (t >= cnt) return;  // uniform per wave; no block-wide barrier below
+    const int32_t u = rows[t];
+    const int32_t b = rp[u], e = rp[u + 1];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int32_t j0 = b; j0 < e; j0 += 64) {
+        const int32_t j = j0 + lane;
+        double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+        if (j < e) {
+            const int32_t c = ci[j];
+            const double w = v[j];
+            if (c == u) {
+                diag[wave] = w;
+            } else {
+                const double *xc = X + (int64_t)c * kTV;
+                p0 = w * xc[0];
+                p1 = w * xc[1];
+                p2 = w * xc[2];
+                p3 = w * xc[3];
+            }
+        }
+        prod[wave][lane][0] = p0;
+        prod[wave][lane][1] = p1;
+        prod[wave][lane][2] = p2;
+        prod[wave][lane][3] = p3;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane == 0) {
+            const int m = (e - j0 < 64) ? (int)(e - j0) : 64;
+            for (int q = 0; q < m; ++q) {
+                a0 = a0 + prod[wave][q][0];
+                a1 = a1 + prod[wave][q][1];
+                a2 = a2 + prod[wave][q][2];
+                a3 = a3 + prod[wave][q][3];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (lane == 0) {
+        const double d = diag[wave];
+        double *xu = X + (int64_t)u * kTV;
+        xu[0] = (0.0 - a0) / d;
+        xu[1] = (0.0 - a1) / d;
+        xu[2] = (0.0 - a2) / d;
+        xu[3] = (0.0 - a3) / d;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Affinity, eq. (2.2): c_uv = (sum_k x_u x_v)^2 / (sum_k x_u^2 * sum_k x_v^2).
 // ---------------------------------------------------------------------------
@@ -548,6 +613,14 @@ void launch_tv_sweep_color(int64_t cnt, const int32_t *rows, const int32_t *rp, 
                            const double *v, double *X, hipStream_t s) {
     if (cnt <= 0) return;
     k_tv_sweep_color<<<grid_for(cnt), kBlock, 0, s>>>(cnt, rows, rp, ci, v, X);
+    LAMG_LAUNCH_CHECK();
+}
+
+void launch_tv_sweep_long(int64_t cnt, const int32_t *rows, const int32_t *rp, const int32_t *ci,
+                          const double *v, double *X, hipStream_t s) {
+    if (cnt <= 0) return;
+    const unsigned blocks = (unsigned)((cnt + kTVLongRowsPerBlock - 1) / kTVLongRowsPerBlock);
+    k_tv_sweep_long<<<blocks, kBlock, 0, s>>>(cnt, rows, rp, ci, v, X);
     LAMG_LAUNCH_CHECK();
 }
 

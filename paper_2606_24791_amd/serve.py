@@ -94,6 +94,7 @@ class Server:
         self.rejected = 0
         self.overshoots = 0  # times the resident bytes could not be brought under the budget
         self.progress_every = 0  # print a progress line every this many results (0: never)
+        self.log_batches = False  # print one line per solved batch
         if use_torch_allocator:
             self._install_allocator()
 
@@ -249,10 +250,17 @@ class Server:
             bh = np.concatenate([r.b for r in batch], axis=0)
             b = torch.tensor(bh, device="cuda")
             phi = torch.empty_like(b)
+            ts = time.perf_counter()
             st = B.lamg_solve(entry["handle"], b, phi, tol=self.tol, precision=self.precision,
                               stream=stream)
             ph = phi.cpu().numpy()
             stream.synchronize()
+            if self.log_batches:
+                import sys
+
+                print(f"[serve] batch {gid} n={g.n} cols={cols} {'hit' if hit else 'miss'} "
+                      f"solve {1e3 * (time.perf_counter() - ts):.1f} ms cycles {st['cycles']}",
+                      file=sys.stderr, flush=True)
             info = B.lamg_hierarchy_info(entry["handle"])
             now = time.perf_counter() - self.t0
             with self.lock:
@@ -342,59 +350,130 @@ class Server:
         B.lamg_set_allocator()
 
 
-def synthetic_stream(n_requests: int, rate: float, n_graphs: int = 16, nmin: float = 1e3,
-                     nmax: float = 1e6, kmax: int = 32, seed: int = 0):
-    """Poisson arrivals at `rate` requests/s over a pool of graphs (2D grids, random
-    geometric graphs of mean degree 10 and Chung-Lu graphs of exponent 2.3 and mean degree
-    12, n log-uniform in [nmin, nmax]) drawn with Zipf(1) popularity; each request has
-    U{1..kmax} right-hand sides N(0,1). Returns (graphs, requests)."""
+def _pool_graph(args):
+    """One graph of the synthetic pool (top level so that worker processes can run it)."""
     from . import inputs as I
 
+    i, n, seed = args
+    fam = i % 3
+    if fam == 0:
+        side = max(2, int(round(np.sqrt(n))))
+        return I.grid2d(side, side, name=f"g{i}_grid{side}")
+    if fam == 1:
+        return I.random_geometric(n, 10.0, seed=seed * 1000 + i, name=f"g{i}_rgg{n}")
+    return I.chung_lu(n, 2.3, 12.0, seed=seed * 1000 + i, name=f"g{i}_cl{n}")
+
+
+def graph_pool(n_graphs: int = 16, nmin: float = 1e3, nmax: float = 1e6, seed: int = 0,
+               workers: int = 1) -> dict:
+    """A pool of 2D grids, random geometric graphs (mean degree 10) and Chung-Lu graphs
+    (exponent 2.3, mean degree 12), n log-uniform in [nmin, nmax]; generated in `workers`
+    processes when above 1."""
     rng = np.random.default_rng(seed)
-    graphs = {}
-    for i in range(n_graphs):
-        n = int(round(10 ** rng.uniform(np.log10(nmin), np.log10(nmax))))
-        fam = i % 3
-        if fam == 0:
-            side = max(2, int(round(np.sqrt(n))))
-            g = I.grid2d(side, side, name=f"g{i}_grid{side}")
-        elif fam == 1:
-            g = I.random_geometric(n, 10.0, seed=seed * 1000 + i, name=f"g{i}_rgg{n}")
-        else:
-            g = I.chung_lu(n, 2.3, 12.0, seed=seed * 1000 + i, name=f"g{i}_cl{n}")
-        graphs[g.name] = g
+    specs = [(i, int(round(10 ** rng.uniform(np.log10(nmin), np.log10(nmax)))), seed)
+             for i in range(n_graphs)]
+    if workers > 1:
+        import concurrent.futures as cf
+        import multiprocessing as mp
+
+        with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+            graphs = list(ex.map(_pool_graph, specs))
+    else:
+        graphs = [_pool_graph(sp) for sp in specs]
+    return {g.name: g for g in graphs}
+
+
+def request_stream(graphs: dict, n_requests: int, rate: float, kmax: int = 32, seed: int = 0,
+                   shared_rhs: bool = False) -> list:
+    """Poisson arrivals at `rate` requests/s (rate <= 0: all at time 0) over the pool with
+    Zipf(1) popularity (in pool order); each request has U{1..kmax} right-hand sides N(0,1).
+    With `shared_rhs`, a request's block is a view into one kmax x n block per graph (at a
+    random offset), which keeps host memory at one block per graph for long streams."""
+    rng = np.random.default_rng(seed + 7919)
     names = list(graphs)
     pop = 1.0 / np.arange(1, len(names) + 1)
     pop /= pop.sum()
+    blocks = {}
     t = 0.0
     reqs = []
     for rid in range(n_requests):
-        t += rng.exponential(1.0 / rate)
+        if rate > 0:
+            t += rng.exponential(1.0 / rate)
         gid = names[rng.choice(len(names), p=pop)]
         k = int(rng.integers(1, kmax + 1))
-        reqs.append(Request(rid, gid, rng.standard_normal((k, graphs[gid].n)), t))
-    return graphs, reqs
+        n = graphs[gid].n
+        if shared_rhs:
+            if gid not in blocks:
+                blocks[gid] = np.random.default_rng(seed * 31 + len(blocks)).standard_normal(
+                    (2 * kmax, n))
+            o = int(rng.integers(0, kmax + 1))
+            b = blocks[gid][o:o + k]
+        else:
+            b = rng.standard_normal((k, n))
+        reqs.append(Request(rid, gid, b, t))
+    return reqs
+
+
+def synthetic_stream(n_requests: int, rate: float, n_graphs: int = 16, nmin: float = 1e3,
+                     nmax: float = 1e6, kmax: int = 32, seed: int = 0):
+    """A graph pool and a request stream over it (see graph_pool, request_stream).
+    Returns (graphs, requests)."""
+    graphs = graph_pool(n_graphs, nmin, nmax, seed)
+    return graphs, request_stream(graphs, n_requests, rate, kmax, seed)
 
 
 def main(argv=None) -> int:
+    """Serving benchmark: a saturation run (every request at time 0) measures the capacity
+    in requests/s; then one run per offered load (a fraction of that capacity) with
+    Poisson arrivals. One JSON line per run."""
     import argparse
     import json
+    import os
+    import sys
 
     ap = argparse.ArgumentParser(description="LAMG+ serving stream on one GPU")
     ap.add_argument("--requests", type=int, default=200)
-    ap.add_argument("--rate", type=float, default=20.0, help="arrivals per second")
     ap.add_argument("--graphs", type=int, default=12)
+    ap.add_argument("--nmin", type=float, default=1e3)
     ap.add_argument("--nmax", type=float, default=1e6)
+    ap.add_argument("--kmax", type=int, default=32)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--loads", default="0.5,0.8,1.0",
+                    help="offered loads as fractions of the measured capacity")
+    ap.add_argument("--rate", type=float, default=None,
+                    help="run one stream at this offered rate (requests/s) instead")
+    ap.add_argument("--log-batches", action="store_true")
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--seed", type=int, default=0)
     a = ap.parse_args(argv)
-    graphs, reqs = synthetic_stream(a.requests, a.rate, a.graphs, nmax=a.nmax, seed=a.seed)
-    srv = Server(graphs, hbm_budget=a.budget_gb * 1e9, slots=a.slots)
-    srv.progress_every = 20
-    out = srv.run(reqs)
-    srv.close()
-    print(json.dumps(out))
+    log = lambda *x: print("[serve]", *x, file=sys.stderr, flush=True)
+    t = time.perf_counter()
+    graphs = graph_pool(a.graphs, a.nmin, a.nmax, a.seed, workers=a.workers)
+    nnz = sorted(g.nnz_laplacian for g in graphs.values())
+    log(f"{len(graphs)} graphs in {time.perf_counter() - t:.1f}s, nnz(L) {nnz[0]}..{nnz[-1]}")
+
+    def one(rate, tag):
+        reqs = request_stream(graphs, a.requests, rate, a.kmax, a.seed, shared_rhs=True)
+        srv = Server(graphs, hbm_budget=a.budget_gb * 1e9, slots=a.slots)
+        srv.progress_every = max(1, a.requests // 10)
+        srv.log_batches = a.log_batches
+        out = srv.run(reqs)
+        srv.close()
+        out.update(run=tag, offered_rate=rate if rate > 0 else None, requests_total=a.requests,
+                   graphs=len(graphs), slots=a.slots, kmax=a.kmax)
+        out["answered_per_s"] = out["answered"] / out["wall_s"]
+        print(json.dumps(out), flush=True)
+        log(f"{tag}: {out['answered_per_s']:.2f} req/s p50 {out['p50_ms']:.1f} ms "
+            f"p99 {out['p99_ms']:.1f} ms")
+        return out
+
+    if a.rate is not None:
+        one(a.rate, f"rate{a.rate:g}")
+        return 0
+    cap = one(0.0, "saturation")["answered_per_s"]
+    for f in (float(x) for x in a.loads.split(",") if x):
+        one(f * cap, f"load{f:g}")
     return 0
 
 
