@@ -84,9 +84,12 @@ typedef struct {
     int32_t keep_setup_data; /* keep canonical operators, colours, strong flags, test vectors,
                                 affinities, moments and aggregates for lamg_export_level (default 0) */
     int32_t tail_rows;       /* levels below the finest with at most this many nodes run their
-                                whole cycle in one single-workgroup launch per visit
-                                (default 2500; 0 = every step is its own kernel). Changes only
-                                how the cycle is executed, not what it computes. */
+                                whole cycle in one single-workgroup launch per visit, together
+                                with the levels right above them (below 65536 nodes) whose many
+                                colours of few rows make one workgroup clearly cheaper than
+                                separate kernels (default 2500; 0 = every step is its own
+                                kernel). Changes only how the cycle is executed, not what it
+                                computes. */
 } lamg_options;
 
 /* Per-level description of a hierarchy. */

@@ -27,7 +27,6 @@ constexpr int kLongRow = 32;        // rows with more off-diagonals go to the wa
 constexpr int kBlock = 256;         // threads per block of every kernel
 constexpr int kRedBlocksMax = 256;  // partial-sum blocks of a reduction
 constexpr int kRedQMax = 14;        // quantities per reduction (4x4 normal equations + rhs)
-constexpr int kTailMaxLevels = 16;  // levels one coarse-tail launch may span
 constexpr int kTVShortRow = 64;     // test-vector rows longer than this get a wave each
 
 // Error carried from the point of failure to the C-ABI boundary.

@@ -122,12 +122,38 @@ struct Cycle {
     int64_t *d_visits;      // its visit counters
 };
 
-// First level (below the finest) whose cycle runs in the coarse-tail kernel.
+// First level (below the finest) whose cycle runs in the coarse-tail kernel: the first
+// level with at most tail_rows nodes, extended upwards over levels whose visit is clearly
+// cheaper as dependent steps of one workgroup than as kernel launches. Such levels have
+// many colours of few rows each (the dense and the chain-like coarse levels of power-law
+// graphs): a visit costs about 3 sweeps x colours launches plus ~15 others, each ~4 us,
+// against the same number of workgroup steps of ~0.5 us plus the rows of a colour pass
+// gathered through one compute unit (~2000 entries per us). Levels with long (hub) rows
+// stay with the per-step kernels, which give each such row a whole block.
 int tail_level(const lamg_handle *h) {
     if (h->opt.tail_rows <= 0) return -1;
+    int l0 = -1;
     for (int l = 1; l < h->nlev; ++l)
-        if (h->lev[l].n <= h->opt.tail_rows) return std::max(l, h->nlev - kTailMaxLevels);
-    return -1;
+        if (h->lev[l].n <= h->opt.tail_rows) {
+            l0 = l;
+            break;
+        }
+    if (l0 < 0) return -1;
+    while (l0 > 1) {
+        const Level &L = h->lev[l0 - 1];
+        const SolveOp &op = L.op;
+        if (L.coarsest || L.n >= 65536) break;
+        const int nc = std::max(1, op.ncolors);
+        const bool has_long = op.blk[2 * nc] > op.blk[nc];
+        if (has_long) break;  // hub rows: a block each in the per-step kernels
+        const double launches = 3.0 * nc + 15.0;
+        const double steps = 3.0 * nc + 15.0;
+        const double entries_per_pass = (double)op.nnz_off / nc;
+        const double tail_us = steps * (0.5 + entries_per_pass / 2000.0);
+        if (tail_us > 0.5 * launches * 4.0) break;
+        --l0;
+    }
+    return l0;
 }
 
 // One gamma-cycle at level l on (x, f): (1,2) multicolour Gauss-Seidel, coarse

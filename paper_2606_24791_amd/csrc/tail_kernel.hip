@@ -171,15 +171,36 @@ __device__ __forceinline__ void csr_rows(int a, int b, int la, int lb, const int
                 out[o] = acc;
         }
     }
+    const int nl = lb - la;
+    if (nl <= 0) return;
+    // long rows: gw waves per row, as many as keep every wave busy when they are few (the
+    // hubs of power-law graphs stay long on every coarse level); the waves' partial sums
+    // are added in wave order after a barrier
+    __shared__ T lpart[TW][32];
+    int gw = 1;
+    while (gw < TW && gw * 2 * nl <= TW) gw *= 2;
     const int wave = tid >> 6, lane = tid & 63;
     const int sub = lane >> lkp, col = lane & (kp - 1), nsub = 64 >> lkp;
-    for (int i = la + wave; i < lb; i += TW) {
-        const int row = rows ? rows[i] : i;
-        const int e0 = rp[row], e1 = rp[row + 1];
+    const int wr = wave / gw, wp = wave - wr * gw, slots = TW / gw;
+    for (int i0 = la; i0 < lb; i0 += slots) {
+        const int i = i0 + wr;
+        int row = 0;
         T acc = T(0);
-        if (col < k) acc = row_sum<T, 4>(ci, v, xin, e0 + sub, e1, nsub, k, col);
+        if (i < lb) {
+            row = rows ? rows[i] : i;
+            const int e0 = rp[row], e1 = rp[row + 1];
+            if (col < k) acc = row_sum<T, 4>(ci, v, xin, e0 + wp * nsub + sub, e1, nsub * gw, k, col);
+        }
         for (int o = kp; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
-        if (sub == 0 && col < k) {
+        if (gw > 1) {
+            if (lane < kp) lpart[wave][lane] = acc;
+            bar();
+            if (wp == 0) {
+                acc = T(0);
+                for (int q = 0; q < gw; ++q) acc += lpart[wr * gw + q][col];
+            }
+        }
+        if (i < lb && wp == 0 && sub == 0 && col < k) {
             const int o = row * k + col;
             if (OP == 0)
                 out[o] = (f[o] - acc) * dd[row];
@@ -188,6 +209,7 @@ __device__ __forceinline__ void csr_rows(int a, int b, int la, int lb, const int
             else
                 out[o] = acc;
         }
+        if (gw > 1) bar();
     }
 }
 
