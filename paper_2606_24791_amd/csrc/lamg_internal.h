@@ -141,6 +141,7 @@ struct SolveOp {
     DArr<int64_t> dblk;            // device copy of blk
     int lpr_short = 1;         // lanes per row of the short-row bin (k = 1)
     int max_short_len = 0;     // longest off-diagonal row; 0 if any row is in the long bin
+    int max_len = 0;           // longest off-diagonal row
     DArr<int32_t> perm;        // solve index -> canonical index
     DArr<int32_t> rp, ci;      // off-diagonal CSR in solve numbering
     DArr<double> v64, d64, dinv64;

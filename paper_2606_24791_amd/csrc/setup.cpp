@@ -316,6 +316,8 @@ static void build_solve_op(lamg_handle *h, int l, const std::vector<int32_t> &pe
     op.nnz_off = srp[n];
     op.lpr_short = pick_lpr(nshort ? short_len / nshort : 1.0);
     op.max_short_len = 0;
+    op.max_len = 0;
+    for (int64_t i = 0; i < n; ++i) op.max_len = std::max(op.max_len, srp[i + 1] - srp[i]);
     if (nshort == n)
         for (int64_t i = 0; i < n; ++i) op.max_short_len = std::max(op.max_short_len, srp[i + 1] - srp[i]);
     op.blk_nnz.resize(op.blk.size());

@@ -41,6 +41,7 @@ constexpr int kFast = 16;  // longest row held in registers
 template <class T>
 constexpr int kGather = sizeof(T) == 4 ? 8 : 4;  // gathers in flight per group
 constexpr int kRedQ = 2;   // quantities per tail reduction
+constexpr int kSplitRow = 256;  // levels with longer rows share a long row between waves
 
 // Level descriptor. Array fields hold device pointers for levels in global memory and
 // byte offsets into the launch's dynamic LDS for LDS-resident levels (Z always global).
@@ -48,6 +49,7 @@ template <class T>
 struct TailLvl {
     int32_t n, ncolors, coarsest, nc;  // nc: rows of the next level
     int32_t n_rlong, maxlen, maxcol, ew;  // maxcol: rows of the largest colour; ew: ELL width
+    int32_t maxrow, pad0;                 // longest off-diagonal row (long ones included)
     double gamma;
     const int64_t *blk;  // 2*ncolors + 1 offsets (class 0 colours, class 1 colours)
     const int32_t *rp, *ci;
@@ -100,6 +102,7 @@ struct Lv {
     static constexpr bool OL = M == kAllLds;  // operator, transfer and other vectors
     static constexpr bool XL = M != kGlobal;  // iterate
     int n, nc, ncol, nrl, maxlen, maxcol, ew;
+    bool split;  // long rows long enough to share them between waves
     const int32_t *eci;
     const T *ev;
     const int64_t *blk;
@@ -112,7 +115,7 @@ struct Lv {
     T *x, *f, *r, *rho, *x1, *rho1;
     __device__ Lv(const TailLvl<T> &D, char *s)
         : n(D.n), nc(D.nc), ncol(D.ncolors), nrl(D.n_rlong), maxlen(D.maxlen), maxcol(D.maxcol),
-          ew(D.ew), eci(D.eci), ev(D.ev),
+          ew(D.ew), split(D.maxrow > kSplitRow), eci(D.eci), ev(D.ev),
           blk(at<OL>(s, D.blk)), rp(at<OL>(s, D.rp)), ci(at<OL>(s, D.ci)), v(at<OL>(s, D.v)),
           d(at<OL>(s, D.d)), dinv(at<OL>(s, D.dinv)), p0(at<OL>(s, D.p0)), p1(at<OL>(s, D.p1)),
           w0(at<OL>(s, D.w0)), w1(at<OL>(s, D.w1)), rrp(at<OL>(s, D.rrp)), rci(at<OL>(s, D.rci)),
@@ -153,7 +156,7 @@ __device__ inline T row_sum(const int32_t *ci, const T *v, const T *x, int j0, i
 template <class T, int OP>
 __device__ __forceinline__ void csr_rows(int a, int b, int la, int lb, const int32_t *rows, int skip_long,
                          const int32_t *rp, const int32_t *ci, const T *v, const T *dd, const T *f,
-                         const T *xin, T *out, int k, int lkp) {
+                         const T *xin, T *out, int k, int lkp, T *lpart, bool split) {
     const int tid = threadIdx.x;
     const int kp = 1 << lkp;
     const int c = tid & (kp - 1);
@@ -175,10 +178,9 @@ __device__ __forceinline__ void csr_rows(int a, int b, int la, int lb, const int
     if (nl <= 0) return;
     // long rows: gw waves per row, as many as keep every wave busy when they are few (the
     // hubs of power-law graphs stay long on every coarse level); the waves' partial sums
-    // are added in wave order after a barrier
-    __shared__ T lpart[TW][32];
+    // are added in wave order after a barrier, through lpart (TW x kp values in LDS)
     int gw = 1;
-    while (gw < TW && gw * 2 * nl <= TW) gw *= 2;
+    while (split && gw < TW && gw * 2 * nl <= TW) gw *= 2;
     const int wave = tid >> 6, lane = tid & 63;
     const int sub = lane >> lkp, col = lane & (kp - 1), nsub = 64 >> lkp;
     const int wr = wave / gw, wp = wave - wr * gw, slots = TW / gw;
@@ -193,11 +195,11 @@ __device__ __forceinline__ void csr_rows(int a, int b, int la, int lb, const int
         }
         for (int o = kp; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
         if (gw > 1) {
-            if (lane < kp) lpart[wave][lane] = acc;
+            if (lane < kp) lpart[wave * kp + lane] = acc;
             bar();
             if (wp == 0) {
                 acc = T(0);
-                for (int q = 0; q < gw; ++q) acc += lpart[wr * gw + q][col];
+                for (int q = 0; q < gw; ++q) acc += lpart[(wr * gw + q) * kp + col];
             }
         }
         if (i < lb && wp == 0 && sub == 0 && col < k) {
@@ -217,7 +219,7 @@ __device__ __forceinline__ void csr_rows(int a, int b, int la, int lb, const int
 // memory with an ELL copy read it coalesced: one thread per (row, column), entry u of all
 // rows at consecutive addresses; the sum runs in entry order as in the CSR pass.
 template <class T, int M>
-__device__ __forceinline__ void residual(const Lv<T, M> &L, T *out, int k, int lkp) {
+__device__ __forceinline__ void residual(const Lv<T, M> &L, T *out, int k, int lkp, T *lp) {
     if (M != kAllLds && L.ew > 0) {
         const int tid = threadIdx.x;
         const int kp = 1 << lkp;
@@ -248,7 +250,7 @@ __device__ __forceinline__ void residual(const Lv<T, M> &L, T *out, int k, int l
     }
     const int nc = L.ncol;
     csr_rows<T, 1>(0, (int)L.blk[nc], (int)L.blk[nc], L.n, nullptr, 0, L.rp, L.ci, L.v, L.d, L.f,
-                   L.x, out, k, lkp);
+                   L.x, out, k, lkp, lp, L.split);
 }
 
 template <class T>
@@ -326,7 +328,8 @@ struct PipeRow {
 // the row's own value with weight 0, so every gather is unconditional), and every colour
 // pass is one gather, one store and one barrier.
 template <class T, int M>
-__device__ __forceinline__ void smooth(const Lv<T, M> &L, int k, int lkp, int sweeps, bool resid) {
+__device__ __forceinline__ void smooth(const Lv<T, M> &L, int k, int lkp, int sweeps, bool resid,
+                                       T *lp) {
     const int tid = threadIdx.x;
     const int kp = 1 << lkp;
     const int nc = L.ncol;
@@ -416,12 +419,12 @@ __device__ __forceinline__ void smooth(const Lv<T, M> &L, int k, int lkp, int sw
             for (int cl = 0; cl < nc; ++cl) {
                 csr_rows<T, 0>((int)L.blk[cl], (int)L.blk[cl + 1], (int)L.blk[nc + cl],
                                (int)L.blk[nc + cl + 1], nullptr, 0, L.rp, L.ci, L.v, L.dinv, L.f,
-                               L.x, L.x, k, lkp);
+                               L.x, L.x, k, lkp, lp, L.split);
                 bar();
             }
     }
     if (resid) {
-        residual<T, M>(L, L.r, k, lkp);
+        residual<T, M>(L, L.r, k, lkp, lp);
         bar();
     }
 }
@@ -516,11 +519,12 @@ __device__ __forceinline__ int visit(const TailArgs &A, const TailLvl<T> &DL, co
     const int k = A.k, lkp = A.lkp, kp = 1 << lkp;
     const Lv<T, ML> L(DL, smem);
     const Lv<T, MC> C(DC, smem);
+    T *lp = reinterpret_cast<T *>(smem + A.red_off);  // long-row partials (reduction area)
     const int s = ws.get_st(l);
     if ((s & 1) == 0) {
-        smooth<T, ML>(L, k, lkp, 1, true);
+        smooth<T, ML>(L, k, lkp, 1, true, lp);
         csr_rows<T, 2>(0, L.nc, 0, L.nrl, L.rlong, L.nrl ? kLongRow : 0, L.rrp, L.rci, L.rw,
-                       nullptr, nullptr, L.r, C.f, k, lkp);
+                       nullptr, nullptr, L.r, C.f, k, lkp, lp, false);
         for (int t = tid; t < C.n * k; t += TB) C.x[t] = T(0);
         bar();
         const int i = ws.get_cnt(l);
@@ -535,7 +539,7 @@ __device__ __forceinline__ int visit(const TailArgs &A, const TailLvl<T> &DL, co
     const int nvis = s >> 9;
     const int c = tid & (kp - 1);
     // rho = f_c - L_c x_c
-    residual<T, MC>(C, C.rho, k, lkp);
+    residual<T, MC>(C, C.rho, k, lkp, lp);
     bar();
     const bool again = j < nvis;
     if (j >= 2) {  // two-iterate recombination across the visits
@@ -608,7 +612,7 @@ __device__ __forceinline__ int visit(const TailArgs &A, const TailLvl<T> &DL, co
             }
         bar();
     }
-    smooth<T, ML>(L, k, lkp, 2, false);
+    smooth<T, ML>(L, k, lkp, 2, false, lp);
     return l - 1;
 }
 
@@ -692,6 +696,7 @@ void tail_fill_desc(void *host_buf, int l, const Level &L, const SolveOp &op, co
     D.nc = (int32_t)op.nc;
     D.n_rlong = (int32_t)op.n_rlong;
     D.maxlen = op.max_short_len;
+    D.maxrow = op.max_len;
     for (int c = 0; c < op.ncolors; ++c)
         D.maxcol = std::max(D.maxcol, (int32_t)(op.blk[c + 1] - op.blk[c]));
     D.gamma = L.gamma;
