@@ -41,12 +41,15 @@ enum { OP_GS = 0, OP_RESID = 1, OP_SPMV = 2 };
 // One kernel body for the three CSR passes. Rows are r0 + (group index) or, with a row
 // list, rows[group index]. `skip_long` > 0 skips rows longer than it (handled by a
 // separate launch over a list).
+// Side outputs (null: none): OP_RESID copies x to sx and the residual to sr (the pair the
+// next two-iterate recombination starts from); OP_SPMV zeroes sx at the output row (the
+// coarse iterate a visit starts from).
 template <class T, int OP, int FINE>
 __global__ void __launch_bounds__(kBlock)
     k_csr(int64_t r0, int64_t nrows, const int32_t *__restrict__ rows, int skip_long,
           const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const T *__restrict__ v,
           const T *__restrict__ dd, const T *__restrict__ f, const T *xin, T *out, int k, int lkp,
-          int llpr) {
+          int llpr, T *sx, T *sr) {
     const int lg = lkp + llpr;
     const int G = 1 << lg;
     const int64_t grp = (int64_t)blockIdx.x * (kBlock >> lg) + (threadIdx.x >> lg);
@@ -71,9 +74,16 @@ __global__ void __launch_bounds__(kBlock)
     if (OP == OP_GS) {
         out[o] = (f[o] - acc) * dd[row];
     } else if (OP == OP_RESID) {
-        out[o] = f[o] - dd[row] * xin[o] - acc;
+        const T xo = xin[o];
+        const T res = f[o] - dd[row] * xo - acc;
+        out[o] = res;
+        if (sx) {
+            sx[o] = xo;
+            sr[o] = res;
+        }
     } else {
         out[o] = acc;
+        if (sx) sx[o] = T(0);
     }
 }
 
@@ -82,7 +92,7 @@ __global__ void __launch_bounds__(kBlock)
 template <class T, int OP, int FINE = 0>
 void launch_csr(int64_t r0, int64_t nrows, const int32_t *rows, int skip_long, const int32_t *rp,
                 const int32_t *ci, const T *v, const T *dd, const T *f, const T *xin, T *out, int k,
-                int lpr, hipStream_t s) {
+                int lpr, hipStream_t s, T *sx = nullptr, T *sr = nullptr) {
     if (nrows <= 0) return;
     int lkp = kp_log2(k);
     int llpr = ilog2(lpr);
@@ -92,7 +102,7 @@ void launch_csr(int64_t r0, int64_t nrows, const int32_t *rows, int skip_long, c
     int64_t groups_per_block = kBlock >> lg;
     unsigned grid = (unsigned)((nrows + groups_per_block - 1) / groups_per_block);
     launch_kernel(k_csr<T, OP, FINE>, dim3(grid), dim3(kBlock), 0, s, r0, nrows, rows, skip_long,
-                  rp, ci, v, dd, f, xin, out, k, lkp, llpr);
+                  rp, ci, v, dd, f, xin, out, k, lkp, llpr, sx, sr);
     LAMG_LAUNCH_CHECK();
 }
 
@@ -106,7 +116,7 @@ template <class T, int OP, int FINE>
 __global__ void __launch_bounds__(kBlock)
     k_csr_long(int64_t r0, const int32_t *__restrict__ rows, const int32_t *__restrict__ rp,
                const int32_t *__restrict__ ci, const T *__restrict__ v, const T *__restrict__ dd,
-               const T *__restrict__ f, const T *xin, T *out, int k, int lkp) {
+               const T *__restrict__ f, const T *xin, T *out, int k, int lkp, T *sx, T *sr) {
     __shared__ T part[kWavesLong][32];
     const int64_t row = rows ? (int64_t)rows[blockIdx.x] : r0 + (int64_t)blockIdx.x;
     const int tid = threadIdx.x;
@@ -127,19 +137,26 @@ __global__ void __launch_bounds__(kBlock)
     if (OP == OP_GS) {
         out[o] = (f[o] - sum) * dd[row];
     } else if (OP == OP_RESID) {
-        out[o] = f[o] - dd[row] * xin[o] - sum;
+        const T xo = xin[o];
+        const T res = f[o] - dd[row] * xo - sum;
+        out[o] = res;
+        if (sx) {
+            sx[o] = xo;
+            sr[o] = res;
+        }
     } else {
         out[o] = sum;
+        if (sx) sx[o] = T(0);
     }
 }
 
 template <class T, int OP, int FINE = 0>
 void launch_csr_long(int64_t r0, int64_t nrows, const int32_t *rows, const int32_t *rp,
                      const int32_t *ci, const T *v, const T *dd, const T *f, const T *xin, T *out,
-                     int k, hipStream_t s) {
+                     int k, hipStream_t s, T *sx = nullptr, T *sr = nullptr) {
     if (nrows <= 0) return;
     launch_kernel(k_csr_long<T, OP, FINE>, dim3((unsigned)nrows), dim3(kBlock), 0, s, r0, rows,
-                  rp, ci, v, dd, f, xin, out, k, kp_log2(k));
+                  rp, ci, v, dd, f, xin, out, k, kp_log2(k), sx, sr);
     LAMG_LAUNCH_CHECK();
 }
 
@@ -413,6 +430,76 @@ __global__ void k_rc2_update(int64_t n, int k, int lkp, T *__restrict__ e, T *__
     rho[t] = rv - a * (rv - rho1[t]);
 }
 
+// Column totals of a two-quantity reduction from its block partials, added in block order
+// as k_red_final adds them, into tot[i][c] of the calling block (followed by a barrier).
+__device__ inline void block_totals2(int nblk, int k, const double *__restrict__ partial,
+                                     double (*tot)[32]) {
+    for (int idx = threadIdx.x; idx < 2 * k; idx += blockDim.x) {
+        const int i = idx >= k ? 1 : 0, c = idx - i * k;
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += partial[((int64_t)b * 2 + i) * k + c];
+        tot[i][c] = s;
+    }
+    __syncthreads();
+}
+
+// Energy correction and prolongation in one launch: every block forms mu per column from
+// the partial sums of run_mu_partial (the arithmetic of k_red_final) and applies
+// x += mu P e_c on its rows.
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+    k_prolong_mu(int64_t n, int k, int lkp, const int32_t *__restrict__ p0,
+                 const int32_t *__restrict__ p1, const T *__restrict__ w0, const T *__restrict__ w1,
+                 const T *__restrict__ ec, int nblk, const double *__restrict__ partial,
+                 T *__restrict__ x) {
+    __shared__ double tot[2][32];
+    __shared__ double mu_s[32];
+    block_totals2(nblk, k, partial, tot);
+    if ((int)threadIdx.x < k) {
+        const int c = threadIdx.x;
+        const double num = tot[0][c], den = tot[1][c];
+        double mu = num / den;
+        if (!(den > 0.0) || !isfinite(mu)) mu = 1.0;
+        mu_s[c] = mu;
+    }
+    __syncthreads();
+    ROWCOL(n, lkp)
+    T pe = w0[u] * ec[(int64_t)p0[u] * k + c];
+    int32_t q = p1[u];
+    if (q >= 0) pe += w1[u] * ec[(int64_t)q * k + c];
+    x[t] += (T)mu_s[c] * pe;
+}
+
+// Two-iterate recombination update in one launch with its coefficient: every block forms
+// alpha = <G, rho> / <G, G> per column from the partial sums, applies
+// e += alpha (e1 - e), rho -= alpha (rho - rho1), and with `keep` saves the result as the
+// next (e1, rho1).
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+    k_rc2_fused(int64_t n, int k, int lkp, T *__restrict__ e, T *__restrict__ rho, T *e1, T *rho1,
+                int nblk, const double *__restrict__ partial, int keep) {
+    __shared__ double tot[2][32];
+    __shared__ double al_s[32];
+    block_totals2(nblk, k, partial, tot);
+    if ((int)threadIdx.x < k) {
+        const int c = threadIdx.x;
+        const double gg = tot[0][c], gr = tot[1][c];
+        al_s[c] = (gg > 0.0) ? gr / gg : 0.0;
+    }
+    __syncthreads();
+    ROWCOL(n, lkp)
+    T a = (T)al_s[c];
+    T ev = e[t], rv = rho[t];
+    const T en = ev + a * (e1[t] - ev);
+    const T rn = rv - a * (rv - rho1[t]);
+    e[t] = en;
+    rho[t] = rn;
+    if (keep) {
+        e1[t] = en;
+        rho1[t] = rn;
+    }
+}
+
 // Coarsest solve y = L^+ f (Z holds the pseudo-inverse, so y has zero mean), FP64. One
 // wave per (row, column); its lanes split the row of the symmetric Z and add by shuffles.
 template <class T>
@@ -537,31 +624,32 @@ void run_gs_color(const SolveOp &op, int c, const T *v, const T *dinv, const T *
 
 template <class T, int FINE>
 static void residual_impl(const SolveOp &op, const T *v, const T *d, const T *x, const T *f, T *r,
-                          int k, hipStream_t s) {
+                          int k, hipStream_t s, T *sx, T *sr) {
     const int nc = op.ncolors;
     int64_t nshort = op.blk[nc];
     launch_csr<T, OP_RESID, FINE>(0, nshort, nullptr, 0, op.rp.p, op.ci.p, v, d, f, x, r, k,
-                                  op.lpr_short, s);
+                                  op.lpr_short, s, sx, sr);
     launch_csr_long<T, OP_RESID, FINE>(nshort, op.n - nshort, nullptr, op.rp.p, op.ci.p, v, d, f,
-                                       x, r, k, s);
+                                       x, r, k, s, sx, sr);
 }
 
 template <class T>
 void run_residual(const SolveOp &op, const T *v, const T *d, const T *x, const T *f, T *r, int k,
-                  hipStream_t s, bool fine) {
+                  hipStream_t s, bool fine, T *x_copy, T *r_copy) {
     if (fine)
-        residual_impl<T, 1>(op, v, d, x, f, r, k, s);
+        residual_impl<T, 1>(op, v, d, x, f, r, k, s, x_copy, r_copy);
     else
-        residual_impl<T, 0>(op, v, d, x, f, r, k, s);
+        residual_impl<T, 0>(op, v, d, x, f, r, k, s, x_copy, r_copy);
 }
 
 template <class T>
-void run_restrict(const SolveOp &op, const T *rw, const T *r, T *fc, int k, hipStream_t s) {
+void run_restrict(const SolveOp &op, const T *rw, const T *r, T *fc, int k, hipStream_t s,
+                  T *zero_xc) {
     launch_csr<T, OP_SPMV>(0, op.nc, nullptr, op.n_rlong ? kLongRow : 0, op.rrp.p, op.rci.p, rw,
-                           nullptr, nullptr, r, fc, k, op.lpr_r, s);
+                           nullptr, nullptr, r, fc, k, op.lpr_r, s, zero_xc, nullptr);
     if (op.n_rlong)
         launch_csr_long<T, OP_SPMV>(0, op.n_rlong, op.rlong.p, op.rrp.p, op.rci.p, rw, nullptr,
-                                    nullptr, r, fc, k, s);
+                                    nullptr, r, fc, k, s, zero_xc, nullptr);
 }
 
 template <class T>
@@ -599,6 +687,30 @@ void run_rc2(int64_t n, T *e, T *rho, const T *e1, const T *rho1, int k, double 
     RedIn in{rho, rho1, nullptr, nullptr, 0, 0};
     reduce<T, R_RC2>(n, k, in, partial, Fin{alpha, nullptr, 1.0, 0}, s);
     k_rc2_update<T><<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), e, rho, e1, rho1, alpha);
+    LAMG_LAUNCH_CHECK();
+}
+
+template <class T>
+void run_mu_prolong(const SolveOp &op, const T *w0, const T *w1, int64_t nc, const T *ec,
+                    const T *fc, const T *rho, int k, double *partial, T *x, hipStream_t s) {
+    const int nblk = red_blocks(nc, k);
+    RedIn in{ec, fc, rho, nullptr, 0, 0};
+    k_red_partial<T, R_MU><<<nblk, kBlock, 0, s>>>(nc, k, kp_log2(k), in, partial);
+    LAMG_LAUNCH_CHECK();
+    launch_kernel(k_prolong_mu<T>, dim3(rc_blocks(op.n, k)), dim3(kBlock), 0, s, op.n, k,
+                  kp_log2(k), op.p0.p, op.p1.p, w0, w1, ec, nblk, (const double *)partial, x);
+    LAMG_LAUNCH_CHECK();
+}
+
+template <class T>
+void run_rc2_keep(int64_t n, T *e, T *rho, T *e1, T *rho1, int k, double *partial, bool keep,
+                  hipStream_t s) {
+    const int nblk = red_blocks(n, k);
+    RedIn in{rho, rho1, nullptr, nullptr, 0, 0};
+    k_red_partial<T, R_RC2><<<nblk, kBlock, 0, s>>>(n, k, kp_log2(k), in, partial);
+    LAMG_LAUNCH_CHECK();
+    k_rc2_fused<T><<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), e, rho, e1, rho1, nblk,
+                                                      partial, keep ? 1 : 0);
     LAMG_LAUNCH_CHECK();
 }
 
@@ -679,10 +791,14 @@ void run_zero_cols(int64_t n, int k, const int32_t *zero_mask, double *x, hipStr
     template void run_gs<T>(const SolveOp &, const T *, const T *, const T *, T *, int, int,      \
                             hipStream_t, bool);                                                   \
     template void run_residual<T>(const SolveOp &, const T *, const T *, const T *, const T *,    \
-                                  T *, int, hipStream_t, bool);                                   \
+                                  T *, int, hipStream_t, bool, T *, T *);                         \
     template void run_gs_color<T>(const SolveOp &, int, const T *, const T *, const T *, T *,     \
                                   int, hipStream_t, bool);                                        \
-    template void run_restrict<T>(const SolveOp &, const T *, const T *, T *, int, hipStream_t);  \
+    template void run_restrict<T>(const SolveOp &, const T *, const T *, T *, int, hipStream_t,   \
+                                  T *);                                                           \
+    template void run_mu_prolong<T>(const SolveOp &, const T *, const T *, int64_t, const T *,    \
+                                    const T *, const T *, int, double *, T *, hipStream_t);       \
+    template void run_rc2_keep<T>(int64_t, T *, T *, T *, T *, int, double *, bool, hipStream_t); \
     template void run_prolong<T>(const SolveOp &, const T *, const T *, const T *,                \
                                  const double *, T *, int, hipStream_t);                          \
     template void run_fill<T>(T *, int64_t, T, hipStream_t);                                      \

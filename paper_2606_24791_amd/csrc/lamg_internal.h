@@ -329,11 +329,22 @@ void run_gs(const SolveOp &op, const T *v, const T *dinv, const T *f, T *x, int 
 template <class T>
 void run_gs_color(const SolveOp &op, int c, const T *v, const T *dinv, const T *f, T *x, int k,
                   hipStream_t s, bool fine);
+// With x_copy / r_copy: also x_copy = x and r_copy = r (same launch).
 template <class T>
 void run_residual(const SolveOp &op, const T *v, const T *d, const T *x, const T *f, T *r, int k,
-                  hipStream_t s, bool fine);
+                  hipStream_t s, bool fine, T *x_copy = nullptr, T *r_copy = nullptr);
+// With zero_xc: also zero_xc = 0 on the coarse rows (same launch).
 template <class T>
-void run_restrict(const SolveOp &op, const T *rw, const T *r, T *fc, int k, hipStream_t s);
+void run_restrict(const SolveOp &op, const T *rw, const T *r, T *fc, int k, hipStream_t s,
+                  T *zero_xc = nullptr);
+// mu = <e_c, f_c> / <e_c, f_c - rho> per column, then x += mu P e_c (two launches).
+template <class T>
+void run_mu_prolong(const SolveOp &op, const T *w0, const T *w1, int64_t nc, const T *ec,
+                    const T *fc, const T *rho, int k, double *partial, T *x, hipStream_t s);
+// Two-iterate recombination (two launches); with keep, (e1, rho1) = the recombined pair.
+template <class T>
+void run_rc2_keep(int64_t n, T *e, T *rho, T *e1, T *rho1, int k, double *partial, bool keep,
+                  hipStream_t s);
 template <class T>
 void run_prolong(const SolveOp &op, const T *w0, const T *w1, const T *ec, const double *mu,
                  T *x, int k, hipStream_t s);

@@ -199,27 +199,27 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
         Timed tm(h, timed ? LAMG_KERNEL_RESIDUAL : -1, prec_id<T>(), bytes_residual(op, k, sz));
         run_residual<T>(op, P::v(op), P::d(op), x, f, me.r.p, k, s, l == 0);
     }
-    {
+    {  // f_c = P^T r, and the coarse iterate starts from zero (same launch)
         Timed tm(h, timed ? LAMG_KERNEL_RESTRICT : -1, prec_id<T>(), bytes_restrict(op, k, sz));
-        run_restrict<T>(op, P::rw(op), me.r.p, cv.f.p, k, s);
+        run_restrict<T>(op, P::rw(op), me.r.p, cv.f.p, k, s, cv.x.p);
     }
     int64_t i = C.visits[l]++;
     int nvis = (int)(std::floor((double)(i + 1) * L.gamma) - std::floor((double)i * L.gamma));
-    run_fill<T>(cv.x.p, Lc.n * k, T(0), s);
     for (int j = 1; j <= nvis; ++j) {
         cycle<T>(C, l + 1, cv.x.p, cv.f.p);
-        run_residual<T>(cop, P::v(cop), P::d(cop), cv.x.p, cv.f.p, cv.rho.p, k, s, false);
-        if (j >= 2)
-            run_rc2<T>(Lc.n, cv.x.p, cv.rho.p, cv.x1.p, cv.rho1.p, k, C.partial, cv.alpha.p, s);
-        if (j < nvis) {
-            run_copy<T>(cv.x1.p, cv.x.p, Lc.n * k, s);
-            run_copy<T>(cv.rho1.p, cv.rho.p, Lc.n * k, s);
+        const bool again = j < nvis;
+        if (j >= 2) {  // recombine with the previous visit's pair, keep it if revisiting
+            run_residual<T>(cop, P::v(cop), P::d(cop), cv.x.p, cv.f.p, cv.rho.p, k, s, false);
+            run_rc2_keep<T>(Lc.n, cv.x.p, cv.rho.p, cv.x1.p, cv.rho1.p, k, C.partial, again, s);
+        } else {  // first visit: the pair (x, rho) is saved by the residual launch
+            run_residual<T>(cop, P::v(cop), P::d(cop), cv.x.p, cv.f.p, cv.rho.p, k, s, false,
+                            again ? cv.x1.p : nullptr, again ? cv.rho1.p : nullptr);
         }
     }
-    run_mu<T>(Lc.n, cv.x.p, cv.f.p, cv.rho.p, k, C.partial, me.mu.p, s);
-    {
+    {  // energy correction and prolongation
         Timed tm(h, timed ? LAMG_KERNEL_PROLONG : -1, prec_id<T>(), bytes_prolong(op, k, sz));
-        run_prolong<T>(op, P::w0(op), P::w1(op), cv.x.p, me.mu.p, x, k, s);
+        run_mu_prolong<T>(op, P::w0(op), P::w1(op), Lc.n, cv.x.p, cv.f.p, cv.rho.p, k, C.partial,
+                          x, s);
     }
     smooth(2);
 }
