@@ -83,6 +83,8 @@ def main() -> int:
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--n-direct", type=int, default=0,
+                    help="levels up to this size are solved directly (0: library default)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the timed region, one device copy of this many MB (calibrates "
                          "the HBM byte counters of a profiler run)")
@@ -108,7 +110,8 @@ def main() -> int:
     t = time.perf_counter()
     g = I.workload(args.workload)
     log(f"graph {args.workload}: n={g.n} nnz(L)={g.nnz_laplacian} ({time.perf_counter() - t:.1f}s)")
-    h = B.lamg_setup(g)
+    opts = B.lamg_default_options(**({"n_direct": args.n_direct} if args.n_direct else {}))
+    h = B.lamg_setup(g, opts)
     torch.cuda.synchronize()
     hi = B.lamg_hierarchy_info(h)
     log(f"setup {hi['setup_seconds']:.2f}s levels={hi['levels']} n={hi['n']}")
@@ -199,7 +202,7 @@ def main() -> int:
         import oracle as O
 
         t = time.perf_counter()
-        oh = O.Hierarchy(g, seed=1)
+        oh = O.Hierarchy(g, seed=1, n_direct=opts.n_direct)
         t_setup = time.perf_counter() - t
         t = time.perf_counter()
         ref, so, _ = oh.solve(bh[0], args.tol, 300)

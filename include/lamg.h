@@ -76,7 +76,7 @@ typedef struct {
  * on (Sec. 3.2). */
 typedef struct {
     uint64_t seed;           /* seed of the counter-based test-vector generator (default 1) */
-    int32_t n_direct;        /* levels with n <= n_direct are solved directly (default 256, max 1024) */
+    int32_t n_direct;        /* levels with n <= n_direct are solved directly (default 512, max 1024) */
     int32_t enable_veto;     /* strength-of-connection veto (default 1) */
     int32_t enable_caliber2; /* selective caliber-2 interpolation (default 1) */
     int32_t kappa;           /* finest-level recombination history, 0..4 (default 4) */

@@ -221,7 +221,7 @@ class OracleError(RuntimeError):
 class Hierarchy:
     """The oracle's LAMG+ hierarchy for one graph."""
 
-    def __init__(self, g, seed: int = 1, n_direct: int = 256, enable_veto: bool = True,
+    def __init__(self, g, seed: int = 1, n_direct: int = 512, enable_veto: bool = True,
                  enable_caliber2: bool = True, kappa: int = 4):
         h = C.c_void_p()
         rc = lib().orc_setup(g.n, g.row_ptr, g.col_idx, np.ascontiguousarray(g.weight, np.float64),

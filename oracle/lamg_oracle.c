@@ -704,7 +704,7 @@ int orc_setup(int n, const int *rp, const int *ci, const double *w, uint64_t see
     ohier *h = (ohier *)calloc(1, sizeof(ohier));
     if (!h) return ORC_ERR_ALLOC;
     h->seed = seed;
-    h->n_direct = n_direct > 0 ? n_direct : 256;
+    h->n_direct = n_direct > 0 ? n_direct : 512;
     h->enable_veto = enable_veto;
     h->enable_caliber2 = enable_caliber2;
     h->q_guard = 2.5;   /* eq. (2.3) */

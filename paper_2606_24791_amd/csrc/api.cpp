@@ -124,7 +124,7 @@ const char *lamg_version(void) { return "lamg-mi355x 0.1 (gfx950)"; }
 void lamg_default_options(lamg_options *opt) {
     if (!opt) return;
     opt->seed = 1;
-    opt->n_direct = 256;
+    opt->n_direct = 512;
     opt->enable_veto = 1;
     opt->enable_caliber2 = 1;
     opt->kappa = 4;

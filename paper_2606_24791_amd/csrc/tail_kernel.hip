@@ -366,10 +366,14 @@ __device__ __forceinline__ void smooth(const Lv<T, M> &L, int k, int lkp, int sw
             mycol = lo;
         }
         T *x = L.x;
-        auto gather = [&]() {  // loads in groups of kGroup, summed in entry order
+        // loads in groups of kGroup, summed in entry order; groups past the level's longest
+        // row (a uniform bound) hold only padding and are skipped
+        const int mlen = L.maxlen;
+        auto gather = [&]() {
             T acc = T(0);
 #pragma unroll
             for (int u0 = 0; u0 < kFast; u0 += kGroup) {
+                if (u0 >= mlen) break;
                 T xx[kGroup];
 #pragma unroll
                 for (int u = 0; u < kGroup; ++u) xx[u] = x[cc[u0 + u]];

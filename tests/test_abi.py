@@ -38,7 +38,7 @@ def test_host_only_entry_points():
     assert B.lamg_status_string(B.NOT_CONVERGED) == "not converged"
     assert "gfx950" in B.lamg_version()
     o = B.lamg_default_options()
-    assert (o.seed, o.n_direct, o.enable_veto, o.enable_caliber2, o.kappa) == (1, 256, 1, 1, 4)
+    assert (o.seed, o.n_direct, o.enable_veto, o.enable_caliber2, o.kappa) == (1, 512, 1, 1, 4)
 
 
 def _graph(n, rows, cols, w):
