@@ -28,6 +28,7 @@ constexpr int kBlock = 256;         // threads per block of every kernel
 constexpr int kRedBlocksMax = 256;  // partial-sum blocks of a reduction
 constexpr int kRedQMax = 14;        // quantities per reduction (4x4 normal equations + rhs)
 constexpr int kTVShortRow = 64;     // test-vector rows longer than this get a wave each
+constexpr int kEllMaxWidth = 32;    // longest row of a level that gets an ELL copy
 
 // Error carried from the point of failure to the C-ABI boundary.
 struct Error : std::runtime_error {
@@ -158,8 +159,8 @@ struct SolveOp {
     DArr<double> rw64;
     DArr<float> rw32;
     // ELL copy of the off-diagonals (entry u of row i at u * n + i, padding: own index and
-    // weight 0) for levels below 65536 rows with short rows, read coalesced by the
-    // single-workgroup coarse-level kernel
+    // weight 0) for levels below 65536 rows whose rows have at most kEllMaxWidth entries,
+    // read coalesced by the single-workgroup coarse-level kernel
     int ell_w = 0;
     DArr<int32_t> ell_ci;
     DArr<double> ell_v64;

@@ -510,6 +510,18 @@ __global__ void k_minus_one_over_n(int64_t n, double *__restrict__ Z) {
     if (t < n * n) Z[t] = Z[t] - 1.0 / (double)n;
 }
 
+// Makes the computed inverse exactly symmetric (it is symmetric up to rounding), so that
+// its rows and columns are interchangeable in the coarsest solve.
+__global__ void k_symmetrize(int64_t n, double *__restrict__ Z) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * n) return;
+    const int64_t i = t / n, j = t - i * n;
+    if (j <= i) return;
+    const double a = 0.5 * (Z[i * n + j] + Z[j * n + i]);
+    Z[i * n + j] = a;
+    Z[j * n + i] = a;
+}
+
 __global__ void k_gj_pivot(int64_t n, int64_t p, double *__restrict__ A, double *__restrict__ col) {
     __shared__ double pinv_s;
     if (threadIdx.x == 0) pinv_s = 1.0 / A[p * n + p];
@@ -770,6 +782,8 @@ void coarsest_inverse(Pool &pool, int64_t n, const int32_t *rp, const int32_t *c
         LAMG_LAUNCH_CHECK();
     }
     k_minus_one_over_n<<<grid_for(n * n), kBlock, 0, s>>>(n, Z);
+    LAMG_LAUNCH_CHECK();
+    k_symmetrize<<<grid_for(n * n), kBlock, 0, s>>>(n, Z);
     LAMG_LAUNCH_CHECK();
     LAMG_HIP(hipStreamSynchronize(s));
 }

@@ -76,8 +76,10 @@ struct TailArgs {
     int64_t *visits;  // per level, persistent within a solve
     void *top_x;      // global iterate of the top level (written back if it lives in LDS)
     int32_t njobs, l0, nlev, l_lds, k, lkp;
-    uint32_t red_off;  // byte offset of the two reduction buffers in the dynamic LDS
-    int32_t l_x;       // level whose iterate alone lives in LDS (-1: none)
+    uint32_t red_off;    // byte offset of the two reduction buffers in the dynamic LDS
+    int32_t l_x;         // level whose iterate alone lives in LDS (-1: none)
+    uint32_t cpart_off;  // byte offset of the coarsest solve's part sums (TB doubles)
+    uint32_t pad;
 };
 
 __device__ inline void bar() { __syncthreads(); }
@@ -253,6 +255,38 @@ __device__ __forceinline__ void residual(const Lv<T, M> &L, T *out, int k, int l
                    L.x, out, k, lkp, lp, L.split);
 }
 
+// One Gauss-Seidel colour pass over rows [a, b) from the ELL copy (coalesced loads, entry
+// order as in the CSR pass); for levels in global memory whose rows are too long for the
+// pipelined register rows.
+template <class T, int M>
+__device__ __forceinline__ void ell_gs_pass(const Lv<T, M> &L, int a, int b, int k, int lkp) {
+    const int tid = threadIdx.x;
+    const int kp = 1 << lkp;
+    const int c = tid & (kp - 1);
+    const int n = L.n, ew = L.ew;
+    constexpr int G = kGather<T>;
+    if (c >= k) return;
+    for (int row = a + (tid >> lkp); row < b; row += TB >> lkp) {
+        T acc = T(0);
+        for (int u0 = 0; u0 < ew; u0 += G) {
+            int jj[G];
+            T vv[G], xx[G];
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const bool ok = u0 + u < ew;
+                jj[u] = ok ? L.eci[(u0 + u) * n + row] : row;
+                vv[u] = ok ? L.ev[(u0 + u) * n + row] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < G; ++u) xx[u] = L.x[jj[u] * k + c];
+#pragma unroll
+            for (int u = 0; u < G; ++u) acc += vv[u] * xx[u];
+        }
+        const int o = row * k + c;
+        L.x[o] = (L.f[o] - acc) * L.dinv[row];
+    }
+}
+
 template <class T>
 constexpr int kPipe = sizeof(T) == 4 ? 16 : 14;  // longest row of the pipelined path (even)
 
@@ -418,6 +452,12 @@ __device__ __forceinline__ void smooth(const Lv<T, M> &L, int k, int lkp, int sw
             if (q + 2 < q_end) A.stage2(L);
             bar();
         }
+    } else if (M != kAllLds && L.ew > 0) {
+        for (int sw = 0; sw < sweeps; ++sw)
+            for (int cl = 0; cl < nc; ++cl) {
+                ell_gs_pass<T, M>(L, (int)L.blk[cl], (int)L.blk[cl + 1], k, lkp);
+                bar();
+            }
     } else {
         for (int sw = 0; sw < sweeps; ++sw)
             for (int cl = 0; cl < nc; ++cl) {
@@ -458,45 +498,56 @@ __device__ inline void column_totals(const double *red, int kp, int c, double (&
     }
 }
 
-// y = Z f on the directly solved level (FP64 pseudo-inverse, global memory), G lanes per
-// (row, column) with kZ loads of Z in flight.
+// y = Z f on the directly solved level (FP64 pseudo-inverse in global memory, exactly
+// symmetric). Column-oriented so that a wave's loads are contiguous: thread (i, c) adds
+// Z[j][i] f[j][c] (= Z[i][j] f[j][c]) over its part of the j range, 16 loads in flight, with
+// f[j][c] broadcast to the wave. The threads are split into P parts of the j range (P as
+// large as the (row, column) units allow, at most 4); the parts' sums are added in part
+// order through LDS (the reduction area, TB doubles), so the result is deterministic.
 template <class T, int M>
-__device__ __forceinline__ void coarsest(const double *Z, const Lv<T, M> &L, int k, int lkp) {
+__device__ __forceinline__ void coarsest(const double *Z, const Lv<T, M> &L, int k, int lkp,
+                                         double *cpart) {
     constexpr int kZ = 16;
     const int tid = threadIdx.x;
     const int kp = 1 << lkp;
     const int n = L.n;
     const int units = n << lkp;
-    int lg = 0;
-    while (lg < 6 && (units << (lg + 1)) <= TB) ++lg;
-    const int G = 1 << lg;
+    int P = 1;
+    while (P < 4 && units * P * 2 <= TB) P *= 2;
+    const int chunk = TB / P;
+    const int part = tid / chunk, uidx = tid - part * chunk;
+    const int jlen = (n + P - 1) / P;
+    const int j0 = part * jlen, j1 = min(n, j0 + jlen);
     const T *f = L.f;
     T *y = L.x;
-    for (int base = 0; base < (units << lg); base += TB) {
-        const int t = base + tid;
-        const int unit = t >> lg;
-        const int p = t & (G - 1);
-        const int u = unit >> lkp;
+    for (int u0 = 0; u0 < units; u0 += chunk) {
+        const int unit = u0 + uidx;
+        const int i = unit >> lkp;
         const int c = unit & (kp - 1);
         const bool live = unit < units && c < k;
         double acc = 0.0;
         if (live) {
-            const double *zr = Z + (int64_t)u * n;
-            for (int j = p; j < n; j += kZ * G) {
-                double zz[kZ], ff[kZ];
+            for (int j = j0; j < j1; j += kZ) {
+                double zz[kZ];
 #pragma unroll
-                for (int w = 0; w < kZ; ++w) {
-                    const int jj = j + w * G;
-                    const bool ok = jj < n;
-                    zz[w] = ok ? zr[jj] : 0.0;
-                    ff[w] = ok ? (double)f[jj * k + c] : 0.0;
-                }
+                for (int w = 0; w < kZ; ++w) zz[w] = (j + w < j1) ? Z[(int64_t)(j + w) * n + i] : 0.0;
 #pragma unroll
-                for (int w = 0; w < kZ; ++w) acc += zz[w] * ff[w];
+                for (int w = 0; w < kZ; ++w)
+                    if (j + w < j1) acc += zz[w] * (double)f[(j + w) * k + c];
             }
         }
-        for (int o = 1; o < G; o <<= 1) acc += __shfl_xor(acc, o, 64);
-        if (live && p == 0) y[u * k + c] = (T)acc;
+        if (P > 1) {
+            cpart[tid] = acc;
+            bar();
+            if (part == 0 && live) {
+                double s = 0.0;
+                for (int q = 0; q < P; ++q) s += cpart[q * chunk + uidx];
+                y[i * k + c] = (T)s;
+            }
+            bar();
+        } else if (live) {
+            y[i * k + c] = (T)acc;
+        }
     }
     bar();
 }
@@ -647,10 +698,11 @@ __global__ void __launch_bounds__(TB) k_tail(TailArgs A, const TailLvl<T> *__res
         l = uni(l);
         const TailLvl<T> &D = G[l];
         if (D.coarsest) {
+            double *cpart = reinterpret_cast<double *>(smem + A.cpart_off);
             if (l >= l_lds)
-                coarsest<T, kAllLds>(D.Z, Lv<T, kAllLds>(D, smem), A.k, A.lkp);
+                coarsest<T, kAllLds>(D.Z, Lv<T, kAllLds>(D, smem), A.k, A.lkp, cpart);
             else
-                coarsest<T, kGlobal>(D.Z, Lv<T, kGlobal>(D, smem), A.k, A.lkp);
+                coarsest<T, kGlobal>(D.Z, Lv<T, kGlobal>(D, smem), A.k, A.lkp, cpart);
             --l;
             continue;
         }
@@ -771,15 +823,16 @@ int tail_lds_plan(const std::vector<Level> &lev, int l0, int k, const void *host
                  al(s * op.nnz_r) + al(4 * op.n_rlong);
         return b;
     };
+    const int64_t cpart_bytes = (int64_t)TB * 8;
     int l_lds = nlev;
-    int64_t total = 16 + al(red_bytes);  // offset 0 means "no array"
+    int64_t total = 16 + al(red_bytes) + cpart_bytes;  // offset 0 means "no array"
     for (int l = nlev - 1; l >= l0; --l) {
         int64_t b = level_bytes(l);
         if (total + b > budget) break;
         total += b;
         l_lds = l;
     }
-    int64_t off = 16 + al(red_bytes);
+    int64_t off = 16 + al(red_bytes) + cpart_bytes;
     std::vector<CopyJob> jv;
     TailLvl<T> *D = reinterpret_cast<TailLvl<T> *>(lds_desc.data());
     for (int l = l_lds; l < nlev; ++l) {
@@ -872,6 +925,11 @@ void run_tail(const TailPlan &tp, int l0, int nlev, int k, int64_t *d_visits, hi
     A.lkp = lkp;
     A.red_off = 16;
     A.l_x = tp.l_x;
+    {
+        int kp = 1;
+        while (kp < k) kp <<= 1;
+        A.cpart_off = (uint32_t)(16 + ((2 * (int64_t)kRedQ * TW * kp * 8 + 15) & ~(int64_t)15));
+    }
     const TailLvl<T> *G = static_cast<const TailLvl<T> *>(tp.lds_desc);
     launch_kernel(k_tail<T>, dim3(1), dim3(TB), (uint32_t)tp.lds_bytes, s, A, G);
     LAMG_LAUNCH_CHECK();
