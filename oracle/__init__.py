@@ -66,8 +66,12 @@ def lib():
         L.orc_galerkin.restype = C.c_longlong
         L.orc_galerkin.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, _i32p, _f64p, _i32p,
                                    _f64p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_elim_select.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, _i32p]
+        L.orc_schur.restype = C.c_longlong
+        L.orc_schur.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, C.c_int, C.c_void_p,
+                                C.c_void_p, C.c_void_p]
         L.orc_setup.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_uint64, C.c_int, C.c_int, C.c_int,
-                                C.c_int, C.POINTER(C.c_void_p)]
+                                C.c_int, C.c_int, C.POINTER(C.c_void_p)]
         L.orc_free.argtypes = [C.c_void_p]
         L.orc_nlevels.argtypes = [C.c_void_p]
         L.orc_level_info.argtypes = [C.c_void_p, C.c_int, np.ctypeslib.ndpointer(np.int64),
@@ -199,6 +203,28 @@ def galerkin(rp, ci, v, nc, p0, w0, p1, w1):
     return Crp, Cci, Cv
 
 
+def elim_select(rp, ci, v, dmax=4):
+    """Low-degree elimination set: returns (cid, nc), cid = coarse id or -1 on F."""
+    n = rp.size - 1
+    cid = np.empty(n, np.int32)
+    nc = lib().orc_elim_select(n, rp, ci, v, dmax, cid)
+    return cid, nc
+
+
+def schur(rp, ci, v, cid, nc):
+    """Schur complement onto the C nodes of an elimination set, canonical CSR."""
+    n = rp.size - 1
+    cid = np.ascontiguousarray(cid, np.int32)
+    nnz = lib().orc_schur(n, rp, ci, v, cid, nc, None, None, None)
+    if nnz < 0:
+        raise MemoryError
+    Crp = np.empty(nc + 1, np.int32)
+    Cci = np.empty(nnz, np.int32)
+    Cv = np.empty(nnz)
+    lib().orc_schur(n, rp, ci, v, cid, nc, _p(Crp), _p(Cci), _p(Cv))
+    return Crp, Cci, Cv
+
+
 def recombine(phi, r, hphi, hr):
     """One fine-level recombination (in place on phi, r) over saved pairs."""
     m = len(hphi)
@@ -222,11 +248,11 @@ class Hierarchy:
     """The oracle's LAMG+ hierarchy for one graph."""
 
     def __init__(self, g, seed: int = 1, n_direct: int = 512, enable_veto: bool = True,
-                 enable_caliber2: bool = True, kappa: int = 4):
+                 enable_caliber2: bool = True, kappa: int = 4, elimination: bool = False):
         h = C.c_void_p()
         rc = lib().orc_setup(g.n, g.row_ptr, g.col_idx, np.ascontiguousarray(g.weight, np.float64),
                              seed, n_direct, int(enable_veto), int(enable_caliber2), kappa,
-                             C.byref(h))
+                             int(elimination), C.byref(h))
         if rc != OK:
             raise OracleError(f"orc_setup failed with code {rc}")
         self._h = h
@@ -247,7 +273,8 @@ class Hierarchy:
         if lib().orc_level_info(self._h, l, s, d) != OK:
             raise IndexError(l)
         return dict(n=int(s[0]), nnz=int(s[1]), ncolors=int(s[2]), nc=int(s[3]),
-                    n_cal2=int(s[4]), coarsest=bool(s[5]), gamma=float(d[0]), tau=float(d[1]))
+                    n_cal2=int(s[4]), coarsest=bool(s[5]), elim=bool(s[6]), gamma=float(d[0]),
+                    tau=float(d[1]))
 
     def export(self, l: int) -> dict:
         info = self.level_info(l)
@@ -257,7 +284,10 @@ class Hierarchy:
         out["col_idx"] = np.empty(nnz, np.int32)
         out["val"] = np.empty(nnz)
         arrs = [out["row_ptr"], out["col_idx"], out["val"]]
-        if not info["coarsest"]:
+        if info["elim"]:
+            out["agg"] = np.empty(n, np.int32)
+            arrs += [None] * 6 + [out["agg"]] + [None] * 4
+        elif not info["coarsest"]:
             out.update(color=np.empty(n, np.int32), strong=np.empty(nnz, np.uint8),
                        X=np.empty((n, K)), affinity=np.empty(nnz), moments=np.empty((n, 9)),
                        seed=np.empty(n, np.int32), agg=np.empty(n, np.int32),

@@ -60,6 +60,7 @@ typedef struct {
     int *agg;         /* n: coarse id A(u) */
     int *p0, *p1;     /* n: interpolation parents (p1 = -1 if none) */
     double *w0, *w1;  /* n: their weights */
+    int elim;         /* 1: low-degree elimination level (agg = coarse id, -1 on F) */
     int nc;           /* size of the next level */
     int n_cal2;       /* rows with two parents */
     double gamma, tau;
@@ -72,8 +73,8 @@ typedef struct {
     /* parameters */
     uint64_t seed;
     int n_direct;
-    int enable_veto, enable_caliber2;
-    double q_guard, tau_soc, snap;
+    int enable_veto, enable_caliber2, enable_elim;
+    double q_guard, tau_soc, snap, elim_min;
     int kappa;
 } ohier;
 
@@ -596,6 +597,173 @@ long long orc_galerkin(int n, const int *rp, const int *ci, const double *v, int
     return nnz;
 }
 
+
+/* ------------------------------------------------------------------------- */
+/* S11: low-degree elimination (Sec. 2, "Low-degree elimination", eq. (2.1))  */
+/* ------------------------------------------------------------------------- */
+
+static double diag_of(const int *rp, const int *ci, const double *v, int u) {
+    for (int j = rp[u]; j < rp[u + 1]; ++j)
+        if (ci[j] == u) return v[j];
+    return 0.0;
+}
+
+static double entry_of(const int *rp, const int *ci, const double *v, int u, int t) {
+    for (int j = rp[u]; j < rp[u + 1]; ++j)
+        if (ci[j] == t) return v[j];
+    return 0.0;
+}
+
+/* F: a maximal independent set among the nodes with at most dmax stored off-diagonals,
+ * taken greedily in natural order (u joins F when it qualifies, its diagonal is positive
+ * and none of its neighbours is in F yet). C = the other nodes, numbered by ascending
+ * fine index: cid[u] = rank of u in C, or -1 for u in F. Returns |C|.
+ * Pinned: independence and maximality by brute force; F empty when no node qualifies. */
+int orc_elim_select(int n, const int *rp, const int *ci, const double *v, int dmax, int *cid) {
+    for (int u = 0; u < n; ++u) cid[u] = 0;
+    for (int u = 0; u < n; ++u) {
+        int deg = rp[u + 1] - rp[u] - 1;
+        if (deg > dmax || !(diag_of(rp, ci, v, u) > 0.0)) continue;
+        int free_ = 1;
+        for (int j = rp[u]; j < rp[u + 1]; ++j)
+            if (ci[j] != u && cid[ci[j]] < 0) free_ = 0;
+        if (free_) cid[u] = -1;
+    }
+    int nc = 0;
+    for (int u = 0; u < n; ++u)
+        if (cid[u] >= 0) cid[u] = nc++;
+    return nc;
+}
+
+/* Exact Schur complement onto C, L^c = L_CC - L_CF L_FF^{-1} L_FC (eq. (2.1)); L_FF is
+ * diagonal because F is independent. Off-diagonal (a, b) of coarse row a = cid[u]:
+ * from +0.0, add L_ub if stored, then for every f in F adjacent to both u and b, in
+ * ascending f, add -((L_fu * L_fb) / L_ff). Every pair reached is stored. The diagonal
+ * is minus the sum of the row's off-diagonals in ascending column order (the Schur
+ * complement of a Laplacian has zero row sums).
+ * Pinned: dense L_CC - L_CF L_FF^{-1} L_FC (numpy); exact for integer weights whose
+ * divisions are exact; exact symmetry; the solution of the eliminated system restricted
+ * to C. Phase 1 (Crp == NULL) returns nnz of L^c; phase 2 fills the caller's CSR. */
+long long orc_schur(int n, const int *rp, const int *ci, const double *v, const int *cid, int nc,
+                    int *Crp, int *Cci, double *Cv) {
+    int *slot = (int *)malloc(sizeof(int) * (size_t)(nc > 0 ? nc : 1));
+    int cap = 64;
+    int *col = (int *)malloc(sizeof(int) * (size_t)cap);
+    double *acc = (double *)malloc(sizeof(double) * (size_t)cap);
+    if (!slot || !col || !acc) {
+        free(slot);
+        free(col);
+        free(acc);
+        return -1;
+    }
+    for (int a = 0; a < nc; ++a) slot[a] = -1;
+    long long nnz = 0;
+    if (Crp) Crp[0] = 0;
+    for (int u = 0; u < n; ++u) {
+        if (cid[u] < 0) continue;
+        int a = cid[u], cnt = 0;
+        /* the entries this row reaches, in the order they are first reached */
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int j = rp[u]; j < rp[u + 1]; ++j) {
+                int t = ci[j];
+                if (t == u) continue;
+                if (pass == 0 && cid[t] < 0) continue;
+                if (pass == 1 && cid[t] >= 0) continue;
+                /* pass 0: the C-C entry itself; pass 1: t = f in F, its other neighbours */
+                int lo = pass == 0 ? j : rp[t], hi = pass == 0 ? j + 1 : rp[t + 1];
+                double lff = pass == 0 ? 0.0 : diag_of(rp, ci, v, t);
+                double lfu = pass == 0 ? 0.0 : entry_of(rp, ci, v, t, u);
+                for (int jj = lo; jj < hi; ++jj) {
+                    int bnode = ci[jj];
+                    if (pass == 1 && (bnode == t || bnode == u)) continue;
+                    double c = pass == 0 ? v[jj] : -((lfu * v[jj]) / lff);
+                    int b = cid[bnode];
+                    if (slot[b] < 0) {
+                        if (cnt == cap) {
+                            cap *= 2;
+                            int *nc2 = (int *)realloc(col, sizeof(int) * (size_t)cap);
+                            double *na = (double *)realloc(acc, sizeof(double) * (size_t)cap);
+                            if (nc2) col = nc2;
+                            if (na) acc = na;
+                            if (!nc2 || !na) {
+                                free(slot);
+                                free(col);
+                                free(acc);
+                                return -1;
+                            }
+                        }
+                        slot[b] = cnt;
+                        col[cnt] = b;
+                        acc[cnt] = 0.0;
+                        ++cnt;
+                    }
+                    acc[slot[b]] = acc[slot[b]] + c;
+                }
+            }
+        }
+        for (int x = 0; x < cnt; ++x) slot[col[x]] = -1;
+        /* ascending columns (insertion sort), diagonal in place */
+        for (int x = 1; x < cnt; ++x) {
+            int cc = col[x];
+            double aa = acc[x];
+            int y = x - 1;
+            while (y >= 0 && col[y] > cc) {
+                col[y + 1] = col[y];
+                acc[y + 1] = acc[y];
+                --y;
+            }
+            col[y + 1] = cc;
+            acc[y + 1] = aa;
+        }
+        if (Crp) {
+            double off = 0.0;
+            for (int x = 0; x < cnt; ++x) off = off + acc[x];
+            long long pos = Crp[a];
+            int placed = 0;
+            for (int x = 0; x < cnt; ++x) {
+                if (!placed && col[x] > a) {
+                    Cci[pos] = a;
+                    Cv[pos] = -off;
+                    ++pos;
+                    placed = 1;
+                }
+                Cci[pos] = col[x];
+                Cv[pos] = acc[x];
+                ++pos;
+            }
+            if (!placed) {
+                Cci[pos] = a;
+                Cv[pos] = -off;
+                ++pos;
+            }
+            Crp[a + 1] = (int)pos;
+        }
+        nnz += cnt + 1;
+    }
+    free(slot);
+    free(col);
+    free(acc);
+    return nnz;
+}
+
+/* The F rows of an elimination level given the C values: phi_f = (f_f - sum_{c} L_fc
+ * phi_c) / L_ff, the phi_F = P_F phi_C + L_FF^{-1} b_F of eq. (2.1). The rows of F are
+ * independent, so the order does not matter. */
+static void elim_relax_f(const olevel *lv, double *phi, const double *f) {
+    const ocsr *A = &lv->L;
+    for (int u = 0; u < A->n; ++u) {
+        if (lv->agg[u] >= 0) continue;
+        double s = 0.0, d = 0.0;
+        for (int j = A->rp[u]; j < A->rp[u + 1]; ++j) {
+            if (A->ci[j] == u)
+                d = A->v[j];
+            else
+                s += A->v[j] * phi[A->ci[j]];
+        }
+        phi[u] = (f[u] - s) / d;
+    }
+}
+
 /* ------------------------------------------------------------------------- */
 /* S12: coarsest level, dense solve of (L + 11^T/n) y = f                       */
 /* ------------------------------------------------------------------------- */
@@ -698,7 +866,7 @@ static int build_level_data(ohier *h, int l) {
 
 /* Options: any value <= 0 (or NAN) selects the default. */
 int orc_setup(int n, const int *rp, const int *ci, const double *w, uint64_t seed, int n_direct,
-              int enable_veto, int enable_caliber2, int kappa, void **out) {
+              int enable_veto, int enable_caliber2, int kappa, int enable_elim, void **out) {
     *out = NULL;
     if (n < 1) return ORC_ERR_ARG;
     ohier *h = (ohier *)calloc(1, sizeof(ohier));
@@ -711,6 +879,8 @@ int orc_setup(int n, const int *rp, const int *ci, const double *w, uint64_t see
     h->tau_soc = 0.05;  /* eq. (3.1) */
     h->snap = 0.01;     /* snapping band of the caliber-2 weight (not stated in the paper) */
     h->kappa = (kappa > 0 && kappa <= 4) ? kappa : 4;
+    h->enable_elim = enable_elim;
+    h->elim_min = 0.1; /* an elimination level must remove at least this fraction of n */
     int rc = ORC_OK;
     /* level 0 */
     olevel *l0 = &h->lev[0];
@@ -731,6 +901,42 @@ int orc_setup(int n, const int *rp, const int *ci, const double *w, uint64_t see
         if (lv->L.n <= h->n_direct) {
             lv->coarsest = 1;
             break;
+        }
+        /* elimination and aggregation alternate: an elimination level (when it removes
+         * enough nodes) comes before each aggregation step, never after another one */
+        if (h->enable_elim && !(l > 0 && h->lev[l - 1].elim) && l + 1 < ORC_MAX_LEVELS) {
+            int *cid = (int *)malloc(sizeof(int) * (size_t)lv->L.n);
+            if (!cid) {
+                rc = ORC_ERR_ALLOC;
+                goto fail;
+            }
+            int nc = orc_elim_select(lv->L.n, lv->L.rp, lv->L.ci, lv->L.v, 4, cid);
+            if ((double)(lv->L.n - nc) >= h->elim_min * (double)lv->L.n) {
+                olevel *nx = &h->lev[l + 1];
+                lv->elim = 1;
+                lv->agg = cid;
+                lv->nc = nc;
+                long long cnnz =
+                    orc_schur(lv->L.n, lv->L.rp, lv->L.ci, lv->L.v, cid, nc, NULL, NULL, NULL);
+                if (cnnz < 0) {
+                    rc = ORC_ERR_ALLOC;
+                    goto fail;
+                }
+                nx->L.n = nc;
+                nx->L.nnz = (int)cnnz;
+                nx->L.rp = (int *)malloc(sizeof(int) * (size_t)(nc + 1));
+                nx->L.ci = (int *)malloc(sizeof(int) * (size_t)cnnz);
+                nx->L.v = (double *)malloc(sizeof(double) * (size_t)cnnz);
+                if (!nx->L.rp || !nx->L.ci || !nx->L.v) {
+                    rc = ORC_ERR_ALLOC;
+                    goto fail;
+                }
+                orc_schur(lv->L.n, lv->L.rp, lv->L.ci, lv->L.v, cid, nc, nx->L.rp, nx->L.ci,
+                          nx->L.v);
+                h->nlev = l + 2;
+                continue;
+            }
+            free(cid);
         }
         rc = build_level_data(h, l);
         if (rc) goto fail;
@@ -778,7 +984,7 @@ int orc_setup(int n, const int *rp, const int *ci, const double *w, uint64_t see
                 if (g > 2.0) g = 2.0;
                 if (g < 1.0) g = 1.0;
             }
-            if (h->lev[l + 1].coarsest) g = 1.0;
+            if (h->lev[l + 1].coarsest || h->lev[l].elim) g = 1.0;
             h->lev[l].gamma = g;
             h->lev[l].tau = tau;
         }
@@ -802,7 +1008,7 @@ void orc_free(void *hp) {
 
 int orc_nlevels(const void *hp) { return ((const ohier *)hp)->nlev; }
 
-/* sizes[0..6] = n, nnz, ncolors, nc, n_cal2, coarsest, (unused); sched = gamma, tau */
+/* sizes[0..6] = n, nnz, ncolors, nc, n_cal2, coarsest, elim; sched = gamma, tau */
 int orc_level_info(const void *hp, int l, long long *sizes, double *sched) {
     const ohier *h = (const ohier *)hp;
     if (l < 0 || l >= h->nlev) return ORC_ERR_ARG;
@@ -813,7 +1019,7 @@ int orc_level_info(const void *hp, int l, long long *sizes, double *sched) {
     sizes[3] = lv->coarsest ? 0 : lv->nc;
     sizes[4] = lv->n_cal2;
     sizes[5] = lv->coarsest;
-    sizes[6] = 0;
+    sizes[6] = lv->elim;
     sched[0] = lv->gamma;
     sched[1] = lv->tau;
     return ORC_OK;
@@ -832,6 +1038,10 @@ int orc_export_level(const void *hp, int l, int *rp, int *ci, double *v, int *co
     if (ci) memcpy(ci, lv->L.ci, sizeof(int) * (size_t)nnz);
     if (v) memcpy(v, lv->L.v, sizeof(double) * (size_t)nnz);
     if (lv->coarsest) return ORC_OK;
+    if (lv->elim) { /* only the coarse ids (-1 on F) */
+        if (agg) memcpy(agg, lv->agg, sizeof(int) * (size_t)n);
+        return ORC_OK;
+    }
     if (color) memcpy(color, lv->color, sizeof(int) * (size_t)n);
     if (strong) memcpy(strong, lv->strong, (size_t)nnz);
     if (X) memcpy(X, lv->X, sizeof(double) * (size_t)n * ORC_K);
@@ -907,6 +1117,24 @@ static void cycle(osolver *S, int l, double *phi, const double *f) {
     const olevel *cl = &h->lev[l + 1];
     int nc = cl->L.n;
     double *r = S->r[l], *fc = S->fc[l], *e = S->e[l], *rho = S->rho[l];
+    if (lv->elim) {
+        /* elimination level (eq. (2.1)), gamma = 1: F rows exact given C; the coarse
+         * right-hand side is then the residual on C (equal to P^T r with r_F = 0); one
+         * visit; C takes the coarse correction; F rows exact again. No smoothing, no
+         * energy correction: the interpolation is exact. */
+        elim_relax_f(lv, phi, f);
+        spmv_resid(&lv->L, phi, f, r);
+        for (int u = 0; u < n; ++u)
+            if (lv->agg[u] >= 0) fc[lv->agg[u]] = r[u];
+        for (int a = 0; a < nc; ++a) e[a] = 0.0;
+        S->visits[l]++;
+        cycle(S, l + 1, e, fc);
+        for (int u = 0; u < n; ++u)
+            if (lv->agg[u] >= 0) phi[u] += e[lv->agg[u]];
+        elim_relax_f(lv, phi, f);
+        S->mu_last[l] = 1.0;
+        return;
+    }
     /* pre-relaxation: one sweep */
     orc_gs_sweep_multi(n, lv->L.rp, lv->L.ci, lv->L.v, lv->color, lv->ncolors, 1, f, phi);
     spmv_resid(&lv->L, phi, f, r);
