@@ -88,6 +88,8 @@ def main() -> int:
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the timed region, one device copy of this many MB (calibrates "
                          "the HBM byte counters of a profiler run)")
+    ap.add_argument("--elimination", action="store_true",
+                    help="low-degree elimination levels before each aggregation step")
     ap.add_argument("--profile-reps", type=int, default=0,
                     help="also time the finest GS colour pass in isolation (back-to-back launches)")
     args = ap.parse_args()
@@ -110,7 +112,10 @@ def main() -> int:
     t = time.perf_counter()
     g = I.workload(args.workload)
     log(f"graph {args.workload}: n={g.n} nnz(L)={g.nnz_laplacian} ({time.perf_counter() - t:.1f}s)")
-    opts = B.lamg_default_options(**({"n_direct": args.n_direct} if args.n_direct else {}))
+    over = {"n_direct": args.n_direct} if args.n_direct else {}
+    if args.elimination:
+        over["elimination"] = 1
+    opts = B.lamg_default_options(**over)
     h = B.lamg_setup(g, opts)
     torch.cuda.synchronize()
     hi = B.lamg_hierarchy_info(h)
@@ -202,7 +207,7 @@ def main() -> int:
         import oracle as O
 
         t = time.perf_counter()
-        oh = O.Hierarchy(g, seed=1, n_direct=opts.n_direct)
+        oh = O.Hierarchy(g, seed=1, n_direct=opts.n_direct, elimination=bool(opts.elimination))
         t_setup = time.perf_counter() - t
         t = time.perf_counter()
         ref, so, _ = oh.solve(bh[0], args.tol, 300)
@@ -217,7 +222,7 @@ def main() -> int:
         log(f"oracle: setup {t_setup:.2f}s solve {t_solve:.2f}s cycles {so['cycles']}; "
             f"err fp32ir {errs.get('fp32ir'):.2e} fp64 {errs.get('fp64'):.2e}")
 
-    traffic = measured_traffic(args.workload, k)
+    traffic = measured_traffic(args.workload, k) if not args.elimination else None
     r = results["fp32ir"]
     line = {
         "metric": "nnz*RHS solved/s to 1e-8 rel resid (FP32 cycles + FP64 refinement)",
@@ -238,6 +243,7 @@ def main() -> int:
             "n": g.n, "nnz_L": g.nnz_laplacian, "nnz_2m": g.nnz, "nrhs": k,
             "levels": hi["levels"], "op_complexity": round(hi["op_complexity"], 3),
             "setup_s": round(hi["setup_seconds"], 3),
+            "elimination_levels": sum(hi["elim"]),
         },
         "latency_ms": {"p50": r["p50_ms"], "p99": r["p99_ms"]},
         "cycles": r["cycles"],

@@ -90,6 +90,14 @@ typedef struct {
                                 separate kernels (default 2500; 0 = every step is its own
                                 kernel). Changes only how the cycle is executed, not what it
                                 computes. */
+    int32_t elimination;     /* low-degree elimination levels (Sec. 2, "Low-degree elimination",
+                                eq. (2.1)); default 0. When 1, before each aggregation step a
+                                maximal independent set F of the nodes with at most 4
+                                neighbours (greedy in natural order) is eliminated exactly --
+                                coarse operator = Schur complement onto the other nodes, F rows
+                                recomputed from them in the cycle, cycle index 1 -- provided F
+                                holds at least a tenth of the level's nodes. Elimination and
+                                aggregation levels alternate. */
 } lamg_options;
 
 /* Per-level description of a hierarchy. */
@@ -107,6 +115,8 @@ typedef struct {
     double setup_seconds;                /* wall time of lamg_setup */
     int64_t bytes_peak;                  /* most device bytes the handle has held at once
                                             (setup temporaries included) */
+    int32_t elim[LAMG_MAX_LEVELS];       /* 1: elimination level (its aggregate export holds the
+                                            coarse id of each kept node and -1 on F) */
 } lamg_hier_info;
 
 /* Solve statistics. The caller may point the array fields at host arrays (or leave them
@@ -128,7 +138,8 @@ typedef struct {
  * NULL to skip it. Sizes: n+1 for row_ptr, nnz for col_idx/val/strong/affinity, n for
  * color/seed/aggregate/p0/p1/w0/w1, 4n for x (node-major, x[u*4+k]), 9n for moments
  * (s0, s1[4], s2[4] per node). Everything but row_ptr/col_idx/val is absent on the last
- * (directly solved) level. */
+ * (directly solved) level; an elimination level has only row_ptr/col_idx/val and
+ * aggregate (coarse id of each kept node, -1 on the eliminated set F). */
 typedef struct {
     int32_t *row_ptr;
     int32_t *col_idx;

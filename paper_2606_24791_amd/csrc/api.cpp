@@ -131,6 +131,7 @@ void lamg_default_options(lamg_options *opt) {
     opt->build_fp32 = 1;
     opt->keep_setup_data = 0;
     opt->tail_rows = 2500;
+    opt->elimination = 0;
 }
 
 lamg_status lamg_setup(const lamg_graph *g, const lamg_options *opt, void *stream,
@@ -141,7 +142,8 @@ lamg_status lamg_setup(const lamg_graph *g, const lamg_options *opt, void *strea
     lamg_options o;
     lamg_default_options(&o);
     if (opt) o = *opt;
-    if (o.n_direct < 1 || o.n_direct > 1024 || o.kappa < 0 || o.kappa > 4 || o.tail_rows < 0)
+    if (o.n_direct < 1 || o.n_direct > 1024 || o.kappa < 0 || o.kappa > 4 || o.tail_rows < 0 ||
+        (o.elimination != 0 && o.elimination != 1))
         return LAMG_INVALID_ARG;
     lamg_handle *h = nullptr;
     lamg_status st = guarded([&]() -> lamg_status {
@@ -234,7 +236,8 @@ lamg_status lamg_hierarchy_info(const lamg_handle *h, lamg_hier_info *info) {
         const Level &L = h->lev[l];
         info->n[l] = L.n;
         info->nnz[l] = L.nnz;
-        info->ncolors[l] = L.coarsest ? 0 : L.ncolors;
+        info->ncolors[l] = (L.coarsest || L.elim) ? 0 : L.ncolors;
+        info->elim[l] = L.elim ? 1 : 0;
         info->n_caliber2[l] = L.coarsest ? 0 : L.n_cal2;
         info->gamma[l] = L.coarsest ? 0.0 : L.gamma;
         info->tau[l] = L.coarsest ? 0.0 : L.tau;
@@ -257,7 +260,9 @@ lamg_status lamg_export_level(const lamg_handle *h, int32_t level, lamg_level_ex
         if (out->row_ptr) L.rp.download(out->row_ptr, n + 1, s);
         if (out->col_idx) L.ci.download(out->col_idx, nnz, s);
         if (out->val) L.val.download(out->val, nnz, s);
-        if (!L.coarsest) {
+        if (L.elim) {
+            if (out->aggregate) std::memcpy(out->aggregate, L.h_agg.data(), 4 * n);
+        } else if (!L.coarsest) {
             if (out->color) std::memcpy(out->color, L.h_color.data(), 4 * n);
             if (out->strong) L.strong.download(out->strong, nnz, s);
             if (out->x) L.X.download(out->x, n * kTV, s);

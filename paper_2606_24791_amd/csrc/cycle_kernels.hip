@@ -204,6 +204,15 @@ __global__ void k_prolong(int64_t n, int k, int lkp, const int32_t *__restrict__
     x[t] += (T)mu[c] * pe;
 }
 
+// x[rows[a]] += e[a] for the kept rows of an elimination level (their interpolation is
+// the identity; the eliminated rows are recomputed afterwards)
+template <class T>
+__global__ void k_inject_add(int64_t nc, int k, int lkp, const int32_t *__restrict__ rows,
+                             const T *__restrict__ ec, T *__restrict__ x) {
+    ROWCOL(nc, lkp)
+    x[(int64_t)rows[u] * k + c] += ec[t];
+}
+
 // ---------------------------------------------------------------------------
 // Deterministic two-pass reductions: blocks write partial sums in a fixed order, one
 // block combines them in block order and finishes the per-column scalar.
@@ -643,6 +652,30 @@ void run_residual(const SolveOp &op, const T *v, const T *d, const T *x, const T
 }
 
 template <class T>
+void run_residual_color(const SolveOp &op, int c, const T *v, const T *d, const T *x, const T *f,
+                        T *r, int k, hipStream_t s, bool fine) {
+    const int nc = op.ncolors;
+    int64_t a = op.blk[c], b = op.blk[c + 1], la = op.blk[nc + c], lb = op.blk[nc + c + 1];
+    if (fine) {
+        launch_csr<T, OP_RESID, 1>(a, b - a, nullptr, 0, op.rp.p, op.ci.p, v, d, f, x, r, k,
+                                   op.lpr_short, s);
+        launch_csr_long<T, OP_RESID, 1>(la, lb - la, nullptr, op.rp.p, op.ci.p, v, d, f, x, r, k, s);
+    } else {
+        launch_csr<T, OP_RESID, 0>(a, b - a, nullptr, 0, op.rp.p, op.ci.p, v, d, f, x, r, k,
+                                   op.lpr_short, s);
+        launch_csr_long<T, OP_RESID, 0>(la, lb - la, nullptr, op.rp.p, op.ci.p, v, d, f, x, r, k, s);
+    }
+}
+
+template <class T>
+void run_inject_add(const SolveOp &op, const T *ec, T *x, int k, hipStream_t s) {
+    if (op.nc <= 0) return;
+    launch_kernel(k_inject_add<T>, dim3(rc_blocks(op.nc, k)), dim3(kBlock), 0, s, op.nc, k,
+                  kp_log2(k), op.rci.p, ec, x);
+    LAMG_LAUNCH_CHECK();
+}
+
+template <class T>
 void run_restrict(const SolveOp &op, const T *rw, const T *r, T *fc, int k, hipStream_t s,
                   T *zero_xc) {
     launch_csr<T, OP_SPMV>(0, op.nc, nullptr, op.n_rlong ? kLongRow : 0, op.rrp.p, op.rci.p, rw,
@@ -796,6 +829,9 @@ void run_zero_cols(int64_t n, int k, const int32_t *zero_mask, double *x, hipStr
                                   int, hipStream_t, bool);                                        \
     template void run_restrict<T>(const SolveOp &, const T *, const T *, T *, int, hipStream_t,   \
                                   T *);                                                           \
+    template void run_residual_color<T>(const SolveOp &, int, const T *, const T *, const T *,    \
+                                        const T *, T *, int, hipStream_t, bool);                  \
+    template void run_inject_add<T>(const SolveOp &, const T *, T *, int, hipStream_t);           \
     template void run_mu_prolong<T>(const SolveOp &, const T *, const T *, int64_t, const T *,    \
                                     const T *, const T *, int, double *, T *, hipStream_t);       \
     template void run_rc2_keep<T>(int64_t, T *, T *, T *, T *, int, double *, bool, hipStream_t); \

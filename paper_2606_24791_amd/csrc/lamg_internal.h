@@ -29,6 +29,8 @@ constexpr int kRedBlocksMax = 256;  // partial-sum blocks of a reduction
 constexpr int kRedQMax = 14;        // quantities per reduction (4x4 normal equations + rhs)
 constexpr int kTVShortRow = 64;     // test-vector rows longer than this get a wave each
 constexpr int kEllMaxWidth = 32;    // longest row of a level that gets an ELL copy
+constexpr int kElimMaxDegree = 4;   // eliminated nodes have at most this many neighbours
+constexpr double kElimMinFrac = 0.1;  // an elimination level removes at least this share
 
 // Error carried from the point of failure to the C-ABI boundary.
 struct Error : std::runtime_error {
@@ -170,6 +172,7 @@ struct SolveOp {
 struct Level {
     int64_t n = 0, nnz = 0;  // canonical Laplacian size (diagonal included)
     bool coarsest = false;
+    bool elim = false;  // elimination level: h_agg = coarse id of kept nodes, -1 on F
     std::vector<int32_t> h_rp, h_ci;  // canonical pattern on the host
     DArr<int32_t> rp, ci;             // canonical CSR on the device
     DArr<double> val;
@@ -308,6 +311,14 @@ int64_t galerkin(Pool &pool, int64_t n, int64_t nnz, const int32_t *rp, const in
                  const double *v, int64_t nc, const int32_t *p0, const double *w0,
                  const int32_t *p1, const double *w1, DArr<int32_t> &crp, DArr<int32_t> &cci,
                  DArr<double> &cv, hipStream_t s);
+// Exact Schur complement onto the kept nodes of an elimination set (cid: coarse id or -1),
+// canonical CSR, bit-reproducible (eq. (2.1)).
+int64_t schur(Pool &pool, int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+              const int32_t *cid, int64_t nc, DArr<int32_t> &crp, DArr<int32_t> &cci,
+              DArr<double> &cv, hipStream_t s);
+// d[u] = the stored diagonal of row u
+void launch_diag(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, double *d,
+                 hipStream_t s);
 // Z = L^+ = (L + 11^T/n)^{-1} - 11^T/n (Gauss-Jordan on the SPD matrix, no pivoting).
 void coarsest_inverse(Pool &pool, int64_t n, const int32_t *rp, const int32_t *ci,
                       const double *v, double *Z, hipStream_t s);
@@ -334,6 +345,13 @@ void run_gs_color(const SolveOp &op, int c, const T *v, const T *dinv, const T *
 template <class T>
 void run_residual(const SolveOp &op, const T *v, const T *d, const T *x, const T *f, T *r, int k,
                   hipStream_t s, bool fine, T *x_copy = nullptr, T *r_copy = nullptr);
+// r = f - L x on the rows of colour c only (both row classes).
+template <class T>
+void run_residual_color(const SolveOp &op, int c, const T *v, const T *d, const T *x, const T *f,
+                        T *r, int k, hipStream_t s, bool fine);
+// x += e_c on the kept rows of an elimination level (its one-entry-per-row P^T).
+template <class T>
+void run_inject_add(const SolveOp &op, const T *ec, T *x, int k, hipStream_t s);
 // With zero_xc: also zero_xc = 0 on the coarse rows (same launch).
 template <class T>
 void run_restrict(const SolveOp &op, const T *rw, const T *r, T *fc, int k, hipStream_t s,

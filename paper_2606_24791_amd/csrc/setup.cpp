@@ -113,6 +113,68 @@ static int greedy_color(int64_t n, const std::vector<int32_t> &rp, const std::ve
 }
 
 // ---------------------------------------------------------------------------
+// Low-degree elimination set (Sec. 2, "Low-degree elimination"): one pass in index order;
+// a node with at most kElimMaxDegree neighbours and a positive diagonal is eliminated
+// unless a neighbour already is, which makes F a maximal independent set of those nodes.
+// The kept nodes are numbered in index order (cid), eliminated ones get -1. Returns |C|.
+// ---------------------------------------------------------------------------
+static int64_t elimination_set(int64_t n, const std::vector<int32_t> &rp,
+                               const std::vector<int32_t> &ci, const std::vector<double> &diag,
+                               std::vector<int32_t> &cid) {
+    std::vector<uint8_t> out(n, 0);
+    for (int64_t u = 0; u < n; ++u) {
+        if (rp[u + 1] - rp[u] - 1 > kElimMaxDegree || !(diag[u] > 0.0)) continue;
+        bool free_ = true;
+        for (int32_t j = rp[u]; j < rp[u + 1] && free_; ++j) free_ = !out[ci[j]];
+        out[u] = free_ ? 1 : 0;
+    }
+    cid.resize(n);
+    int64_t nc = 0;
+    for (int64_t u = 0; u < n; ++u) cid[u] = out[u] ? -1 : (int32_t)nc++;
+    return nc;
+}
+
+// Makes level l an elimination level with its Schur complement as level l + 1 when the
+// elimination set holds at least kElimMinFrac of the nodes; returns whether it did.
+static bool try_elimination(lamg_handle *h, int l) {
+    Pool &pool = *h->pool;
+    hipStream_t s = h->stream;
+    Level &L = h->lev[l];
+    const int64_t n = L.n;
+    std::vector<double> diag(n);
+    {
+        DArr<double> d;
+        d.alloc(pool, n);
+        launch_diag(n, L.rp.p, L.ci.p, L.val.p, d.p, s);
+        d.download(diag.data(), n, s);
+        LAMG_HIP(hipStreamSynchronize(s));
+    }
+    std::vector<int32_t> cid;
+    const int64_t nc = elimination_set(n, L.h_rp, L.h_ci, diag, cid);
+    if (!((double)(n - nc) >= kElimMinFrac * (double)n)) return false;
+    L.elim = true;
+    L.nc = nc;
+    L.h_agg = std::move(cid);
+    L.ncolors = 2;  // solve layout: eliminated rows first, then the kept ones
+    L.h_color.resize(n);
+    for (int64_t u = 0; u < n; ++u) L.h_color[u] = L.h_agg[u] < 0 ? 0 : 1;
+    h->lev.emplace_back();
+    Level &C = h->lev[l + 1];
+    Level &F = h->lev[l];
+    DArr<int32_t> d_cid;
+    d_cid.alloc(pool, n);
+    d_cid.upload(F.h_agg.data(), n, s);
+    C.n = nc;
+    C.nnz = schur(pool, n, F.rp.p, F.ci.p, F.val.p, d_cid.p, nc, C.rp, C.ci, C.val, s);
+    C.h_rp.resize(C.n + 1);
+    C.h_ci.resize(C.nnz);
+    C.rp.download(C.h_rp.data(), C.n + 1, s);
+    C.ci.download(C.h_ci.data(), C.nnz, s);
+    LAMG_HIP(hipStreamSynchronize(s));
+    return true;
+}
+
+// ---------------------------------------------------------------------------
 // Greedy aggregation (Sec. 2 "Caliber-1 aggregation", Sec. 3.1): one pass in index
 // order; an undecided node joins the admissible strong neighbour (undecided or seed)
 // of largest affinity -- first in CSR order on ties -- which becomes a seed; with none
@@ -354,14 +416,26 @@ static void build_solve_op(lamg_handle *h, int l, const std::vector<int32_t> &pe
     LAMG_HIP(hipStreamSynchronize(s));
     if (L.coarsest) return;
 
-    // interpolation rows in solve numbering (coarse ids in the next level's numbering)
+    // interpolation rows in solve numbering (coarse ids in the next level's numbering); an
+    // elimination level injects the coarse values into its kept rows (weight 1) and gives
+    // its eliminated rows no parent (entry 0 with weight 0: they are recomputed exactly)
     std::vector<int32_t> hp0(n), hp1(n);
     std::vector<double> hw0(n), hw1(n);
-    L.p0.download(hp0.data(), n, s);
-    L.p1.download(hp1.data(), n, s);
-    L.w0.download(hw0.data(), n, s);
-    L.w1.download(hw1.data(), n, s);
-    LAMG_HIP(hipStreamSynchronize(s));
+    if (L.elim) {
+        for (int64_t u = 0; u < n; ++u) {
+            const bool kept = L.h_agg[u] >= 0;
+            hp0[u] = kept ? L.h_agg[u] : 0;
+            hw0[u] = kept ? 1.0 : 0.0;
+            hp1[u] = -1;
+            hw1[u] = 0.0;
+        }
+    } else {
+        L.p0.download(hp0.data(), n, s);
+        L.p1.download(hp1.data(), n, s);
+        L.w0.download(hw0.data(), n, s);
+        L.w1.download(hw1.data(), n, s);
+        LAMG_HIP(hipStreamSynchronize(s));
+    }
     const std::vector<int32_t> &ipn = *iperm_next;
     const int64_t nc = L.nc;
     std::vector<int32_t> sp0(n), sp1(n);
@@ -392,8 +466,9 @@ static void build_solve_op(lamg_handle *h, int l, const std::vector<int32_t> &pe
     // restriction P^T (coarse row -> fine rows ascending)
     op.nc = nc;
     std::vector<int32_t> rrp(nc + 1, 0);
+    // rows with a zero weight (the eliminated rows) stay out of P^T
     for (int64_t i = 0; i < n; ++i) {
-        rrp[sp0[i] + 1]++;
+        if (sw0[i] != 0.0) rrp[sp0[i] + 1]++;
         if (sp1[i] >= 0) rrp[sp1[i] + 1]++;
     }
     for (int64_t a = 0; a < nc; ++a) rrp[a + 1] += rrp[a];
@@ -403,8 +478,10 @@ static void build_solve_op(lamg_handle *h, int l, const std::vector<int32_t> &pe
         std::vector<int32_t> pos(rrp.begin(), rrp.end() - 1);
         for (int64_t i = 0; i < n; ++i) {
             int32_t a = sp0[i];
-            rci[pos[a]] = (int32_t)i;
-            rw[pos[a]++] = sw0[i];
+            if (sw0[i] != 0.0) {
+                rci[pos[a]] = (int32_t)i;
+                rw[pos[a]++] = sw0[i];
+            }
             if (sp1[i] >= 0) {
                 a = sp1[i];
                 rci[pos[a]] = (int32_t)i;
@@ -499,6 +576,11 @@ void run_setup(lamg_handle *h, const lamg_graph *g) {
             L.coarsest = true;
             break;
         }
+        // elimination and aggregation alternate: an elimination level comes before each
+        // aggregation step (when it removes enough nodes), never after another one
+        if (h->opt.elimination && !(l > 0 && h->lev[l - 1].elim) && l + 1 < kMaxLevels &&
+            try_elimination(h, l))
+            continue;
         setup_level(h, l);
         if (L.nc >= L.n || l + 1 >= kMaxLevels) {
             if (L.n <= kStallDirectMax) {
@@ -537,7 +619,7 @@ void run_setup(lamg_handle *h, const lamg_graph *g) {
                 if (gmm > 2.0) gmm = 2.0;
                 if (gmm < 1.0) gmm = 1.0;
             }
-            if (h->lev[l + 1].coarsest) gmm = 1.0;
+            if (h->lev[l + 1].coarsest || h->lev[l].elim) gmm = 1.0;
             h->lev[l].gamma = gmm;
             h->lev[l].tau = tau;
         }

@@ -469,6 +469,85 @@ __global__ void k_row_fill(int64_t nc, const int32_t *__restrict__ crp, const in
 }
 
 // ---------------------------------------------------------------------------
+// Low-degree elimination (Sec. 2, eq. (2.1)): Schur complement onto the kept nodes C.
+// Contributions in generation order: first every kept entry L_ab (fine rows ascending),
+// then, for each eliminated node f ascending, -((L_fa * L_fb) / L_ff) for every ordered
+// pair (a, b) of distinct neighbours of f. The stable sort by (a, b) and the in-order
+// segment sums then add each coarse entry's terms in that order.
+// ---------------------------------------------------------------------------
+__global__ void k_diag(int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                       const double *__restrict__ v, double *__restrict__ d) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    double x = 0.0;
+    for (int32_t j = rp[u]; j < rp[u + 1]; ++j)
+        if (ci[j] == (int32_t)u) x = v[j];
+    d[u] = x;
+}
+
+// cnt[u]: kept entries of a kept row; cnt[n + u]: fill pairs of an eliminated row
+__global__ void k_schur_count(int64_t n, const int32_t *__restrict__ rp,
+                              const int32_t *__restrict__ ci, const int32_t *__restrict__ cid,
+                              int64_t *__restrict__ cnt) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    const int32_t b = rp[u], e = rp[u + 1];
+    if (cid[u] >= 0) {
+        int64_t c = 0;
+        for (int32_t j = b; j < e; ++j) c += (ci[j] != (int32_t)u && cid[ci[j]] >= 0);
+        cnt[u] = c;
+        cnt[n + u] = 0;
+    } else {
+        const int64_t d = e - b - 1;
+        cnt[u] = 0;
+        cnt[n + u] = d * (d - 1);
+    }
+}
+
+__global__ void k_schur_expand(int64_t n, int64_t nc, const int32_t *__restrict__ rp,
+                               const int32_t *__restrict__ ci, const double *__restrict__ v,
+                               const int32_t *__restrict__ cid, const int64_t *__restrict__ off,
+                               uint64_t *__restrict__ key, double *__restrict__ val) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    const int32_t b = rp[u], e = rp[u + 1];
+    const int32_t a = cid[u];
+    if (a >= 0) {
+        int64_t o = off[u];
+        for (int32_t j = b; j < e; ++j) {
+            const int32_t t = ci[j];
+            if (t == (int32_t)u || cid[t] < 0) continue;
+            key[o] = (uint64_t)a * (uint64_t)nc + (uint64_t)cid[t];
+            val[o] = v[j];
+            ++o;
+        }
+        return;
+    }
+    // eliminated row: at most kElimMaxDegree neighbours, all kept
+    int32_t nb[kElimMaxDegree];
+    double w[kElimMaxDegree];
+    double dg = 0.0;
+    int d = 0;
+    for (int32_t j = b; j < e; ++j) {
+        if (ci[j] == (int32_t)u) {
+            dg = v[j];
+        } else if (d < kElimMaxDegree) {
+            nb[d] = cid[ci[j]];
+            w[d] = v[j];
+            ++d;
+        }
+    }
+    int64_t o = off[n + u];
+    for (int x = 0; x < d; ++x)
+        for (int y = 0; y < d; ++y) {
+            if (y == x) continue;
+            key[o] = (uint64_t)nb[x] * (uint64_t)nc + (uint64_t)nb[y];
+            val[o] = -((w[x] * w[y]) / dg);
+            ++o;
+        }
+}
+
+// ---------------------------------------------------------------------------
 // Coarsest level: (L + 11^T/n)^{-1} (SPD for a connected graph) by in-place Gauss-Jordan
 // elimination without pivoting, then L^+ = that inverse - 11^T/n.
 // ---------------------------------------------------------------------------
@@ -659,26 +738,12 @@ void launch_interp(int64_t n, const int32_t *rp, const int32_t *ci, const uint8_
     LAMG_LAUNCH_CHECK();
 }
 
-int64_t galerkin(Pool &pool, int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
-                 const double *v, int64_t nc, const int32_t *p0, const double *w0,
-                 const int32_t *p1, const double *w1, DArr<int32_t> &crp, DArr<int32_t> &cci,
-                 DArr<double> &cv, hipStream_t s) {
-    // 1. contributions per stored entry, exclusive scan -> generation-order offsets
-    DArr<int64_t> cnt, off;
-    cnt.alloc(pool, nnz + 1);
-    off.alloc(pool, nnz + 1);
-    k_gal_count<<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, p0, w0, p1, w1, cnt.p);
-    LAMG_LAUNCH_CHECK();
-    LAMG_HIP(hipMemsetAsync(cnt.p + nnz, 0, sizeof(int64_t), s));
-    size_t tmp_bytes = 0;
-    LAMG_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt.p, off.p, (int)(nnz + 1), s));
-    DArr<char> tmp;
-    tmp.alloc(pool, (int64_t)tmp_bytes);
-    LAMG_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.p, tmp_bytes, cnt.p, off.p, (int)(nnz + 1), s));
-    int64_t m = 0;
-    LAMG_HIP(hipMemcpyAsync(&m, off.p + nnz, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    LAMG_HIP(hipStreamSynchronize(s));
-    cnt.release();
+// Coarse CSR from m generated contributions (key = a * nc + b, value), consumed here:
+// stable radix sort by key (equal keys keep generation order), in-order segment sums,
+// canonical rows with the diagonal = minus the sum of the row's off-diagonals.
+static int64_t assemble_coarse(Pool &pool, int64_t m, DArr<uint64_t> &key, DArr<double> &val,
+                               int64_t nc, DArr<int32_t> &crp, DArr<int32_t> &cci,
+                               DArr<double> &cv, hipStream_t s) {
     crp.alloc(pool, nc + 1);
     if (m == 0) {  // no coupling at all (only possible for nc == 1)
         std::vector<int32_t> hrp(nc + 1);
@@ -686,37 +751,33 @@ int64_t galerkin(Pool &pool, int64_t n, int64_t nnz, const int32_t *rp, const in
         cci.alloc(pool, nc);
         cv.alloc(pool, nc);
         std::vector<int32_t> hci(nc);
-        std::vector<double> hv(nc, 0.0);
+        std::vector<double> hv(nc, -0.0);  // minus an empty sum
         for (int64_t a = 0; a < nc; ++a) hci[a] = (int32_t)a;
         crp.upload(hrp.data(), nc + 1, s);
         cci.upload(hci.data(), nc, s);
         cv.upload(hv.data(), nc, s);
         LAMG_HIP(hipStreamSynchronize(s));
+        key.release();
+        val.release();
         return nc;
     }
-    // 2. expand
-    DArr<uint64_t> key, key2;
-    DArr<double> val, val2;
-    key.alloc(pool, m);
-    val.alloc(pool, m);
-    k_gal_expand<<<grid_for(n), kBlock, 0, s>>>(n, nc, rp, ci, v, p0, w0, p1, w1, off.p, key.p, val.p);
-    LAMG_LAUNCH_CHECK();
-    off.release();
-    // 3. stable radix sort by (a,b): equal keys keep generation order
+    DArr<uint64_t> key2;
+    DArr<double> val2;
     key2.alloc(pool, m);
     val2.alloc(pool, m);
     uint64_t maxkey = (uint64_t)nc * (uint64_t)nc;
     int end_bit = 1;
     while (end_bit < 64 && ((uint64_t)1 << end_bit) < maxkey) ++end_bit;
-    tmp_bytes = 0;
+    size_t tmp_bytes = 0;
     LAMG_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, key.p, key2.p, val.p, val2.p,
                                                 (int)m, 0, end_bit, s));
+    DArr<char> tmp;
     tmp.alloc(pool, (int64_t)tmp_bytes);
     LAMG_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.p, tmp_bytes, key.p, key2.p, val.p, val2.p,
                                                 (int)m, 0, end_bit, s));
     key.release();
     val.release();
-    // 4. segments
+    // segments
     DArr<int64_t> head, segid;
     head.alloc(pool, m);
     segid.alloc(pool, m);
@@ -751,7 +812,7 @@ int64_t galerkin(Pool &pool, int64_t n, int64_t nnz, const int32_t *rp, const in
     key2.release();
     val2.release();
     start.release();
-    // 5. coarse CSR
+    // coarse CSR
     tmp_bytes = 0;
     LAMG_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, rowcnt.p, crp.p, (int)(nc + 1), s));
     tmp.alloc(pool, (int64_t)tmp_bytes);
@@ -763,6 +824,73 @@ int64_t galerkin(Pool &pool, int64_t n, int64_t nnz, const int32_t *rp, const in
     LAMG_LAUNCH_CHECK();
     LAMG_HIP(hipStreamSynchronize(s));
     return cnnz;
+}
+
+// Exclusive scan of `count` generation counts into offsets; returns the total.
+static int64_t scan_counts(Pool &pool, DArr<int64_t> &cnt, int64_t count, DArr<int64_t> &off,
+                           hipStream_t s) {
+    off.alloc(pool, count + 1);
+    LAMG_HIP(hipMemsetAsync(cnt.p + count, 0, sizeof(int64_t), s));
+    size_t tmp_bytes = 0;
+    LAMG_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt.p, off.p, (int)(count + 1), s));
+    DArr<char> tmp;
+    tmp.alloc(pool, (int64_t)tmp_bytes);
+    LAMG_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.p, tmp_bytes, cnt.p, off.p, (int)(count + 1), s));
+    int64_t m = 0;
+    LAMG_HIP(hipMemcpyAsync(&m, off.p + count, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    LAMG_HIP(hipStreamSynchronize(s));
+    return m;
+}
+
+int64_t galerkin(Pool &pool, int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
+                 const double *v, int64_t nc, const int32_t *p0, const double *w0,
+                 const int32_t *p1, const double *w1, DArr<int32_t> &crp, DArr<int32_t> &cci,
+                 DArr<double> &cv, hipStream_t s) {
+    // contributions per stored entry, exclusive scan -> generation-order offsets
+    DArr<int64_t> cnt, off;
+    cnt.alloc(pool, nnz + 1);
+    k_gal_count<<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, p0, w0, p1, w1, cnt.p);
+    LAMG_LAUNCH_CHECK();
+    const int64_t m = scan_counts(pool, cnt, nnz, off, s);
+    cnt.release();
+    DArr<uint64_t> key;
+    DArr<double> val;
+    if (m > 0) {
+        key.alloc(pool, m);
+        val.alloc(pool, m);
+        k_gal_expand<<<grid_for(n), kBlock, 0, s>>>(n, nc, rp, ci, v, p0, w0, p1, w1, off.p,
+                                                    key.p, val.p);
+        LAMG_LAUNCH_CHECK();
+    }
+    off.release();
+    return assemble_coarse(pool, m, key, val, nc, crp, cci, cv, s);
+}
+
+int64_t schur(Pool &pool, int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+              const int32_t *cid, int64_t nc, DArr<int32_t> &crp, DArr<int32_t> &cci,
+              DArr<double> &cv, hipStream_t s) {
+    DArr<int64_t> cnt, off;
+    cnt.alloc(pool, 2 * n + 1);
+    k_schur_count<<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, cid, cnt.p);
+    LAMG_LAUNCH_CHECK();
+    const int64_t m = scan_counts(pool, cnt, 2 * n, off, s);
+    cnt.release();
+    DArr<uint64_t> key;
+    DArr<double> val;
+    if (m > 0) {
+        key.alloc(pool, m);
+        val.alloc(pool, m);
+        k_schur_expand<<<grid_for(n), kBlock, 0, s>>>(n, nc, rp, ci, v, cid, off.p, key.p, val.p);
+        LAMG_LAUNCH_CHECK();
+    }
+    off.release();
+    return assemble_coarse(pool, m, key, val, nc, crp, cci, cv, s);
+}
+
+void launch_diag(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, double *d,
+                 hipStream_t s) {
+    k_diag<<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, v, d);
+    LAMG_LAUNCH_CHECK();
 }
 
 void coarsest_inverse(Pool &pool, int64_t n, const int32_t *rp, const int32_t *ci,

@@ -183,6 +183,38 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
     LevelVecs<T> &cv = (*C.v)[l + 1];
     const bool timed = l == 0 && h->timer.on;
     const double sz = sizeof(T);
+    if (L.elim) {
+        // elimination level (eq. (2.1)), cycle index 1: the eliminated rows (colour 0) are
+        // set exactly from the kept ones, the coarse right-hand side is the residual of the
+        // kept rows (colour 1; it equals P^T r since the eliminated rows' residual is then
+        // zero), one coarse visit, the kept rows take the coarse correction, and the
+        // eliminated rows are set exactly again. No smoothing or energy correction: the
+        // interpolation is exact.
+        auto relax_f = [&]() {
+            Timed tm(h, timed ? LAMG_KERNEL_GS_COLOR : -1, prec_id<T>(),
+                     bytes_gs_color(op, 0, k, sz));
+            run_gs_color<T>(op, 0, P::v(op), P::dinv(op), f, x, k, s, l == 0);
+        };
+        relax_f();
+        {
+            Timed tm(h, timed ? LAMG_KERNEL_RESIDUAL : -1, prec_id<T>(),
+                     bytes_gs_color(op, 1, k, sz));
+            run_residual_color<T>(op, 1, P::v(op), P::d(op), x, f, me.r.p, k, s, l == 0);
+        }
+        {
+            Timed tm(h, timed ? LAMG_KERNEL_RESTRICT : -1, prec_id<T>(), bytes_restrict(op, k, sz));
+            run_restrict<T>(op, P::rw(op), me.r.p, cv.f.p, k, s, cv.x.p);
+        }
+        C.visits[l]++;
+        cycle<T>(C, l + 1, cv.x.p, cv.f.p);
+        {
+            Timed tm(h, timed ? LAMG_KERNEL_PROLONG : -1, prec_id<T>(),
+                     4.0 * op.nc + 3.0 * k * op.nc * sz);
+            run_inject_add<T>(op, cv.x.p, x, k, s);
+        }
+        relax_f();
+        return;
+    }
     auto smooth = [&](int sweeps) {
         if (!timed) {
             run_gs<T>(op, P::v(op), P::dinv(op), f, x, k, sweeps, s, l == 0);

@@ -49,7 +49,8 @@ template <class T>
 struct TailLvl {
     int32_t n, ncolors, coarsest, nc;  // nc: rows of the next level
     int32_t n_rlong, maxlen, maxcol, ew;  // maxcol: rows of the largest colour; ew: ELL width
-    int32_t maxrow, pad0;                 // longest off-diagonal row (long ones included)
+    int32_t maxrow;                       // longest off-diagonal row (long ones included)
+    int32_t elim;                         // 1: elimination level (colour 0 = eliminated rows)
     double gamma;
     const int64_t *blk;  // 2*ncolors + 1 offsets (class 0 colours, class 1 colours)
     const int32_t *rp, *ci;
@@ -105,6 +106,7 @@ struct Lv {
     static constexpr bool XL = M != kGlobal;  // iterate
     int n, nc, ncol, nrl, maxlen, maxcol, ew;
     bool split;  // long rows long enough to share them between waves
+    bool elim;   // elimination level
     const int32_t *eci;
     const T *ev;
     const int64_t *blk;
@@ -117,7 +119,7 @@ struct Lv {
     T *x, *f, *r, *rho, *x1, *rho1;
     __device__ Lv(const TailLvl<T> &D, char *s)
         : n(D.n), nc(D.nc), ncol(D.ncolors), nrl(D.n_rlong), maxlen(D.maxlen), maxcol(D.maxcol),
-          ew(D.ew), split(D.maxrow > kSplitRow), eci(D.eci), ev(D.ev),
+          ew(D.ew), split(D.maxrow > kSplitRow), elim(D.elim != 0), eci(D.eci), ev(D.ev),
           blk(at<OL>(s, D.blk)), rp(at<OL>(s, D.rp)), ci(at<OL>(s, D.ci)), v(at<OL>(s, D.v)),
           d(at<OL>(s, D.d)), dinv(at<OL>(s, D.dinv)), p0(at<OL>(s, D.p0)), p1(at<OL>(s, D.p1)),
           w0(at<OL>(s, D.w0)), w1(at<OL>(s, D.w1)), rrp(at<OL>(s, D.rrp)), rci(at<OL>(s, D.rci)),
@@ -367,6 +369,18 @@ __device__ __forceinline__ void smooth(const Lv<T, M> &L, int k, int lkp, int sw
     const int tid = threadIdx.x;
     const int kp = 1 << lkp;
     const int nc = L.ncol;
+    if (L.elim) {
+        // elimination level: its eliminated rows (colour 0, independent, all short) are set
+        // exactly from the kept ones, once, whatever the sweep count
+        csr_rows<T, 0>((int)L.blk[0], (int)L.blk[1], (int)L.blk[nc], (int)L.blk[nc + 1], nullptr,
+                       0, L.rp, L.ci, L.v, L.dinv, L.f, L.x, L.x, k, lkp, lp, L.split);
+        bar();
+        if (resid) {
+            residual<T, M>(L, L.r, k, lkp, lp);
+            bar();
+        }
+        return;
+    }
     const bool fast = L.maxlen > 0 && L.maxlen <= kFast && (L.n << lkp) <= TB;
     constexpr int kGroup = kGather<T>;
     if (fast) {
@@ -593,6 +607,17 @@ __device__ __forceinline__ int visit(const TailArgs &A, const TailLvl<T> &DL, co
     const int j = ((s >> 1) & 255) + 1;
     const int nvis = s >> 9;
     const int c = tid & (kp - 1);
+    if (DL.elim) {
+        // elimination level (one visit): the kept rows take the coarse values (P has weight
+        // 1 there and 0 on the eliminated rows), no recombination or energy correction;
+        // the eliminated rows are then set exactly again
+        if (c < k)
+            for (int i = tid >> lkp; i < L.n; i += TB >> lkp)
+                L.x[i * k + c] += L.w0[i] * C.x[L.p0[i] * k + c];
+        bar();
+        smooth<T, ML>(L, k, lkp, 1, false, lp);
+        return l - 1;
+    }
     // rho = f_c - L_c x_c
     residual<T, MC>(C, C.rho, k, lkp, lp);
     bar();
@@ -753,6 +778,7 @@ void tail_fill_desc(void *host_buf, int l, const Level &L, const SolveOp &op, co
     D.n_rlong = (int32_t)op.n_rlong;
     D.maxlen = op.max_short_len;
     D.maxrow = op.max_len;
+    D.elim = L.elim ? 1 : 0;
     for (int c = 0; c < op.ncolors; ++c)
         D.maxcol = std::max(D.maxcol, (int32_t)(op.blk[c + 1] - op.blk[c]));
     D.gamma = L.gamma;

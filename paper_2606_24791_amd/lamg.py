@@ -34,7 +34,8 @@ class lamg_graph(C.Structure):
 class lamg_options(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("n_direct", C.c_int32), ("enable_veto", C.c_int32),
                 ("enable_caliber2", C.c_int32), ("kappa", C.c_int32), ("build_fp32", C.c_int32),
-                ("keep_setup_data", C.c_int32), ("tail_rows", C.c_int32)]
+                ("keep_setup_data", C.c_int32), ("tail_rows", C.c_int32),
+                ("elimination", C.c_int32)]
 
 
 class lamg_hier_info(C.Structure):
@@ -43,7 +44,7 @@ class lamg_hier_info(C.Structure):
                 ("n_caliber2", C.c_int64 * MAX_LEVELS), ("gamma", C.c_double * MAX_LEVELS),
                 ("tau", C.c_double * MAX_LEVELS), ("bytes_device", C.c_int64),
                 ("op_complexity", C.c_double), ("setup_seconds", C.c_double),
-                ("bytes_peak", C.c_int64)]
+                ("bytes_peak", C.c_int64), ("elim", C.c_int32 * MAX_LEVELS)]
 
 
 class lamg_solve_info(C.Structure):
@@ -275,7 +276,8 @@ def lamg_hierarchy_info(h: Handle) -> dict:
                 ncolors=list(info.ncolors[:L]), n_caliber2=list(info.n_caliber2[:L]),
                 gamma=list(info.gamma[:L]), tau=list(info.tau[:L]),
                 bytes_device=int(info.bytes_device), op_complexity=float(info.op_complexity),
-                setup_seconds=float(info.setup_seconds), bytes_peak=int(info.bytes_peak))
+                setup_seconds=float(info.setup_seconds), bytes_peak=int(info.bytes_peak),
+                elim=[bool(e) for e in info.elim[:L]])
 
 
 def lamg_export_level(h: Handle, level: int) -> dict:
@@ -288,7 +290,9 @@ def lamg_export_level(h: Handle, level: int) -> dict:
     last = level == hi["levels"] - 1
     arrs = dict(row_ptr=np.empty(n + 1, np.int32), col_idx=np.empty(nnz, np.int32),
                 val=np.empty(nnz))
-    if not last:
+    if hi["elim"][level]:
+        arrs["aggregate"] = np.empty(n, np.int32)
+    elif not last:
         arrs.update(color=np.empty(n, np.int32), strong=np.empty(nnz, np.uint8),
                     x=np.empty((n, 4)), affinity=np.empty(nnz), moments=np.empty((n, 9)),
                     seed=np.empty(n, np.int32), aggregate=np.empty(n, np.int32),

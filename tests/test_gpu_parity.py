@@ -69,10 +69,16 @@ def compare_hierarchies(B, h, oh):
         ol = oh.export(l)
         gl = B.lamg_export_level(h, l)
         assert info["n"][l] == ol["n"] and info["nnz"][l] == ol["nnz"]
+        assert info["elim"][l] == ol["elim"], l
         assert_same(f"L{l}.row_ptr", gl["row_ptr"], ol["row_ptr"])
         assert_same(f"L{l}.col_idx", gl["col_idx"], ol["col_idx"])
         assert_same(f"L{l}.val", gl["val"], ol["val"])
         if ol["coarsest"]:
+            continue
+        if ol["elim"]:
+            assert info["ncolors"][l] == 0 and info["n_caliber2"][l] == 0
+            assert info["gamma"][l] == ol["gamma"] == 1.0 and info["tau"][l] == ol["tau"]
+            assert_same(f"L{l}.aggregate", gl["aggregate"], ol["agg"])
             continue
         assert info["ncolors"][l] == ol["ncolors"]
         assert info["gamma"][l] == ol["gamma"] and info["tau"][l] == ol["tau"]
@@ -100,11 +106,11 @@ def test_setup_bit_exact(B, name):
     h.close()
 
 
-def solve_both(B, g, k, precision, seed=11, tol=TOL):
+def solve_both(B, g, k, precision, seed=11, tol=TOL, elimination=False):
     import torch
 
-    oh = O.Hierarchy(g, seed=1)
-    h = B.lamg_setup(g)
+    oh = O.Hierarchy(g, seed=1, elimination=elimination)
+    h = B.lamg_setup(g, B.lamg_default_options(elimination=int(elimination)))
     bh = I.rhs(g.n, k, seed=seed)
     b = torch.tensor(bh, device="cuda")
     phi = torch.empty_like(b)
@@ -293,3 +299,69 @@ def test_in_situ_timing_counts_launches_and_leaves_results_unchanged(B):
         assert sum(t["launches"] for t in kt.values()) == 16
         assert torch.equal(phi, ref)
     h.close()
+
+
+# --- low-degree elimination levels (Sec. 2, eq. (2.1)) ----------------------------------
+
+def star(nleaves):
+    """Hub 0 joined to nleaves leaves: every leaf is eliminated, one node is kept."""
+    n = nleaves + 1
+    rp = np.concatenate([[0, nleaves], nleaves + np.arange(1, nleaves + 1)]).astype(np.int32)
+    ci = np.concatenate([np.arange(1, n), np.zeros(nleaves)]).astype(np.int32)
+    w = np.concatenate([np.linspace(1.0, 2.0, nleaves)] * 2)
+    return I.Graph(n, rp, ci, w, name=f"star{nleaves}")
+
+
+ELIM_GRAPHS = {
+    "grid64": lambda: I.grid2d(64, 64),
+    "aniso_ragged": lambda: I.grid2d(257, 131, 1.0, 1e-3),
+    "chunglu": lambda: I.chung_lu(30000, 2.1, 16, seed=5),
+    "treelike": lambda: I.random_connected(8000, 2500, seed=8),
+    "star": lambda: star(700),
+}
+
+
+@pytest.mark.parametrize("name", list(ELIM_GRAPHS))
+def test_setup_bit_exact_elimination(B, name):
+    g = ELIM_GRAPHS[name]()
+    note(f"elimination setup parity {name} n={g.n} nnz={g.nnz}")
+    oh = O.Hierarchy(g, seed=1, elimination=True)
+    assert any(oh.level_info(l)["elim"] for l in range(oh.nlevels))
+    h = B.lamg_setup(g, B.lamg_default_options(keep_setup_data=1, elimination=1))
+    compare_hierarchies(B, h, oh)
+    h.close()
+
+
+@pytest.mark.parametrize("name", list(ELIM_GRAPHS))
+@pytest.mark.parametrize("prec", ["fp64", "fp32ir"])
+def test_solve_parity_elimination(B, name, prec):
+    g = ELIM_GRAPHS[name]()
+    k = 3 if name == "grid64" else 1
+    note(f"elimination solve parity {name} {prec} k={k}")
+    p = B.FP64 if prec == "fp64" else B.FP32_IR
+    st, ph, bh, refs = solve_both(B, g, k, p, elimination=True)
+    check_solution(g, st, ph, bh, refs)
+
+
+@pytest.mark.parametrize("name", ["chunglu", "treelike"])
+@pytest.mark.parametrize("tail_rows", [0, 2500])
+def test_elimination_execution_modes_agree(B, name, tail_rows):
+    """Per-step kernels and the coarse-tail kernel (which runs elimination levels too: the
+    tree-like graph has one at level 2) compute the same cycle."""
+    import torch
+
+    g = ELIM_GRAPHS[name]()
+    note(f"elimination {name} tail_rows={tail_rows}")
+    bh = I.rhs(g.n, 2, seed=4)
+    out = []
+    for tr in (tail_rows, 100000):
+        h = B.lamg_setup(g, B.lamg_default_options(elimination=1, tail_rows=tr))
+        b = torch.tensor(bh, device="cuda")
+        phi = torch.empty_like(b)
+        st = B.lamg_solve(h, b, phi, precision=B.FP32_IR)
+        assert st["converged"]
+        out.append(phi.cpu().numpy())
+        h.close()
+    for c in range(2):
+        err = np.linalg.norm(out[0][c] - out[1][c]) / np.linalg.norm(out[1][c])
+        assert err <= 1e-6, err
