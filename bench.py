@@ -8,10 +8,13 @@ from a zero start, hierarchy resident on the device and b already in HBM.
 
 Default workload: the 1024 x 1024 grid-aligned anisotropic 5-point Laplacian (x-weight 1,
 y-weight 1e-3; n = 1,048,576, nnz(L) = 2m + n = 5,238,784), b ~ N(0,1) (mean removed by
-the solver), one right-hand side.
+the solver), one right-hand side. Default hierarchy: low-degree elimination levels
+alternating with aggregation (--no-elimination: aggregation only).
 
 The JSON line also carries
-  roofline: the finest-level FP32 Gauss-Seidel colour pass (the dominant bandwidth kernel):
+  roofline: the FP32 Gauss-Seidel colour pass of the finest aggregation level (the largest
+            full smoothing pass, the dominant bandwidth kernel; the finest level itself is an
+            elimination level on the grids):
             its algorithmic bytes per launch over its mean launch time, both summed over
             every launch in the timed FP32+IR region (HIP events around each launch on the
             solve stream), against 8 TB/s HBM;
@@ -42,7 +45,7 @@ WORKLOADS = {
 
 
 def kernel_source_hash() -> str:
-    """Hash of the sources the finest-level cycle kernels are built from."""
+    """Hash of the sources the cycle kernels are built from."""
     import hashlib
 
     h = hashlib.sha256()
@@ -52,17 +55,19 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, k: int):
-    """HBM bytes per launch of the finest FP32 Gauss-Seidel colour pass from the committed
+def measured_traffic(workload: str, k: int, elimination: bool):
+    """HBM bytes per launch of the timed FP32 Gauss-Seidel colour pass from the committed
     rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on a copy kernel), or None
-    when it does not cover this workload or the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "traffic_gs_color_finest.json")
+    when it does not cover this workload and hierarchy or the kernel sources changed since
+    it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_gs_color.json")
     try:
         with open(path) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
     if t.get("workload") != workload or t.get("nrhs") != k or \
+            bool(t.get("elimination")) != elimination or \
             t.get("source_hash") != kernel_source_hash():
         return None
     return t.get("bytes_per_launch")
@@ -88,10 +93,11 @@ def main() -> int:
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the timed region, one device copy of this many MB (calibrates "
                          "the HBM byte counters of a profiler run)")
-    ap.add_argument("--elimination", action="store_true",
-                    help="low-degree elimination levels before each aggregation step")
+    ap.add_argument("--no-elimination", action="store_true",
+                    help="aggregation-only hierarchy (no low-degree elimination levels)")
     ap.add_argument("--profile-reps", type=int, default=0,
-                    help="also time the finest GS colour pass in isolation (back-to-back launches)")
+                    help="also time the timed level's GS colour pass in isolation (back-to-back "
+                         "launches)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the solver has no multi-GPU path); got --gpus "
@@ -113,13 +119,16 @@ def main() -> int:
     g = I.workload(args.workload)
     log(f"graph {args.workload}: n={g.n} nnz(L)={g.nnz_laplacian} ({time.perf_counter() - t:.1f}s)")
     over = {"n_direct": args.n_direct} if args.n_direct else {}
-    if args.elimination:
-        over["elimination"] = 1
+    if args.no_elimination:
+        over["elimination"] = 0
     opts = B.lamg_default_options(**over)
     h = B.lamg_setup(g, opts)
     torch.cuda.synchronize()
     hi = B.lamg_hierarchy_info(h)
-    log(f"setup {hi['setup_seconds']:.2f}s levels={hi['levels']} n={hi['n']}")
+    lt = hi["timed_level"]
+    log(f"setup {hi['setup_seconds']:.2f}s levels={hi['levels']} n={hi['n']} "
+        f"elimination levels={[l for l, e in enumerate(hi['elim']) if e]} "
+        f"tail from level {hi['tail_level']}, timed level {lt}")
     k = args.nrhs
     bh = I.rhs(g.n, k, seed=0)
     b = torch.tensor(bh, device=dev)
@@ -127,7 +136,7 @@ def main() -> int:
 
     def run_steps(prec, phi, timed):
         """K solves between synchronisations; with `timed`, the library brackets every launch
-        of the finest-level kernels and of the coarse tail with HIP events on `stream`."""
+        of the timed level's kernels and of the coarse tail with HIP events on `stream`."""
         torch.cuda.synchronize()
         if timed:
             B.lamg_timing_start(h, 65536)
@@ -175,7 +184,7 @@ def main() -> int:
     sec = gs["seconds"] / gs["launches"]
     byt = gs["bytes"] / gs["launches"]
     achieved = byt / sec / 1e9
-    log(f"gs colour pass (finest, fp32, in situ): {gs['launches']} launches, {sec * 1e6:.2f} us, "
+    log(f"gs colour pass (level {lt}, fp32, in situ): {gs['launches']} launches, {sec * 1e6:.2f} us, "
         f"{byt / 1e6:.2f} MB -> {achieved:.0f} GB/s")
     other = {"residual": kstat(B.KERNEL_RESIDUAL, B.FP32_IR),
              "restrict": kstat(B.KERNEL_RESTRICT, B.FP32_IR),
@@ -186,7 +195,7 @@ def main() -> int:
     log(f"coarse tail (fp32, in situ): {tail}")
     isolated = None
     if args.profile_reps > 0:
-        s2, b2 = B.lamg_profile_kernel(h, 0, B.KERNEL_GS_COLOR, B.FP32_IR, k, args.profile_reps,
+        s2, b2 = B.lamg_profile_kernel(h, lt, B.KERNEL_GS_COLOR, B.FP32_IR, k, args.profile_reps,
                                        stream=stream)
         isolated = dict(us_per_launch=s2 * 1e6, GBs=b2 / s2 / 1e9, reps=args.profile_reps)
 
@@ -222,7 +231,7 @@ def main() -> int:
         log(f"oracle: setup {t_setup:.2f}s solve {t_solve:.2f}s cycles {so['cycles']}; "
             f"err fp32ir {errs.get('fp32ir'):.2e} fp64 {errs.get('fp64'):.2e}")
 
-    traffic = measured_traffic(args.workload, k) if not args.elimination else None
+    traffic = measured_traffic(args.workload, k, bool(opts.elimination))
     r = results["fp32ir"]
     line = {
         "metric": "nnz*RHS solved/s to 1e-8 rel resid (FP32 cycles + FP64 refinement)",
@@ -243,7 +252,8 @@ def main() -> int:
             "n": g.n, "nnz_L": g.nnz_laplacian, "nnz_2m": g.nnz, "nrhs": k,
             "levels": hi["levels"], "op_complexity": round(hi["op_complexity"], 3),
             "setup_s": round(hi["setup_seconds"], 3),
-            "elimination_levels": sum(hi["elim"]),
+            "elimination": bool(opts.elimination), "elimination_levels": sum(hi["elim"]),
+            "tail_level": hi["tail_level"],
         },
         "latency_ms": {"p50": r["p50_ms"], "p99": r["p99_ms"]},
         "cycles": r["cycles"],
@@ -253,13 +263,15 @@ def main() -> int:
                  "p50_ms": results["fp64"]["p50_ms"], "p99_ms": results["fp64"]["p99_ms"],
                  "cycles": results["fp64"]["cycles"], "relres": results["fp64"]["relres"],
                  "err_vs_oracle": errs.get("fp64")},
-        "roofline": {"bound": "hbm", "kernel": "k_csr<float, GS, finest> (one colour pass)",
+        "roofline": {"bound": "hbm",
+                     "kernel": f"k_csr<float, GS> one colour pass of level {lt} (n={hi['n'][lt]}"
+                               f"{', elimination level: its eliminated rows' if hi['elim'][lt] else ''})",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": byt, "us_per_launch": sec * 1e6,
                      "launches": gs["launches"], "timing": "HIP events attached to every launch "
                      "(dispatch timestamps) in the timed FP32+IR region, on the solve stream"},
-        "kernels_finest": other,
+        "kernels_timed_level": dict(other, level=lt),
         "coarse_tail": dict(tail or {}, bound="latency (dependent steps of one workgroup)",
                             kernel="k_tail<float>"),
         "events_overhead": {"fp32ir_ms_no_events": r32["ms_no_events"],

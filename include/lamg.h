@@ -91,7 +91,7 @@ typedef struct {
                                 kernel). Changes only how the cycle is executed, not what it
                                 computes. */
     int32_t elimination;     /* low-degree elimination levels (Sec. 2, "Low-degree elimination",
-                                eq. (2.1)); default 0. When 1, before each aggregation step a
+                                eq. (2.1)); default 1 (0: aggregation only). Before each aggregation step a
                                 maximal independent set F of the nodes with at most 4
                                 neighbours (greedy in natural order) is eliminated exactly --
                                 coarse operator = Schur complement onto the other nodes, F rows
@@ -117,6 +117,11 @@ typedef struct {
                                             (setup temporaries included) */
     int32_t elim[LAMG_MAX_LEVELS];       /* 1: elimination level (its aggregate export holds the
                                             coarse id of each kept node and -1 on F) */
+    int32_t tail_level;                  /* first level whose cycle runs in the coarse-tail
+                                            kernel (-1: none) */
+    int32_t timed_level;                 /* level whose per-step kernels the in-situ timer
+                                            records (the finest aggregation level unless that
+                                            one runs in the coarse tail; then 0) */
 } lamg_hier_info;
 
 /* Solve statistics. The caller may point the array fields at host arrays (or leave them
@@ -233,10 +238,11 @@ lamg_status lamg_profile_kernel(lamg_handle *h, int32_t level, lamg_kernel kerne
                                 void *stream);
 
 /* In-situ kernel timing (measurement aid). Between lamg_timing_start and lamg_timing_stop,
- * every lamg_solve on the handle attaches a pair of HIP events to each launch of the finest
- * level's cycle kernels (every Gauss-Seidel colour pass, residual, restriction,
- * prolongation, in the precision they run in; the FP64 outer residual of an FP32+IR solve
- * counts as an FP64 residual) and of the coarse-tail kernel, on the solve's stream. The
+ * every lamg_solve on the handle attaches a pair of HIP events to each launch of the cycle
+ * kernels of level timed_level (lamg_hier_info; every Gauss-Seidel colour pass, residual,
+ * restriction, prolongation, in the precision they run in; the FP64 outer residual of an
+ * FP32+IR solve, on the finest level, counts as an FP64 residual) and of the coarse-tail
+ * kernel, on the solve's stream. The
  * events take the dispatch's own start and end times (hipExtLaunchKernel), so a pair spans
  * the kernel's execution alone; they add no synchronisation and no stream markers. Timing
  * stops recording after `max_launches` launches (the events are created by

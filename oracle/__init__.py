@@ -248,7 +248,7 @@ class Hierarchy:
     """The oracle's LAMG+ hierarchy for one graph."""
 
     def __init__(self, g, seed: int = 1, n_direct: int = 512, enable_veto: bool = True,
-                 enable_caliber2: bool = True, kappa: int = 4, elimination: bool = False):
+                 enable_caliber2: bool = True, kappa: int = 4, elimination: bool = True):
         h = C.c_void_p()
         rc = lib().orc_setup(g.n, g.row_ptr, g.col_idx, np.ascontiguousarray(g.weight, np.float64),
                              seed, n_direct, int(enable_veto), int(enable_caliber2), kappa,

@@ -13,6 +13,8 @@ lamg_status run_solve(lamg_handle *h, const double *b, int nrhs, double tol, int
                       lamg_precision prec, double *phi, lamg_solve_info *info);
 lamg_status run_profile(lamg_handle *h, int level, int kernel, lamg_precision prec, int k,
                         int reps, double *sec, double *bytes);
+int plan_tail_level(const lamg_handle *h);
+int plan_timed_level(const lamg_handle *h);
 
 static std::mutex g_alloc_mu;
 static Allocator g_alloc;
@@ -131,7 +133,7 @@ void lamg_default_options(lamg_options *opt) {
     opt->build_fp32 = 1;
     opt->keep_setup_data = 0;
     opt->tail_rows = 2500;
-    opt->elimination = 0;
+    opt->elimination = 1;
 }
 
 lamg_status lamg_setup(const lamg_graph *g, const lamg_options *opt, void *stream,
@@ -247,6 +249,8 @@ lamg_status lamg_hierarchy_info(const lamg_handle *h, lamg_hier_info *info) {
     info->op_complexity = tot / nnz0;
     info->setup_seconds = h->setup_seconds;
     info->bytes_peak = h->pool->peak();
+    info->tail_level = plan_tail_level(h);
+    info->timed_level = plan_timed_level(h);
     return LAMG_OK;
 }
 

@@ -118,6 +118,7 @@ struct Cycle {
     std::vector<int64_t> visits;  // entries into each level's coarse-correction phase
     double *partial;
     int l0;                 // first level run by the coarse-tail kernel (-1: none)
+    int lt;                 // level whose per-step kernels the in-situ timer records
     const TailPlan *plan;   // its descriptors and LDS layout
     int64_t *d_visits;      // its visit counters
 };
@@ -156,6 +157,19 @@ int tail_level(const lamg_handle *h) {
     return l0;
 }
 
+// Level whose per-step cycle kernels the in-situ timer records and whose kernels carry the
+// separate "finest" symbols: the finest aggregation level (elimination levels run no full
+// smoothing pass), or the finest level when that aggregation level runs in the coarse tail.
+int timed_level(const lamg_handle *h) {
+    const int l0 = tail_level(h);
+    for (int l = 0; l < h->nlev; ++l) {
+        const Level &L = h->lev[l];
+        if (L.coarsest) break;
+        if (!L.elim) return (l0 < 0 || l < l0) ? l : 0;
+    }
+    return 0;
+}
+
 // One gamma-cycle at level l on (x, f): (1,2) multicolour Gauss-Seidel, coarse
 // correction by `nvis` visits to level l+1 (Beatty counts of the fractional cycle index)
 // with two-iterate recombination across the visits, energy correction
@@ -181,7 +195,7 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
     const SolveOp &cop = Lc.op;
     LevelVecs<T> &me = (*C.v)[l];
     LevelVecs<T> &cv = (*C.v)[l + 1];
-    const bool timed = l == 0 && h->timer.on;
+    const bool timed = l == C.lt && h->timer.on;
     const double sz = sizeof(T);
     if (L.elim) {
         // elimination level (eq. (2.1)), cycle index 1: the eliminated rows (colour 0) are
@@ -193,13 +207,13 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
         auto relax_f = [&]() {
             Timed tm(h, timed ? LAMG_KERNEL_GS_COLOR : -1, prec_id<T>(),
                      bytes_gs_color(op, 0, k, sz));
-            run_gs_color<T>(op, 0, P::v(op), P::dinv(op), f, x, k, s, l == 0);
+            run_gs_color<T>(op, 0, P::v(op), P::dinv(op), f, x, k, s, l == C.lt);
         };
         relax_f();
         {
             Timed tm(h, timed ? LAMG_KERNEL_RESIDUAL : -1, prec_id<T>(),
                      bytes_gs_color(op, 1, k, sz));
-            run_residual_color<T>(op, 1, P::v(op), P::d(op), x, f, me.r.p, k, s, l == 0);
+            run_residual_color<T>(op, 1, P::v(op), P::d(op), x, f, me.r.p, k, s, l == C.lt);
         }
         {
             Timed tm(h, timed ? LAMG_KERNEL_RESTRICT : -1, prec_id<T>(), bytes_restrict(op, k, sz));
@@ -217,7 +231,7 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
     }
     auto smooth = [&](int sweeps) {
         if (!timed) {
-            run_gs<T>(op, P::v(op), P::dinv(op), f, x, k, sweeps, s, l == 0);
+            run_gs<T>(op, P::v(op), P::dinv(op), f, x, k, sweeps, s, l == C.lt);
             return;
         }
         for (int sw = 0; sw < sweeps; ++sw)
@@ -229,7 +243,7 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
     smooth(1);
     {
         Timed tm(h, timed ? LAMG_KERNEL_RESIDUAL : -1, prec_id<T>(), bytes_residual(op, k, sz));
-        run_residual<T>(op, P::v(op), P::d(op), x, f, me.r.p, k, s, l == 0);
+        run_residual<T>(op, P::v(op), P::d(op), x, f, me.r.p, k, s, l == C.lt);
     }
     {  // f_c = P^T r, and the coarse iterate starts from zero (same launch)
         Timed tm(h, timed ? LAMG_KERNEL_RESTRICT : -1, prec_id<T>(), bytes_restrict(op, k, sz));
@@ -423,9 +437,10 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
     }
 
     const int l0 = tail_level(h);
-    Cycle<double> c64{h, k, s, &w.lv64, std::vector<int64_t>(h->nlev, 0), w.partial.p, l0,
+    const int lt = timed_level(h);
+    Cycle<double> c64{h, k, s, &w.lv64, std::vector<int64_t>(h->nlev, 0), w.partial.p, l0, lt,
                       &w.plan64, w.visits.p};
-    Cycle<float> c32{h, k, s, &w.lv32, std::vector<int64_t>(h->nlev, 0), w.partial.p, l0,
+    Cycle<float> c32{h, k, s, &w.lv32, std::vector<int64_t>(h->nlev, 0), w.partial.p, l0, lt,
                      &w.plan32, w.visits.p};
     int cyc = 0;
     while (n_active > 0 && cyc < max_cycles) {
@@ -515,7 +530,7 @@ void profile_impl(lamg_handle *h, int level, int kernel, int k, int reps, double
     ensure_level_vecs<T>(h, k);
     Level &L = h->lev[level];
     const SolveOp &op = L.op;
-    const bool fine = level == 0;
+    const bool fine = level == timed_level(h);
     const int64_t n = L.n;
     LevelVecs<T> &me = lv[level];
     run_fill<T>(me.x.p, n * k, T(1), s);
@@ -666,5 +681,8 @@ lamg_status run_solve(lamg_handle *h, const double *b, int nrhs, double tol, int
     }
     return st;
 }
+
+int plan_tail_level(const lamg_handle *h) { return tail_level(h); }
+int plan_timed_level(const lamg_handle *h) { return timed_level(h); }
 
 }  // namespace lamg

@@ -44,7 +44,8 @@ class lamg_hier_info(C.Structure):
                 ("n_caliber2", C.c_int64 * MAX_LEVELS), ("gamma", C.c_double * MAX_LEVELS),
                 ("tau", C.c_double * MAX_LEVELS), ("bytes_device", C.c_int64),
                 ("op_complexity", C.c_double), ("setup_seconds", C.c_double),
-                ("bytes_peak", C.c_int64), ("elim", C.c_int32 * MAX_LEVELS)]
+                ("bytes_peak", C.c_int64), ("elim", C.c_int32 * MAX_LEVELS),
+                ("tail_level", C.c_int32), ("timed_level", C.c_int32)]
 
 
 class lamg_solve_info(C.Structure):
@@ -277,7 +278,8 @@ def lamg_hierarchy_info(h: Handle) -> dict:
                 gamma=list(info.gamma[:L]), tau=list(info.tau[:L]),
                 bytes_device=int(info.bytes_device), op_complexity=float(info.op_complexity),
                 setup_seconds=float(info.setup_seconds), bytes_peak=int(info.bytes_peak),
-                elim=[bool(e) for e in info.elim[:L]])
+                elim=[bool(e) for e in info.elim[:L]], tail_level=int(info.tail_level),
+                timed_level=int(info.timed_level))
 
 
 def lamg_export_level(h: Handle, level: int) -> dict:

@@ -81,6 +81,9 @@ def test_lognormal128_full_parity(B):
             same(f"L{l}.{key_g}", gl[key_g], ol[key_o])
         if ol["coarsest"]:
             continue
+        if ol["elim"]:
+            same(f"L{l}.aggregate", gl["aggregate"], ol["agg"])
+            continue
         for key_g, key_o in (("color", "color"), ("strong", "strong"), ("x", "X"),
                              ("affinity", "affinity"), ("moments", "moments"),
                              ("aggregate", "agg"), ("p0", "p0"), ("p1", "p1"), ("w0", "w0"),
@@ -107,11 +110,26 @@ def test_chunglu2m_finest_levels_and_solve_properties(B):
     import torch
 
     g = I.workload("chunglu2m")
-    note(f"chunglu2m n={g.n} nnz={g.nnz}: GPU setup")
+    note(f"chunglu2m n={g.n} nnz={g.nnz}: GPU setup, elimination at the finest level")
     h = B.lamg_setup(g, B.lamg_default_options(keep_setup_data=1))
+    assert B.lamg_hierarchy_info(h)["elim"][0]
+    g0 = B.lamg_export_level(h, 0)
+    rp, ci, v = O.laplacian(g)
+    same("L0.row_ptr", g0["row_ptr"], rp)
+    same("L0.val", g0["val"], v)
+    note("oracle elimination set and Schur complement")
+    cid, nce = O.elim_select(rp, ci, v)
+    same("L0.elimination ids", g0["aggregate"], cid)
+    Srp, Sci, Sv = O.schur(rp, ci, v, cid, nce)
+    g1 = B.lamg_export_level(h, 1)
+    same("L1.row_ptr", g1["row_ptr"], Srp)
+    same("L1.col_idx", g1["col_idx"], Sci)
+    same("L1.val", g1["val"], Sv)
+    h.close()
+    note("aggregation-only hierarchy: GPU setup")
+    h = B.lamg_setup(g, B.lamg_default_options(keep_setup_data=1, elimination=0))
     g0 = B.lamg_export_level(h, 0)
     note("oracle steps on level 0")
-    rp, ci, v = O.laplacian(g)
     same("L0.row_ptr", g0["row_ptr"], rp)
     same("L0.col_idx", g0["col_idx"], ci)
     same("L0.val", g0["val"], v)

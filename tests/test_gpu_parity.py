@@ -97,16 +97,19 @@ def compare_hierarchies(B, h, oh):
 
 
 @pytest.mark.parametrize("name", list(GRAPHS))
-def test_setup_bit_exact(B, name):
+@pytest.mark.parametrize("elimination", [1, 0])
+def test_setup_bit_exact(B, name, elimination):
+    """Default hierarchy (elimination levels where they remove a tenth of the nodes) and
+    the aggregation-only one."""
     g = GRAPHS[name]()
-    note(f"setup parity {name} n={g.n} nnz={g.nnz}")
-    oh = O.Hierarchy(g, seed=1)
-    h = B.lamg_setup(g, B.lamg_default_options(keep_setup_data=1))
+    note(f"setup parity {name} elimination={elimination} n={g.n} nnz={g.nnz}")
+    oh = O.Hierarchy(g, seed=1, elimination=bool(elimination))
+    h = B.lamg_setup(g, B.lamg_default_options(keep_setup_data=1, elimination=elimination))
     compare_hierarchies(B, h, oh)
     h.close()
 
 
-def solve_both(B, g, k, precision, seed=11, tol=TOL, elimination=False):
+def solve_both(B, g, k, precision, seed=11, tol=TOL, elimination=True):
     import torch
 
     oh = O.Hierarchy(g, seed=1, elimination=elimination)
@@ -145,6 +148,16 @@ def test_solve_parity(B, name, prec):
     g = GRAPHS[name]()
     note(f"solve parity {name} {prec} n={g.n}")
     st, ph, bh, refs = solve_both(B, g, 1, B.FP64 if prec == "fp64" else B.FP32_IR)
+    check_solution(g, st, ph, bh, refs)
+
+
+@pytest.mark.parametrize("name", ["grid64", "aniso_ragged", "chunglu"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32ir"])
+def test_solve_parity_aggregation_only(B, name, prec):
+    g = GRAPHS[name]()
+    note(f"solve parity (aggregation only) {name} {prec} n={g.n}")
+    st, ph, bh, refs = solve_both(B, g, 1, B.FP64 if prec == "fp64" else B.FP32_IR,
+                                  elimination=False)
     check_solution(g, st, ph, bh, refs)
 
 
@@ -257,14 +270,18 @@ def test_cycle_execution_modes_agree(B, tail_rows):
 
 def test_in_situ_timing_counts_launches_and_leaves_results_unchanged(B):
     """The event timer brackets launches only: a timed solve returns the untimed solve's
-    bits; every finest-level kernel and the coarse tail are counted, with positive
-    durations and the algorithmic bytes of their rows; after stop, solves are untimed."""
+    bits; every kernel of the timed level (the finest aggregation level: the finest level
+    of this grid is an elimination level, visited once per cycle) and the coarse tail are
+    counted, with positive durations and the algorithmic bytes of their rows; after stop,
+    solves are untimed."""
     import torch
 
     g = GRAPHS["aniso_ragged"]()
     note("in-situ timing")
     h = B.lamg_setup(g)
     info = B.lamg_hierarchy_info(h)
+    lt = info["timed_level"]
+    assert info["elim"][0] and lt == 1 and 1 < info["tail_level"]
     b = torch.tensor(I.rhs(g.n, 2, seed=5), device="cuda")
     for prec in (B.FP32_IR, B.FP64):
         ref = torch.empty_like(b)
@@ -275,7 +292,7 @@ def test_in_situ_timing_counts_launches_and_leaves_results_unchanged(B):
         kt = B.lamg_timing_stop(h)
         assert torch.equal(phi, ref) and st["cycles"] == st0["cycles"]
         cyc = st["cycles"]
-        ncol = info["ncolors"][0]
+        ncol = info["ncolors"][lt]
         gs = kt[(B.KERNEL_GS_COLOR, prec)]
         assert gs["launches"] == 3 * ncol * cyc and gs["seconds"] > 0 and gs["bytes"] > 0
         for kern in (B.KERNEL_RESTRICT, B.KERNEL_PROLONG):
@@ -289,7 +306,7 @@ def test_in_situ_timing_counts_launches_and_leaves_results_unchanged(B):
         assert kt[(B.KERNEL_TAIL, prec)]["launches"] >= cyc
         assert kt[(B.KERNEL_TAIL, prec)]["bytes"] == 0.0
         # bytes per GS launch: whole-level sum over colours equals one residual's matrix part
-        n, e = info["n"][0], info["nnz"][0] - info["n"][0]
+        n, e = info["n"][lt], info["nnz"][lt] - info["n"][lt]
         s = 4 if prec == B.FP32_IR else 8
         per_sweep = gs["bytes"] / (3 * cyc)
         assert per_sweep == pytest.approx(e * (4 + s) + 4 * (n + ncol) + n * s + 3 * 2 * n * s)
@@ -312,10 +329,10 @@ def star(nleaves):
     return I.Graph(n, rp, ci, w, name=f"star{nleaves}")
 
 
+# graphs whose hierarchies have elimination levels below the finest, or a single kept node
+# (the default-option tests above cover elimination at the finest level of the grids and
+# the Chung-Lu graph)
 ELIM_GRAPHS = {
-    "grid64": lambda: I.grid2d(64, 64),
-    "aniso_ragged": lambda: I.grid2d(257, 131, 1.0, 1e-3),
-    "chunglu": lambda: I.chung_lu(30000, 2.1, 16, seed=5),
     "treelike": lambda: I.random_connected(8000, 2500, seed=8),
     "star": lambda: star(700),
 }
@@ -336,7 +353,7 @@ def test_setup_bit_exact_elimination(B, name):
 @pytest.mark.parametrize("prec", ["fp64", "fp32ir"])
 def test_solve_parity_elimination(B, name, prec):
     g = ELIM_GRAPHS[name]()
-    k = 3 if name == "grid64" else 1
+    k = 3 if name == "treelike" else 1
     note(f"elimination solve parity {name} {prec} k={k}")
     p = B.FP64 if prec == "fp64" else B.FP32_IR
     st, ph, bh, refs = solve_both(B, g, k, p, elimination=True)
@@ -350,7 +367,7 @@ def test_elimination_execution_modes_agree(B, name, tail_rows):
     tree-like graph has one at level 2) compute the same cycle."""
     import torch
 
-    g = ELIM_GRAPHS[name]()
+    g = ELIM_GRAPHS[name]() if name in ELIM_GRAPHS else GRAPHS[name]()
     note(f"elimination {name} tail_rows={tail_rows}")
     bh = I.rhs(g.n, 2, seed=4)
     out = []

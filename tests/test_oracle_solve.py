@@ -32,15 +32,16 @@ def test_direct_level_equals_pseudoinverse():
     assert st["cycles"] == 1
 
 
+@pytest.mark.parametrize("elimination", [True, False])
 @pytest.mark.parametrize("gen", [
     lambda: I.random_connected(1500, 5000, seed=3),
     lambda: I.grid2d(40, 36, 1.0, 1e-3),
     lambda: I.grid3d(12, 11, 10, "lognormal", seed=4),
     lambda: I.chung_lu(2000, 2.1, 16, seed=5),
 ])
-def test_solve_reaches_tolerance_and_pinv(gen):
+def test_solve_reaches_tolerance_and_pinv(gen, elimination):
     g = gen()
-    h = O.Hierarchy(g)
+    h = O.Hierarchy(g, elimination=elimination)
     assert h.nlevels >= 2
     b = I.rhs(g.n, 1, seed=6)[0]
     phi, st, hist = h.solve(b, 1e-8, 100)
@@ -59,7 +60,7 @@ def test_energy_correction_is_one_under_exact_coarse_solve():
     """Two levels with an exactly solved coarse level: the energy-optimal multiple of
     the coarse correction is 1 (the Galerkin correction is already L-optimal)."""
     g = I.grid2d(30, 20)
-    h = O.Hierarchy(g, n_direct=400)
+    h = O.Hierarchy(g, n_direct=400, elimination=False)
     assert h.nlevels == 2 and h.level_info(1)["coarsest"]
     rng = np.random.default_rng(0)
     f = rng.standard_normal(g.n)
@@ -72,7 +73,7 @@ def test_energy_correction_never_increases_energy_error():
     """A cycle's error in the L-norm never grows (smoothing and the energy-optimal
     coarse step are each L-norm non-expansive)."""
     g = I.grid2d(48, 40, 1.0, 1e-2)
-    h = O.Hierarchy(g)
+    h = O.Hierarchy(g, elimination=False)
     L = dense_L(g)
     rng = np.random.default_rng(1)
     b = rng.standard_normal(g.n)
@@ -126,7 +127,7 @@ def test_soft_target_anisotropic_grids():
     this multicolour, aggregation-only reading must stay below 0.4 (caliber-1 ML level)."""
     for eps in (1e-1, 1e-2, 1e-4):
         g = I.grid2d(64, 64, 1.0, eps)
-        h = O.Hierarchy(g)
+        h = O.Hierarchy(g, elimination=False)
         _, st, _ = h.solve(I.rhs(g.n, 1, 0)[0], 1e-8, 60)
         assert st["converged"] and st["acf"] < 0.4, (eps, st)
 
@@ -134,6 +135,6 @@ def test_soft_target_anisotropic_grids():
 def test_soft_target_caliber2_beats_caliber1_on_anisotropy():
     g = I.grid2d(64, 64, 1.0, 1e-4)
     b = I.rhs(g.n, 1, 0)[0]
-    _, on, _ = O.Hierarchy(g).solve(b, 1e-8, 100)
-    _, off, _ = O.Hierarchy(g, enable_caliber2=False).solve(b, 1e-8, 100)
+    _, on, _ = O.Hierarchy(g, elimination=False).solve(b, 1e-8, 100)
+    _, off, _ = O.Hierarchy(g, enable_caliber2=False, elimination=False).solve(b, 1e-8, 100)
     assert on["cycles"] < off["cycles"]
