@@ -93,6 +93,8 @@ def main() -> int:
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the timed region, one device copy of this many MB (calibrates "
                          "the HBM byte counters of a profiler run)")
+    ap.add_argument("--tail-rows", type=int, default=-1,
+                    help="coarse-tail threshold option (-1: library default)")
     ap.add_argument("--no-elimination", action="store_true",
                     help="aggregation-only hierarchy (no low-degree elimination levels)")
     ap.add_argument("--profile-reps", type=int, default=0,
@@ -121,6 +123,8 @@ def main() -> int:
     over = {"n_direct": args.n_direct} if args.n_direct else {}
     if args.no_elimination:
         over["elimination"] = 0
+    if args.tail_rows >= 0:
+        over["tail_rows"] = args.tail_rows
     opts = B.lamg_default_options(**over)
     h = B.lamg_setup(g, opts)
     torch.cuda.synchronize()

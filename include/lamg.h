@@ -88,8 +88,9 @@ typedef struct {
                                 with the levels right above them (below 65536 nodes) whose many
                                 colours of few rows make one workgroup clearly cheaper than
                                 separate kernels (default 2500; 0 = every step is its own
-                                kernel). Changes only how the cycle is executed, not what it
-                                computes. */
+                                kernel). Applies to solves of at most 2 columns (wider
+                                solves run every step as its own kernel). Changes only how
+                                the cycle is executed, not what it computes. */
     int32_t elimination;     /* low-degree elimination levels (Sec. 2, "Low-degree elimination",
                                 eq. (2.1)); default 1 (0: aggregation only). Before each aggregation step a
                                 maximal independent set F of the nodes with at most 4
@@ -118,10 +119,11 @@ typedef struct {
     int32_t elim[LAMG_MAX_LEVELS];       /* 1: elimination level (its aggregate export holds the
                                             coarse id of each kept node and -1 on F) */
     int32_t tail_level;                  /* first level whose cycle runs in the coarse-tail
-                                            kernel (-1: none) */
+                                            kernel in a 1-column solve (-1: none) */
     int32_t timed_level;                 /* level whose per-step kernels the in-situ timer
-                                            records (the finest aggregation level unless that
-                                            one runs in the coarse tail; then 0) */
+                                            records in a 1-column solve (the finest
+                                            aggregation level unless that one runs in the
+                                            coarse tail; then 0) */
 } lamg_hier_info;
 
 /* Solve statistics. The caller may point the array fields at host arrays (or leave them

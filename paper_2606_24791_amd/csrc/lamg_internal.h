@@ -29,6 +29,7 @@ constexpr int kRedBlocksMax = 256;  // partial-sum blocks of a reduction
 constexpr int kRedQMax = 14;        // quantities per reduction (4x4 normal equations + rhs)
 constexpr int kTVShortRow = 64;     // test-vector rows longer than this get a wave each
 constexpr int kEllMaxWidth = 32;    // longest row of a level that gets an ELL copy
+constexpr int kTailMaxCols = 2;     // solves with more columns run every step as its own kernel
 constexpr int kElimMaxDegree = 4;   // eliminated nodes have at most this many neighbours
 constexpr double kElimMinFrac = 0.1;  // an elimination level removes at least this share
 

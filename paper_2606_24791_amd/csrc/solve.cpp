@@ -131,8 +131,12 @@ struct Cycle {
 // against the same number of workgroup steps of ~0.5 us plus the rows of a colour pass
 // gathered through one compute unit (~2000 entries per us). Levels with long (hub) rows
 // stay with the per-step kernels, which give each such row a whole block.
-int tail_level(const lamg_handle *h) {
-    if (h->opt.tail_rows <= 0) return -1;
+// Only solves of at most kTailMaxCols columns use the tail: with more columns a level's
+// steps carry enough work that one compute unit is slower than the per-step kernels over
+// the whole chip (measured: 4 columns of the anisotropic grid 109 ms without the tail
+// against 126 ms with it, 32 columns of the 128^3 grid 711 ms against 1369 ms).
+int tail_level(const lamg_handle *h, int k) {
+    if (h->opt.tail_rows <= 0 || k > kTailMaxCols) return -1;
     int l0 = -1;
     for (int l = 1; l < h->nlev; ++l)
         if (h->lev[l].n <= h->opt.tail_rows) {
@@ -160,8 +164,8 @@ int tail_level(const lamg_handle *h) {
 // Level whose per-step cycle kernels the in-situ timer records and whose kernels carry the
 // separate "finest" symbols: the finest aggregation level (elimination levels run no full
 // smoothing pass), or the finest level when that aggregation level runs in the coarse tail.
-int timed_level(const lamg_handle *h) {
-    const int l0 = tail_level(h);
+int timed_level(const lamg_handle *h, int k) {
+    const int l0 = tail_level(h, k);
     for (int l = 0; l < h->nlev; ++l) {
         const Level &L = h->lev[l];
         if (L.coarsest) break;
@@ -311,7 +315,10 @@ void ensure_level_vecs(lamg_handle *h, int k) {
     tp.l_lds = h->nlev;
     std::vector<char> lds_desc, jobs;
     size_t lds_bytes = 0;
-    const int l0 = tail_level(h);
+    // the plan serves every later solve that uses the tail (at most kTailMaxCols columns),
+    // including narrower solves reusing vectors sized for a wider one, so it is built for
+    // the tail level of such solves whatever k these vectors were sized for
+    const int l0 = tail_level(h, 1);
     int l_x = -1;
     int l_lds = tail_lds_plan<T>(h->lev, l0, k, host.data(), lds_desc, jobs, lds_bytes, l_x);
     if (l0 >= 0) {
@@ -436,8 +443,8 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
         run_scatter_cols(n, k, op0.perm.p, w.phi.p, w.mask.p, phi_out, s);
     }
 
-    const int l0 = tail_level(h);
-    const int lt = timed_level(h);
+    const int l0 = tail_level(h, k);
+    const int lt = timed_level(h, k);
     Cycle<double> c64{h, k, s, &w.lv64, std::vector<int64_t>(h->nlev, 0), w.partial.p, l0, lt,
                       &w.plan64, w.visits.p};
     Cycle<float> c32{h, k, s, &w.lv32, std::vector<int64_t>(h->nlev, 0), w.partial.p, l0, lt,
@@ -530,7 +537,7 @@ void profile_impl(lamg_handle *h, int level, int kernel, int k, int reps, double
     ensure_level_vecs<T>(h, k);
     Level &L = h->lev[level];
     const SolveOp &op = L.op;
-    const bool fine = level == timed_level(h);
+    const bool fine = level == timed_level(h, k);
     const int64_t n = L.n;
     LevelVecs<T> &me = lv[level];
     run_fill<T>(me.x.p, n * k, T(1), s);
@@ -682,7 +689,7 @@ lamg_status run_solve(lamg_handle *h, const double *b, int nrhs, double tol, int
     return st;
 }
 
-int plan_tail_level(const lamg_handle *h) { return tail_level(h); }
-int plan_timed_level(const lamg_handle *h) { return timed_level(h); }
+int plan_tail_level(const lamg_handle *h) { return tail_level(h, 1); }
+int plan_timed_level(const lamg_handle *h) { return timed_level(h, 1); }
 
 }  // namespace lamg

@@ -250,7 +250,8 @@ def test_full_size_anisotropic_1024(B):
 def test_cycle_execution_modes_agree(B, tail_rows):
     """Every split between per-step kernels and the single-workgroup coarse tail (with its
     LDS-resident levels) computes the same cycle: each reaches the tolerance and the
-    oracle's solution, in both precisions, for 1 and 3 right-hand sides."""
+    oracle's solution, in both precisions, for 1, 2 and 3 right-hand sides (3 columns run
+    every step as its own kernel whatever the threshold)."""
     import torch
 
     g = GRAPHS["aniso_ragged"]()
@@ -260,11 +261,42 @@ def test_cycle_execution_modes_agree(B, tail_rows):
     bh = I.rhs(g.n, 3, seed=21)
     refs = [oh.solve(bh[c], TOL, 100) for c in range(3)]
     for prec in (B.FP64, B.FP32_IR):
-        for k in (1, 3):
+        for k in (1, 2, 3):
             b = torch.tensor(bh[:k], device="cuda")
             phi = torch.empty_like(b)
             st = B.lamg_solve(h, b, phi, precision=prec)
             check_solution(g, st, phi.cpu().numpy(), bh[:k], refs[:k])
+    h.close()
+
+
+def test_narrow_solve_after_wide_solve_on_one_handle(B):
+    """A solve of more than two columns (every step its own kernel) sizes the cached
+    workspace; a later one- or two-column solve on the same handle runs the coarse tail in
+    that workspace and must give the fresh handle's result."""
+    import torch
+
+    g = GRAPHS["aniso_ragged"]()
+    note("narrow after wide solve")
+    bh = I.rhs(g.n, 4, seed=13)
+    fresh = B.lamg_setup(g)
+    ref = {}
+    for k in (1, 2):
+        b = torch.tensor(bh[:k], device="cuda")
+        phi = torch.empty_like(b)
+        assert B.lamg_solve(fresh, b, phi, precision=B.FP32_IR)["converged"]
+        ref[k] = phi.cpu().numpy()
+    fresh.close()
+    h = B.lamg_setup(g)
+    b4 = torch.tensor(bh, device="cuda")
+    assert B.lamg_solve(h, b4, torch.empty_like(b4), precision=B.FP32_IR)["converged"]
+    for k in (1, 2):
+        b = torch.tensor(bh[:k], device="cuda")
+        phi = torch.empty_like(b)
+        assert B.lamg_solve(h, b, phi, precision=B.FP32_IR)["converged"]
+        got = phi.cpu().numpy()
+        for c in range(k):
+            err = np.linalg.norm(got[c] - ref[k][c]) / np.linalg.norm(ref[k][c])
+            assert err <= 1e-12, (k, c, err)
     h.close()
 
 
