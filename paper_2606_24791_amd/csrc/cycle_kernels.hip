@@ -44,15 +44,17 @@ enum { OP_GS = 0, OP_RESID = 1, OP_SPMV = 2 };
 // Side outputs (null: none): OP_RESID copies x to sx and the residual to sr (the pair the
 // next two-iterate recombination starts from); OP_SPMV zeroes sx at the output row (the
 // coarse iterate a visit starts from).
-template <class T, int OP, int FINE>
-__global__ void __launch_bounds__(kBlock)
-    k_csr(int64_t r0, int64_t nrows, const int32_t *__restrict__ rows, int skip_long,
-          const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const T *__restrict__ v,
-          const T *__restrict__ dd, const T *__restrict__ f, const T *xin, T *out, int k, int lkp,
-          int llpr, T *sx, T *sr) {
+// Short-row body: group `grp` of this launch handles one row.
+template <class T, int OP>
+__device__ __forceinline__ void csr_short_rows(int64_t grp, int64_t r0, int64_t nrows,
+                                               const int32_t *__restrict__ rows, int skip_long,
+                                               const int32_t *__restrict__ rp,
+                                               const int32_t *__restrict__ ci,
+                                               const T *__restrict__ v, const T *__restrict__ dd,
+                                               const T *__restrict__ f, const T *xin, T *out,
+                                               int k, int lkp, int llpr, T *sx, T *sr) {
     const int lg = lkp + llpr;
     const int G = 1 << lg;
-    const int64_t grp = (int64_t)blockIdx.x * (kBlock >> lg) + (threadIdx.x >> lg);
     const int g = threadIdx.x & (G - 1);
     const int col = g & ((1 << lkp) - 1);
     const int sub = g >> lkp;
@@ -87,52 +89,38 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
-// FINE = 1 marks launches on the finest level: the code is identical, the separate
-// symbol lets a kernel trace attribute finest-level time on its own.
-template <class T, int OP, int FINE = 0>
-void launch_csr(int64_t r0, int64_t nrows, const int32_t *rows, int skip_long, const int32_t *rp,
-                const int32_t *ci, const T *v, const T *dd, const T *f, const T *xin, T *out, int k,
-                int lpr, hipStream_t s, T *sx = nullptr, T *sr = nullptr) {
-    if (nrows <= 0) return;
-    int lkp = kp_log2(k);
-    int llpr = ilog2(lpr);
-    if (lkp + llpr > 6) llpr = 6 - lkp;
-    if (llpr < 0) llpr = 0;
-    int lg = lkp + llpr;
-    int64_t groups_per_block = kBlock >> lg;
-    unsigned grid = (unsigned)((nrows + groups_per_block - 1) / groups_per_block);
-    launch_kernel(k_csr<T, OP, FINE>, dim3(grid), dim3(kBlock), 0, s, r0, nrows, rows, skip_long,
-                  rp, ci, v, dd, f, xin, out, k, lkp, llpr, sx, sr);
-    LAMG_LAUNCH_CHECK();
-}
-
 // Long rows (more than kLongRow off-diagonals: the hubs of power-law graphs and of their
-// dense coarse levels): one block of kBlock threads per row, kp column lanes times
-// kBlock/kp entry lanes, each with 8 loads in flight; the entry lanes' partial sums are
-// combined by a wave shuffle tree and then across the waves in wave order.
-constexpr int kWavesLong = kBlock / 64;
+// dense coarse levels): one block of NT threads per row, kp column lanes times NT/kp entry
+// lanes, each with 8 loads in flight; the entry lanes' partial sums are combined by a wave
+// shuffle tree and then across the waves in wave order. NT = kBlock in general; launches
+// of only a few long rows (the colours of dense levels that hold a handful of hubs, where
+// the chip is idle but for those rows) use kLongWide threads per row, so that a row of
+// thousands of entries spends a quarter of the steps in its chain of dependent loads.
+constexpr int kLongWide = 1024;
+constexpr int kLongWideRows = 64;  // launches of fewer long rows take the wide blocks
 
-template <class T, int OP, int FINE>
-__global__ void __launch_bounds__(kBlock)
-    k_csr_long(int64_t r0, const int32_t *__restrict__ rows, const int32_t *__restrict__ rp,
-               const int32_t *__restrict__ ci, const T *__restrict__ v, const T *__restrict__ dd,
-               const T *__restrict__ f, const T *xin, T *out, int k, int lkp, T *sx, T *sr) {
-    __shared__ T part[kWavesLong][32];
-    const int64_t row = rows ? (int64_t)rows[blockIdx.x] : r0 + (int64_t)blockIdx.x;
+template <class T, int OP, int NT = kBlock>
+__device__ __forceinline__ void csr_long_row(int64_t row, const int32_t *__restrict__ rp,
+                                             const int32_t *__restrict__ ci,
+                                             const T *__restrict__ v, const T *__restrict__ dd,
+                                             const T *__restrict__ f, const T *xin, T *out, int k,
+                                             int lkp, T *sx, T *sr) {
+    constexpr int kWaves = NT / 64;
+    __shared__ T part[kWaves][32];
     const int tid = threadIdx.x;
     const int kp = 1 << lkp;
     const int col = tid & (kp - 1);
     const int sub = tid >> lkp;
     const int32_t b = rp[row], e = rp[row + 1];
     T acc = T(0);
-    if (col < k) acc = row_dot<T, 8>(ci, v, xin, b + sub, e, kBlock >> lkp, k, col);
+    if (col < k) acc = row_dot<T, 8>(ci, v, xin, b + sub, e, NT >> lkp, k, col);
     for (int o = kp; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
     const int wave = tid >> 6, lane = tid & 63;
     if (lane < kp) part[wave][lane] = acc;
     __syncthreads();
     if (tid >= k) return;
     T sum = T(0);
-    for (int w = 0; w < kWavesLong; ++w) sum += part[w][tid];
+    for (int w = 0; w < kWaves; ++w) sum += part[w][tid];
     const int64_t o = row * k + tid;
     if (OP == OP_GS) {
         out[o] = (f[o] - sum) * dd[row];
@@ -150,13 +138,118 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
+// One kernel body for the three CSR passes. Rows are r0 + (group index) or, with a row
+// list, rows[group index]. `skip_long` > 0 skips rows longer than it (handled by a
+// separate launch over a list).
+// Side outputs (null: none): OP_RESID copies x to sx and the residual to sr (the pair the
+// next two-iterate recombination starts from); OP_SPMV zeroes sx at the output row (the
+// coarse iterate a visit starts from).
+template <class T, int OP, int FINE>
+__global__ void __launch_bounds__(kBlock)
+    k_csr(int64_t r0, int64_t nrows, const int32_t *__restrict__ rows, int skip_long,
+          const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const T *__restrict__ v,
+          const T *__restrict__ dd, const T *__restrict__ f, const T *xin, T *out, int k, int lkp,
+          int llpr, T *sx, T *sr) {
+    const int64_t grp = (int64_t)blockIdx.x * (kBlock >> (lkp + llpr)) + (threadIdx.x >> (lkp + llpr));
+    csr_short_rows<T, OP>(grp, r0, nrows, rows, skip_long, rp, ci, v, dd, f, xin, out, k, lkp,
+                          llpr, sx, sr);
+}
+
+template <class T, int OP, int FINE, int NT>
+__global__ void __launch_bounds__(NT)
+    k_csr_long(int64_t r0, const int32_t *__restrict__ rows, const int32_t *__restrict__ rp,
+               const int32_t *__restrict__ ci, const T *__restrict__ v, const T *__restrict__ dd,
+               const T *__restrict__ f, const T *xin, T *out, int k, int lkp, T *sx, T *sr) {
+    const int64_t row = rows ? (int64_t)rows[blockIdx.x] : r0 + (int64_t)blockIdx.x;
+    csr_long_row<T, OP, NT>(row, rp, ci, v, dd, f, xin, out, k, lkp, sx, sr);
+}
+
+// Short and long rows of one pass in a single launch: the first `sblocks` blocks take the
+// short rows as k_csr does, each further block one long row as k_csr_long does (the
+// arithmetic of every row is that of the separate kernels). Dense coarse levels of
+// power-law graphs have both kinds in every colour; one launch instead of two halves the
+// dispatches of their many colour passes.
+template <class T, int OP, int FINE>
+__global__ void __launch_bounds__(kBlock)
+    k_csr_mixed(int64_t sblocks, int64_t r0, int64_t nrows, const int32_t *__restrict__ rows,
+                int skip_long, int64_t lr0, const int32_t *__restrict__ lrows,
+                const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                const T *__restrict__ v, const T *__restrict__ dd, const T *__restrict__ f,
+                const T *xin, T *out, int k, int lkp, int llpr, T *sx, T *sr) {
+    const int64_t bid = blockIdx.x;
+    if (bid < sblocks) {
+        const int64_t grp = bid * (kBlock >> (lkp + llpr)) + (threadIdx.x >> (lkp + llpr));
+        csr_short_rows<T, OP>(grp, r0, nrows, rows, skip_long, rp, ci, v, dd, f, xin, out, k,
+                              lkp, llpr, sx, sr);
+    } else {
+        const int64_t j = bid - sblocks;
+        const int64_t row = lrows ? (int64_t)lrows[j] : lr0 + j;
+        csr_long_row<T, OP>(row, rp, ci, v, dd, f, xin, out, k, lkp, sx, sr);
+    }
+}
+
+// Lane split of a short-row launch: log2 of the lanes per row, at most a wave per row.
+inline int short_llpr(int lkp, int lpr) {
+    int llpr = ilog2(lpr);
+    if (lkp + llpr > 6) llpr = 6 - lkp;
+    if (llpr < 0) llpr = 0;
+    return llpr;
+}
+
+// FINE = 1 marks launches on the timed level: the code is identical, the separate
+// symbol lets a kernel trace attribute that level's time on its own.
+template <class T, int OP, int FINE = 0>
+void launch_csr(int64_t r0, int64_t nrows, const int32_t *rows, int skip_long, const int32_t *rp,
+                const int32_t *ci, const T *v, const T *dd, const T *f, const T *xin, T *out, int k,
+                int lpr, hipStream_t s, T *sx = nullptr, T *sr = nullptr) {
+    if (nrows <= 0) return;
+    int lkp = kp_log2(k);
+    int llpr = short_llpr(lkp, lpr);
+    int lg = lkp + llpr;
+    int64_t groups_per_block = kBlock >> lg;
+    unsigned grid = (unsigned)((nrows + groups_per_block - 1) / groups_per_block);
+    launch_kernel(k_csr<T, OP, FINE>, dim3(grid), dim3(kBlock), 0, s, r0, nrows, rows, skip_long,
+                  rp, ci, v, dd, f, xin, out, k, lkp, llpr, sx, sr);
+    LAMG_LAUNCH_CHECK();
+}
+
 template <class T, int OP, int FINE = 0>
 void launch_csr_long(int64_t r0, int64_t nrows, const int32_t *rows, const int32_t *rp,
                      const int32_t *ci, const T *v, const T *dd, const T *f, const T *xin, T *out,
                      int k, hipStream_t s, T *sx = nullptr, T *sr = nullptr) {
     if (nrows <= 0) return;
-    launch_kernel(k_csr_long<T, OP, FINE>, dim3((unsigned)nrows), dim3(kBlock), 0, s, r0, rows,
-                  rp, ci, v, dd, f, xin, out, k, kp_log2(k), sx, sr);
+    if (nrows < kLongWideRows)
+        launch_kernel(k_csr_long<T, OP, FINE, kLongWide>, dim3((unsigned)nrows), dim3(kLongWide),
+                      0, s, r0, rows, rp, ci, v, dd, f, xin, out, k, kp_log2(k), sx, sr);
+    else
+        launch_kernel(k_csr_long<T, OP, FINE, kBlock>, dim3((unsigned)nrows), dim3(kBlock), 0, s,
+                      r0, rows, rp, ci, v, dd, f, xin, out, k, kp_log2(k), sx, sr);
+    LAMG_LAUNCH_CHECK();
+}
+
+// Short rows [r0, r0 + nrows) (or the list `rows`) and long rows [lr0, lr0 + nlong) (or the
+// list `lrows`) of one pass: one launch when both are present, else the one that is.
+template <class T, int OP, int FINE = 0>
+void launch_csr_both(int64_t r0, int64_t nrows, const int32_t *rows, int skip_long, int64_t lr0,
+                     int64_t nlong, const int32_t *lrows, const int32_t *rp, const int32_t *ci,
+                     const T *v, const T *dd, const T *f, const T *xin, T *out, int k, int lpr,
+                     hipStream_t s, T *sx = nullptr, T *sr = nullptr) {
+    if (nrows <= 0) {
+        launch_csr_long<T, OP, FINE>(lr0, nlong, lrows, rp, ci, v, dd, f, xin, out, k, s, sx, sr);
+        return;
+    }
+    if (nlong <= 0) {
+        launch_csr<T, OP, FINE>(r0, nrows, rows, skip_long, rp, ci, v, dd, f, xin, out, k, lpr, s,
+                                sx, sr);
+        return;
+    }
+    int lkp = kp_log2(k);
+    int llpr = short_llpr(lkp, lpr);
+    int64_t groups_per_block = kBlock >> (lkp + llpr);
+    int64_t sblocks = (nrows + groups_per_block - 1) / groups_per_block;
+    launch_kernel(k_csr_mixed<T, OP, FINE>, dim3((unsigned)(sblocks + nlong)), dim3(kBlock), 0, s,
+                  sblocks, r0, nrows, rows, skip_long, lr0, lrows, rp, ci, v, dd, f, xin, out, k,
+                  lkp, llpr, sx, sr);
     LAMG_LAUNCH_CHECK();
 }
 
@@ -602,12 +695,10 @@ template <class T, int FINE>
 static void gs_color(const SolveOp &op, int c, const T *v, const T *dinv, const T *f, T *x, int k,
                      hipStream_t s) {
     const int nc = op.ncolors;
-    int64_t a = op.blk[c], b = op.blk[c + 1];  // short rows of colour c
-    launch_csr<T, OP_GS, FINE>(a, b - a, nullptr, 0, op.rp.p, op.ci.p, v, dinv, f, x, x, k,
-                               op.lpr_short, s);
+    int64_t a = op.blk[c], b = op.blk[c + 1];              // short rows of colour c
     int64_t la = op.blk[nc + c], lb = op.blk[nc + c + 1];  // long rows of colour c
-    launch_csr_long<T, OP_GS, FINE>(la, lb - la, nullptr, op.rp.p, op.ci.p, v, dinv, f, x, x, k,
-                                    s);
+    launch_csr_both<T, OP_GS, FINE>(a, b - a, nullptr, 0, la, lb - la, nullptr, op.rp.p, op.ci.p,
+                                    v, dinv, f, x, x, k, op.lpr_short, s);
 }
 
 template <class T>
@@ -636,10 +727,9 @@ static void residual_impl(const SolveOp &op, const T *v, const T *d, const T *x,
                           int k, hipStream_t s, T *sx, T *sr) {
     const int nc = op.ncolors;
     int64_t nshort = op.blk[nc];
-    launch_csr<T, OP_RESID, FINE>(0, nshort, nullptr, 0, op.rp.p, op.ci.p, v, d, f, x, r, k,
-                                  op.lpr_short, s, sx, sr);
-    launch_csr_long<T, OP_RESID, FINE>(nshort, op.n - nshort, nullptr, op.rp.p, op.ci.p, v, d, f,
-                                       x, r, k, s, sx, sr);
+    launch_csr_both<T, OP_RESID, FINE>(0, nshort, nullptr, 0, nshort, op.n - nshort, nullptr,
+                                       op.rp.p, op.ci.p, v, d, f, x, r, k, op.lpr_short, s, sx,
+                                       sr);
 }
 
 template <class T>
@@ -656,15 +746,12 @@ void run_residual_color(const SolveOp &op, int c, const T *v, const T *d, const 
                         T *r, int k, hipStream_t s, bool fine) {
     const int nc = op.ncolors;
     int64_t a = op.blk[c], b = op.blk[c + 1], la = op.blk[nc + c], lb = op.blk[nc + c + 1];
-    if (fine) {
-        launch_csr<T, OP_RESID, 1>(a, b - a, nullptr, 0, op.rp.p, op.ci.p, v, d, f, x, r, k,
-                                   op.lpr_short, s);
-        launch_csr_long<T, OP_RESID, 1>(la, lb - la, nullptr, op.rp.p, op.ci.p, v, d, f, x, r, k, s);
-    } else {
-        launch_csr<T, OP_RESID, 0>(a, b - a, nullptr, 0, op.rp.p, op.ci.p, v, d, f, x, r, k,
-                                   op.lpr_short, s);
-        launch_csr_long<T, OP_RESID, 0>(la, lb - la, nullptr, op.rp.p, op.ci.p, v, d, f, x, r, k, s);
-    }
+    if (fine)
+        launch_csr_both<T, OP_RESID, 1>(a, b - a, nullptr, 0, la, lb - la, nullptr, op.rp.p,
+                                        op.ci.p, v, d, f, x, r, k, op.lpr_short, s);
+    else
+        launch_csr_both<T, OP_RESID, 0>(a, b - a, nullptr, 0, la, lb - la, nullptr, op.rp.p,
+                                        op.ci.p, v, d, f, x, r, k, op.lpr_short, s);
 }
 
 template <class T>
@@ -678,11 +765,9 @@ void run_inject_add(const SolveOp &op, const T *ec, T *x, int k, hipStream_t s) 
 template <class T>
 void run_restrict(const SolveOp &op, const T *rw, const T *r, T *fc, int k, hipStream_t s,
                   T *zero_xc) {
-    launch_csr<T, OP_SPMV>(0, op.nc, nullptr, op.n_rlong ? kLongRow : 0, op.rrp.p, op.rci.p, rw,
-                           nullptr, nullptr, r, fc, k, op.lpr_r, s, zero_xc, nullptr);
-    if (op.n_rlong)
-        launch_csr_long<T, OP_SPMV>(0, op.n_rlong, op.rlong.p, op.rrp.p, op.rci.p, rw, nullptr,
-                                    nullptr, r, fc, k, s, zero_xc, nullptr);
+    launch_csr_both<T, OP_SPMV>(0, op.nc, nullptr, op.n_rlong ? kLongRow : 0, 0, op.n_rlong,
+                                op.rlong.p, op.rrp.p, op.rci.p, rw, nullptr, nullptr, r, fc, k,
+                                op.lpr_r, s, zero_xc, nullptr);
 }
 
 template <class T>
