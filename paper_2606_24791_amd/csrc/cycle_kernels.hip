@@ -44,6 +44,19 @@ enum { OP_GS = 0, OP_RESID = 1, OP_SPMV = 2 };
 // Side outputs (null: none): OP_RESID copies x to sx and the residual to sr (the pair the
 // next two-iterate recombination starts from); OP_SPMV zeroes sx at the output row (the
 // coarse iterate a visit starts from).
+// Workgroups are dispatched to the eight XCDs round-robin (block b to XCD b mod 8), and each
+// XCD has its own L2. Rows of neighbouring blocks share gathered x values, so a launch's
+// blocks are renumbered such that each XCD takes one contiguous slice of the rows: XCD x
+// gets the logical blocks [start(x), start(x) + count(x)) in dispatch order. A bijection
+// of [0, nb): which block computes which row changes, not any row's arithmetic.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+    const int64_t q = nb / kXcds, r = nb % kXcds;
+    const int64_t x = b % kXcds, s = b / kXcds;
+    return x < r ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
+}
+
 // Short-row body: group `grp` of this launch handles one row.
 template <class T, int OP>
 __device__ __forceinline__ void csr_short_rows(int64_t grp, int64_t r0, int64_t nrows,
@@ -150,7 +163,8 @@ __global__ void __launch_bounds__(kBlock)
           const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const T *__restrict__ v,
           const T *__restrict__ dd, const T *__restrict__ f, const T *xin, T *out, int k, int lkp,
           int llpr, T *sx, T *sr) {
-    const int64_t grp = (int64_t)blockIdx.x * (kBlock >> (lkp + llpr)) + (threadIdx.x >> (lkp + llpr));
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t grp = blk * (kBlock >> (lkp + llpr)) + (threadIdx.x >> (lkp + llpr));
     csr_short_rows<T, OP>(grp, r0, nrows, rows, skip_long, rp, ci, v, dd, f, xin, out, k, lkp,
                           llpr, sx, sr);
 }
@@ -178,7 +192,9 @@ __global__ void __launch_bounds__(kBlock)
                 const T *xin, T *out, int k, int lkp, int llpr, T *sx, T *sr) {
     const int64_t bid = blockIdx.x;
     if (bid < sblocks) {
-        const int64_t grp = bid * (kBlock >> (lkp + llpr)) + (threadIdx.x >> (lkp + llpr));
+        // the short-row blocks come first in dispatch order; renumber them among themselves
+        const int64_t grp = xcd_block(bid, sblocks) * (kBlock >> (lkp + llpr)) +
+                            (threadIdx.x >> (lkp + llpr));
         csr_short_rows<T, OP>(grp, r0, nrows, rows, skip_long, rp, ci, v, dd, f, xin, out, k,
                               lkp, llpr, sx, sr);
     } else {
