@@ -78,7 +78,7 @@ struct TailArgs {
     void *top_x;      // global iterate of the top level (written back if it lives in LDS)
     int32_t njobs, l0, nlev, l_lds, k, lkp;
     uint32_t red_off;    // byte offset of the two reduction buffers in the dynamic LDS
-    int32_t l_x;         // level whose iterate alone lives in LDS (-1: none)
+    int32_t l_x;         // levels [l_x, l_lds) have their iterate alone in LDS (-1: none)
     uint32_t cpart_off;  // byte offset of the coarsest solve's part sums (TB doubles)
     uint32_t pad;
 };
@@ -733,8 +733,10 @@ __global__ void __launch_bounds__(TB) k_tail(TailArgs A, const TailLvl<T> *__res
         }
         if (l >= l_lds)
             l = visit<T, kAllLds, kAllLds>(A, D, G[l + 1], l, smem, ws, rbuf);
-        else if (l == l_x)
+        else if (l_x >= 0 && l >= l_x && l + 1 >= l_lds)
             l = visit<T, kXLds, kAllLds>(A, D, G[l + 1], l, smem, ws, rbuf);
+        else if (l_x >= 0 && l >= l_x)
+            l = visit<T, kXLds, kXLds>(A, D, G[l + 1], l, smem, ws, rbuf);
         else if (l + 1 == l_x)
             l = visit<T, kGlobal, kXLds>(A, D, G[l + 1], l, smem, ws, rbuf);
         else if (l + 1 >= l_lds)
@@ -742,7 +744,7 @@ __global__ void __launch_bounds__(TB) k_tail(TailArgs A, const TailLvl<T> *__res
         else
             l = visit<T, kGlobal, kGlobal>(A, D, G[l + 1], l, smem, ws, rbuf);
     }
-    if (l0 >= l_lds || l0 == l_x) {  // the top level's iterate lives in LDS: write it back
+    if (l0 >= l_lds || (l_x >= 0 && l0 >= l_x)) {  // the top level's iterate is in LDS: write it back
         const TailLvl<T> &D = G[l0];
         const T *lx = at<true>(smem, D.x);
         T *gx = static_cast<T *>(A.top_x);
@@ -810,7 +812,8 @@ void tail_fill_desc(void *host_buf, int l, const Level &L, const SolveOp &op, co
 
 // Lays out the launch's dynamic LDS: the two reduction buffers, then the coarsest levels
 // of the tail starting at l0 whose operators and vectors fit together in what is left,
-// then, if it still fits, the iterate of the level right above them (l_x, else -1).
+// then, as far as they fit, the iterates of the levels right above them, from the bottom up
+// (levels [l_x, l_lds); l_x = -1: none).
 // Writes the launch's descriptor array (arrays in LDS carry offsets) and the copy jobs.
 // Returns l_lds (nlev: no level in LDS) and the dynamic LDS bytes.
 template <class T>
@@ -911,19 +914,19 @@ int tail_lds_plan(const std::vector<Level> &lev, int l0, int k, const void *host
             E.x1 = E.rho1 = nullptr;
         }
     }
-    // the level right above: its iterate alone, if it fits
+    // the levels right above: their iterates alone (gathered by every colour pass, residual
+    // and prolongation of the level), from the bottom up while they fit
     l_x = -1;
-    if (l_lds > l0 && l_lds < nlev) {
-        const int l = l_lds - 1;
+    for (int l = l_lds - 1; l >= l0 && l_lds < nlev; --l) {
         const int64_t xb = (int64_t)sizeof(T) * lev[l].n * k;
-        if (off + al(xb) <= budget) {
-            TailLvl<T> &E = D[l];
-            const void *src = (const void *)E.x;
-            E.x = reinterpret_cast<T *>((uintptr_t)off);
-            if (l == l0) jv.push_back(CopyJob{src, (uint32_t)off, (uint32_t)xb});
-            off += al(xb);
-            l_x = l;
-        }
+        if (off + al(xb) > budget) break;
+        TailLvl<T> &E = D[l];
+        E = G[l];
+        const void *src = (const void *)E.x;
+        E.x = reinterpret_cast<T *>((uintptr_t)off);
+        if (l == l0) jv.push_back(CopyJob{src, (uint32_t)off, (uint32_t)xb});
+        off += al(xb);
+        l_x = l;
     }
     lds_bytes = (size_t)off;
     jobs.resize(jv.size() * sizeof(CopyJob));
