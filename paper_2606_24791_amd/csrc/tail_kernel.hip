@@ -104,7 +104,7 @@ template <class T, int M>
 struct Lv {
     static constexpr bool OL = M == kAllLds;  // operator, transfer and other vectors
     static constexpr bool XL = M != kGlobal;  // iterate
-    int n, nc, ncol, nrl, maxlen, maxcol, ew;
+    int n, nc, ncol, nrl, maxlen, maxcol, ew, maxrow;
     bool split;  // long rows long enough to share them between waves
     bool elim;   // elimination level
     const int32_t *eci;
@@ -119,7 +119,7 @@ struct Lv {
     T *x, *f, *r, *rho, *x1, *rho1;
     __device__ Lv(const TailLvl<T> &D, char *s)
         : n(D.n), nc(D.nc), ncol(D.ncolors), nrl(D.n_rlong), maxlen(D.maxlen), maxcol(D.maxcol),
-          ew(D.ew), split(D.maxrow > kSplitRow), elim(D.elim != 0), eci(D.eci), ev(D.ev),
+          ew(D.ew), maxrow(D.maxrow), split(D.maxrow > kSplitRow), elim(D.elim != 0), eci(D.eci), ev(D.ev),
           blk(at<OL>(s, D.blk)), rp(at<OL>(s, D.rp)), ci(at<OL>(s, D.ci)), v(at<OL>(s, D.v)),
           d(at<OL>(s, D.d)), dinv(at<OL>(s, D.dinv)), p0(at<OL>(s, D.p0)), p1(at<OL>(s, D.p1)),
           w0(at<OL>(s, D.w0)), w1(at<OL>(s, D.w1)), rrp(at<OL>(s, D.rrp)), rci(at<OL>(s, D.rci)),
@@ -151,24 +151,31 @@ __device__ inline T row_sum(const int32_t *ci, const T *v, const T *x, int j0, i
     return acc;
 }
 
-// CSR pass over rows [a, b) (short rows) and [la, lb) (long rows, through `rows` if given):
-//   OP 0: x[r] = (f[r] - sum_off) * dd[r]      (Gauss-Seidel colour pass, in place)
-//   OP 1: out[r] = f[r] - dd[r] x[r] - sum_off  (residual)
-//   OP 2: out[r] = sum_off                      (P^T r)
-// Short rows: one thread per (row, column); rows longer than skip_long (> 0) are left to
-// the long list. Long rows: one wave per row, the 64 lanes split as kp columns x (64/kp).
+// Short rows [a, b) by groups of kp x lpr lanes: lpr (up to 2^max_llpr, as long as every
+// row keeps at least two groups' worth of threads) lanes split a row's entries, and the
+// partial sums are combined by shuffles inside the group. Used for the few short rows of a
+// colour pass on the denser levels, whose rows run up to kLongRow entries.
 template <class T, int OP>
-__device__ __forceinline__ void csr_rows(int a, int b, int la, int lb, const int32_t *rows, int skip_long,
-                         const int32_t *rp, const int32_t *ci, const T *v, const T *dd, const T *f,
-                         const T *xin, T *out, int k, int lkp, T *lpart, bool split) {
+__device__ __forceinline__ void csr_short_split(int a, int b, int skip_long,
+                                                           const int32_t *rp, const int32_t *ci,
+                                                           const T *v, const T *dd, const T *f,
+                                                           const T *xin, T *out, int k, int lkp,
+                                                           int max_llpr) {
     const int tid = threadIdx.x;
     const int kp = 1 << lkp;
-    const int c = tid & (kp - 1);
-    if (c < k) {
-        for (int row = a + (tid >> lkp); row < b; row += (TB >> lkp)) {
-            const int e0 = rp[row], e1 = rp[row + 1];
-            if (skip_long > 0 && e1 - e0 > skip_long) continue;
-            const T acc = row_sum<T, 8>(ci, v, xin, e0, e1, 1, k, c);
+    const int nrow = b - a;
+    int llpr = 0;
+    while (llpr < max_llpr && lkp + llpr < 6 && (nrow << (lkp + llpr + 1)) <= TB) ++llpr;
+    const int lg = lkp + llpr, G = 1 << lg, lpr = 1 << llpr;
+    const int g = tid & (G - 1);
+    const int c = g & (kp - 1), sub = g >> lkp;
+    for (int row = a + (tid >> lg); row < b; row += (TB >> lg)) {
+        const int e0 = rp[row], e1 = rp[row + 1];
+        if (skip_long > 0 && e1 - e0 > skip_long) continue;
+        T acc = T(0);
+        if (c < k) acc = row_sum<T, 4>(ci, v, xin, e0 + sub, e1, lpr, k, c);
+        for (int o = kp; o < G; o <<= 1) acc += __shfl_xor(acc, o, 64);
+        if (sub == 0 && c < k) {
             const int o = row * k + c;
             if (OP == 0)
                 out[o] = (f[o] - acc) * dd[row];
@@ -176,6 +183,42 @@ __device__ __forceinline__ void csr_rows(int a, int b, int la, int lb, const int
                 out[o] = f[o] - dd[row] * xin[o] - acc;
             else
                 out[o] = acc;
+        }
+    }
+}
+
+// CSR pass over rows [a, b) (short rows) and [la, lb) (long rows, through `rows` if given):
+//   OP 0: x[r] = (f[r] - sum_off) * dd[r]      (Gauss-Seidel colour pass, in place)
+//   OP 1: out[r] = f[r] - dd[r] x[r] - sum_off  (residual)
+//   OP 2: out[r] = sum_off                      (P^T r)
+// Short rows: one thread per (row, column); rows longer than skip_long (> 0) are left to
+// the long list. Long rows: one wave per row, the 64 lanes split as kp columns x (64/kp).
+template <class T, int OP, bool SPLIT = false>
+__device__ __forceinline__ void csr_rows(int a, int b, int la, int lb, const int32_t *rows, int skip_long,
+                         const int32_t *rp, const int32_t *ci, const T *v, const T *dd, const T *f,
+                         const T *xin, T *out, int k, int lkp, T *lpart, bool split,
+                         int max_llpr) {
+    const int tid = threadIdx.x;
+    const int kp = 1 << lkp;
+    // SPLIT (the denser levels) and few short rows: several lanes split each row; a separate
+    // instantiation, so the other levels run the plain loop
+    if (SPLIT && ((b - a) << (lkp + 2)) <= TB && lkp < 6) {
+        csr_short_split<T, OP>(a, b, skip_long, rp, ci, v, dd, f, xin, out, k, lkp, max_llpr);
+    } else {
+        const int c = tid & (kp - 1);
+        if (c < k) {
+            for (int row = a + (tid >> lkp); row < b; row += (TB >> lkp)) {
+                const int e0 = rp[row], e1 = rp[row + 1];
+                if (skip_long > 0 && e1 - e0 > skip_long) continue;
+                const T acc = row_sum<T, 8>(ci, v, xin, e0, e1, 1, k, c);
+                const int o = row * k + c;
+                if (OP == 0)
+                    out[o] = (f[o] - acc) * dd[row];
+                else if (OP == 1)
+                    out[o] = f[o] - dd[row] * xin[o] - acc;
+                else
+                    out[o] = acc;
+            }
         }
     }
     const int nl = lb - la;
@@ -253,8 +296,12 @@ __device__ __forceinline__ void residual(const Lv<T, M> &L, T *out, int k, int l
         return;
     }
     const int nc = L.ncol;
-    csr_rows<T, 1>(0, (int)L.blk[nc], (int)L.blk[nc], L.n, nullptr, 0, L.rp, L.ci, L.v, L.d, L.f,
-                   L.x, out, k, lkp, lp, L.split);
+    if (L.maxrow > kLongRow)
+        csr_rows<T, 1, true>(0, (int)L.blk[nc], (int)L.blk[nc], L.n, nullptr, 0, L.rp, L.ci, L.v,
+                             L.d, L.f, L.x, out, k, lkp, lp, L.split, 3);
+    else
+        csr_rows<T, 1>(0, (int)L.blk[nc], (int)L.blk[nc], L.n, nullptr, 0, L.rp, L.ci, L.v, L.d,
+                       L.f, L.x, out, k, lkp, lp, L.split, 0);
 }
 
 // One Gauss-Seidel colour pass over rows [a, b) from the ELL copy (coalesced loads, entry
@@ -373,7 +420,7 @@ __device__ __forceinline__ void smooth(const Lv<T, M> &L, int k, int lkp, int sw
         // elimination level: its eliminated rows (colour 0, independent, all short) are set
         // exactly from the kept ones, once, whatever the sweep count
         csr_rows<T, 0>((int)L.blk[0], (int)L.blk[1], (int)L.blk[nc], (int)L.blk[nc + 1], nullptr,
-                       0, L.rp, L.ci, L.v, L.dinv, L.f, L.x, L.x, k, lkp, lp, L.split);
+                       0, L.rp, L.ci, L.v, L.dinv, L.f, L.x, L.x, k, lkp, lp, L.split, 0);
         bar();
         if (resid) {
             residual<T, M>(L, L.r, k, lkp, lp);
@@ -475,9 +522,14 @@ __device__ __forceinline__ void smooth(const Lv<T, M> &L, int k, int lkp, int sw
     } else {
         for (int sw = 0; sw < sweeps; ++sw)
             for (int cl = 0; cl < nc; ++cl) {
-                csr_rows<T, 0>((int)L.blk[cl], (int)L.blk[cl + 1], (int)L.blk[nc + cl],
-                               (int)L.blk[nc + cl + 1], nullptr, 0, L.rp, L.ci, L.v, L.dinv, L.f,
-                               L.x, L.x, k, lkp, lp, L.split);
+                if (L.maxrow > kLongRow)
+                    csr_rows<T, 0, true>((int)L.blk[cl], (int)L.blk[cl + 1], (int)L.blk[nc + cl],
+                                         (int)L.blk[nc + cl + 1], nullptr, 0, L.rp, L.ci, L.v,
+                                         L.dinv, L.f, L.x, L.x, k, lkp, lp, L.split, 3);
+                else
+                    csr_rows<T, 0>((int)L.blk[cl], (int)L.blk[cl + 1], (int)L.blk[nc + cl],
+                                   (int)L.blk[nc + cl + 1], nullptr, 0, L.rp, L.ci, L.v, L.dinv,
+                                   L.f, L.x, L.x, k, lkp, lp, L.split, 0);
                 bar();
             }
     }
@@ -593,7 +645,7 @@ __device__ __forceinline__ int visit(const TailArgs &A, const TailLvl<T> &DL, co
     if ((s & 1) == 0) {
         smooth<T, ML>(L, k, lkp, 1, true, lp);
         csr_rows<T, 2>(0, L.nc, 0, L.nrl, L.rlong, L.nrl ? kLongRow : 0, L.rrp, L.rci, L.rw,
-                       nullptr, nullptr, L.r, C.f, k, lkp, lp, false);
+                       nullptr, nullptr, L.r, C.f, k, lkp, lp, false, 0);
         for (int t = tid; t < C.n * k; t += TB) C.x[t] = T(0);
         bar();
         const int i = ws.get_cnt(l);
