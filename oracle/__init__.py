@@ -71,7 +71,11 @@ def lib():
         L.orc_schur.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, C.c_int, C.c_void_p,
                                 C.c_void_p, C.c_void_p]
         L.orc_setup.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_uint64, C.c_int, C.c_int, C.c_int,
-                                C.c_int, C.c_int, C.POINTER(C.c_void_p)]
+                                C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)]
+        L.orc_gershgorin.restype = C.c_double
+        L.orc_gershgorin.argtypes = [C.c_int, _i32p, _i32p, _f64p]
+        L.orc_cheb_sweep.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_double, C.c_double, C.c_int,
+                                     C.c_void_p, _f64p, _f64p, _f64p]
         L.orc_free.argtypes = [C.c_void_p]
         L.orc_nlevels.argtypes = [C.c_void_p]
         L.orc_level_info.argtypes = [C.c_void_p, C.c_int, np.ctypeslib.ndpointer(np.int64),
@@ -225,6 +229,19 @@ def schur(rp, ci, v, cid, nc):
     return Crp, Cci, Cv
 
 
+def gershgorin(rp, ci, v) -> float:
+    return float(lib().orc_gershgorin(rp.size - 1, rp, ci, v))
+
+
+def cheb_sweep(rp, ci, v, lmax, f, x, ratio=30.0, degree=2):
+    """One Chebyshev sweep in place on x (f may be None for L x = 0)."""
+    n = rp.size - 1
+    x = np.ascontiguousarray(x, np.float64)
+    fp = None if f is None else np.ascontiguousarray(f, np.float64)
+    lib().orc_cheb_sweep(n, rp, ci, v, lmax, ratio, degree, _p(fp), x, np.empty(n), np.empty(n))
+    return x
+
+
 def recombine(phi, r, hphi, hr):
     """One fine-level recombination (in place on phi, r) over saved pairs."""
     m = len(hphi)
@@ -248,11 +265,12 @@ class Hierarchy:
     """The oracle's LAMG+ hierarchy for one graph."""
 
     def __init__(self, g, seed: int = 1, n_direct: int = 512, enable_veto: bool = True,
-                 enable_caliber2: bool = True, kappa: int = 4, elimination: bool = True):
+                 enable_caliber2: bool = True, kappa: int = 4, elimination: bool = True,
+                 smoother: int = 0):
         h = C.c_void_p()
         rc = lib().orc_setup(g.n, g.row_ptr, g.col_idx, np.ascontiguousarray(g.weight, np.float64),
                              seed, n_direct, int(enable_veto), int(enable_caliber2), kappa,
-                             int(elimination), C.byref(h))
+                             int(elimination), int(smoother), C.byref(h))
         if rc != OK:
             raise OracleError(f"orc_setup failed with code {rc}")
         self._h = h
@@ -268,13 +286,13 @@ class Hierarchy:
         return lib().orc_nlevels(self._h)
 
     def level_info(self, l: int) -> dict:
-        s = np.zeros(7, np.int64)
-        d = np.zeros(2)
+        s = np.zeros(8, np.int64)
+        d = np.zeros(3)
         if lib().orc_level_info(self._h, l, s, d) != OK:
             raise IndexError(l)
         return dict(n=int(s[0]), nnz=int(s[1]), ncolors=int(s[2]), nc=int(s[3]),
-                    n_cal2=int(s[4]), coarsest=bool(s[5]), elim=bool(s[6]), gamma=float(d[0]),
-                    tau=float(d[1]))
+                    n_cal2=int(s[4]), coarsest=bool(s[5]), elim=bool(s[6]), cheb=bool(s[7]),
+                    gamma=float(d[0]), tau=float(d[1]), cheb_lmax=float(d[2]))
 
     def export(self, l: int) -> dict:
         info = self.level_info(l)

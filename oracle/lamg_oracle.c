@@ -61,6 +61,8 @@ typedef struct {
     int *p0, *p1;     /* n: interpolation parents (p1 = -1 if none) */
     double *w0, *w1;  /* n: their weights */
     int elim;         /* 1: low-degree elimination level (agg = coarse id, -1 on F) */
+    int cheb;         /* 1: smoothed by Chebyshev polynomials instead of Gauss-Seidel */
+    double cheb_lmax; /* Gershgorin bound of the spectrum of D^{-1} L */
     int nc;           /* size of the next level */
     int n_cal2;       /* rows with two parents */
     double gamma, tau;
@@ -74,6 +76,10 @@ typedef struct {
     uint64_t seed;
     int n_direct;
     int enable_veto, enable_caliber2, enable_elim;
+    int smoother;       /* 0: multicolour GS; 1: Chebyshev on levels with many colours */
+    int cheb_colors;    /* ... more than this many colours */
+    int cheb_degree;    /* residual evaluations per Chebyshev sweep */
+    double cheb_ratio;  /* smoothed interval [lmax / ratio, lmax] */
     double q_guard, tau_soc, snap, elim_min;
     int kappa;
 } ohier;
@@ -765,6 +771,64 @@ static void elim_relax_f(const olevel *lv, double *phi, const double *f) {
 }
 
 /* ------------------------------------------------------------------------- */
+/* S13: Chebyshev polynomial smoother, the parallel substitute for Gauss-Seidel  */
+/* that Sec. 5 ("On the feasibility of a parallel LAMG+") names, after Adams,   */
+/* Brezina, Hu and Tuminaro (2003)                                              */
+/* ------------------------------------------------------------------------- */
+
+/* Upper bound of the spectrum of D^{-1} L by Gershgorin's theorem: the largest
+ * sum_j |L_uj| / L_uu over the rows (sum in CSR order from +0.0, diagonal included).
+ * Pinned: >= the largest eigenvalue (dense eig), = 2 for a graph Laplacian with
+ * non-negative weights. */
+double orc_gershgorin(int n, const int *rp, const int *ci, const double *v) {
+    double best = 0.0;
+    for (int u = 0; u < n; ++u) {
+        double s = 0.0, d = 0.0;
+        for (int j = rp[u]; j < rp[u + 1]; ++j) {
+            s = s + fabs(v[j]);
+            if (ci[j] == u) d = v[j];
+        }
+        double q = s / d;
+        if (q > best) best = q;
+    }
+    return best;
+}
+
+/* One Chebyshev sweep of `degree` residual evaluations on L x = f with the Jacobi
+ * preconditioner D = diag(L), damping the eigencomponents of D^{-1} L in [a, b] =
+ * [lmax / ratio, lmax]: the three-term Chebyshev semi-iteration (theta = (a+b)/2,
+ * delta = (b-a)/2, sigma = theta/delta):
+ *   rho_0 = 1/sigma, d = D^{-1} r / theta, x += d;
+ *   then for each further step: r = f - L x, rho_1 = 1/(2 sigma - rho_0),
+ *   d = rho_1 rho_0 d + (2 rho_1 / delta) D^{-1} r, x += d, rho_0 = rho_1.
+ * Pinned: on an eigenvector of D^{-1} L the error is multiplied by the scaled
+ * Chebyshev polynomial T_m((theta - lambda)/delta) / T_m(sigma). */
+void orc_cheb_sweep(int n, const int *rp, const int *ci, const double *v, double lmax,
+                    double ratio, int degree, const double *f, double *x, double *r, double *d) {
+    const double b = lmax, a = lmax / ratio;
+    const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
+    double rho0 = 1.0 / sigma;
+    for (int step = 0; step < degree; ++step) {
+        for (int u = 0; u < n; ++u) {
+            double acc = 0.0, dg = 0.0;
+            for (int j = rp[u]; j < rp[u + 1]; ++j) {
+                acc += v[j] * x[ci[j]];
+                if (ci[j] == u) dg = v[j];
+            }
+            r[u] = ((f ? f[u] : 0.0) - acc) / dg; /* D^{-1} r */
+        }
+        if (step == 0) {
+            for (int u = 0; u < n; ++u) d[u] = r[u] / theta;
+        } else {
+            const double rho1 = 1.0 / (2.0 * sigma - rho0);
+            for (int u = 0; u < n; ++u) d[u] = rho1 * rho0 * d[u] + (2.0 * rho1 / delta) * r[u];
+            rho0 = rho1;
+        }
+        for (int u = 0; u < n; ++u) x[u] += d[u];
+    }
+}
+
+/* ------------------------------------------------------------------------- */
 /* S12: coarsest level, dense solve of (L + 11^T/n) y = f                       */
 /* ------------------------------------------------------------------------- */
 
@@ -866,7 +930,8 @@ static int build_level_data(ohier *h, int l) {
 
 /* Options: any value <= 0 (or NAN) selects the default. */
 int orc_setup(int n, const int *rp, const int *ci, const double *w, uint64_t seed, int n_direct,
-              int enable_veto, int enable_caliber2, int kappa, int enable_elim, void **out) {
+              int enable_veto, int enable_caliber2, int kappa, int enable_elim, int smoother,
+              void **out) {
     *out = NULL;
     if (n < 1) return ORC_ERR_ARG;
     ohier *h = (ohier *)calloc(1, sizeof(ohier));
@@ -881,6 +946,10 @@ int orc_setup(int n, const int *rp, const int *ci, const double *w, uint64_t see
     h->kappa = (kappa > 0 && kappa <= 4) ? kappa : 4;
     h->enable_elim = enable_elim;
     h->elim_min = 0.1; /* an elimination level must remove at least this fraction of n */
+    h->smoother = smoother;
+    h->cheb_colors = 32;
+    h->cheb_degree = 3;
+    h->cheb_ratio = 5.0;
     int rc = ORC_OK;
     /* level 0 */
     olevel *l0 = &h->lev[0];
@@ -940,6 +1009,10 @@ int orc_setup(int n, const int *rp, const int *ci, const double *w, uint64_t see
         }
         rc = build_level_data(h, l);
         if (rc) goto fail;
+        if (h->smoother == 1 && lv->ncolors > h->cheb_colors) {
+            lv->cheb = 1;
+            lv->cheb_lmax = orc_gershgorin(lv->L.n, lv->L.rp, lv->L.ci, lv->L.v);
+        }
         if (lv->nc >= lv->L.n || l + 1 >= ORC_MAX_LEVELS) {
             /* no coarsening: a small level becomes the coarsest, a large one is an error */
             if (lv->L.n <= 1024) {
@@ -1008,7 +1081,8 @@ void orc_free(void *hp) {
 
 int orc_nlevels(const void *hp) { return ((const ohier *)hp)->nlev; }
 
-/* sizes[0..6] = n, nnz, ncolors, nc, n_cal2, coarsest, elim; sched = gamma, tau */
+/* sizes[0..7] = n, nnz, ncolors, nc, n_cal2, coarsest, elim, cheb; sched = gamma, tau,
+ * Chebyshev spectral bound */
 int orc_level_info(const void *hp, int l, long long *sizes, double *sched) {
     const ohier *h = (const ohier *)hp;
     if (l < 0 || l >= h->nlev) return ORC_ERR_ARG;
@@ -1020,8 +1094,10 @@ int orc_level_info(const void *hp, int l, long long *sizes, double *sched) {
     sizes[4] = lv->n_cal2;
     sizes[5] = lv->coarsest;
     sizes[6] = lv->elim;
+    sizes[7] = lv->cheb;
     sched[0] = lv->gamma;
     sched[1] = lv->tau;
+    sched[2] = lv->cheb_lmax;
     return ORC_OK;
 }
 
@@ -1070,6 +1146,8 @@ typedef struct {
     double *rho[ORC_MAX_LEVELS];      /* coarse residual fc - L_{l+1} e */
     double *e1[ORC_MAX_LEVELS];       /* first coarse iterate of a visit */
     double *rho1[ORC_MAX_LEVELS];
+    double *cr[ORC_MAX_LEVELS];       /* Chebyshev work vectors of level l */
+    double *cd[ORC_MAX_LEVELS];
     double mu_last[ORC_MAX_LEVELS];
 } osolver;
 
@@ -1106,6 +1184,18 @@ static void recombine2(int n, double *e, double *rho, const double *e1, const do
     }
 }
 
+/* One relaxation sweep of a level: multicolour Gauss-Seidel, or a Chebyshev sweep on
+ * the levels marked for it (work vectors r, d of the level's size). */
+static void smooth_level(const ohier *h, const olevel *lv, double *r, double *d, const double *f,
+                         double *phi) {
+    if (lv->cheb)
+        orc_cheb_sweep(lv->L.n, lv->L.rp, lv->L.ci, lv->L.v, lv->cheb_lmax, h->cheb_ratio,
+                       h->cheb_degree, f, phi, r, d);
+    else
+        orc_gs_sweep_multi(lv->L.n, lv->L.rp, lv->L.ci, lv->L.v, lv->color, lv->ncolors, 1, f,
+                           phi);
+}
+
 static void cycle(osolver *S, int l, double *phi, const double *f) {
     const ohier *h = S->h;
     const olevel *lv = &h->lev[l];
@@ -1136,7 +1226,7 @@ static void cycle(osolver *S, int l, double *phi, const double *f) {
         return;
     }
     /* pre-relaxation: one sweep */
-    orc_gs_sweep_multi(n, lv->L.rp, lv->L.ci, lv->L.v, lv->color, lv->ncolors, 1, f, phi);
+    smooth_level(h, lv, S->cr[l], S->cd[l], f, phi);
     spmv_resid(&lv->L, phi, f, r);
     for (int a = 0; a < nc; ++a) fc[a] = 0.0;
     for (int u = 0; u < n; ++u) {
@@ -1172,8 +1262,8 @@ static void cycle(osolver *S, int l, double *phi, const double *f) {
         phi[u] += mu * pe;
     }
     /* post-relaxation: two sweeps */
-    orc_gs_sweep_multi(n, lv->L.rp, lv->L.ci, lv->L.v, lv->color, lv->ncolors, 1, f, phi);
-    orc_gs_sweep_multi(n, lv->L.rp, lv->L.ci, lv->L.v, lv->color, lv->ncolors, 1, f, phi);
+    smooth_level(h, lv, S->cr[l], S->cd[l], f, phi);
+    smooth_level(h, lv, S->cr[l], S->cd[l], f, phi);
 }
 
 /* Minimal-residual recombination over up to kappa saved pairs (phi_i, r_i):
@@ -1284,6 +1374,8 @@ int orc_solve(const void *hp, const double *b_in, double tol, int max_cycles, do
         S.rho[l] = (double *)malloc(sizeof(double) * (size_t)nc);
         S.e1[l] = (double *)malloc(sizeof(double) * (size_t)nc);
         S.rho1[l] = (double *)malloc(sizeof(double) * (size_t)nc);
+        S.cr[l] = (double *)malloc(sizeof(double) * (size_t)nf);
+        S.cd[l] = (double *)malloc(sizeof(double) * (size_t)nf);
     }
     double mb = 0.0;
     for (int i = 0; i < n; ++i) mb += b_in[i];
@@ -1358,6 +1450,8 @@ done:
         free(S.rho[l]);
         free(S.e1[l]);
         free(S.rho1[l]);
+        free(S.cr[l]);
+        free(S.cd[l]);
     }
     return rc;
 }
@@ -1377,6 +1471,8 @@ double orc_cycle_once(const void *hp, double *phi, const double *f) {
         S.rho[l] = (double *)malloc(sizeof(double) * (size_t)nc);
         S.e1[l] = (double *)malloc(sizeof(double) * (size_t)nc);
         S.rho1[l] = (double *)malloc(sizeof(double) * (size_t)nc);
+        S.cr[l] = (double *)malloc(sizeof(double) * (size_t)nf);
+        S.cd[l] = (double *)malloc(sizeof(double) * (size_t)nf);
     }
     S.mu_last[0] = 1.0;
     cycle(&S, 0, phi, f);
@@ -1388,6 +1484,8 @@ double orc_cycle_once(const void *hp, double *phi, const double *f) {
         free(S.rho[l]);
         free(S.e1[l]);
         free(S.rho1[l]);
+        free(S.cr[l]);
+        free(S.cd[l]);
     }
     return mu;
 }
