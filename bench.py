@@ -95,6 +95,8 @@ def main() -> int:
                          "the HBM byte counters of a profiler run)")
     ap.add_argument("--tail-rows", type=int, default=-1,
                     help="coarse-tail threshold option (-1: library default)")
+    ap.add_argument("--smoother", type=int, default=0,
+                    help="0: multicolour Gauss-Seidel; 1: Chebyshev on levels with > 32 colours")
     ap.add_argument("--no-elimination", action="store_true",
                     help="aggregation-only hierarchy (no low-degree elimination levels)")
     ap.add_argument("--profile-reps", type=int, default=0,
@@ -125,6 +127,8 @@ def main() -> int:
         over["elimination"] = 0
     if args.tail_rows >= 0:
         over["tail_rows"] = args.tail_rows
+    if args.smoother:
+        over["smoother"] = args.smoother
     opts = B.lamg_default_options(**over)
     h = B.lamg_setup(g, opts)
     torch.cuda.synchronize()
@@ -220,7 +224,8 @@ def main() -> int:
         import oracle as O
 
         t = time.perf_counter()
-        oh = O.Hierarchy(g, seed=1, n_direct=opts.n_direct, elimination=bool(opts.elimination))
+        oh = O.Hierarchy(g, seed=1, n_direct=opts.n_direct, elimination=bool(opts.elimination),
+                         smoother=int(opts.smoother))
         t_setup = time.perf_counter() - t
         t = time.perf_counter()
         ref, so, _ = oh.solve(bh[0], args.tol, 300)
@@ -257,6 +262,8 @@ def main() -> int:
             "levels": hi["levels"], "op_complexity": round(hi["op_complexity"], 3),
             "setup_s": round(hi["setup_seconds"], 3),
             "elimination": bool(opts.elimination), "elimination_levels": sum(hi["elim"]),
+            "smoother": "chebyshev on levels with > 32 colours" if opts.smoother else "gauss-seidel",
+            "chebyshev_levels": sum(hi["cheb"]),
             "tail_level": hi["tail_level"],
         },
         "latency_ms": {"p50": r["p50_ms"], "p99": r["p99_ms"]},

@@ -99,6 +99,14 @@ typedef struct {
                                 recomputed from them in the cycle, cycle index 1 -- provided F
                                 holds at least a tenth of the level's nodes. Elimination and
                                 aggregation levels alternate. */
+    int32_t smoother;        /* 0 (default): multicolour Gauss-Seidel on every level. 1: levels
+                                with more than 32 colours (the dense coarse levels of power-law
+                                graphs, where a Gauss-Seidel sweep is hundreds of dependent
+                                colour passes) are smoothed instead by Chebyshev polynomials in
+                                the Jacobi-scaled operator D^{-1} L -- the polynomial substitute
+                                for Gauss-Seidel named in Sec. 5 -- of degree 3 on
+                                [lmax / 5, lmax], lmax = the Gershgorin bound of D^{-1} L; one
+                                polynomial per Gauss-Seidel sweep it replaces. */
 } lamg_options;
 
 /* Per-level description of a hierarchy. */
@@ -124,6 +132,8 @@ typedef struct {
                                             records in a 1-column solve (the finest
                                             aggregation level unless that one runs in the
                                             coarse tail; then 0) */
+    int32_t cheb[LAMG_MAX_LEVELS];       /* 1: smoothed by Chebyshev polynomials (smoother 1) */
+    double cheb_lmax[LAMG_MAX_LEVELS];   /* their Gershgorin bound of D^{-1} L (0 otherwise) */
 } lamg_hier_info;
 
 /* Solve statistics. The caller may point the array fields at host arrays (or leave them

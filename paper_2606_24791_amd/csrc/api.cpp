@@ -134,6 +134,7 @@ void lamg_default_options(lamg_options *opt) {
     opt->keep_setup_data = 0;
     opt->tail_rows = 2500;
     opt->elimination = 1;
+    opt->smoother = 0;
 }
 
 lamg_status lamg_setup(const lamg_graph *g, const lamg_options *opt, void *stream,
@@ -145,7 +146,7 @@ lamg_status lamg_setup(const lamg_graph *g, const lamg_options *opt, void *strea
     lamg_default_options(&o);
     if (opt) o = *opt;
     if (o.n_direct < 1 || o.n_direct > 1024 || o.kappa < 0 || o.kappa > 4 || o.tail_rows < 0 ||
-        (o.elimination != 0 && o.elimination != 1))
+        (o.elimination != 0 && o.elimination != 1) || (o.smoother != 0 && o.smoother != 1))
         return LAMG_INVALID_ARG;
     lamg_handle *h = nullptr;
     lamg_status st = guarded([&]() -> lamg_status {
@@ -240,6 +241,8 @@ lamg_status lamg_hierarchy_info(const lamg_handle *h, lamg_hier_info *info) {
         info->nnz[l] = L.nnz;
         info->ncolors[l] = (L.coarsest || L.elim) ? 0 : L.ncolors;
         info->elim[l] = L.elim ? 1 : 0;
+        info->cheb[l] = L.cheb ? 1 : 0;
+        info->cheb_lmax[l] = L.cheb ? L.cheb_lmax : 0.0;
         info->n_caliber2[l] = L.coarsest ? 0 : L.n_cal2;
         info->gamma[l] = L.coarsest ? 0.0 : L.gamma;
         info->tau[l] = L.coarsest ? 0.0 : L.tau;

@@ -36,7 +36,15 @@ __device__ inline T group_sum(T v, int lkp, int G) {
     return v;
 }
 
-enum { OP_GS = 0, OP_RESID = 1, OP_SPMV = 2 };
+enum { OP_GS = 0, OP_RESID = 1, OP_SPMV = 2, OP_CHEB = 3 };
+
+// Scalars of an OP_CHEB pass: out = c1 * out + c2 * (f - L x) / L_uu (out ignored when
+// c1 == 0); the inverse diagonal comes in `dinv`.
+template <class T>
+struct ChebArgs {
+    T c1 = T(0), c2 = T(0);
+    const T *dinv = nullptr;
+};
 
 // One kernel body for the three CSR passes. Rows are r0 + (group index) or, with a row
 // list, rows[group index]. `skip_long` > 0 skips rows longer than it (handled by a
@@ -65,7 +73,7 @@ __device__ __forceinline__ void csr_short_rows(int64_t grp, int64_t r0, int64_t 
                                                const int32_t *__restrict__ ci,
                                                const T *__restrict__ v, const T *__restrict__ dd,
                                                const T *__restrict__ f, const T *xin, T *out,
-                                               int k, int lkp, int llpr, T *sx, T *sr) {
+                                               int k, int lkp, int llpr, T *sx, T *sr, ChebArgs<T> ch) {
     const int lg = lkp + llpr;
     const int G = 1 << lg;
     const int g = threadIdx.x & (G - 1);
@@ -88,6 +96,9 @@ __device__ __forceinline__ void csr_short_rows(int64_t grp, int64_t r0, int64_t 
     const int64_t o = row * k + col;
     if (OP == OP_GS) {
         out[o] = (f[o] - acc) * dd[row];
+    } else if (OP == OP_CHEB) {
+        const T res = (f[o] - dd[row] * xin[o] - acc) * ch.dinv[row];
+        out[o] = ch.c1 == T(0) ? ch.c2 * res : ch.c1 * out[o] + ch.c2 * res;
     } else if (OP == OP_RESID) {
         const T xo = xin[o];
         const T res = f[o] - dd[row] * xo - acc;
@@ -117,7 +128,7 @@ __device__ __forceinline__ void csr_long_row(int64_t row, const int32_t *__restr
                                              const int32_t *__restrict__ ci,
                                              const T *__restrict__ v, const T *__restrict__ dd,
                                              const T *__restrict__ f, const T *xin, T *out, int k,
-                                             int lkp, T *sx, T *sr) {
+                                             int lkp, T *sx, T *sr, ChebArgs<T> ch) {
     constexpr int kWaves = NT / 64;
     __shared__ T part[kWaves][32];
     const int tid = threadIdx.x;
@@ -137,6 +148,9 @@ __device__ __forceinline__ void csr_long_row(int64_t row, const int32_t *__restr
     const int64_t o = row * k + tid;
     if (OP == OP_GS) {
         out[o] = (f[o] - sum) * dd[row];
+    } else if (OP == OP_CHEB) {
+        const T res = (f[o] - dd[row] * xin[o] - sum) * ch.dinv[row];
+        out[o] = ch.c1 == T(0) ? ch.c2 * res : ch.c1 * out[o] + ch.c2 * res;
     } else if (OP == OP_RESID) {
         const T xo = xin[o];
         const T res = f[o] - dd[row] * xo - sum;
@@ -162,20 +176,20 @@ __global__ void __launch_bounds__(kBlock)
     k_csr(int64_t r0, int64_t nrows, const int32_t *__restrict__ rows, int skip_long,
           const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const T *__restrict__ v,
           const T *__restrict__ dd, const T *__restrict__ f, const T *xin, T *out, int k, int lkp,
-          int llpr, T *sx, T *sr) {
+          int llpr, T *sx, T *sr, ChebArgs<T> ch) {
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int64_t grp = blk * (kBlock >> (lkp + llpr)) + (threadIdx.x >> (lkp + llpr));
     csr_short_rows<T, OP>(grp, r0, nrows, rows, skip_long, rp, ci, v, dd, f, xin, out, k, lkp,
-                          llpr, sx, sr);
+                          llpr, sx, sr, ch);
 }
 
 template <class T, int OP, int FINE, int NT>
 __global__ void __launch_bounds__(NT)
     k_csr_long(int64_t r0, const int32_t *__restrict__ rows, const int32_t *__restrict__ rp,
                const int32_t *__restrict__ ci, const T *__restrict__ v, const T *__restrict__ dd,
-               const T *__restrict__ f, const T *xin, T *out, int k, int lkp, T *sx, T *sr) {
+               const T *__restrict__ f, const T *xin, T *out, int k, int lkp, T *sx, T *sr, ChebArgs<T> ch) {
     const int64_t row = rows ? (int64_t)rows[blockIdx.x] : r0 + (int64_t)blockIdx.x;
-    csr_long_row<T, OP, NT>(row, rp, ci, v, dd, f, xin, out, k, lkp, sx, sr);
+    csr_long_row<T, OP, NT>(row, rp, ci, v, dd, f, xin, out, k, lkp, sx, sr, ch);
 }
 
 // Short and long rows of one pass in a single launch: the first `sblocks` blocks take the
@@ -189,18 +203,18 @@ __global__ void __launch_bounds__(kBlock)
                 int skip_long, int64_t lr0, const int32_t *__restrict__ lrows,
                 const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                 const T *__restrict__ v, const T *__restrict__ dd, const T *__restrict__ f,
-                const T *xin, T *out, int k, int lkp, int llpr, T *sx, T *sr) {
+                const T *xin, T *out, int k, int lkp, int llpr, T *sx, T *sr, ChebArgs<T> ch) {
     const int64_t bid = blockIdx.x;
     if (bid < sblocks) {
         // the short-row blocks come first in dispatch order; renumber them among themselves
         const int64_t grp = xcd_block(bid, sblocks) * (kBlock >> (lkp + llpr)) +
                             (threadIdx.x >> (lkp + llpr));
         csr_short_rows<T, OP>(grp, r0, nrows, rows, skip_long, rp, ci, v, dd, f, xin, out, k,
-                              lkp, llpr, sx, sr);
+                              lkp, llpr, sx, sr, ch);
     } else {
         const int64_t j = bid - sblocks;
         const int64_t row = lrows ? (int64_t)lrows[j] : lr0 + j;
-        csr_long_row<T, OP>(row, rp, ci, v, dd, f, xin, out, k, lkp, sx, sr);
+        csr_long_row<T, OP>(row, rp, ci, v, dd, f, xin, out, k, lkp, sx, sr, ch);
     }
 }
 
@@ -217,7 +231,8 @@ inline int short_llpr(int lkp, int lpr) {
 template <class T, int OP, int FINE = 0>
 void launch_csr(int64_t r0, int64_t nrows, const int32_t *rows, int skip_long, const int32_t *rp,
                 const int32_t *ci, const T *v, const T *dd, const T *f, const T *xin, T *out, int k,
-                int lpr, hipStream_t s, T *sx = nullptr, T *sr = nullptr) {
+                int lpr, hipStream_t s, T *sx = nullptr, T *sr = nullptr,
+                ChebArgs<T> ch = ChebArgs<T>()) {
     if (nrows <= 0) return;
     int lkp = kp_log2(k);
     int llpr = short_llpr(lkp, lpr);
@@ -225,21 +240,22 @@ void launch_csr(int64_t r0, int64_t nrows, const int32_t *rows, int skip_long, c
     int64_t groups_per_block = kBlock >> lg;
     unsigned grid = (unsigned)((nrows + groups_per_block - 1) / groups_per_block);
     launch_kernel(k_csr<T, OP, FINE>, dim3(grid), dim3(kBlock), 0, s, r0, nrows, rows, skip_long,
-                  rp, ci, v, dd, f, xin, out, k, lkp, llpr, sx, sr);
+                  rp, ci, v, dd, f, xin, out, k, lkp, llpr, sx, sr, ch);
     LAMG_LAUNCH_CHECK();
 }
 
 template <class T, int OP, int FINE = 0>
 void launch_csr_long(int64_t r0, int64_t nrows, const int32_t *rows, const int32_t *rp,
                      const int32_t *ci, const T *v, const T *dd, const T *f, const T *xin, T *out,
-                     int k, hipStream_t s, T *sx = nullptr, T *sr = nullptr) {
+                     int k, hipStream_t s, T *sx = nullptr, T *sr = nullptr,
+                     ChebArgs<T> ch = ChebArgs<T>()) {
     if (nrows <= 0) return;
     if (nrows < kLongWideRows)
         launch_kernel(k_csr_long<T, OP, FINE, kLongWide>, dim3((unsigned)nrows), dim3(kLongWide),
-                      0, s, r0, rows, rp, ci, v, dd, f, xin, out, k, kp_log2(k), sx, sr);
+                      0, s, r0, rows, rp, ci, v, dd, f, xin, out, k, kp_log2(k), sx, sr, ch);
     else
         launch_kernel(k_csr_long<T, OP, FINE, kBlock>, dim3((unsigned)nrows), dim3(kBlock), 0, s,
-                      r0, rows, rp, ci, v, dd, f, xin, out, k, kp_log2(k), sx, sr);
+                      r0, rows, rp, ci, v, dd, f, xin, out, k, kp_log2(k), sx, sr, ch);
     LAMG_LAUNCH_CHECK();
 }
 
@@ -249,14 +265,16 @@ template <class T, int OP, int FINE = 0>
 void launch_csr_both(int64_t r0, int64_t nrows, const int32_t *rows, int skip_long, int64_t lr0,
                      int64_t nlong, const int32_t *lrows, const int32_t *rp, const int32_t *ci,
                      const T *v, const T *dd, const T *f, const T *xin, T *out, int k, int lpr,
-                     hipStream_t s, T *sx = nullptr, T *sr = nullptr) {
+                     hipStream_t s, T *sx = nullptr, T *sr = nullptr,
+                     ChebArgs<T> ch = ChebArgs<T>()) {
     if (nrows <= 0) {
-        launch_csr_long<T, OP, FINE>(lr0, nlong, lrows, rp, ci, v, dd, f, xin, out, k, s, sx, sr);
+        launch_csr_long<T, OP, FINE>(lr0, nlong, lrows, rp, ci, v, dd, f, xin, out, k, s, sx, sr,
+                                     ch);
         return;
     }
     if (nlong <= 0) {
         launch_csr<T, OP, FINE>(r0, nrows, rows, skip_long, rp, ci, v, dd, f, xin, out, k, lpr, s,
-                                sx, sr);
+                                sx, sr, ch);
         return;
     }
     int lkp = kp_log2(k);
@@ -265,7 +283,7 @@ void launch_csr_both(int64_t r0, int64_t nrows, const int32_t *rows, int skip_lo
     int64_t sblocks = (nrows + groups_per_block - 1) / groups_per_block;
     launch_kernel(k_csr_mixed<T, OP, FINE>, dim3((unsigned)(sblocks + nlong)), dim3(kBlock), 0, s,
                   sblocks, r0, nrows, rows, skip_long, lr0, lrows, rp, ci, v, dd, f, xin, out, k,
-                  lkp, llpr, sx, sr);
+                  lkp, llpr, sx, sr, ch);
     LAMG_LAUNCH_CHECK();
 }
 
@@ -771,6 +789,53 @@ void run_residual_color(const SolveOp &op, int c, const T *v, const T *d, const 
 }
 
 template <class T>
+__global__ void k_add_into(T *__restrict__ x, const T *__restrict__ d, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] += d[i];
+}
+
+// Chebyshev semi-iteration on L x = f with the Jacobi preconditioner, damping the spectrum
+// of D^{-1} L on [lmax / kChebRatio, lmax] (Adams, Brezina, Hu and Tuminaro 2003): step 0
+// d = D^{-1} r / theta; step j > 0 d = rho_j rho_{j-1} d + (2 rho_j / delta) D^{-1} r with
+// rho_0 = 1 / sigma, rho_j = 1 / (2 sigma - rho_{j-1}); x += d after each step. All rows of
+// a step read the same x (one CSR pass into d, then the update), so any row order gives the
+// same result.
+template <class T>
+void run_cheb_sweep(const SolveOp &op, double lmax, const T *v, const T *d, const T *dinv,
+                    const T *f, T *x, T *dvec, int k, hipStream_t s, bool fine) {
+    const double b = lmax, a = lmax / kChebRatio;
+    const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
+    double rho0 = 1.0 / sigma;
+    const int nc = op.ncolors;
+    const int64_t nshort = op.blk[nc];
+    const int64_t nk = op.n * k;
+    for (int step = 0; step < kChebDegree; ++step) {
+        ChebArgs<T> ch;
+        ch.dinv = dinv;
+        if (step == 0) {
+            ch.c1 = T(0);
+            ch.c2 = (T)(1.0 / theta);
+        } else {
+            const double rho1 = 1.0 / (2.0 * sigma - rho0);
+            ch.c1 = (T)(rho1 * rho0);
+            ch.c2 = (T)(2.0 * rho1 / delta);
+            rho0 = rho1;
+        }
+        if (fine)
+            launch_csr_both<T, OP_CHEB, 1>(0, nshort, nullptr, 0, nshort, op.n - nshort, nullptr,
+                                           op.rp.p, op.ci.p, v, d, f, x, dvec, k, op.lpr_short, s,
+                                           nullptr, nullptr, ch);
+        else
+            launch_csr_both<T, OP_CHEB, 0>(0, nshort, nullptr, 0, nshort, op.n - nshort, nullptr,
+                                           op.rp.p, op.ci.p, v, d, f, x, dvec, k, op.lpr_short, s,
+                                           nullptr, nullptr, ch);
+        launch_kernel(k_add_into<T>, dim3(blocks_for(nk)), dim3(kBlock), 0, s, x, (const T *)dvec,
+                      nk);
+        LAMG_LAUNCH_CHECK();
+    }
+}
+
+template <class T>
 void run_inject_add(const SolveOp &op, const T *ec, T *x, int k, hipStream_t s) {
     if (op.nc <= 0) return;
     launch_kernel(k_inject_add<T>, dim3(rc_blocks(op.nc, k)), dim3(kBlock), 0, s, op.nc, k,
@@ -933,6 +998,8 @@ void run_zero_cols(int64_t n, int k, const int32_t *zero_mask, double *x, hipStr
     template void run_residual_color<T>(const SolveOp &, int, const T *, const T *, const T *,    \
                                         const T *, T *, int, hipStream_t, bool);                  \
     template void run_inject_add<T>(const SolveOp &, const T *, T *, int, hipStream_t);           \
+    template void run_cheb_sweep<T>(const SolveOp &, double, const T *, const T *, const T *,     \
+                                    const T *, T *, T *, int, hipStream_t, bool);                 \
     template void run_mu_prolong<T>(const SolveOp &, const T *, const T *, int64_t, const T *,    \
                                     const T *, const T *, int, double *, T *, hipStream_t);       \
     template void run_rc2_keep<T>(int64_t, T *, T *, T *, T *, int, double *, bool, hipStream_t); \

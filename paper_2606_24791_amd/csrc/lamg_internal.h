@@ -29,7 +29,10 @@ constexpr int kRedBlocksMax = 256;  // partial-sum blocks of a reduction
 constexpr int kRedQMax = 14;        // quantities per reduction (4x4 normal equations + rhs)
 constexpr int kTVShortRow = 64;     // test-vector rows longer than this get a wave each
 constexpr int kEllMaxWidth = 32;    // longest row of a level that gets an ELL copy
-constexpr int kTailMaxCols = 2;     // solves with more columns run every step as its own kernel
+constexpr int kTailMaxCols = 2;
+constexpr int kChebColors = 32;      // smoother 1: levels with more colours use Chebyshev
+constexpr int kChebDegree = 3;       // residual evaluations per Chebyshev sweep
+constexpr double kChebRatio = 5.0;   // smoothed interval [lmax / kChebRatio, lmax]     // solves with more columns run every step as its own kernel
 constexpr int kElimMaxDegree = 4;   // eliminated nodes have at most this many neighbours
 constexpr double kElimMinFrac = 0.1;  // an elimination level removes at least this share
 
@@ -174,6 +177,8 @@ struct Level {
     int64_t n = 0, nnz = 0;  // canonical Laplacian size (diagonal included)
     bool coarsest = false;
     bool elim = false;  // elimination level: h_agg = coarse id of kept nodes, -1 on F
+    bool cheb = false;        // smoothed by Chebyshev polynomials (smoother option 1)
+    double cheb_lmax = 0.0;   // Gershgorin bound of the spectrum of D^{-1} L
     std::vector<int32_t> h_rp, h_ci;  // canonical pattern on the host
     DArr<int32_t> rp, ci;             // canonical CSR on the device
     DArr<double> val;
@@ -317,6 +322,9 @@ int64_t galerkin(Pool &pool, int64_t n, int64_t nnz, const int32_t *rp, const in
 int64_t schur(Pool &pool, int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
               const int32_t *cid, int64_t nc, DArr<int32_t> &crp, DArr<int32_t> &cci,
               DArr<double> &cv, hipStream_t s);
+// q[u] = (sum_j |L_uj|, CSR order from +0.0) / L_uu: the Gershgorin row bound of D^{-1} L
+void launch_gershgorin_rows(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                            double *q, hipStream_t s);
 // d[u] = the stored diagonal of row u
 void launch_diag(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, double *d,
                  hipStream_t s);
@@ -350,6 +358,10 @@ void run_residual(const SolveOp &op, const T *v, const T *d, const T *x, const T
 template <class T>
 void run_residual_color(const SolveOp &op, int c, const T *v, const T *d, const T *x, const T *f,
                         T *r, int k, hipStream_t s, bool fine);
+// One Chebyshev sweep (kChebDegree residual evaluations) on L x = f; dvec (n*k) is work space.
+template <class T>
+void run_cheb_sweep(const SolveOp &op, double lmax, const T *v, const T *d, const T *dinv,
+                    const T *f, T *x, T *dvec, int k, hipStream_t s, bool fine);
 // x += e_c on the kept rows of an elimination level (its one-entry-per-row P^T).
 template <class T>
 void run_inject_add(const SolveOp &op, const T *ec, T *x, int k, hipStream_t s);

@@ -582,6 +582,20 @@ void run_setup(lamg_handle *h, const lamg_graph *g) {
             try_elimination(h, l))
             continue;
         setup_level(h, l);
+        if (h->opt.smoother == 1 && L.ncolors > kChebColors) {
+            // Chebyshev smoothing on this dense level: the Gershgorin bound of D^{-1} L
+            std::vector<double> q(L.n);
+            DArr<double> dq;
+            dq.alloc(*h->pool, L.n);
+            launch_gershgorin_rows(L.n, L.rp.p, L.ci.p, L.val.p, dq.p, h->stream);
+            dq.download(q.data(), L.n, h->stream);
+            LAMG_HIP(hipStreamSynchronize(h->stream));
+            double lmax = 0.0;
+            for (double x : q)
+                if (x > lmax) lmax = x;
+            L.cheb = true;
+            L.cheb_lmax = lmax;
+        }
         if (L.nc >= L.n || l + 1 >= kMaxLevels) {
             if (L.n <= kStallDirectMax) {
                 L.coarsest = true;

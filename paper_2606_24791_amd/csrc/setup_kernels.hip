@@ -475,6 +475,19 @@ __global__ void k_row_fill(int64_t nc, const int32_t *__restrict__ crp, const in
 // pair (a, b) of distinct neighbours of f. The stable sort by (a, b) and the in-order
 // segment sums then add each coarse entry's terms in that order.
 // ---------------------------------------------------------------------------
+__global__ void k_gershgorin_rows(int64_t n, const int32_t *__restrict__ rp,
+                                  const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                  double *__restrict__ q) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    double s = 0.0, d = 0.0;
+    for (int32_t j = rp[u]; j < rp[u + 1]; ++j) {
+        s = s + fabs(v[j]);
+        if (ci[j] == (int32_t)u) d = v[j];
+    }
+    q[u] = s / d;
+}
+
 __global__ void k_diag(int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                        const double *__restrict__ v, double *__restrict__ d) {
     int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -885,6 +898,12 @@ int64_t schur(Pool &pool, int64_t n, const int32_t *rp, const int32_t *ci, const
     }
     off.release();
     return assemble_coarse(pool, m, key, val, nc, crp, cci, cv, s);
+}
+
+void launch_gershgorin_rows(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                            double *q, hipStream_t s) {
+    k_gershgorin_rows<<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, v, q);
+    LAMG_LAUNCH_CHECK();
 }
 
 void launch_diag(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, double *d,

@@ -144,7 +144,15 @@ int tail_level(const lamg_handle *h, int k) {
             break;
         }
     if (l0 < 0) return -1;
+    // levels smoothed by Chebyshev polynomials stay with the per-step kernels
+    for (int l = h->nlev - 1; l >= 0; --l)
+        if (h->lev[l].cheb) {
+            if (l0 <= l) l0 = l + 1;
+            break;
+        }
+    if (l0 >= h->nlev) return -1;
     while (l0 > 1) {
+        if (h->lev[l0 - 1].cheb) break;
         const Level &L = h->lev[l0 - 1];
         const SolveOp &op = L.op;
         if (L.coarsest || L.n >= 65536) break;
@@ -234,6 +242,15 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
         return;
     }
     auto smooth = [&](int sweeps) {
+        if (L.cheb) {  // Chebyshev sweeps (smoother option 1), in me.r as work space
+            for (int sw = 0; sw < sweeps; ++sw) {
+                Timed tm(h, timed ? LAMG_KERNEL_GS_COLOR : -1, prec_id<T>(),
+                         kChebDegree * (bytes_residual(op, k, sz) + 3.0 * k * op.n * sz));
+                run_cheb_sweep<T>(op, L.cheb_lmax, P::v(op), P::d(op), P::dinv(op), f, x, me.r.p,
+                                  k, s, l == C.lt);
+            }
+            return;
+        }
         if (!timed) {
             run_gs<T>(op, P::v(op), P::dinv(op), f, x, k, sweeps, s, l == C.lt);
             return;

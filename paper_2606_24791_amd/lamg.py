@@ -35,7 +35,7 @@ class lamg_options(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("n_direct", C.c_int32), ("enable_veto", C.c_int32),
                 ("enable_caliber2", C.c_int32), ("kappa", C.c_int32), ("build_fp32", C.c_int32),
                 ("keep_setup_data", C.c_int32), ("tail_rows", C.c_int32),
-                ("elimination", C.c_int32)]
+                ("elimination", C.c_int32), ("smoother", C.c_int32)]
 
 
 class lamg_hier_info(C.Structure):
@@ -45,7 +45,8 @@ class lamg_hier_info(C.Structure):
                 ("tau", C.c_double * MAX_LEVELS), ("bytes_device", C.c_int64),
                 ("op_complexity", C.c_double), ("setup_seconds", C.c_double),
                 ("bytes_peak", C.c_int64), ("elim", C.c_int32 * MAX_LEVELS),
-                ("tail_level", C.c_int32), ("timed_level", C.c_int32)]
+                ("tail_level", C.c_int32), ("timed_level", C.c_int32),
+                ("cheb", C.c_int32 * MAX_LEVELS), ("cheb_lmax", C.c_double * MAX_LEVELS)]
 
 
 class lamg_solve_info(C.Structure):
@@ -279,7 +280,8 @@ def lamg_hierarchy_info(h: Handle) -> dict:
                 bytes_device=int(info.bytes_device), op_complexity=float(info.op_complexity),
                 setup_seconds=float(info.setup_seconds), bytes_peak=int(info.bytes_peak),
                 elim=[bool(e) for e in info.elim[:L]], tail_level=int(info.tail_level),
-                timed_level=int(info.timed_level))
+                timed_level=int(info.timed_level), cheb=[bool(c) for c in info.cheb[:L]],
+                cheb_lmax=list(info.cheb_lmax[:L]))
 
 
 def lamg_export_level(h: Handle, level: int) -> dict:

@@ -109,11 +109,11 @@ def test_setup_bit_exact(B, name, elimination):
     h.close()
 
 
-def solve_both(B, g, k, precision, seed=11, tol=TOL, elimination=True):
+def solve_both(B, g, k, precision, seed=11, tol=TOL, elimination=True, smoother=0):
     import torch
 
-    oh = O.Hierarchy(g, seed=1, elimination=elimination)
-    h = B.lamg_setup(g, B.lamg_default_options(elimination=int(elimination)))
+    oh = O.Hierarchy(g, seed=1, elimination=elimination, smoother=smoother)
+    h = B.lamg_setup(g, B.lamg_default_options(elimination=int(elimination), smoother=smoother))
     bh = I.rhs(g.n, k, seed=seed)
     b = torch.tensor(bh, device="cuda")
     phi = torch.empty_like(b)
@@ -414,3 +414,41 @@ def test_elimination_execution_modes_agree(B, name, tail_rows):
     for c in range(2):
         err = np.linalg.norm(out[0][c] - out[1][c]) / np.linalg.norm(out[1][c])
         assert err <= 1e-6, err
+
+
+# --- Chebyshev smoothing of the dense levels (smoother option 1) -------------------------
+
+CHEB_GRAPHS = {
+    "chunglu": lambda: I.chung_lu(30000, 2.1, 16, seed=5),
+    "chunglu_dense": lambda: I.chung_lu(10000, 2.1, 24, seed=3),  # elimination only below
+}
+
+
+@pytest.mark.parametrize("name", list(CHEB_GRAPHS))
+def test_chebyshev_levels_and_bounds_bit_exact(B, name):
+    g = CHEB_GRAPHS[name]()
+    note(f"chebyshev setup {name}")
+    oh = O.Hierarchy(g, seed=1, smoother=1)
+    h = B.lamg_setup(g, B.lamg_default_options(smoother=1))
+    info = B.lamg_hierarchy_info(h)
+    assert info["levels"] == oh.nlevels
+    for l in range(oh.nlevels):
+        ol = oh.level_info(l)
+        assert info["cheb"][l] == ol["cheb"], l
+        if ol["cheb"]:
+            assert bits(np.array([info["cheb_lmax"][l]])) == bits(np.array([ol["cheb_lmax"]]))
+    assert any(info["cheb"])
+    assert info["tail_level"] < 0 or info["tail_level"] > max(
+        l for l in range(info["levels"]) if info["cheb"][l])
+    h.close()
+
+
+@pytest.mark.parametrize("name", list(CHEB_GRAPHS))
+@pytest.mark.parametrize("prec", ["fp64", "fp32ir"])
+def test_solve_parity_chebyshev(B, name, prec):
+    g = CHEB_GRAPHS[name]()
+    k = 3 if name == "chunglu" else 1
+    note(f"chebyshev solve parity {name} {prec} k={k}")
+    p = B.FP64 if prec == "fp64" else B.FP32_IR
+    st, ph, bh, refs = solve_both(B, g, k, p, smoother=1)
+    check_solution(g, st, ph, bh, refs)
