@@ -60,7 +60,7 @@ struct WsSel<float> {
     static TailPlan &plan(Workspace &w) { return w.plan32; }
 };
 
-// Algorithmic (compulsory) bytes of one launch of the finest-level cycle kernels, s = value
+// Algorithmic (compulsory) bytes of one launch of a level's cycle kernels, s = value
 // and vector element size: every matrix index and value, row pointer and diagonal once,
 // every vector element the launch reads or writes once.
 double bytes_gs_color(const SolveOp &op, int c, int k, double s) {

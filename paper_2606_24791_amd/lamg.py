@@ -324,7 +324,8 @@ def lamg_profile_kernel(h: Handle, level: int, kernel: int, precision: int = FP6
 
 
 def lamg_timing_start(h: Handle, max_launches: int = 16384) -> None:
-    """Starts in-situ event timing of the finest-level cycle kernels and the coarse tail."""
+    """Starts in-situ event timing of the cycle kernels of the timed level (timed_level in
+    lamg_hierarchy_info) and of the coarse tail."""
     st = _lib.lamg_timing_start(h.ptr, int(max_launches))
     if st != OK:
         raise LamgError(st, "lamg_timing_start")
