@@ -125,55 +125,61 @@ __global__ void k_tv_sweep_color(int64_t cnt, const int32_t *__restrict__ rows,
     xu[3] = (0.0 - a3) / d;
 }
 
-// The same update for long rows, one wave per row: the lanes load 64 entries at a time
-// and form their products (each product is rounded on its own, as in the per-row loop),
-// then lane 0 adds them to the four running sums in CSR order. The diagonal and the
-// lanes past the row's end contribute +0.0, which leaves a sum that started at +0.0
-// unchanged, so every sum is the left-to-right sum of the per-row loop bit for bit.
+// The same update for long rows, one wave per row: the lanes load kTVChunk entries at a time
+// (kTVChunk / 64 gathers in flight per lane) and form their products (each product rounded
+// on its own, as in the per-row loop) into LDS, then lane 0 adds them to the four running
+// sums in CSR order. The diagonal contributes +0.0, which leaves a sum that started at
+// +0.0 unchanged, so every sum is the left-to-right sum of the per-row loop bit for bit.
 constexpr int kTVLongRowsPerBlock = kBlock / 64;
+constexpr int kTVChunk = 512;
 
 __global__ void __launch_bounds__(kBlock)
     k_tv_sweep_long(int64_t cnt, const int32_t *__restrict__ rows, const int32_t *__restrict__ rp,
                     const int32_t *__restrict__ ci, const double *__restrict__ v,
                     double *__restrict__ X) {
-    __shared__ double prod[kTVLongRowsPerBlock][64][kTV];
+    extern __shared__ __align__(16) double tv_lds[];
+    double(*prod)[kTV] = reinterpret_cast<double(*)[kTV]>(tv_lds);  // [rows per block][chunk]
     __shared__ double diag[kTVLongRowsPerBlock];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t t = (int64_t)blockIdx.x * kTVLongRowsPerBlock + wave;
     if (t >= cnt) return;  // uniform per wave; no block-wide barrier below
+    double(*my)[kTV] = prod + (int64_t)wave * kTVChunk;
     const int32_t u = rows[t];
     const int32_t b = rp[u], e = rp[u + 1];
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    for (int32_t j0 = b; j0 < e; j0 += 64) {
-        const int32_t j = j0 + lane;
-        double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
-        if (j < e) {
-            const int32_t c = ci[j];
-            const double w = v[j];
-            if (c == u) {
-                diag[wave] = w;
-            } else {
-                const double *xc = X + (int64_t)c * kTV;
-                p0 = w * xc[0];
-                p1 = w * xc[1];
-                p2 = w * xc[2];
-                p3 = w * xc[3];
+    for (int32_t j0 = b; j0 < e; j0 += kTVChunk) {
+        const int m = (e - j0 < kTVChunk) ? (int)(e - j0) : kTVChunk;
+#pragma unroll 8
+        for (int q = lane; q < kTVChunk; q += 64) {
+            double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+            if (q < m) {
+                const int32_t j = j0 + q;
+                const int32_t c = ci[j];
+                const double w = v[j];
+                if (c == u) {
+                    diag[wave] = w;
+                } else {
+                    const double *xc = X + (int64_t)c * kTV;
+                    p0 = w * xc[0];
+                    p1 = w * xc[1];
+                    p2 = w * xc[2];
+                    p3 = w * xc[3];
+                }
             }
+            my[q][0] = p0;
+            my[q][1] = p1;
+            my[q][2] = p2;
+            my[q][3] = p3;
         }
-        prod[wave][lane][0] = p0;
-        prod[wave][lane][1] = p1;
-        prod[wave][lane][2] = p2;
-        prod[wave][lane][3] = p3;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (lane == 0) {
-            const int m = (e - j0 < 64) ? (int)(e - j0) : 64;
             for (int q = 0; q < m; ++q) {
-                a0 = a0 + prod[wave][q][0];
-                a1 = a1 + prod[wave][q][1];
-                a2 = a2 + prod[wave][q][2];
-                a3 = a3 + prod[wave][q][3];
+                a0 = a0 + my[q][0];
+                a1 = a1 + my[q][1];
+                a2 = a2 + my[q][2];
+                a3 = a3 + my[q][3];
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -724,7 +730,10 @@ void launch_tv_sweep_long(int64_t cnt, const int32_t *rows, const int32_t *rp, c
                           const double *v, double *X, hipStream_t s) {
     if (cnt <= 0) return;
     const unsigned blocks = (unsigned)((cnt + kTVLongRowsPerBlock - 1) / kTVLongRowsPerBlock);
-    k_tv_sweep_long<<<blocks, kBlock, 0, s>>>(cnt, rows, rp, ci, v, X);
+    const size_t lds = sizeof(double) * kTV * kTVChunk * kTVLongRowsPerBlock;
+    LAMG_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tv_sweep_long),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    k_tv_sweep_long<<<blocks, kBlock, lds, s>>>(cnt, rows, rp, ci, v, X);
     LAMG_LAUNCH_CHECK();
 }
 
