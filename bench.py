@@ -16,8 +16,10 @@ The JSON line also carries
             full smoothing pass, the dominant bandwidth kernel; the finest level itself is an
             elimination level on the grids):
             its algorithmic bytes per launch over its mean launch time, both summed over
-            every launch in the timed FP32+IR region (HIP events around each launch on the
-            solve stream), against 8 TB/s HBM;
+            every launch in a second timed FP32+IR region of the same K solves with HIP
+            events attached to every launch on the solve stream (the throughput region runs
+            without events; with --graphs it replays each cycle as a HIP graph, which needs
+            events off), against 8 TB/s HBM;
   coarse_tail: the same timing of the single-workgroup coarse-level kernel, which takes the
             largest share of the solve and is bound by dependent steps, not bytes;
   cpu_baseline: the CPU oracle (single-threaded, FP64) solving the same system once.
@@ -97,6 +99,8 @@ def main() -> int:
                     help="coarse-tail threshold option (-1: library default)")
     ap.add_argument("--smoother", type=int, default=0,
                     help="0: multicolour Gauss-Seidel; 1: Chebyshev on levels with > 32 colours")
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay each cycle as a HIP graph from the second solve on")
     ap.add_argument("--no-elimination", action="store_true",
                     help="aggregation-only hierarchy (no low-degree elimination levels)")
     ap.add_argument("--profile-reps", type=int, default=0,
@@ -129,6 +133,8 @@ def main() -> int:
         over["tail_rows"] = args.tail_rows
     if args.smoother:
         over["smoother"] = args.smoother
+    if args.graphs:
+        over["graphs"] = 1
     opts = B.lamg_default_options(**over)
     h = B.lamg_setup(g, opts)
     torch.cuda.synchronize()
@@ -164,15 +170,17 @@ def main() -> int:
         phi = torch.empty_like(b)
         for _ in range(args.warmup):
             B.lamg_solve(h, b, phi, tol=args.tol, precision=prec, stream=stream)
-        wall, lat, stats, kt = run_steps(prec, phi, True)
-        wall_plain, _, _, _ = run_steps(prec, phi, False)
+        wall, lat, stats, _ = run_steps(prec, phi, False)
+        wall_ev, _, _, kt = run_steps(prec, phi, True)
         ms = 1e3 * wall / args.steps
         results[name] = dict(ms=ms, value=g.nnz_laplacian * k / (wall / args.steps),
                              p50_ms=1e3 * percentile(lat, 50), p99_ms=1e3 * percentile(lat, 99),
                              cycles=stats["cycles"], relres=stats["relres_max"],
                              converged=bool(stats["converged"]), phi=phi.cpu().numpy(),
-                             kt=kt, ms_no_events=1e3 * wall_plain / args.steps, wall=wall)
-        log(f"{name}: {ms:.3f} ms/solve ({results[name]['ms_no_events']:.3f} without events), "
+                             graph_cycles=stats["graph_cycles"],
+                             kt=kt, ms_events=1e3 * wall_ev / args.steps, wall=wall_ev)
+        log(f"{name}: {ms:.3f} ms/solve ({stats['graph_cycles']} of {stats['cycles']} cycles "
+            f"as graphs; {results[name]['ms_events']:.3f} kernel by kernel with events), "
             f"{results[name]['value']:.3e} nnz*RHS/s, cycles={stats['cycles']} "
             f"relres={stats['relres_max']:.2e}")
 
@@ -281,12 +289,14 @@ def main() -> int:
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": byt, "us_per_launch": sec * 1e6,
                      "launches": gs["launches"], "timing": "HIP events attached to every launch "
-                     "(dispatch timestamps) in the timed FP32+IR region, on the solve stream"},
+                     "(dispatch timestamps) in a second timed FP32+IR region of the same K solves, "
+                     "launched kernel by kernel, on the solve stream"},
         "kernels_timed_level": dict(other, level=lt),
         "coarse_tail": dict(tail or {}, bound="latency (dependent steps of one workgroup)",
                             kernel="k_tail<float>"),
-        "events_overhead": {"fp32ir_ms_no_events": r32["ms_no_events"],
-                            "fp64_ms_no_events": results["fp64"]["ms_no_events"]},
+        "launch_modes": {"graph_cycles_per_solve": r32["graph_cycles"],
+                         "fp32ir_ms_kernel_by_kernel_with_events": r32["ms_events"],
+                         "fp64_ms_kernel_by_kernel_with_events": results["fp64"]["ms_events"]},
         "gs_color_isolated": isolated,
         "cpu_baseline": cpu,
         "paper_context": "0.19 us/edge median solve, 1 CPU thread Apple M5 Pro (Julia), "

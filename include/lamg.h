@@ -107,6 +107,17 @@ typedef struct {
                                 for Gauss-Seidel named in Sec. 5 -- of degree 3 on
                                 [lmax / 5, lmax], lmax = the Gershgorin bound of D^{-1} L; one
                                 polynomial per Gauss-Seidel sweep it replaces. */
+    int32_t graphs;          /* 1: from the second solve with the same precision and column
+                                count, each cycle's launch sequence (which depends only on the
+                                cycle's index within the solve) is captured once as a HIP graph
+                                on a stream of the handle and replayed on the caller's stream;
+                                cycles of more than 20000 launches, cycles after the 64th, and
+                                solves timed by lamg_timing_start run as separate launches.
+                                Graphs of two (precision, columns) pairs are kept; a solve that
+                                enlarges the handle's vectors drops them. Pays off only where
+                                launch latency dominates (systems of a few thousand rows).
+                                0 (default): never. Changes only how the cycle is launched,
+                                not what it computes. */
 } lamg_options;
 
 /* Per-level description of a hierarchy. */
@@ -149,6 +160,8 @@ typedef struct {
     int32_t *col_cycles;   /* optional [nrhs] */
     double *history;       /* optional [max_cycles + 1] */
     int32_t history_len;   /* written: entries of history filled */
+    int32_t graph_cycles;  /* written: cycles launched as HIP graphs (captured in this call or
+                              replayed), summed over the call's 32-column chunks */
 } lamg_solve_info;
 
 /* One level of the hierarchy copied to host buffers (parity dumps). Any pointer may be

@@ -82,6 +82,9 @@ static lamg_status guarded(F &&f) {
 
 lamg_handle::~lamg_handle() {
     timer.release();
+    lamg::clear_graphs(ws);
+    if (ws.cap_stream) (void)hipStreamDestroy(ws.cap_stream);
+    ws.cap_stream = nullptr;
     // pinned host mirrors; device arrays are released by their owners before the pool
     if (ws.h_rel) (void)hipHostFree(ws.h_rel);
     if (ws.h_mask) (void)hipHostFree(ws.h_mask);
@@ -135,6 +138,7 @@ void lamg_default_options(lamg_options *opt) {
     opt->tail_rows = 2500;
     opt->elimination = 1;
     opt->smoother = 0;
+    opt->graphs = 0;
 }
 
 lamg_status lamg_setup(const lamg_graph *g, const lamg_options *opt, void *stream,
@@ -146,7 +150,8 @@ lamg_status lamg_setup(const lamg_graph *g, const lamg_options *opt, void *strea
     lamg_default_options(&o);
     if (opt) o = *opt;
     if (o.n_direct < 1 || o.n_direct > 1024 || o.kappa < 0 || o.kappa > 4 || o.tail_rows < 0 ||
-        (o.elimination != 0 && o.elimination != 1) || (o.smoother != 0 && o.smoother != 1))
+        (o.elimination != 0 && o.elimination != 1) || (o.smoother != 0 && o.smoother != 1) ||
+        (o.graphs != 0 && o.graphs != 1))
         return LAMG_INVALID_ARG;
     lamg_handle *h = nullptr;
     lamg_status st = guarded([&]() -> lamg_status {

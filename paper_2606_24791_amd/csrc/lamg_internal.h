@@ -30,6 +30,9 @@ constexpr int kRedQMax = 14;        // quantities per reduction (4x4 normal equa
 constexpr int kTVShortRow = 64;     // test-vector rows longer than this get a wave each
 constexpr int kEllMaxWidth = 32;    // longest row of a level that gets an ELL copy
 constexpr int kTailMaxCols = 2;
+constexpr int kGraphMaxNodes = 20000;  // longer cycles are launched kernel by kernel
+constexpr int kGraphSets = 2;          // (precision, columns) pairs with cached graphs
+constexpr int kGraphMaxCycles = 64;    // later cycles of a solve are launched kernel by kernel
 constexpr int kChebColors = 32;      // smoother 1: levels with more colours use Chebyshev
 constexpr int kChebDegree = 3;       // residual evaluations per Chebyshev sweep
 constexpr double kChebRatio = 5.0;   // smoothed interval [lmax / kChebRatio, lmax]     // solves with more columns run every step as its own kernel
@@ -230,7 +233,24 @@ struct Workspace {
     DArr<char> tlds64, tlds32, tjobs64, tjobs32;  // LDS-resident tail levels
     TailPlan plan64, plan32;
     DArr<int64_t> visits;       // coarse-tail visit counters (per level)
+    // HIP graphs of whole cycles, replayed in later solves with the same precision and column
+    // count: the launch sequence of the i-th cycle of a solve depends only on i (the visit
+    // counters start from zero in every solve; column freezing changes data, not launches)
+    struct CycleGraph {
+        hipGraphExec_t exec = nullptr;
+        std::vector<int64_t> visits_after;  // the host visit counters after the cycle
+    };
+    struct GraphSet {
+        int prec = 0, k = 0;
+        int solves = 0;          // completed solves with this precision and column count
+        bool direct = false;     // a cycle exceeded kGraphMaxNodes or capture failed
+        std::vector<CycleGraph> cycles;
+    };
+    std::vector<GraphSet> gsets;  // least recently used first
+    hipStream_t cap_stream = nullptr;
 };
+// Destroys the cached cycle graphs (their kernel arguments point into the workspace).
+void clear_graphs(Workspace &w);
 
 // In-situ launch timer: a pair of HIP events per timed launch, recorded by the launch
 // itself (hipExtLaunchKernel takes the dispatch's own start and end timestamps), so the

@@ -298,6 +298,7 @@ void ensure_level_vecs(lamg_handle *h, int k) {
     Workspace &w = h->ws;
     std::vector<LevelVecs<T>> &lv = W::lv(w);
     if (W::k(w) >= k && (int)lv.size() == h->nlev) return;
+    clear_graphs(w);  // their kernel arguments point into the vectors replaced here
     Pool &pool = *h->pool;
     lv.clear();
     lv.resize(h->nlev);
@@ -360,6 +361,7 @@ void ensure_level_vecs(lamg_handle *h, int k) {
 void ensure_fine(lamg_handle *h, int k) {
     Workspace &w = h->ws;
     if (w.kf >= k) return;
+    clear_graphs(w);
     Pool &pool = *h->pool;
     int64_t m = h->lev[0].n * k;
     w.phi.alloc(pool, m);
@@ -386,6 +388,67 @@ void ensure_fine(lamg_handle *h, int k) {
     w.kf = k;
 }
 
+// The graph set of solves with this precision and column count, created (evicting the
+// least recently used set beyond kGraphSets) if there is none, and moved to the back.
+Workspace::GraphSet &graph_set(Workspace &w, int prec, int k) {
+    auto it = std::find_if(w.gsets.begin(), w.gsets.end(),
+                           [&](const Workspace::GraphSet &g) { return g.prec == prec && g.k == k; });
+    Workspace::GraphSet g;
+    if (it != w.gsets.end()) {
+        g = std::move(*it);
+        w.gsets.erase(it);
+    } else {
+        g.prec = prec;
+        g.k = k;
+        if ((int)w.gsets.size() >= kGraphSets) {
+            for (Workspace::CycleGraph &c : w.gsets.front().cycles)
+                if (c.exec) (void)hipGraphExecDestroy(c.exec);
+            w.gsets.erase(w.gsets.begin());
+        }
+    }
+    w.gsets.push_back(std::move(g));
+    return w.gsets.back();
+}
+
+// Records the launches `body` makes on a capture stream of the handle into a graph,
+// instantiates it and launches it on `s`. Returns nullptr, having launched nothing, if
+// capture is not possible or the graph has more than kGraphMaxNodes nodes; the caller
+// then runs `body` on `s` itself.
+template <class F>
+hipGraphExec_t capture_and_launch(lamg_handle *h, hipStream_t s, F &&body) {
+    Workspace &w = h->ws;
+    if (!w.cap_stream && hipStreamCreateWithFlags(&w.cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        w.cap_stream = nullptr;
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (hipStreamBeginCapture(w.cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    try {
+        body(w.cap_stream);
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        if (hipStreamEndCapture(w.cap_stream, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(w.cap_stream, &graph);
+    hipGraphExec_t exec = nullptr;
+    size_t nodes = 0;
+    if (e == hipSuccess && graph && hipGraphGetNodes(graph, nullptr, &nodes) == hipSuccess &&
+        nodes <= (size_t)kGraphMaxNodes &&
+        hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        LAMG_HIP(hipGraphLaunch(exec, s));
+        return exec;
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return nullptr;
+}
+
 double acf_of(const std::vector<double> &hist) {
     int last = (int)hist.size() - 1;
     int cnt = std::min(last, 5);
@@ -409,7 +472,7 @@ void emit_columns(lamg_handle *h, int k, const int32_t *d_mask, double *phi_out)
 lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol, int max_cycles,
                         bool fp32, double *phi_out, std::vector<double> &relres,
                         std::vector<int32_t> &cycles, std::vector<double> &acf,
-                        std::vector<double> &hist0) {
+                        std::vector<double> &hist0, int &graph_cycles) {
     hipStream_t s = h->stream;
     Workspace &w = h->ws;
     Level &L0 = h->lev[0];
@@ -466,33 +529,69 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
                       &w.plan64, w.visits.p};
     Cycle<float> c32{h, k, s, &w.lv32, std::vector<int64_t>(h->nlev, 0), w.partial.p, l0, lt,
                      &w.plan32, w.visits.p};
-    int cyc = 0;
-    while (n_active > 0 && cyc < max_cycles) {
+    // One cycle with its fine-level residual, recombination and relative residuals: the
+    // launches depend only on the cycle's index (through the Beatty visit counters and
+    // the history slots), so from the second solve of this precision and column count
+    // each index's launches are captured once and replayed as a graph.
+    auto cycle_body = [&](hipStream_t st) {
+        c64.s = st;
+        c32.s = st;
         if (!fp32) {
             cycle<double>(c64, 0, w.phi.p, w.b.p);
         } else {
             // FP32 cycle on the scaled residual equation, FP64 update
-            run_maxabs(n, k, w.r.p, w.partial.p, w.scale.p, s);
+            run_maxabs(n, k, w.r.p, w.partial.p, w.scale.p, st);
             LevelVecs<float> &v0 = w.lv32[0];
-            run_to_f32_scaled(n, k, w.r.p, w.scale.p, v0.f.p, s);
-            run_fill<float>(v0.x.p, nk, 0.0f, s);
+            run_to_f32_scaled(n, k, w.r.p, w.scale.p, v0.f.p, st);
+            run_fill<float>(v0.x.p, nk, 0.0f, st);
             cycle<float>(c32, 0, v0.x.p, v0.f.p);
-            run_add_scaled_f32(n, k, v0.x.p, w.scale.p, w.phi.p, s);
+            run_add_scaled_f32(n, k, v0.x.p, w.scale.p, w.phi.p, st);
         }
         {
             Timed tm(h, LAMG_KERNEL_RESIDUAL, 0, bytes_residual(op0, k, 8.0));
-            run_residual<double>(op0, op0.v64.p, op0.d64.p, w.phi.p, w.b.p, w.r.p, k, s, true);
+            run_residual<double>(op0, op0.v64.p, op0.d64.p, w.phi.p, w.b.p, w.r.p, k, st, true);
         }
         if (!direct && kappa > 0) {
-            run_recombine_fine(n, k, hm, w.phi.p, w.r.p, w.hphi.p, w.hr.p, w.partial.p, w.alpha_f.p, s);
+            run_recombine_fine(n, k, hm, w.phi.p, w.r.p, w.hphi.p, w.hr.p, w.partial.p, w.alpha_f.p, st);
             int slot = hnext % kappa;
-            run_copy<double>(w.hphi.p + slot * nk, w.phi.p, nk, s);
-            run_copy<double>(w.hr.p + slot * nk, w.r.p, nk, s);
+            run_copy<double>(w.hphi.p + slot * nk, w.phi.p, nk, st);
+            run_copy<double>(w.hr.p + slot * nk, w.r.p, nk, st);
+        }
+        run_relres(n, k, w.r.p, w.nb.p, w.partial.p, w.rel.p, st);
+        c64.s = s;
+        c32.s = s;
+    };
+    Workspace::GraphSet *gset = nullptr, *gs = nullptr;
+    if (h->opt.graphs && !h->timer.on) {
+        gset = &graph_set(w, fp32 ? 1 : 0, k);
+        if (gset->solves > 0 && !gset->direct) gs = gset;  // the first solve runs directly
+    }
+    int cyc = 0;
+    while (n_active > 0 && cyc < max_cycles) {
+        std::vector<int64_t> &vis = fp32 ? c32.visits : c64.visits;
+        if (cyc >= kGraphMaxCycles) gs = nullptr;
+        if (gs && cyc < (int)gs->cycles.size()) {
+            LAMG_HIP(hipGraphLaunch(gs->cycles[cyc].exec, s));
+            vis = gs->cycles[cyc].visits_after;
+            ++graph_cycles;
+        } else if (gs) {
+            hipGraphExec_t ex = capture_and_launch(h, s, cycle_body);
+            if (ex) {
+                gs->cycles.push_back(Workspace::CycleGraph{ex, vis});
+                ++graph_cycles;
+            } else {
+                gs->direct = true;
+                gs = nullptr;
+                cycle_body(s);
+            }
+        } else {
+            cycle_body(s);
+        }
+        if (!direct && kappa > 0) {
             ++hnext;
             if (hm < kappa) ++hm;
         }
         ++cyc;
-        run_relres(n, k, w.r.p, w.nb.p, w.partial.p, w.rel.p, s);
         w.rel.download(w.h_rel, k, s);
         LAMG_HIP(hipStreamSynchronize(s));
         bool any_new = false;
@@ -541,6 +640,7 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
         acf[c] = acf_of(hist[c]);
     }
     hist0 = hist[0];
+    if (gset) ++gset->solves;
     return st;
 }
 
@@ -605,6 +705,13 @@ void profile_impl(lamg_handle *h, int level, int kernel, int k, int reps, double
 }
 
 }  // namespace
+
+void clear_graphs(Workspace &w) {
+    for (Workspace::GraphSet &g : w.gsets)
+        for (Workspace::CycleGraph &c : g.cycles)
+            if (c.exec) (void)hipGraphExecDestroy(c.exec);
+    w.gsets.clear();
+}
 
 thread_local LaunchEvents *t_launch_events = nullptr;
 
@@ -678,12 +785,13 @@ lamg_status run_solve(lamg_handle *h, const double *b, int nrhs, double tol, int
     int32_t cyc_max = 0;
     double rel_max = 0.0, acf_max = 0.0;
     std::vector<double> hist0;
+    int graph_cycles = 0;
     for (int c0 = 0; c0 < nrhs; c0 += 32) {
         int k = std::min(32, nrhs - c0);
         std::vector<double> rel(k), acf(k), hist;
         std::vector<int32_t> cyc(k);
         lamg_status s2 = solve_chunk(h, b + (int64_t)c0 * n, k, tol, max_cycles, fp32,
-                                     phi + (int64_t)c0 * n, rel, cyc, acf, hist);
+                                     phi + (int64_t)c0 * n, rel, cyc, acf, hist, graph_cycles);
         if (s2 != LAMG_OK) st = s2;
         if (c0 == 0) hist0 = hist;
         for (int c = 0; c < k; ++c) {
@@ -701,6 +809,7 @@ lamg_status run_solve(lamg_handle *h, const double *b, int nrhs, double tol, int
         info->history_len = (int32_t)std::min<size_t>(hist0.size(), (size_t)max_cycles + 1);
         if (info->history)
             for (int i = 0; i < info->history_len; ++i) info->history[i] = hist0[i];
+        info->graph_cycles = graph_cycles;
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return st;

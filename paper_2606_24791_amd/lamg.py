@@ -35,7 +35,7 @@ class lamg_options(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("n_direct", C.c_int32), ("enable_veto", C.c_int32),
                 ("enable_caliber2", C.c_int32), ("kappa", C.c_int32), ("build_fp32", C.c_int32),
                 ("keep_setup_data", C.c_int32), ("tail_rows", C.c_int32),
-                ("elimination", C.c_int32), ("smoother", C.c_int32)]
+                ("elimination", C.c_int32), ("smoother", C.c_int32), ("graphs", C.c_int32)]
 
 
 class lamg_hier_info(C.Structure):
@@ -52,7 +52,7 @@ class lamg_hier_info(C.Structure):
 class lamg_solve_info(C.Structure):
     _fields_ = [("cycles", C.c_int32), ("relres_max", C.c_double), ("acf_max", C.c_double),
                 ("seconds", C.c_double), ("relres", C.c_void_p), ("col_cycles", C.c_void_p),
-                ("history", C.c_void_p), ("history_len", C.c_int32)]
+                ("history", C.c_void_p), ("history_len", C.c_int32), ("graph_cycles", C.c_int32)]
 
 
 class lamg_level_export(C.Structure):
@@ -258,7 +258,8 @@ def lamg_solve(h: Handle, b, phi, tol: float = 1e-8, max_cycles: int = 300,
         raise LamgError(st, "lamg_solve")
     out = dict(status=st, converged=(st == OK), cycles=int(info.cycles),
                relres_max=float(info.relres_max), acf_max=float(info.acf_max),
-               seconds=float(info.seconds), relres=rel, col_cycles=cyc)
+               seconds=float(info.seconds), relres=rel, col_cycles=cyc,
+               graph_cycles=int(info.graph_cycles))
     if hist is not None:
         out["history"] = hist[: info.history_len].copy()
     return out

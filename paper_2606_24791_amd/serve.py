@@ -71,9 +71,11 @@ def hierarchy_estimate(graph) -> int:
 class Server:
     def __init__(self, graphs: dict, hbm_budget: float = 200e9, slots: int = 4,
                  precision: int = B.FP32_IR, tol: float = 1e-8, max_columns: int = 32,
-                 use_torch_allocator: bool = True, estimate=None, smoother: int = 0):
+                 use_torch_allocator: bool = True, estimate=None, smoother: int = 0,
+                 hip_graphs: bool = False):
         self.graphs = graphs
         self.smoother = smoother  # setup option: 1 = Chebyshev on levels with many colours
+        self.hip_graphs = hip_graphs  # setup option: replay repeated cycles as HIP graphs
         # device bytes charged for a graph's setup before its hierarchy exists
         self.estimate = estimate or hierarchy_estimate
         self.budget = float(hbm_budget)
@@ -234,7 +236,9 @@ class Server:
                     self.cache.move_to_end(gid)
             hit = entry is not None
             if not hit:
-                h = B.lamg_setup(g, B.lamg_default_options(smoother=self.smoother), stream=stream)
+                h = B.lamg_setup(g, B.lamg_default_options(smoother=self.smoother,
+                                                           graphs=int(self.hip_graphs)),
+                                 stream=stream)
                 info = B.lamg_hierarchy_info(h)
                 entry = dict(handle=h, levels=info["n"], bytes=float(info["bytes_device"]), ws=0.0)
                 ws_est = float(workspace_bytes(info["n"], cols, fp32))
@@ -447,6 +451,8 @@ def main(argv=None) -> int:
     ap.add_argument("--log-batches", action="store_true")
     ap.add_argument("--smoother", type=int, default=0,
                     help="0: multicolour Gauss-Seidel; 1: Chebyshev on levels with > 32 colours")
+    ap.add_argument("--hip-graphs", action="store_true",
+                    help="replay each cycle of repeated (precision, columns) solves as a HIP graph")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--seed", type=int, default=0)
     a = ap.parse_args(argv)
@@ -458,13 +464,15 @@ def main(argv=None) -> int:
 
     def one(rate, tag):
         reqs = request_stream(graphs, a.requests, rate, a.kmax, a.seed, shared_rhs=True)
-        srv = Server(graphs, hbm_budget=a.budget_gb * 1e9, slots=a.slots, smoother=a.smoother)
+        srv = Server(graphs, hbm_budget=a.budget_gb * 1e9, slots=a.slots, smoother=a.smoother,
+                     hip_graphs=a.hip_graphs)
         srv.progress_every = max(1, a.requests // 10)
         srv.log_batches = a.log_batches
         out = srv.run(reqs)
         srv.close()
         out.update(run=tag, offered_rate=rate if rate > 0 else None, requests_total=a.requests,
-                   graphs=len(graphs), slots=a.slots, kmax=a.kmax, smoother=a.smoother)
+                   graphs=len(graphs), slots=a.slots, kmax=a.kmax, smoother=a.smoother,
+                   hip_graphs=a.hip_graphs)
         out["answered_per_s"] = out["answered"] / out["wall_s"]
         print(json.dumps(out), flush=True)
         log(f"{tag}: {out['answered_per_s']:.2f} req/s p50 {out['p50_ms']:.1f} ms "

@@ -217,6 +217,46 @@ def test_repeat_solves_are_bitwise_identical(B):
     h.close()
 
 
+@pytest.mark.parametrize("name", ["chunglu", "aniso_ragged"])
+def test_graph_replay_matches_kernel_by_kernel_launches(B, name):
+    """Cycles replayed as HIP graphs (from the second solve of a precision and column count)
+    give the kernel-by-kernel results bit for bit, on every replay, with other work and
+    synchronisations between the replays; a wider solve reallocates the workspace and a
+    later narrow one captures afresh."""
+    import torch
+
+    g = GRAPHS[name]()
+    note(f"graph replay {name}")
+    bh = I.rhs(g.n, 4, seed=21)
+    hg = B.lamg_setup(g, B.lamg_default_options(graphs=1))
+    hd = B.lamg_setup(g)
+    seq = [(B.FP32_IR, 1)] * 3 + [(B.FP64, 1)] * 3 + [(B.FP32_IR, 4)] * 2 + [(B.FP32_IR, 1)] * 3
+    seen = {}
+    for i, (prec, k) in enumerate(seq):
+        b = torch.tensor(bh[:k], device="cuda")
+        out = []
+        for h in (hg, hd):
+            phi = torch.empty_like(b)
+            st = B.lamg_solve(h, b, phi, precision=prec)
+            assert st["converged"]
+            out.append((phi.cpu().numpy(), st))
+            x = torch.randn(1 << 16, device="cuda")  # eager work between the replays
+            (x * 2.0).sum().item()
+            torch.cuda.synchronize()
+        (pg, sg), (pd, sd) = out
+        assert sd["graph_cycles"] == 0
+        # the first solve of a (precision, columns) pair and the first after the
+        # reallocation run kernel by kernel; every later one replays all its cycles
+        key = (prec, k, i >= 8)
+        expect = sg["cycles"] if key in seen else 0
+        seen[key] = True
+        assert sg["graph_cycles"] == expect, (i, sg["graph_cycles"], expect)
+        assert np.array_equal(pg, pd), i
+        assert sg["cycles"] == sd["cycles"] and np.array_equal(sg["relres"], sd["relres"])
+    hg.close()
+    hd.close()
+
+
 def test_not_converged_still_returns_iterate(B):
     import torch
 
