@@ -124,7 +124,7 @@ def solve_both(B, g, k, precision, seed=11, tol=TOL, elimination=True, smoother=
     return st, ph, bh, refs
 
 
-def check_solution(g, st, ph, bh, refs, tol=TOL):
+def check_solution(g, st, ph, bh, refs, tol=TOL, sol_tol=SOL_TOL):
     import scipy.sparse as sp
 
     W = sp.csr_matrix((g.weight, g.col_idx, g.row_ptr), shape=(g.n, g.n))
@@ -137,7 +137,7 @@ def check_solution(g, st, ph, bh, refs, tol=TOL):
         assert abs(st["relres"][c] - r) <= 1e-3 * tol
         assert abs(ph[c].mean()) <= 1e-12 * np.abs(ph[c]).max()
         err = np.linalg.norm(ph[c] - phi_o) / np.linalg.norm(phi_o)
-        assert err <= SOL_TOL, (c, err)
+        assert err <= sol_tol, (c, err)
         assert abs(st["col_cycles"][c] - so["cycles"]) <= 2, (st["col_cycles"][c], so["cycles"])
 
 
@@ -159,6 +159,19 @@ def test_solve_parity_aggregation_only(B, name, prec):
     st, ph, bh, refs = solve_both(B, g, 1, B.FP64 if prec == "fp64" else B.FP32_IR,
                                   elimination=False)
     check_solution(g, st, ph, bh, refs)
+
+
+@pytest.mark.parametrize("name", ["grid64", "aniso_ragged", "chunglu"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32ir"])
+def test_solve_parity_low_accuracy(B, name, prec):
+    """Relative residual 1e-4 (the lower-accuracy setting of the evaluation, Sec. 4): the
+    solve stops after the oracle's cycle count, at the oracle's iterate: to rounding in FP64;
+    FP32 cycles differ from it by their rounding, well inside the four digits asked for."""
+    g = GRAPHS[name]()
+    note(f"solve parity tol 1e-4 {name} {prec} n={g.n}")
+    st, ph, bh, refs = solve_both(B, g, 1, B.FP64 if prec == "fp64" else B.FP32_IR, tol=1e-4)
+    check_solution(g, st, ph, bh, refs, tol=1e-4, sol_tol=1e-9 if prec == "fp64" else 1e-5)
+    assert st["cycles"] == refs[0][1]["cycles"]
 
 
 def test_multi_rhs_columns_match_oracle_and_single_solves(B):
