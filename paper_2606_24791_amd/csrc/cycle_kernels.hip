@@ -494,24 +494,45 @@ __device__ inline void solve_rcf(const double *q, int m, double *alpha) {
     for (int i = 0; i < 4; ++i) alpha[i] = (i < m) ? a[i] * s[i] : 0.0;
 }
 
+// Totals over nblk block partials (partial[(b Q + i) k + c]) of Q x k quantities into
+// tot[i * 32 + c] (then a barrier). A group of G lanes takes one quantity (G the largest
+// power of two up to 64 with Q k G <= blockDim; groups loop over the quantities): lane g
+// combines the partials b = g, g + G, ... in order and the group then combines its lanes
+// by an xor butterfly, lane 0's value being the total. The order depends only on nblk, k
+// and blockDim, so every launch of the same shape gives the same bits.
+template <int Q, bool MAX>
+__device__ inline void group_totals(int nblk, int k, const double *__restrict__ partial,
+                                    double *tot) {
+    const int nq = Q * k;
+    int G = 64;
+    while (G > 1 && nq * G > (int)blockDim.x) G >>= 1;
+    const int groups = (int)blockDim.x / G;
+    const int grp = (int)threadIdx.x / G, g = (int)threadIdx.x & (G - 1);
+    for (int q0 = 0; q0 < nq; q0 += groups) {
+        const int idx = q0 + grp;
+        const bool live = idx < nq;
+        const int i = live ? idx / k : 0, c = live ? idx - i * k : 0;
+        double s = 0.0;
+        if (live)
+            for (int b = g; b < nblk; b += G) {
+                const double v = partial[((int64_t)b * Q + i) * k + c];
+                s = MAX ? fmax(s, v) : s + v;
+            }
+        for (int o = G >> 1; o > 0; o >>= 1) {
+            const double t = __shfl_xor(s, o, 64);
+            s = MAX ? fmax(s, t) : s + t;
+        }
+        if (live && g == 0) tot[i * 32 + c] = s;
+    }
+    __syncthreads();
+}
+
 template <int R>
 __global__ void __launch_bounds__(kBlock)
     k_red_final(int nblk, int k, const double *__restrict__ partial, Fin fin) {
     constexpr int Q = RedQ<R>::Q;
     __shared__ double tot[Q * 32];
-    for (int idx = threadIdx.x; idx < Q * k; idx += blockDim.x) {
-        int i = idx / k, c = idx % k;
-        double s = (R == R_MAXABS) ? 0.0 : 0.0;
-        for (int b = 0; b < nblk; ++b) {
-            double v = partial[((int64_t)b * Q + i) * k + c];
-            if (R == R_MAXABS)
-                s = fmax(s, v);
-            else
-                s += v;
-        }
-        tot[i * 32 + c] = s;
-    }
-    __syncthreads();
+    group_totals<Q, R == R_MAXABS>(nblk, k, partial, tot);
     int c = threadIdx.x;
     if (c >= k) return;
     if (R == R_MU) {
@@ -536,6 +557,13 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
+// Whether the blocks of an n x k update can each add the nblk partial sums of a
+// two-quantity reduction themselves (the fused launch) instead of reading scalars formed
+// once by one block: their extra reads, blocks x nblk x 2k doubles from L2, must stay small.
+inline bool fuse_totals(int64_t n, int k, int nblk) {
+    return (int64_t)rc_blocks(n, k) * nblk * 2 * k <= kFuseTotalsMax;
+}
+
 inline int red_blocks(int64_t n, int k) {
     int lkp = kp_log2(k);
     int64_t rows_blk = kBlock >> lkp;
@@ -554,29 +582,28 @@ void reduce(int64_t n, int k, RedIn in, double *partial, Fin fin, hipStream_t s)
     LAMG_LAUNCH_CHECK();
 }
 
-// e += alpha (e1 - e); rho -= alpha (rho - rho1)
+// e += alpha (e1 - e); rho -= alpha (rho - rho1); with keep, (e1, rho1) = the result
 template <class T>
 __global__ void k_rc2_update(int64_t n, int k, int lkp, T *__restrict__ e, T *__restrict__ rho,
-                             const T *__restrict__ e1, const T *__restrict__ rho1,
-                             const double *__restrict__ alpha) {
+                             T *e1, T *rho1, const double *__restrict__ alpha, int keep) {
     ROWCOL(n, lkp)
     T a = (T)alpha[c];
     T ev = e[t], rv = rho[t];
-    e[t] = ev + a * (e1[t] - ev);
-    rho[t] = rv - a * (rv - rho1[t]);
+    const T en = ev + a * (e1[t] - ev);
+    const T rn = rv - a * (rv - rho1[t]);
+    e[t] = en;
+    rho[t] = rn;
+    if (keep) {
+        e1[t] = en;
+        rho1[t] = rn;
+    }
 }
 
-// Column totals of a two-quantity reduction from its block partials, added in block order
-// as k_red_final adds them, into tot[i][c] of the calling block (followed by a barrier).
+// Column totals of a two-quantity reduction from its block partials, in k_red_final's
+// order (same block size), into tot[i][c] of the calling block (followed by a barrier).
 __device__ inline void block_totals2(int nblk, int k, const double *__restrict__ partial,
                                      double (*tot)[32]) {
-    for (int idx = threadIdx.x; idx < 2 * k; idx += blockDim.x) {
-        const int i = idx >= k ? 1 : 0, c = idx - i * k;
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += partial[((int64_t)b * 2 + i) * k + c];
-        tot[i][c] = s;
-    }
-    __syncthreads();
+    group_totals<2, false>(nblk, k, partial, &tot[0][0]);
 }
 
 // Energy correction and prolongation in one launch: every block forms mu per column from
@@ -885,31 +912,45 @@ void run_rc2(int64_t n, T *e, T *rho, const T *e1, const T *rho1, int k, double 
              double *alpha, hipStream_t s) {
     RedIn in{rho, rho1, nullptr, nullptr, 0, 0};
     reduce<T, R_RC2>(n, k, in, partial, Fin{alpha, nullptr, 1.0, 0}, s);
-    k_rc2_update<T><<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), e, rho, e1, rho1, alpha);
+    k_rc2_update<T><<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), e, rho, const_cast<T *>(e1),
+                                                       const_cast<T *>(rho1), alpha, 0);
     LAMG_LAUNCH_CHECK();
 }
 
 template <class T>
 void run_mu_prolong(const SolveOp &op, const T *w0, const T *w1, int64_t nc, const T *ec,
-                    const T *fc, const T *rho, int k, double *partial, T *x, hipStream_t s) {
+                    const T *fc, const T *rho, int k, double *partial, double *scal, T *x,
+                    hipStream_t s) {
     const int nblk = red_blocks(nc, k);
     RedIn in{ec, fc, rho, nullptr, 0, 0};
     k_red_partial<T, R_MU><<<nblk, kBlock, 0, s>>>(nc, k, kp_log2(k), in, partial);
     LAMG_LAUNCH_CHECK();
-    launch_kernel(k_prolong_mu<T>, dim3(rc_blocks(op.n, k)), dim3(kBlock), 0, s, op.n, k,
-                  kp_log2(k), op.p0.p, op.p1.p, w0, w1, ec, nblk, (const double *)partial, x);
+    if (fuse_totals(op.n, k, nblk)) {
+        launch_kernel(k_prolong_mu<T>, dim3(rc_blocks(op.n, k)), dim3(kBlock), 0, s, op.n, k,
+                      kp_log2(k), op.p0.p, op.p1.p, w0, w1, ec, nblk, (const double *)partial, x);
+    } else {
+        k_red_final<R_MU><<<1, kBlock, 0, s>>>(nblk, k, partial, Fin{scal, nullptr, 1.0, 0});
+        launch_kernel(k_prolong<T>, dim3(rc_blocks(op.n, k)), dim3(kBlock), 0, s, op.n, k,
+                      kp_log2(k), op.p0.p, op.p1.p, w0, w1, ec, (const double *)scal, x);
+    }
     LAMG_LAUNCH_CHECK();
 }
 
 template <class T>
-void run_rc2_keep(int64_t n, T *e, T *rho, T *e1, T *rho1, int k, double *partial, bool keep,
-                  hipStream_t s) {
+void run_rc2_keep(int64_t n, T *e, T *rho, T *e1, T *rho1, int k, double *partial,
+                  double *scal, bool keep, hipStream_t s) {
     const int nblk = red_blocks(n, k);
     RedIn in{rho, rho1, nullptr, nullptr, 0, 0};
     k_red_partial<T, R_RC2><<<nblk, kBlock, 0, s>>>(n, k, kp_log2(k), in, partial);
     LAMG_LAUNCH_CHECK();
-    k_rc2_fused<T><<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), e, rho, e1, rho1, nblk,
-                                                      partial, keep ? 1 : 0);
+    if (fuse_totals(n, k, nblk)) {
+        k_rc2_fused<T><<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), e, rho, e1, rho1, nblk,
+                                                          partial, keep ? 1 : 0);
+    } else {
+        k_red_final<R_RC2><<<1, kBlock, 0, s>>>(nblk, k, partial, Fin{scal, nullptr, 1.0, 0});
+        k_rc2_update<T><<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), e, rho, e1, rho1, scal,
+                                                           keep ? 1 : 0);
+    }
     LAMG_LAUNCH_CHECK();
 }
 
@@ -1001,8 +1042,10 @@ void run_zero_cols(int64_t n, int k, const int32_t *zero_mask, double *x, hipStr
     template void run_cheb_sweep<T>(const SolveOp &, double, const T *, const T *, const T *,     \
                                     const T *, T *, T *, int, hipStream_t, bool);                 \
     template void run_mu_prolong<T>(const SolveOp &, const T *, const T *, int64_t, const T *,    \
-                                    const T *, const T *, int, double *, T *, hipStream_t);       \
-    template void run_rc2_keep<T>(int64_t, T *, T *, T *, T *, int, double *, bool, hipStream_t); \
+                                    const T *, const T *, int, double *, double *, T *,           \
+                                    hipStream_t);                                                 \
+    template void run_rc2_keep<T>(int64_t, T *, T *, T *, T *, int, double *, double *, bool,     \
+                                  hipStream_t);                                                   \
     template void run_prolong<T>(const SolveOp &, const T *, const T *, const T *,                \
                                  const double *, T *, int, hipStream_t);                          \
     template void run_fill<T>(T *, int64_t, T, hipStream_t);                                      \

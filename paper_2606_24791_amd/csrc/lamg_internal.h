@@ -27,6 +27,9 @@ constexpr int kLongRow = 32;        // rows with more off-diagonals go to the wa
 constexpr int kBlock = 256;         // threads per block of every kernel
 constexpr int kRedBlocksMax = 256;  // partial-sum blocks of a reduction
 constexpr int kRedQMax = 14;        // quantities per reduction (4x4 normal equations + rhs)
+// Largest number of partial-sum reads (doubles, over all blocks) that an update launch
+// may spend on forming its per-column scalars itself.
+constexpr int64_t kFuseTotalsMax = 1 << 15;
 constexpr int kTVShortRow = 64;     // test-vector rows longer than this get a wave each
 constexpr int kEllMaxWidth = 32;    // longest row of a level that gets an ELL copy
 constexpr int kTailMaxCols = 2;
@@ -389,14 +392,18 @@ void run_inject_add(const SolveOp &op, const T *ec, T *x, int k, hipStream_t s);
 template <class T>
 void run_restrict(const SolveOp &op, const T *rw, const T *r, T *fc, int k, hipStream_t s,
                   T *zero_xc = nullptr);
-// mu = <e_c, f_c> / <e_c, f_c - rho> per column, then x += mu P e_c (two launches).
+// mu = <e_c, f_c> / <e_c, f_c - rho> per column, then x += mu P e_c. Two launches when
+// every block of the update can afford to add the partial sums itself, else three (the
+// per-column scalars formed once into `scal`, k doubles); the arithmetic is the same.
 template <class T>
 void run_mu_prolong(const SolveOp &op, const T *w0, const T *w1, int64_t nc, const T *ec,
-                    const T *fc, const T *rho, int k, double *partial, T *x, hipStream_t s);
-// Two-iterate recombination (two launches); with keep, (e1, rho1) = the recombined pair.
+                    const T *fc, const T *rho, int k, double *partial, double *scal, T *x,
+                    hipStream_t s);
+// Two-iterate recombination (two or three launches, as above); with keep, (e1, rho1) = the
+// recombined pair.
 template <class T>
-void run_rc2_keep(int64_t n, T *e, T *rho, T *e1, T *rho1, int k, double *partial, bool keep,
-                  hipStream_t s);
+void run_rc2_keep(int64_t n, T *e, T *rho, T *e1, T *rho1, int k, double *partial,
+                  double *scal, bool keep, hipStream_t s);
 template <class T>
 void run_prolong(const SolveOp &op, const T *w0, const T *w1, const T *ec, const double *mu,
                  T *x, int k, hipStream_t s);

@@ -277,7 +277,8 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
         const bool again = j < nvis;
         if (j >= 2) {  // recombine with the previous visit's pair, keep it if revisiting
             run_residual<T>(cop, P::v(cop), P::d(cop), cv.x.p, cv.f.p, cv.rho.p, k, s, false);
-            run_rc2_keep<T>(Lc.n, cv.x.p, cv.rho.p, cv.x1.p, cv.rho1.p, k, C.partial, again, s);
+            run_rc2_keep<T>(Lc.n, cv.x.p, cv.rho.p, cv.x1.p, cv.rho1.p, k, C.partial, cv.alpha.p,
+                            again, s);
         } else {  // first visit: the pair (x, rho) is saved by the residual launch
             run_residual<T>(cop, P::v(cop), P::d(cop), cv.x.p, cv.f.p, cv.rho.p, k, s, false,
                             again ? cv.x1.p : nullptr, again ? cv.rho1.p : nullptr);
@@ -286,7 +287,7 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
     {  // energy correction and prolongation
         Timed tm(h, timed ? LAMG_KERNEL_PROLONG : -1, prec_id<T>(), bytes_prolong(op, k, sz));
         run_mu_prolong<T>(op, P::w0(op), P::w1(op), Lc.n, cv.x.p, cv.f.p, cv.rho.p, k, C.partial,
-                          x, s);
+                          cv.mu.p, x, s);
     }
     smooth(2);
 }
