@@ -219,7 +219,14 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // Lane split of a short-row launch: log2 of the lanes per row, at most a wave per row.
-inline int short_llpr(int lkp, int lpr) {
+// With 16 or more columns a row's column lanes alone hold half a wave or more; when the
+// launch has rows enough for at least 4096 such waves (rows x column lanes >= 2^18) they
+// do not split the entries further: each lane then keeps its row's loads in flight on its
+// own and no shuffle combines the parts (measured 1.3-1.8x faster per pass on levels of
+// 50 K rows and more at k = 16 and 32; on smaller launches the split stays faster).
+constexpr int64_t kNoSplitLanes = 1 << 18;
+inline int short_llpr(int lkp, int lpr, int64_t nrows) {
+    if (lkp >= 4 && (nrows << lkp) >= kNoSplitLanes) return 0;
     int llpr = ilog2(lpr);
     if (lkp + llpr > 6) llpr = 6 - lkp;
     if (llpr < 0) llpr = 0;
@@ -235,7 +242,7 @@ void launch_csr(int64_t r0, int64_t nrows, const int32_t *rows, int skip_long, c
                 ChebArgs<T> ch = ChebArgs<T>()) {
     if (nrows <= 0) return;
     int lkp = kp_log2(k);
-    int llpr = short_llpr(lkp, lpr);
+    int llpr = short_llpr(lkp, lpr, nrows);
     int lg = lkp + llpr;
     int64_t groups_per_block = kBlock >> lg;
     unsigned grid = (unsigned)((nrows + groups_per_block - 1) / groups_per_block);
@@ -278,7 +285,7 @@ void launch_csr_both(int64_t r0, int64_t nrows, const int32_t *rows, int skip_lo
         return;
     }
     int lkp = kp_log2(k);
-    int llpr = short_llpr(lkp, lpr);
+    int llpr = short_llpr(lkp, lpr, nrows);
     int64_t groups_per_block = kBlock >> (lkp + llpr);
     int64_t sblocks = (nrows + groups_per_block - 1) / groups_per_block;
     launch_kernel(k_csr_mixed<T, OP, FINE>, dim3((unsigned)(sblocks + nlong)), dim3(kBlock), 0, s,

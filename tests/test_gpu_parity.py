@@ -174,6 +174,37 @@ def test_solve_parity_low_accuracy(B, name, prec):
     assert st["cycles"] == refs[0][1]["cycles"]
 
 
+@pytest.mark.parametrize("name,k", [("aniso_ragged", 32), ("aniso_ragged", 16),
+                                    ("lognormal40", 32)])
+def test_wide_blocks_of_columns(B, name, k):
+    """16 and 32 columns: passes over enough rows give each row its column lanes only (no
+    split of the entries), smaller ones split them; every column meets the tolerance in
+    the true residual and the first and last agree with the oracle's solves."""
+    import scipy.sparse as sp
+    import torch
+
+    g = I.grid3d(40, 40, 40, "lognormal", seed=4) if name == "lognormal40" else GRAPHS[name]()
+    note(f"wide block {name} k={k} n={g.n}")
+    bh = I.rhs(g.n, k, seed=17)
+    h = B.lamg_setup(g)
+    b = torch.tensor(bh, device="cuda")
+    phi = torch.empty_like(b)
+    st = B.lamg_solve(h, b, phi, tol=TOL, max_cycles=100, precision=B.FP32_IR)
+    h.close()
+    assert st["converged"], st
+    ph = phi.cpu().numpy()
+    W = sp.csr_matrix((g.weight, g.col_idx, g.row_ptr), shape=(g.n, g.n))
+    L = sp.diags(np.asarray(W.sum(1)).ravel()) - W
+    for c in range(k):
+        bc = bh[c] - bh[c].mean()
+        assert np.linalg.norm(bc - L @ ph[c]) / np.linalg.norm(bc) <= TOL * 1.0001, c
+    oh = O.Hierarchy(g, seed=1)
+    for c in (0, k - 1):
+        ref, _, _ = oh.solve(bh[c], TOL, 100)
+        err = np.linalg.norm(ph[c] - ref) / np.linalg.norm(ref)
+        assert err <= SOL_TOL, (c, err)
+
+
 def test_multi_rhs_columns_match_oracle_and_single_solves(B):
     import torch
 
