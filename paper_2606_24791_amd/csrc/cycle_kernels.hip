@@ -369,36 +369,52 @@ struct RedIn {
     int64_t hstride;            // RCF: elements between history slots
 };
 
+// One element's operands of a reduction (load) and its terms (add), kept apart so that
+// several elements' loads can be in flight before their terms are added in order.
 template <class T, int R>
-__device__ inline void red_elem(const RedIn &in, int64_t o, double *q) {
-    if (R == R_MU) {  // a = e, b = fc, c = rho: <e,fc>, <e, fc - rho>
-        double e = (double)((const T *)in.a)[o], fc = (double)((const T *)in.b)[o];
-        double rho = (double)((const T *)in.c)[o];
-        q[0] += e * fc;
-        q[1] += e * (fc - rho);
-    } else if (R == R_RC2) {  // a = rho, b = rho1: G = rho - rho1: <G,G>, <G,rho>
-        double r = (double)((const T *)in.a)[o], r1 = (double)((const T *)in.b)[o];
-        double g = r - r1;
-        q[0] += g * g;
-        q[1] += g * r;
-    } else if (R == R_NORM2) {
-        double x = (double)((const T *)in.a)[o];
-        q[0] += x * x;
-    } else if (R == R_SUM) {
-        q[0] += (double)((const T *)in.a)[o];
-    } else if (R == R_MAXABS) {
-        q[0] = fmax(q[0], fabs((double)((const T *)in.a)[o]));
-    } else {  // RCF: a = r, b = history residuals (m slots): G_i = r - r_i
-        const double *r = (const double *)in.a;
-        const double *hr = (const double *)in.b;
-        double rv = r[o], G[4];
-        for (int i = 0; i < 4; ++i) G[i] = (i < in.m) ? rv - hr[i * in.hstride + o] : 0.0;
-        int t = 0;
-        for (int i = 0; i < 4; ++i)
-            for (int j = i; j < 4; ++j) q[t++] += G[i] * G[j];
-        for (int i = 0; i < 4; ++i) q[10 + i] += G[i] * rv;
+struct RedElem {
+    double a[5];
+    __device__ inline void load(const RedIn &in, int64_t o) {
+        if (R == R_MU) {  // a = e, b = fc, c = rho
+            a[0] = (double)((const T *)in.a)[o];
+            a[1] = (double)((const T *)in.b)[o];
+            a[2] = (double)((const T *)in.c)[o];
+        } else if (R == R_RC2) {  // a = rho, b = rho1
+            a[0] = (double)((const T *)in.a)[o];
+            a[1] = (double)((const T *)in.b)[o];
+        } else if (R == R_NORM2 || R == R_SUM || R == R_MAXABS) {
+            a[0] = (double)((const T *)in.a)[o];
+        } else {  // RCF: a = r, b = history residuals (m slots; slots past m reread m - 1)
+            const double *hr = (const double *)in.b;
+            a[0] = ((const double *)in.a)[o];
+            for (int i = 0; i < 4; ++i) a[1 + i] = hr[(int64_t)min(i, in.m - 1) * in.hstride + o];
+        }
     }
-}
+    __device__ inline void add(const RedIn &in, double *q) const {
+        if (R == R_MU) {  // <e, fc>, <e, fc - rho>
+            q[0] += a[0] * a[1];
+            q[1] += a[0] * (a[1] - a[2]);
+        } else if (R == R_RC2) {  // G = rho - rho1: <G, G>, <G, rho>
+            const double g = a[0] - a[1];
+            q[0] += g * g;
+            q[1] += g * a[0];
+        } else if (R == R_NORM2) {
+            q[0] += a[0] * a[0];
+        } else if (R == R_SUM) {
+            q[0] += a[0];
+        } else if (R == R_MAXABS) {
+            q[0] = fmax(q[0], fabs(a[0]));
+        } else {  // RCF: G_i = r - r_i (0 past m)
+            const double rv = a[0];
+            double G[4];
+            for (int i = 0; i < 4; ++i) G[i] = (i < in.m) ? rv - a[1 + i] : 0.0;
+            int t = 0;
+            for (int i = 0; i < 4; ++i)
+                for (int j = i; j < 4; ++j) q[t++] += G[i] * G[j];
+            for (int i = 0; i < 4; ++i) q[10 + i] += G[i] * rv;
+        }
+    }
+};
 
 template <class T, int R>
 __global__ void __launch_bounds__(kBlock)
@@ -413,9 +429,21 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int i = 0; i < Q; ++i) q[i] = 0.0;
     if (col < k) {
-        for (int64_t row = (int64_t)blockIdx.x * rows_blk + rloc; row < n;
-             row += (int64_t)gridDim.x * rows_blk)
-            red_elem<T, R>(in, row * k + col, q);
+        // four rows per step: their loads are issued together, their terms added in row order
+        const int64_t step = (int64_t)gridDim.x * rows_blk;
+        int64_t row = (int64_t)blockIdx.x * rows_blk + rloc;
+        for (; row + 3 * step < n; row += 4 * step) {
+            RedElem<T, R> el[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) el[u].load(in, (row + u * step) * k + col);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) el[u].add(in, q);
+        }
+        for (; row < n; row += step) {
+            RedElem<T, R> el;
+            el.load(in, row * k + col);
+            el.add(in, q);
+        }
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i) sh[i][threadIdx.x] = q[i];
@@ -521,9 +549,16 @@ __device__ inline void group_totals(int nblk, int k, const double *__restrict__ 
         const int i = live ? idx / k : 0, c = live ? idx - i * k : 0;
         double s = 0.0;
         if (live)
-            for (int b = g; b < nblk; b += G) {
-                const double v = partial[((int64_t)b * Q + i) * k + c];
-                s = MAX ? fmax(s, v) : s + v;
+            for (int b0 = g; b0 < nblk; b0 += 8 * G) {  // 8 loads in flight, added in order
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int b = b0 + u * G;
+                    v[u] = b < nblk ? partial[((int64_t)b * Q + i) * k + c] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (b0 + u * G < nblk) s = MAX ? fmax(s, v[u]) : s + v[u];
             }
         for (int o = G >> 1; o > 0; o >>= 1) {
             const double t = __shfl_xor(s, o, 64);
