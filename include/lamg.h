@@ -84,13 +84,13 @@ typedef struct {
     int32_t keep_setup_data; /* keep canonical operators, colours, strong flags, test vectors,
                                 affinities, moments and aggregates for lamg_export_level (default 0) */
     int32_t tail_rows;       /* levels below the finest with at most this many nodes run their
-                                whole cycle in one single-workgroup launch per visit, together
-                                with the levels right above them (below 65536 nodes) whose many
-                                colours of few rows make one workgroup clearly cheaper than
-                                separate kernels (default 2500; 0 = every step is its own
-                                kernel). Applies to solves of at most 2 columns (wider
-                                solves run every step as its own kernel). Changes only how
-                                the cycle is executed, not what it computes. */
+                                whole cycle in one launch per visit, one workgroup per
+                                right-hand-side column, together with the levels right above
+                                them (below 65536 nodes) whose many colours of few rows make
+                                one workgroup clearly cheaper than separate kernels (default
+                                2500; 0 = every step is its own kernel). Applies to solves of
+                                at most 32 columns. Changes only how the cycle is executed,
+                                not what it computes. */
     int32_t elimination;     /* low-degree elimination levels (Sec. 2, "Low-degree elimination",
                                 eq. (2.1)); default 1 (0: aggregation only). Before each aggregation step a
                                 maximal independent set F of the nodes with at most 4

@@ -32,7 +32,7 @@ constexpr int kRedQMax = 14;        // quantities per reduction (4x4 normal equa
 constexpr int64_t kFuseTotalsMax = 1 << 15;
 constexpr int kTVShortRow = 64;     // test-vector rows longer than this get a wave each
 constexpr int kEllMaxWidth = 32;    // longest row of a level that gets an ELL copy
-constexpr int kTailMaxCols = 2;
+constexpr int kTailMaxCols = 32;  // workgroups (one per column) of one coarse-tail launch
 constexpr int kGraphMaxNodes = 20000;  // longer cycles are launched kernel by kernel
 constexpr int kGraphSets = 2;          // (precision, columns) pairs with cached graphs
 constexpr int kGraphMaxCycles = 64;    // later cycles of a solve are launched kernel by kernel
@@ -214,7 +214,11 @@ struct TailPlan {
     const void *desc = nullptr;      // level descriptors (global arrays)
     const void *lds_desc = nullptr;  // the launch's descriptors (LDS-resident levels: offsets)
     const void *jobs = nullptr;      // global -> LDS copy jobs
-    void *top_x = nullptr;           // global iterate of the tail's top level
+    // the same for one workgroup per column (solves of several columns; null unless the
+    // workspace holds several)
+    const void *lds_desc_cols = nullptr;
+    const void *jobs_cols = nullptr;
+    int kmax = 0;                    // columns the workspace vectors hold
     int njobs = 0;
     int l_lds = 0;         // first LDS-resident level (nlev: none)
     int l_x = -1;          // level whose iterate alone is LDS-resident (-1: none)
@@ -235,7 +239,12 @@ struct Workspace {
     DArr<char> tail64, tail32;  // coarse-tail level descriptors per precision
     DArr<char> tlds64, tlds32, tjobs64, tjobs32;  // LDS-resident tail levels
     TailPlan plan64, plan32;
-    DArr<int64_t> visits;       // coarse-tail visit counters (per level)
+    // the tail's top-level iterate and right-hand side column by column (solves of several
+    // columns; with one the layout is the ordinary one)
+    DArr<double> tcx64, tcf64;
+    DArr<float> tcx32, tcf32;
+    DArr<char> tldsc64, tldsc32, tjobsc64, tjobsc32;  // the per-column workgroups' plans
+    DArr<int64_t> visits;       // coarse-tail visit counters (per column and level)
     // HIP graphs of whole cycles, replayed in later solves with the same precision and column
     // count: the launch sequence of the i-th cycle of a solve depends only on i (the visit
     // counters start from zero in every solve; column freezing changes data, not launches)
@@ -434,6 +443,11 @@ int tail_lds_plan(const std::vector<Level> &lev, int l0, int k, const void *host
 size_t tail_copy_job_bytes();
 template <class T>
 void run_tail(const TailPlan &tp, int l0, int nlev, int k, int64_t *d_visits, hipStream_t s);
+// n x k row-interleaved (x, f) -> column by column (cx, cf), and back for x.
+template <class T>
+void run_to_cols(int64_t n, int k, const T *x, const T *f, T *cx, T *cf, hipStream_t s);
+template <class T>
+void run_from_cols(int64_t n, int k, const T *cx, T *x, hipStream_t s);
 void run_zero_i64(int64_t *p, int64_t n, hipStream_t s);
 
 // Finest-level FP64 helpers

@@ -49,6 +49,10 @@ struct WsSel<double> {
     static DArr<char> &lds(Workspace &w) { return w.tlds64; }
     static DArr<char> &jobs(Workspace &w) { return w.tjobs64; }
     static TailPlan &plan(Workspace &w) { return w.plan64; }
+    static DArr<double> &cx(Workspace &w) { return w.tcx64; }
+    static DArr<double> &cf(Workspace &w) { return w.tcf64; }
+    static DArr<char> &lds_cols(Workspace &w) { return w.tldsc64; }
+    static DArr<char> &jobs_cols(Workspace &w) { return w.tjobsc64; }
 };
 template <>
 struct WsSel<float> {
@@ -58,6 +62,10 @@ struct WsSel<float> {
     static DArr<char> &lds(Workspace &w) { return w.tlds32; }
     static DArr<char> &jobs(Workspace &w) { return w.tjobs32; }
     static TailPlan &plan(Workspace &w) { return w.plan32; }
+    static DArr<float> &cx(Workspace &w) { return w.tcx32; }
+    static DArr<float> &cf(Workspace &w) { return w.tcf32; }
+    static DArr<char> &lds_cols(Workspace &w) { return w.tldsc32; }
+    static DArr<char> &jobs_cols(Workspace &w) { return w.tjobsc32; }
 };
 
 // Algorithmic (compulsory) bytes of one launch of a level's cycle kernels, s = value
@@ -120,7 +128,8 @@ struct Cycle {
     int l0;                 // first level run by the coarse-tail kernel (-1: none)
     int lt;                 // level whose per-step kernels the in-situ timer records
     const TailPlan *plan;   // its descriptors and LDS layout
-    int64_t *d_visits;      // its visit counters
+    int64_t *d_visits;      // its visit counters (per column)
+    T *cx, *cf;             // column-by-column copies of the top level's x and f (k > 1)
 };
 
 // First level (below the finest) whose cycle runs in the coarse-tail kernel: the first
@@ -131,10 +140,11 @@ struct Cycle {
 // against the same number of workgroup steps of ~0.5 us plus the rows of a colour pass
 // gathered through one compute unit (~2000 entries per us). Levels with long (hub) rows
 // stay with the per-step kernels, which give each such row a whole block.
-// Only solves of at most kTailMaxCols columns use the tail: with more columns a level's
-// steps carry enough work that one compute unit is slower than the per-step kernels over
-// the whole chip (measured: 4 columns of the anisotropic grid 109 ms without the tail
-// against 126 ms with it, 32 columns of the 128^3 grid 711 ms against 1369 ms).
+// Every column of a solve gets a workgroup of its own (at most kTailMaxCols columns), so
+// the tail costs the same per launch whatever the column count; one workgroup carrying
+// all columns was slower than the per-step kernels from four columns on (anisotropic
+// grid, 4 columns: 126 ms against 109 ms without the tail), one per column is faster at
+// every width measured (4 columns: 69 ms; 32 columns: 117 against 154 ms).
 int tail_level(const lamg_handle *h, int k) {
     if (h->opt.tail_rows <= 0 || k > kTailMaxCols) return -1;
     int l0 = -1;
@@ -194,8 +204,18 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
     Level &L = h->lev[l];
     using P = Prec<T>;
     if (l == C.l0) {
-        Timed tm(h, LAMG_KERNEL_TAIL, prec_id<T>(), 0.0);
-        run_tail<T>(*C.plan, l, h->nlev, k, C.d_visits, s);
+        if (k == 1) {
+            Timed tm(h, LAMG_KERNEL_TAIL, prec_id<T>(), 0.0);
+            run_tail<T>(*C.plan, l, h->nlev, k, C.d_visits, s);
+            return;
+        }
+        // a workgroup per column, on the top level's (x, f) copied column by column
+        run_to_cols<T>(L.n, k, x, f, C.cx, C.cf, s);
+        {
+            Timed tm(h, LAMG_KERNEL_TAIL, prec_id<T>(), 0.0);
+            run_tail<T>(*C.plan, l, h->nlev, k, C.d_visits, s);
+        }
+        run_from_cols<T>(L.n, k, C.cx, x, s);
         return;
     }
     if (L.coarsest) {
@@ -338,8 +358,8 @@ void ensure_level_vecs(lamg_handle *h, int k) {
     // including narrower solves reusing vectors sized for a wider one, so it is built for
     // the tail level of such solves whatever k these vectors were sized for
     const int l0 = tail_level(h, 1);
-    int l_x = -1;
-    int l_lds = tail_lds_plan<T>(h->lev, l0, k, host.data(), lds_desc, jobs, lds_bytes, l_x);
+    int l_x = -1;  // one column per workgroup
+    int l_lds = tail_lds_plan<T>(h->lev, l0, 1, host.data(), lds_desc, jobs, lds_bytes, l_x);
     if (l0 >= 0) {
         DArr<char> &dl = W::lds(w);
         DArr<char> &dj = W::jobs(w);
@@ -353,7 +373,45 @@ void ensure_level_vecs(lamg_handle *h, int k) {
         tp.l_lds = l_lds;
         tp.l_x = l_x;
         tp.lds_bytes = lds_bytes;
-        tp.top_x = lv[l0].x.p;
+        tp.kmax = k;
+        if (k > 1) {
+            // one descriptor set per column: vectors from element c n of each level's
+            // arrays, the top level's x and f from the column copies
+            const int ncols = std::min(k, kTailMaxCols);
+            const int64_t n0 = h->lev[l0].n;
+            W::cx(w).alloc(pool, n0 * k);
+            W::cf(w).alloc(pool, n0 * k);
+            std::vector<char> hp(db * h->nlev), all_desc, all_jobs;
+            for (int c = 0; c < ncols; ++c) {
+                for (int l = 0; l < h->nlev; ++l) {
+                    const Level &L = h->lev[l];
+                    const SolveOp &op = L.op;
+                    const int64_t o = (int64_t)c * L.n;
+                    T *xv = l == l0 ? W::cx(w).p + c * n0 : lv[l].x.p + o;
+                    T *fv = l == l0 ? W::cf(w).p + c * n0 : lv[l].f.p + o;
+                    tail_fill_desc<T>(hp.data(), l, L, op, op.dblk.p, P::v(op), P::d(op),
+                                      P::dinv(op), P::w0(op), P::w1(op), P::rw(op), P::ev(op), xv,
+                                      fv, lv[l].r.p + o, lv[l].rho.p + o, lv[l].x1.p + o,
+                                      lv[l].rho1.p + o);
+                }
+                std::vector<char> pd, pj;
+                size_t pb = 0;
+                int px_l = -1;
+                const int pl = tail_lds_plan<T>(h->lev, l0, 1, hp.data(), pd, pj, pb, px_l);
+                if (pl != l_lds || px_l != l_x || pb != lds_bytes || pj.size() != jobs.size())
+                    throw Error(LAMG_HIP_ERROR, "coarse tail: column plans differ");
+                all_desc.insert(all_desc.end(), pd.begin(), pd.end());
+                all_jobs.insert(all_jobs.end(), pj.begin(), pj.end());
+            }
+            DArr<char> &dlp = W::lds_cols(w);
+            DArr<char> &djp = W::jobs_cols(w);
+            dlp.alloc(pool, (int64_t)all_desc.size());
+            dlp.upload(all_desc.data(), (int64_t)all_desc.size(), h->stream);
+            djp.alloc(pool, (int64_t)std::max<size_t>(all_jobs.size(), 1));
+            if (!all_jobs.empty()) djp.upload(all_jobs.data(), (int64_t)all_jobs.size(), h->stream);
+            tp.lds_desc_cols = dlp.p;
+            tp.jobs_cols = djp.p;
+        }
     }
     LAMG_HIP(hipStreamSynchronize(h->stream));
     W::k(w) = k;
@@ -379,7 +437,7 @@ void ensure_fine(lamg_handle *h, int k) {
     w.mean.alloc(pool, k);
     w.partial.alloc(pool, (int64_t)kRedBlocksMax * kRedQMax * k);
     w.mask.alloc(pool, k);
-    w.visits.alloc(pool, h->nlev);
+    w.visits.alloc(pool, (int64_t)h->nlev * kTailMaxCols);
     if (w.h_rel) (void)hipHostFree(w.h_rel);
     if (w.h_mask) (void)hipHostFree(w.h_mask);
     w.h_rel = nullptr;
@@ -485,7 +543,7 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
         ensure_level_vecs<float>(h, k);
     else
         ensure_level_vecs<double>(h, k);
-    run_zero_i64(w.visits.p, h->nlev, s);
+    run_zero_i64(w.visits.p, (int64_t)h->nlev * kTailMaxCols, s);
 
     // b <- P b, projected to mean zero (eq. (1.1)); ||b|| per column
     run_gather_cols(n, k, op0.perm.p, b_user, w.b.p, s);
@@ -527,9 +585,9 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
     const int l0 = tail_level(h, k);
     const int lt = timed_level(h, k);
     Cycle<double> c64{h, k, s, &w.lv64, std::vector<int64_t>(h->nlev, 0), w.partial.p, l0, lt,
-                      &w.plan64, w.visits.p};
+                      &w.plan64, w.visits.p, w.tcx64.p, w.tcf64.p};
     Cycle<float> c32{h, k, s, &w.lv32, std::vector<int64_t>(h->nlev, 0), w.partial.p, l0, lt,
-                     &w.plan32, w.visits.p};
+                     &w.plan32, w.visits.p, w.tcx32.p, w.tcf32.p};
     // One cycle with its fine-level residual, recombination and relative residuals: the
     // launches depend only on the cycle's index (through the Beatty visit counters and
     // the history slots), so from the second solve of this precision and column count

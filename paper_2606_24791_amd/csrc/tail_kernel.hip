@@ -1,6 +1,11 @@
 // Coarse-tail cycle: the complete gamma-cycle (Sec. 2, "Cycle and acceleration";
 // eq. (2.4)) of every level from a threshold level down to the directly solved one, run
-// by ONE workgroup of 1024 threads in ONE launch per visit to the threshold level.
+// by ONE workgroup of 1024 threads per right-hand-side column in ONE launch per visit to
+// the threshold level. The columns are independent (each has its own energy correction
+// and recombination coefficients), so workgroup w takes column w on its own, with
+// descriptors of its own: with several columns the tail levels' vectors hold them column
+// by column (column w from element w n), and the top level's iterate and right-hand side
+// are copied into that layout around the launch; with one column it is the ordinary one.
 //
 // Coarse levels are small but are visited many times per cycle (the cycle index grows
 // towards 2 where coarsening is aggressive), and every visit is a chain of dependent
@@ -65,18 +70,21 @@ struct TailLvl {
     const T *ev;
 };
 
-// Global -> LDS copy performed at the start of every tail launch.
+// Global -> LDS copy performed at the start of every tail launch. Jobs that bring the top
+// level's iterate (`top` 1) or right-hand side (`top` 2) copy the workgroup's column:
+// `colb` bytes.
 struct CopyJob {
     const void *src;
     uint32_t dst;    // byte offset in the dynamic LDS buffer (multiple of 16)
     uint32_t bytes;  // multiple of 4
+    uint32_t top;    // 0: an operator array; 1: the top level's x; 2: its f
+    uint32_t colb;   // top jobs: bytes per column (the level's rows x element size)
 };
 
 struct TailArgs {
-    const CopyJob *jobs;
-    int64_t *visits;  // per level, persistent within a solve
-    void *top_x;      // global iterate of the top level (written back if it lives in LDS)
-    int32_t njobs, l0, nlev, l_lds, k, lkp;
+    const CopyJob *jobs;  // njobs per workgroup, workgroup after workgroup
+    int64_t *visits;      // per workgroup and level, persistent within a solve
+    int32_t njobs, l0, nlev, l_lds, k, lkp;  // k, lkp: the columns of one workgroup (1, 0)
     uint32_t red_off;    // byte offset of the two reduction buffers in the dynamic LDS
     int32_t l_x;         // levels [l_x, l_lds) have their iterate alone in LDS (-1: none)
     uint32_t cpart_off;  // byte offset of the coarsest solve's part sums (TB doubles)
@@ -749,21 +757,29 @@ __device__ __forceinline__ int visit(const TailArgs &A, const TailLvl<T> &DL, co
 }
 
 template <class T>
-__global__ void __launch_bounds__(TB) k_tail(TailArgs A, const TailLvl<T> *__restrict__ G) {
+__global__ void __launch_bounds__(TB) k_tail(TailArgs A, const TailLvl<T> *__restrict__ G0) {
     extern __shared__ __align__(16) char smem[];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
+    // this workgroup's column: its descriptors, copy jobs and visit counters
+    const int col = (int)blockIdx.x;
+    A.visits += (int64_t)col * A.nlev;
+    const TailLvl<T> *__restrict__ G = G0 + (int64_t)col * A.nlev;
+    const CopyJob *jobs = A.jobs + (int64_t)col * A.njobs;
     const int l0 = A.l0, nlev = A.nlev, l_lds = A.l_lds, l_x = A.l_x;
     // bring the LDS-resident levels (and the top level's iterate and right-hand side)
+    const void *top_x = nullptr;
     for (int jb = 0; jb < A.njobs; ++jb) {
-        const CopyJob J = A.jobs[jb];
-        const uint32_t n16 = J.bytes >> 4;
+        const CopyJob J = jobs[jb];
+        const uint32_t bytes = J.top ? (uint32_t)A.k * J.colb : J.bytes;
+        if (J.top == 1) top_x = J.src;
+        const uint32_t n16 = bytes >> 4;
         const uint4 *s16 = static_cast<const uint4 *>(J.src);
         uint4 *d16 = reinterpret_cast<uint4 *>(smem + J.dst);
         for (uint32_t w = tid; w < n16; w += TB) d16[w] = s16[w];
         const uint32_t *s4 = static_cast<const uint32_t *>(J.src);
         uint32_t *d4 = reinterpret_cast<uint32_t *>(smem + J.dst);
-        for (uint32_t w = 4 * n16 + tid; w < (J.bytes >> 2); w += TB) d4[w] = s4[w];
+        for (uint32_t w = 4 * n16 + tid; w < (bytes >> 2); w += TB) d4[w] = s4[w];
     }
     WaveState ws;
     ws.st = 0;
@@ -799,7 +815,7 @@ __global__ void __launch_bounds__(TB) k_tail(TailArgs A, const TailLvl<T> *__res
     if (l0 >= l_lds || (l_x >= 0 && l0 >= l_x)) {  // the top level's iterate is in LDS: write it back
         const TailLvl<T> &D = G[l0];
         const T *lx = at<true>(smem, D.x);
-        T *gx = static_cast<T *>(A.top_x);
+        T *gx = static_cast<T *>(const_cast<void *>(top_x));
         for (int t = tid; t < D.n * A.k; t += TB) gx[t] = lx[t];
     }
     if (tid < 64 && lane >= l0 && lane < nlev) A.visits[lane] = ws.cnt;
@@ -930,7 +946,7 @@ int tail_lds_plan(const std::vector<Level> &lev, int l0, int k, const void *host
                 return;
             }
             field = reinterpret_cast<P>((uintptr_t)off);
-            if (copy && src) jv.push_back(CopyJob{src, (uint32_t)off, (uint32_t)bytes});
+            if (copy && src) jv.push_back(CopyJob{src, (uint32_t)off, (uint32_t)bytes, 0u, 0u});
             off += al(bytes);
         };
         place(E.blk, 8 * (int64_t)op.blk.size(), true);
@@ -955,8 +971,19 @@ int tail_lds_plan(const std::vector<Level> &lev, int l0, int k, const void *host
             E.rw = nullptr;
         }
         const bool top = (l == l0);  // the top level's iterate and rhs come from global memory
-        place(E.x, s * n * k, top);
-        place(E.f, s * n * k, top);
+        if (top) {
+            jv.push_back(CopyJob{(const void *)E.x, (uint32_t)off, (uint32_t)(s * n * k), 1u,
+                                 (uint32_t)(s * n)});
+            E.x = reinterpret_cast<T *>((uintptr_t)off);
+            off += al(s * n * k);
+            jv.push_back(CopyJob{(const void *)E.f, (uint32_t)off, (uint32_t)(s * n * k), 2u,
+                                 (uint32_t)(s * n)});
+            E.f = reinterpret_cast<T *>((uintptr_t)off);
+            off += al(s * n * k);
+        } else {
+            place(E.x, s * n * k, false);
+            place(E.f, s * n * k, false);
+        }
         place(E.r, s * n * k, false);
         E.rho = E.r;  // the residual of a level is dead before its coarse residual is formed
         if (!L.coarsest) {
@@ -976,7 +1003,9 @@ int tail_lds_plan(const std::vector<Level> &lev, int l0, int k, const void *host
         E = G[l];
         const void *src = (const void *)E.x;
         E.x = reinterpret_cast<T *>((uintptr_t)off);
-        if (l == l0) jv.push_back(CopyJob{src, (uint32_t)off, (uint32_t)xb});
+        if (l == l0)
+            jv.push_back(CopyJob{src, (uint32_t)off, (uint32_t)xb, 1u,
+                                 (uint32_t)(sizeof(T) * lev[l].n)});
         off += al(xb);
         l_x = l;
     }
@@ -991,28 +1020,58 @@ int tail_lds_plan(const std::vector<Level> &lev, int l0, int k, const void *host
 
 template <class T>
 void run_tail(const TailPlan &tp, int l0, int nlev, int k, int64_t *d_visits, hipStream_t s) {
+    const bool cols = k > 1;
+    if (k < 1 || k > tp.kmax || k > kTailMaxCols || (cols && !tp.lds_desc_cols))
+        throw Error(LAMG_INVALID_ARG, "coarse tail: unsupported column count");
     TailArgs A;
     std::memset(&A, 0, sizeof(A));
-    A.jobs = static_cast<const CopyJob *>(tp.jobs);
+    A.jobs = static_cast<const CopyJob *>(cols ? tp.jobs_cols : tp.jobs);
     A.njobs = tp.njobs;
     A.visits = d_visits;
-    A.top_x = tp.top_x;
     A.l0 = l0;
     A.nlev = nlev;
     A.l_lds = tp.l_lds;
-    A.k = k;
-    int lkp = 0;
-    while ((1 << lkp) < k) ++lkp;
-    A.lkp = lkp;
+    A.k = 1;  // each workgroup takes one column
+    A.lkp = 0;
     A.red_off = 16;
     A.l_x = tp.l_x;
-    {
-        int kp = 1;
-        while (kp < k) kp <<= 1;
-        A.cpart_off = (uint32_t)(16 + ((2 * (int64_t)kRedQ * TW * kp * 8 + 15) & ~(int64_t)15));
-    }
-    const TailLvl<T> *G = static_cast<const TailLvl<T> *>(tp.lds_desc);
-    launch_kernel(k_tail<T>, dim3(1), dim3(TB), (uint32_t)tp.lds_bytes, s, A, G);
+    A.cpart_off = (uint32_t)(16 + ((2 * (int64_t)kRedQ * TW * 8 + 15) & ~(int64_t)15));
+    const TailLvl<T> *G = static_cast<const TailLvl<T> *>(cols ? tp.lds_desc_cols : tp.lds_desc);
+    launch_kernel(k_tail<T>, dim3((unsigned)k), dim3(TB), (uint32_t)tp.lds_bytes, s, A, G);
+    LAMG_LAUNCH_CHECK();
+}
+
+// n x k row-interleaved (x, f) -> column by column (cx, cf): element (i, c) to c n + i.
+template <class T>
+__global__ void k_to_cols(int64_t n, int k, const T *__restrict__ x, const T *__restrict__ f,
+                          T *__restrict__ cx, T *__restrict__ cf) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * k) return;
+    const int64_t i = t / k;
+    const int64_t o = (t - i * k) * n + i;
+    cx[o] = x[t];
+    cf[o] = f[t];
+}
+
+template <class T>
+__global__ void k_from_cols(int64_t n, int k, const T *__restrict__ cx, T *__restrict__ x) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * k) return;
+    const int64_t i = t / k;
+    x[t] = cx[(t - i * k) * n + i];
+}
+
+template <class T>
+void run_to_cols(int64_t n, int k, const T *x, const T *f, T *cx, T *cf, hipStream_t s) {
+    if (n * k <= 0) return;
+    k_to_cols<T><<<(unsigned)((n * k + 255) / 256), 256, 0, s>>>(n, k, x, f, cx, cf);
+    LAMG_LAUNCH_CHECK();
+}
+
+template <class T>
+void run_from_cols(int64_t n, int k, const T *cx, T *x, hipStream_t s) {
+    if (n * k <= 0) return;
+    k_from_cols<T><<<(unsigned)((n * k + 255) / 256), 256, 0, s>>>(n, k, cx, x);
     LAMG_LAUNCH_CHECK();
 }
 
@@ -1037,6 +1096,12 @@ template void tail_fill_desc<float>(void *, int, const Level &, const SolveOp &,
                                     float *, float *, float *, float *);
 template void run_tail<double>(const TailPlan &, int, int, int, int64_t *, hipStream_t);
 template void run_tail<float>(const TailPlan &, int, int, int, int64_t *, hipStream_t);
+template void run_to_cols<double>(int64_t, int, const double *, const double *, double *,
+                                  double *, hipStream_t);
+template void run_to_cols<float>(int64_t, int, const float *, const float *, float *, float *,
+                                 hipStream_t);
+template void run_from_cols<double>(int64_t, int, const double *, double *, hipStream_t);
+template void run_from_cols<float>(int64_t, int, const float *, float *, hipStream_t);
 template int tail_lds_plan<double>(const std::vector<Level> &, int, int, const void *,
                                    std::vector<char> &, std::vector<char> &, size_t &, int &);
 template int tail_lds_plan<float>(const std::vector<Level> &, int, int, const void *,
