@@ -332,20 +332,20 @@ def test_full_size_anisotropic_1024(B):
 
 @pytest.mark.parametrize("tail_rows", [0, 400, 2500, 100000])
 def test_cycle_execution_modes_agree(B, tail_rows):
-    """Every split between per-step kernels and the single-workgroup coarse tail (with its
-    LDS-resident levels) computes the same cycle: each reaches the tolerance and the
-    oracle's solution, in both precisions, for 1, 2 and 3 right-hand sides (3 columns run
-    every step as its own kernel whatever the threshold)."""
+    """Every split between per-step kernels and the coarse tail (with its LDS-resident
+    levels) computes the same cycle: each reaches the tolerance and the oracle's solution,
+    in both precisions, for 1 to 5 right-hand sides (one tail workgroup per column, the
+    columns copied into and out of the tail's column-by-column layout from 2 on)."""
     import torch
 
     g = GRAPHS["aniso_ragged"]()
     note(f"execution mode tail_rows={tail_rows}")
     oh = O.Hierarchy(g, seed=1)
     h = B.lamg_setup(g, B.lamg_default_options(tail_rows=tail_rows))
-    bh = I.rhs(g.n, 3, seed=21)
-    refs = [oh.solve(bh[c], TOL, 100) for c in range(3)]
+    bh = I.rhs(g.n, 5, seed=21)
+    refs = [oh.solve(bh[c], TOL, 100) for c in range(5)]
     for prec in (B.FP64, B.FP32_IR):
-        for k in (1, 2, 3):
+        for k in (1, 2, 3, 5):
             b = torch.tensor(bh[:k], device="cuda")
             phi = torch.empty_like(b)
             st = B.lamg_solve(h, b, phi, precision=prec)
@@ -354,9 +354,9 @@ def test_cycle_execution_modes_agree(B, tail_rows):
 
 
 def test_narrow_solve_after_wide_solve_on_one_handle(B):
-    """A solve of more than two columns (every step its own kernel) sizes the cached
-    workspace; a later one- or two-column solve on the same handle runs the coarse tail in
-    that workspace and must give the fresh handle's result."""
+    """A solve of four columns sizes the cached workspace (and its tail descriptors for one
+    workgroup per column); later one- and two-column solves on the same handle run the
+    coarse tail in that workspace and must give the fresh handle's result."""
     import torch
 
     g = GRAPHS["aniso_ragged"]()
