@@ -205,6 +205,39 @@ def test_wide_blocks_of_columns(B, name, k):
         assert err <= SOL_TOL, (c, err)
 
 
+@pytest.mark.parametrize("name", ["aniso_small", "chunglu_small"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32ir"])
+def test_recovers_a_known_solution(B, name, prec):
+    """b = L x_true with x_true ~ N(0,1), mean zero (the paper's RHS protocol, Sec. 4): the
+    GPU solve returns x_true within the spectral bound of its residual (a pin that needs
+    neither the oracle nor a pseudo-inverse)."""
+    import scipy.sparse as sp
+    import torch
+
+    g = (I.grid2d(64, 40, 1.0, 1e-3) if name == "aniso_small"
+         else I.chung_lu(3000, 2.1, 8, seed=7))
+    note(f"known solution {name} {prec} n={g.n}")
+    W = sp.csr_matrix((g.weight, g.col_idx, g.row_ptr), shape=(g.n, g.n))
+    L = sp.diags(np.asarray(W.sum(1)).ravel()) - W
+    x = I.rhs(g.n, 2, seed=8)
+    x -= x.mean(1, keepdims=True)
+    bh = np.stack([L @ x[c] for c in range(2)])
+    h = B.lamg_setup(g)
+    b = torch.tensor(bh, device="cuda")
+    phi = torch.empty_like(b)
+    st = B.lamg_solve(h, b, phi, tol=1e-10, max_cycles=100,
+                      precision=B.FP64 if prec == "fp64" else B.FP32_IR)
+    h.close()
+    assert st["converged"], st
+    ph = phi.cpu().numpy()
+    lam2 = np.linalg.eigvalsh(L.toarray())[1]
+    for c in range(2):
+        r = np.linalg.norm(bh[c] - L @ ph[c]) / np.linalg.norm(bh[c])
+        assert r <= 1e-10 * 1.0001, (c, r)
+        err = np.linalg.norm(ph[c] - x[c])
+        assert err <= 1.01 * r * np.linalg.norm(bh[c]) / lam2, (c, err)
+
+
 def test_multi_rhs_columns_match_oracle_and_single_solves(B):
     import torch
 

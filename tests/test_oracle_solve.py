@@ -56,6 +56,27 @@ def test_solve_reaches_tolerance_and_pinv(gen, elimination):
     assert np.all(np.diff(hist) < 0)  # residual decreases every cycle
 
 
+@pytest.mark.parametrize("gen", [
+    lambda: I.grid2d(48, 30, 1.0, 1e-3),
+    lambda: I.chung_lu(2500, 2.1, 8, seed=7),
+])
+def test_recovers_a_known_solution(gen):
+    """b = L x_true with x_true ~ N(0,1), mean zero (the paper's RHS protocol, Sec. 4): the
+    solve returns x_true within the spectral bound of its residual, no pseudo-inverse
+    needed."""
+    g = gen()
+    L = dense_L(g)
+    x = I.rhs(g.n, 1, seed=8)[0]
+    x -= x.mean()
+    b = L @ x
+    phi, st, _ = O.Hierarchy(g).solve(b, 1e-10, 100)
+    assert st["converged"]
+    relres = np.linalg.norm(b - L @ phi) / np.linalg.norm(b)
+    lam2 = np.linalg.eigvalsh(L)[1]
+    assert np.linalg.norm(phi - x) <= 1.01 * relres * np.linalg.norm(b) / lam2
+    assert np.linalg.norm(phi - x) <= 1e-6 * np.linalg.norm(x)
+
+
 def test_energy_correction_is_one_under_exact_coarse_solve():
     """Two levels with an exactly solved coarse level: the energy-optimal multiple of
     the coarse correction is 1 (the Galerkin correction is already L-optimal)."""
