@@ -205,6 +205,37 @@ def test_wide_blocks_of_columns(B, name, k):
         assert err <= SOL_TOL, (c, err)
 
 
+def test_more_columns_than_one_chunk(B):
+    """35 right-hand sides: the library solves chunks of 32 and 3 columns, each through the
+    coarse tail with a workgroup per column (the second in vectors sized for the first);
+    every column meets the tolerance and the first, 33rd and last agree with the oracle."""
+    import scipy.sparse as sp
+    import torch
+
+    g = GRAPHS["aniso_ragged"]()
+    note(f"35 columns n={g.n}")
+    k = 35
+    bh = I.rhs(g.n, k, seed=23)
+    h = B.lamg_setup(g)
+    b = torch.tensor(bh, device="cuda")
+    phi = torch.empty_like(b)
+    st = B.lamg_solve(h, b, phi, tol=TOL, max_cycles=100, precision=B.FP32_IR)
+    h.close()
+    assert st["converged"], st
+    ph = phi.cpu().numpy()
+    W = sp.csr_matrix((g.weight, g.col_idx, g.row_ptr), shape=(g.n, g.n))
+    L = sp.diags(np.asarray(W.sum(1)).ravel()) - W
+    for c in range(k):
+        bc = bh[c] - bh[c].mean()
+        r = np.linalg.norm(bc - L @ ph[c]) / np.linalg.norm(bc)
+        assert r <= TOL * 1.0001 and abs(st["relres"][c] - r) <= 1e-3 * TOL, (c, r)
+    oh = O.Hierarchy(g, seed=1)
+    for c in (0, 32, k - 1):
+        ref, _, _ = oh.solve(bh[c], TOL, 100)
+        err = np.linalg.norm(ph[c] - ref) / np.linalg.norm(ref)
+        assert err <= SOL_TOL, (c, err)
+
+
 @pytest.mark.parametrize("name", ["aniso_small", "chunglu_small"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32ir"])
 def test_recovers_a_known_solution(B, name, prec):
