@@ -20,7 +20,7 @@ The JSON line also carries
             events attached to every launch on the solve stream (the throughput region runs
             without events; with --graphs it replays each cycle as a HIP graph, which needs
             events off), against 8 TB/s HBM;
-  coarse_tail: the same timing of the single-workgroup coarse-level kernel, which takes the
+  coarse_tail: the same timing of the coarse-level kernel (one workgroup per column), which takes the
             largest share of the solve and is bound by dependent steps, not bytes;
   cpu_baseline: the CPU oracle (single-threaded, FP64) solving the same system once.
 """

@@ -244,8 +244,8 @@ typedef enum {
     LAMG_KERNEL_RESIDUAL = 1, /* r = f - L x over the whole level */
     LAMG_KERNEL_RESTRICT = 2, /* f_c = P^T r from the level to the next */
     LAMG_KERNEL_PROLONG = 3,  /* x += mu P e_c from the next level */
-    LAMG_KERNEL_TAIL = 4      /* one launch of the single-workgroup coarse-level cycle
-                                 (in-situ timer only) */
+    LAMG_KERNEL_TAIL = 4      /* one launch of the coarse-level cycle (one workgroup per
+                                 column; in-situ timer only) */
 } lamg_kernel;
 
 /* Measurement aid for roofline reporting: launches one cycle kernel of level `level`
