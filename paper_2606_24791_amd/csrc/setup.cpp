@@ -6,8 +6,10 @@
 // Compiled with -ffp-contract=off: the guard comparison below must round exactly like
 // the canonical arithmetic of the setup kernels.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <thread>
 
 #include "lamg_internal.h"
 
@@ -62,14 +64,35 @@ static HostGraph read_graph(const lamg_graph *g, hipStream_t s) {
             if (!(w > 0.0) || !std::isfinite(w)) throw Error(LAMG_BAD_WEIGHT, "graph: weight");
         }
     }
-    for (int64_t u = 0; u < h.n; ++u) {
-        for (int32_t j = h.rp[u]; j < h.rp[u + 1]; ++j) {
-            int32_t v = h.ci[j];
-            const int32_t *b = h.ci.data() + h.rp[v], *e = h.ci.data() + h.rp[v + 1];
-            const int32_t *it = std::lower_bound(b, e, (int32_t)u);
-            if (it == e || *it != u || h.w[it - h.ci.data()] != h.w[j])
-                throw Error(LAMG_NOT_SYMMETRIC, "graph: not symmetric");
-        }
+    // symmetry: every stored (u, v, w) has its (v, u, w); the entries are split evenly over
+    // up to 16 host threads (the binary searches into other rows are cache misses, so the
+    // check is latency-bound and scales with threads)
+    {
+        const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        std::atomic<bool> sym{true};
+        auto check = [&](int t) {
+            const int64_t e0 = h.nnz * t / nt, e1 = h.nnz * (t + 1) / nt;
+            int64_t u = std::upper_bound(h.rp.begin(), h.rp.end(), (int32_t)e0) - h.rp.begin() - 1;
+            for (; u < h.n && h.rp[u] < e1; ++u) {
+                if (!sym.load(std::memory_order_relaxed)) return;
+                const int32_t ja = (int32_t)std::max<int64_t>(h.rp[u], e0);
+                const int32_t jb = (int32_t)std::min<int64_t>(h.rp[u + 1], e1);
+                for (int32_t j = ja; j < jb; ++j) {
+                    const int32_t v = h.ci[j];
+                    const int32_t *b = h.ci.data() + h.rp[v], *e = h.ci.data() + h.rp[v + 1];
+                    const int32_t *it = std::lower_bound(b, e, (int32_t)u);
+                    if (it == e || *it != u || h.w[it - h.ci.data()] != h.w[j]) {
+                        sym.store(false, std::memory_order_relaxed);
+                        return;
+                    }
+                }
+            }
+        };
+        std::vector<std::thread> th;
+        for (int t = 1; t < nt; ++t) th.emplace_back(check, t);
+        check(0);
+        for (std::thread &x : th) x.join();
+        if (!sym.load()) throw Error(LAMG_NOT_SYMMETRIC, "graph: not symmetric");
     }
     // connectivity (breadth-first search from node 0)
     std::vector<uint8_t> seen(h.n, 0);
