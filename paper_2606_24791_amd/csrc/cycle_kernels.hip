@@ -754,10 +754,11 @@ __global__ void k_sub_col(int64_t n, int k, int lkp, double *__restrict__ x,
 }
 
 // phi += sum_i a_i (phi_i - phi); r -= sum_i a_i (r - r_i)
+// ... and the recombined pair is saved in history slot `slot` (the slot may be one of the
+// m read: each thread reads its element of every slot before writing it)
 __global__ void k_rcf_update(int64_t n, int k, int lkp, int m, double *__restrict__ phi,
-                             double *__restrict__ r, const double *__restrict__ hphi,
-                             const double *__restrict__ hr, int64_t hstride,
-                             const double *__restrict__ alpha) {
+                             double *__restrict__ r, double *hphi, double *hr, int64_t hstride,
+                             const double *__restrict__ alpha, int slot) {
     ROWCOL(n, lkp)
     double p = phi[t], rv = r[t], dp = 0.0, dr = 0.0;
     for (int i = 0; i < m; ++i) {
@@ -765,15 +766,21 @@ __global__ void k_rcf_update(int64_t n, int k, int lkp, int m, double *__restric
         dp += a * (hphi[i * hstride + t] - p);
         dr += a * (rv - hr[i * hstride + t]);
     }
-    phi[t] = p + dp;
-    r[t] = rv - dr;
+    const double pn = p + dp, rn = rv - dr;
+    phi[t] = pn;
+    r[t] = rn;
+    hphi[slot * hstride + t] = pn;
+    hr[slot * hstride + t] = rn;
 }
 
+// d = r / scale (per column) in FP32; zx (if given) = 0, the FP32 iterate a cycle starts from
 __global__ void k_to_f32_scaled(int64_t n, int k, int lkp, const double *__restrict__ r,
-                                const double *__restrict__ sc, float *__restrict__ d) {
+                                const double *__restrict__ sc, float *__restrict__ d,
+                                float *__restrict__ zx) {
     ROWCOL(n, lkp)
     double s = sc[c];
     d[t] = (float)(s > 0.0 ? r[t] / s : 0.0);
+    if (zx) zx[t] = 0.0f;
 }
 
 __global__ void k_add_scaled_f32(int64_t n, int k, int lkp, const float *__restrict__ e,
@@ -1042,19 +1049,23 @@ void run_relres(int64_t n, int k, const double *r, const double *nb, double *par
     reduce<double, R_NORM2>(n, k, in, partial, Fin{out, nb, 1.0, 0}, s);
 }
 
-void run_recombine_fine(int64_t n, int k, int m, double *phi, double *r, const double *hphi,
-                        const double *hr, double *partial, double *alpha, hipStream_t s) {
-    if (m <= 0) return;
+void run_recombine_fine(int64_t n, int k, int m, double *phi, double *r, double *hphi, double *hr,
+                        int slot, double *partial, double *alpha, hipStream_t s) {
+    if (m <= 0) {  // nothing to recombine with: only save the pair
+        run_copy<double>(hphi + (int64_t)slot * n * k, phi, n * k, s);
+        run_copy<double>(hr + (int64_t)slot * n * k, r, n * k, s);
+        return;
+    }
     RedIn in{r, hr, nullptr, nullptr, m, n * k};
     reduce<double, R_RCF>(n, k, in, partial, Fin{alpha, nullptr, 1.0, m}, s);
     k_rcf_update<<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), m, phi, r, hphi, hr, n * k,
-                                                     alpha);
+                                                     alpha, slot);
     LAMG_LAUNCH_CHECK();
 }
 
 void run_to_f32_scaled(int64_t n, int k, const double *r, const double *scale, float *dst,
-                       hipStream_t s) {
-    k_to_f32_scaled<<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), r, scale, dst);
+                       float *zero_x, hipStream_t s) {
+    k_to_f32_scaled<<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), r, scale, dst, zero_x);
     LAMG_LAUNCH_CHECK();
 }
 

@@ -462,10 +462,12 @@ void run_norm2(int64_t n, int k, const double *x, double *partial, double *out, 
 void run_maxabs(int64_t n, int k, const double *x, double *partial, double *out, hipStream_t s);
 void run_relres(int64_t n, int k, const double *r, const double *nb, double *partial, double *out,
                 hipStream_t s);
-void run_recombine_fine(int64_t n, int k, int m, double *phi, double *r, const double *hphi,
-                        const double *hr, double *partial, double *alpha, hipStream_t s);
+// Fine-level recombination over m history pairs (Sec. 2, "Cycle and acceleration"); the
+// recombined (phi, r) is also saved in history slot `slot`.
+void run_recombine_fine(int64_t n, int k, int m, double *phi, double *r, double *hphi, double *hr,
+                        int slot, double *partial, double *alpha, hipStream_t s);
 void run_to_f32_scaled(int64_t n, int k, const double *r, const double *scale, float *dst,
-                       hipStream_t s);  // dst = r / scale[c]
+                       float *zero_x, hipStream_t s);  // dst = r / scale[c]; zero_x = 0
 void run_add_scaled_f32(int64_t n, int k, const float *e, const double *scale, double *phi,
                         hipStream_t s);  // phi += scale[c] * e
 void run_zero_cols(int64_t n, int k, const int32_t *zero_mask, double *x, hipStream_t s);

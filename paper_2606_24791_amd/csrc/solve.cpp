@@ -601,8 +601,7 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
             // FP32 cycle on the scaled residual equation, FP64 update
             run_maxabs(n, k, w.r.p, w.partial.p, w.scale.p, st);
             LevelVecs<float> &v0 = w.lv32[0];
-            run_to_f32_scaled(n, k, w.r.p, w.scale.p, v0.f.p, st);
-            run_fill<float>(v0.x.p, nk, 0.0f, st);
+            run_to_f32_scaled(n, k, w.r.p, w.scale.p, v0.f.p, v0.x.p, st);
             cycle<float>(c32, 0, v0.x.p, v0.f.p);
             run_add_scaled_f32(n, k, v0.x.p, w.scale.p, w.phi.p, st);
         }
@@ -611,10 +610,9 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
             run_residual<double>(op0, op0.v64.p, op0.d64.p, w.phi.p, w.b.p, w.r.p, k, st, true);
         }
         if (!direct && kappa > 0) {
-            run_recombine_fine(n, k, hm, w.phi.p, w.r.p, w.hphi.p, w.hr.p, w.partial.p, w.alpha_f.p, st);
-            int slot = hnext % kappa;
-            run_copy<double>(w.hphi.p + slot * nk, w.phi.p, nk, st);
-            run_copy<double>(w.hr.p + slot * nk, w.r.p, nk, st);
+            // recombination; the recombined pair goes into the next history slot
+            run_recombine_fine(n, k, hm, w.phi.p, w.r.p, w.hphi.p, w.hr.p, hnext % kappa,
+                               w.partial.p, w.alpha_f.p, st);
         }
         run_relres(n, k, w.r.p, w.nb.p, w.partial.p, w.rel.p, st);
         c64.s = s;
