@@ -9,6 +9,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <system_error>
 #include <thread>
 
 #include "lamg_internal.h"
@@ -89,7 +90,13 @@ static HostGraph read_graph(const lamg_graph *g, hipStream_t s) {
             }
         };
         std::vector<std::thread> th;
-        for (int t = 1; t < nt; ++t) th.emplace_back(check, t);
+        for (int t = 1; t < nt; ++t) {
+            try {
+                th.emplace_back(check, t);
+            } catch (const std::system_error &) {
+                check(t);  // no thread available: this share runs here
+            }
+        }
         check(0);
         for (std::thread &x : th) x.join();
         if (!sym.load()) throw Error(LAMG_NOT_SYMMETRIC, "graph: not symmetric");
