@@ -84,6 +84,8 @@ def lib():
         L.orc_solve.argtypes = [C.c_void_p, _f64p, C.c_double, C.c_int, _f64p, C.c_void_p, _f64p]
         L.orc_cycle_once.restype = C.c_double
         L.orc_cycle_once.argtypes = [C.c_void_p, _f64p, _f64p]
+        L.orc_cycles.restype = C.c_double
+        L.orc_cycles.argtypes = [C.c_void_p, _f64p, _f64p, C.c_int, C.c_void_p]
         L.orc_recombine.argtypes = [C.c_int, C.c_int, _f64p, _f64p, C.c_void_p, C.c_void_p]
         _lib = L
     return _lib
@@ -332,3 +334,11 @@ class Hierarchy:
     def cycle_once(self, phi, f) -> float:
         phi = np.ascontiguousarray(phi, np.float64)
         return float(lib().orc_cycle_once(self._h, phi, np.ascontiguousarray(f, np.float64)))
+
+    def cycle_visits(self, phi, f, ncyc: int):
+        """Runs ncyc cycles in place on phi (counters persisting, as in one solve); returns
+        the entries into each level's correction phase."""
+        visits = np.zeros(self.nlevels, np.int64)
+        lib().orc_cycles(self._h, phi, np.ascontiguousarray(f, np.float64), int(ncyc),
+                         visits.ctypes.data)
+        return visits

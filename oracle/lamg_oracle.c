@@ -1456,9 +1456,11 @@ done:
     return rc;
 }
 
-/* Two-level diagnostic: one cycle from phi with f, returning the finest-level energy
- * correction factor mu (used to pin mu = 1 under an exact coarse solve). */
-double orc_cycle_once(const void *hp, double *phi, const double *f) {
+/* Diagnostic: ncyc cycles from phi with f (visit counters persisting across them, as in
+ * one solve), returning the finest-level energy correction factor mu of the last (used to
+ * pin mu = 1 under an exact coarse solve); visits_out (nullable, nlev entries) receives
+ * the entries into each level's correction phase (used to pin the cycle schedule). */
+double orc_cycles(const void *hp, double *phi, const double *f, int ncyc, long long *visits_out) {
     const ohier *h = (const ohier *)hp;
     osolver S;
     memset(&S, 0, sizeof(S));
@@ -1475,8 +1477,10 @@ double orc_cycle_once(const void *hp, double *phi, const double *f) {
         S.cd[l] = (double *)malloc(sizeof(double) * (size_t)nf);
     }
     S.mu_last[0] = 1.0;
-    cycle(&S, 0, phi, f);
+    for (int c = 0; c < ncyc; ++c) cycle(&S, 0, phi, f);
     double mu = S.mu_last[0];
+    if (visits_out)
+        for (int l = 0; l < h->nlev; ++l) visits_out[l] = S.visits[l];
     for (int l = 0; l < ORC_MAX_LEVELS; ++l) {
         free(S.r[l]);
         free(S.fc[l]);
@@ -1488,6 +1492,10 @@ double orc_cycle_once(const void *hp, double *phi, const double *f) {
         free(S.cd[l]);
     }
     return mu;
+}
+
+double orc_cycle_once(const void *hp, double *phi, const double *f) {
+    return orc_cycles(hp, phi, f, 1, NULL);
 }
 
 /* Exposed for the recombination pin: one fine-level recombination on caller data. */

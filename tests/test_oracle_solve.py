@@ -77,6 +77,34 @@ def test_recovers_a_known_solution(gen):
     assert np.linalg.norm(phi - x) <= 1e-6 * np.linalg.norm(x)
 
 
+@pytest.mark.parametrize("gen,frac", [
+    (lambda: I.chung_lu(3000, 2.1, 8, seed=5), False),  # 1.5 on the large levels
+    (lambda: I.grid3d(48, 48, 48, "lognormal", seed=1), True),  # also min(2, 0.7/tau)
+])
+def test_cycle_schedule_is_the_beatty_sequence(gen, frac):
+    """The gamma-cycle schedule (eq. (2.4) and the fractional cycle index): entry i into
+    level l's correction phase visits level l+1 floor((i+1) gamma_l) - floor(i gamma_l)
+    times, with counters kept across the cycles of one solve, so after E entries level l+1
+    has been entered floor(E gamma_l) times (a telescoping sum); the directly solved level
+    has no correction phase."""
+    import math
+
+    g = gen()
+    h = O.Hierarchy(g)
+    assert h.nlevels >= 3
+    gam = [h.level_info(l)["gamma"] for l in range(h.nlevels - 1)]
+    assert 1.5 in gam
+    assert any(x not in (1.0, 1.5, 2.0) for x in gam) == frac, gam
+    f = I.rhs(g.n, 1, seed=3)[0]
+    f -= f.mean()
+    for ncyc in (1, 3, 7):
+        v = h.cycle_visits(np.zeros(g.n), f, ncyc)
+        assert v[0] == ncyc
+        for l in range(h.nlevels - 2):
+            assert v[l + 1] == math.floor(v[l] * gam[l]), (ncyc, l, v, gam)
+        assert v[h.nlevels - 1] == 0
+
+
 def test_energy_correction_is_one_under_exact_coarse_solve():
     """Two levels with an exactly solved coarse level: the energy-optimal multiple of
     the coarse correction is 1 (the Galerkin correction is already L-optimal)."""
