@@ -352,7 +352,7 @@ __global__ void k_inject_add(int64_t nc, int k, int lkp, const int32_t *__restri
 // block combines them in block order and finishes the per-column scalar.
 // Element mapping: block of 256 threads = (256/kp) rows x kp columns.
 // ---------------------------------------------------------------------------
-enum { R_MU = 0, R_RC2 = 1, R_NORM2 = 2, R_SUM = 3, R_MAXABS = 4, R_RCF = 5 };
+enum { R_MU = 0, R_RC2 = 1, R_NORM2 = 2, R_SUM = 3, R_MAXABS = 4, R_RCF = 5, R_RES2 = 6 };
 
 template <int R>
 struct RedQ;
@@ -361,6 +361,12 @@ template <> struct RedQ<R_RC2> { static constexpr int Q = 2; };
 template <> struct RedQ<R_NORM2> { static constexpr int Q = 1; };
 template <> struct RedQ<R_SUM> { static constexpr int Q = 1; };
 template <> struct RedQ<R_MAXABS> { static constexpr int Q = 1; };
+template <> struct RedQ<R_RES2> { static constexpr int Q = 2; };  // ||r||^2 and max |r|
+// Quantities of a reduction combined by max instead of sum (bit i: quantity i).
+template <int R>
+constexpr int red_max_mask() {
+    return R == R_MAXABS ? 1 : (R == R_RES2 ? 2 : 0);
+}
 template <> struct RedQ<R_RCF> { static constexpr int Q = 14; };
 
 struct RedIn {
@@ -382,7 +388,7 @@ struct RedElem {
         } else if (R == R_RC2) {  // a = rho, b = rho1
             a[0] = (double)((const T *)in.a)[o];
             a[1] = (double)((const T *)in.b)[o];
-        } else if (R == R_NORM2 || R == R_SUM || R == R_MAXABS) {
+        } else if (R == R_NORM2 || R == R_SUM || R == R_MAXABS || R == R_RES2) {
             a[0] = (double)((const T *)in.a)[o];
         } else {  // RCF: a = r, b = history residuals (m slots; slots past m reread m - 1)
             const double *hr = (const double *)in.b;
@@ -404,6 +410,9 @@ struct RedElem {
             q[0] += a[0];
         } else if (R == R_MAXABS) {
             q[0] = fmax(q[0], fabs(a[0]));
+        } else if (R == R_RES2) {
+            q[0] += a[0] * a[0];
+            q[1] = fmax(q[1], fabs(a[0]));
         } else {  // RCF: G_i = r - r_i (0 past m)
             const double rv = a[0];
             double G[4];
@@ -452,7 +461,7 @@ __global__ void __launch_bounds__(kBlock)
         if (rloc < st) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                if (R == R_MAXABS)
+                if ((red_max_mask<R>() >> i) & 1)
                     sh[i][threadIdx.x] = fmax(sh[i][threadIdx.x], sh[i][threadIdx.x + (st << lkp)]);
                 else
                     sh[i][threadIdx.x] += sh[i][threadIdx.x + (st << lkp)];
@@ -472,6 +481,7 @@ struct Fin {
     const double *aux;  // per-column auxiliary input (e.g. ||b|| for relres)
     double scale;
     int m;
+    double *out2 = nullptr;  // R_RES2: per-column max |r|
 };
 
 __device__ inline void solve_rcf(const double *q, int m, double *alpha) {
@@ -535,7 +545,7 @@ __device__ inline void solve_rcf(const double *q, int m, double *alpha) {
 // combines the partials b = g, g + G, ... in order and the group then combines its lanes
 // by an xor butterfly, lane 0's value being the total. The order depends only on nblk, k
 // and blockDim, so every launch of the same shape gives the same bits.
-template <int Q, bool MAX>
+template <int Q, int MAXMASK>
 __device__ inline void group_totals(int nblk, int k, const double *__restrict__ partial,
                                     double *tot) {
     const int nq = Q * k;
@@ -547,6 +557,7 @@ __device__ inline void group_totals(int nblk, int k, const double *__restrict__ 
         const int idx = q0 + grp;
         const bool live = idx < nq;
         const int i = live ? idx / k : 0, c = live ? idx - i * k : 0;
+        const bool MAX = (MAXMASK >> i) & 1;  // uniform within the group
         double s = 0.0;
         if (live)
             for (int b0 = g; b0 < nblk; b0 += 8 * G) {  // 8 loads in flight, added in order
@@ -574,7 +585,7 @@ __global__ void __launch_bounds__(kBlock)
     k_red_final(int nblk, int k, const double *__restrict__ partial, Fin fin) {
     constexpr int Q = RedQ<R>::Q;
     __shared__ double tot[Q * 32];
-    group_totals<Q, R == R_MAXABS>(nblk, k, partial, tot);
+    group_totals<Q, red_max_mask<R>()>(nblk, k, partial, tot);
     int c = threadIdx.x;
     if (c >= k) return;
     if (R == R_MU) {
@@ -592,6 +603,10 @@ __global__ void __launch_bounds__(kBlock)
         fin.out[c] = fin.scale * tot[c];
     } else if (R == R_MAXABS) {
         fin.out[c] = tot[c];
+    } else if (R == R_RES2) {  // relative residual (as R_NORM2 with aux) and max |r|
+        double v = sqrt(tot[c]);
+        fin.out[c] = fin.aux[c] > 0.0 ? v / fin.aux[c] : 0.0;
+        fin.out2[c] = tot[32 + c];
     } else {
         double q[14];
         for (int i = 0; i < 14; ++i) q[i] = tot[i * 32 + c];
@@ -645,7 +660,7 @@ __global__ void k_rc2_update(int64_t n, int k, int lkp, T *__restrict__ e, T *__
 // order (same block size), into tot[i][c] of the calling block (followed by a barrier).
 __device__ inline void block_totals2(int nblk, int k, const double *__restrict__ partial,
                                      double (*tot)[32]) {
-    group_totals<2, false>(nblk, k, partial, &tot[0][0]);
+    group_totals<2, 0>(nblk, k, partial, &tot[0][0]);
 }
 
 // Energy correction and prolongation in one launch: every block forms mu per column from
@@ -1047,6 +1062,14 @@ void run_relres(int64_t n, int k, const double *r, const double *nb, double *par
                 hipStream_t s) {
     RedIn in{r, nullptr, nullptr, nullptr, 0, 0};
     reduce<double, R_NORM2>(n, k, in, partial, Fin{out, nb, 1.0, 0}, s);
+}
+
+void run_relres_maxabs(int64_t n, int k, const double *r, const double *nb, double *partial,
+                       double *rel, double *maxabs, hipStream_t s) {
+    RedIn in{r, nullptr, nullptr, nullptr, 0, 0};
+    Fin fin{rel, nb, 1.0, 0};
+    fin.out2 = maxabs;
+    reduce<double, R_RES2>(n, k, in, partial, fin, s);
 }
 
 void run_recombine_fine(int64_t n, int k, int m, double *phi, double *r, double *hphi, double *hr,

@@ -462,6 +462,9 @@ void run_norm2(int64_t n, int k, const double *x, double *partial, double *out, 
 void run_maxabs(int64_t n, int k, const double *x, double *partial, double *out, hipStream_t s);
 void run_relres(int64_t n, int k, const double *r, const double *nb, double *partial, double *out,
                 hipStream_t s);
+// The relative residual of run_relres and, from the same pass, max |r| per column.
+void run_relres_maxabs(int64_t n, int k, const double *r, const double *nb, double *partial,
+                       double *rel, double *maxabs, hipStream_t s);
 // Fine-level recombination over m history pairs (Sec. 2, "Cycle and acceleration"); the
 // recombined (phi, r) is also saved in history slot `slot`.
 void run_recombine_fine(int64_t n, int k, int m, double *phi, double *r, double *hphi, double *hr,

@@ -567,6 +567,7 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
     // zero columns: phi = 0; everything else starts from phi = 0, r = b
     run_fill<double>(w.phi.p, nk, 0.0, s);
     run_copy<double>(w.r.p, w.b.p, nk, s);
+    if (fp32) run_maxabs(n, k, w.r.p, w.partial.p, w.scale.p, s);  // the first cycle's scale
     const bool direct = L0.coarsest;
     const int kappa = std::max(0, std::min(4, (int)h->opt.kappa));
     int hm = 0, hnext = 0;
@@ -598,8 +599,8 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
         if (!fp32) {
             cycle<double>(c64, 0, w.phi.p, w.b.p);
         } else {
-            // FP32 cycle on the scaled residual equation, FP64 update
-            run_maxabs(n, k, w.r.p, w.partial.p, w.scale.p, st);
+            // FP32 cycle on the residual equation scaled by max |r| (w.scale, formed with
+            // the previous relative residuals, or before the first cycle), FP64 update
             LevelVecs<float> &v0 = w.lv32[0];
             run_to_f32_scaled(n, k, w.r.p, w.scale.p, v0.f.p, v0.x.p, st);
             cycle<float>(c32, 0, v0.x.p, v0.f.p);
@@ -614,7 +615,7 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
             run_recombine_fine(n, k, hm, w.phi.p, w.r.p, w.hphi.p, w.hr.p, hnext % kappa,
                                w.partial.p, w.alpha_f.p, st);
         }
-        run_relres(n, k, w.r.p, w.nb.p, w.partial.p, w.rel.p, st);
+        run_relres_maxabs(n, k, w.r.p, w.nb.p, w.partial.p, w.rel.p, w.scale.p, st);
         c64.s = s;
         c32.s = s;
     };
