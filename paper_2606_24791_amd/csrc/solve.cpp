@@ -668,9 +668,12 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
         }
         if (any_new) {
             // freeze: emit the converged columns, then zero their state so later cycles
-            // leave them untouched
+            // leave them untouched (no later cycle once every column has converged, and a
+            // solve re-initialises all of this state)
             w.mask.upload(w.h_mask, k, s);
             emit_columns(h, k, w.mask.p, phi_out);
+        }
+        if (any_new && n_active > 0) {
             run_zero_cols(n, k, w.mask.p, w.phi.p, s);
             run_zero_cols(n, k, w.mask.p, w.b.p, s);
             run_zero_cols(n, k, w.mask.p, w.r.p, s);
