@@ -87,6 +87,10 @@ def lib():
         L.orc_cycles.restype = C.c_double
         L.orc_cycles.argtypes = [C.c_void_p, _f64p, _f64p, C.c_int, C.c_void_p]
         L.orc_recombine.argtypes = [C.c_int, C.c_int, _f64p, _f64p, C.c_void_p, C.c_void_p]
+        L.orc_recombine2.argtypes = [C.c_int, _f64p, _f64p, _f64p, _f64p]
+        L.orc_recombine2.restype = None
+        L.orc_acf.argtypes = [_f64p, C.c_int]
+        L.orc_acf.restype = C.c_double
         _lib = L
     return _lib
 
@@ -253,6 +257,21 @@ def recombine(phi, r, hphi, hr):
     RA = (C.c_void_p * max(m, 1))(*[a.ctypes.data for a in hr])
     lib().orc_recombine(phi.size, m, phi, r, C.cast(PA, C.c_void_p), C.cast(RA, C.c_void_p))
     return phi, r
+
+
+def recombine2(e, rho, e1, rho1):
+    """One coarse two-iterate recombination (in place on copies of e, rho), returned."""
+    e = np.array(e, np.float64)
+    rho = np.array(rho, np.float64)
+    lib().orc_recombine2(e.size, e, rho, np.ascontiguousarray(e1, np.float64),
+                         np.ascontiguousarray(rho1, np.float64))
+    return e, rho
+
+
+def acf(rels) -> float:
+    """Asymptotic convergence factor of a relative-residual history (rels[0] = start)."""
+    r = np.ascontiguousarray(rels, np.float64)
+    return float(lib().orc_acf(r, r.size))
 
 
 # ---------------------------------------------------------------------------

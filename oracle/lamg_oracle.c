@@ -1343,12 +1343,27 @@ static void recombine_fine(int n, int m, double *phi, double *r, double **hphi, 
     }
 }
 
+/* Asymptotic convergence factor (Sec. 4.1): the geometric mean of the last five
+ * per-cycle reductions rels[i] / rels[i-1], i.e. (rels[last] / rels[last-5])^(1/5), or of all
+ * of them when fewer than five cycles ran. rels[0] is the starting relative residual (1).
+ * 0 when there is no reduction to average or an end point is not positive.
+ * Pinned: geometric histories give their ratio; hand-built histories against the mean of
+ * their printed ratios. */
+double orc_acf(const double *rels, int nrels) {
+    int last = nrels - 1, cnt = last < 5 ? last : 5;
+    if (cnt <= 0 || !(rels[last - cnt] > 0.0) || !(rels[last] > 0.0)) return 0.0;
+    return pow(rels[last] / rels[last - cnt], 1.0 / cnt);
+}
+
 /* Solve L phi = b (eq. (1.1)) for one right-hand side: b is projected to mean zero,
  * cycles run until ||r||/||b|| <= tol or max_cycles; phi is returned mean-zero.
  * hist (max_cycles+1 entries, may be NULL) receives relres after each cycle (hist[0]=1).
  * stats[0] = cycles, stats[1] = final true relres, stats[2] = ACF (geometric mean of
  * the last <= 5 per-cycle reductions), stats[3] = last finest-level mu.
- * Returns ORC_OK or ORC_NOT_CONVERGED. */
+ * Returns ORC_OK, ORC_NOT_CONVERGED (the tolerance was not met within max_cycles, or the
+ * relative residual stopped being a finite number: cycling stops there), or ORC_ERR_ARG
+ * when b holds a value that is not finite (its norm is then not finite either: eq. (1.1)
+ * has no solution to approach; phi is set to 0). */
 int orc_solve(const void *hp, const double *b_in, double tol, int max_cycles, double *phi,
               double *hist, double *stats) {
     const ohier *h = (const ohier *)hp;
@@ -1386,6 +1401,14 @@ int orc_solve(const void *hp, const double *b_in, double tol, int max_cycles, do
     if (hist) hist[0] = 1.0;
     int cyc = 0;
     double rel = 1.0, acf = 0.0;
+    if (!isfinite(nb)) {
+        stats[0] = 0;
+        stats[1] = NAN;
+        stats[2] = 0.0;
+        stats[3] = 1.0;
+        rc = ORC_ERR_ARG;
+        goto done;
+    }
     if (nb == 0.0) {
         stats[0] = 0;
         stats[1] = 0.0;
@@ -1402,7 +1425,7 @@ int orc_solve(const void *hp, const double *b_in, double tol, int max_cycles, do
     double rels[1024];
     int nrels = 0;
     rels[nrels++] = 1.0;
-    while (rel > tol && cyc < max_cycles) {
+    while (!(rel <= tol) && isfinite(rel) && cyc < max_cycles) {
         cycle(&S, 0, phi, b);
         spmv_resid(&l0->L, phi, b, r);
         if (!l0->coarsest) {
@@ -1418,12 +1441,7 @@ int orc_solve(const void *hp, const double *b_in, double tol, int max_cycles, do
         if (hist) hist[cyc] = rel;
         if (nrels < 1024) rels[nrels++] = rel;
     }
-    /* ACF: geometric mean of the last (up to) five per-cycle reductions */
-    {
-        int last = nrels - 1, cnt = last < 5 ? last : 5;
-        if (cnt > 0 && rels[last - cnt] > 0.0 && rels[last] > 0.0)
-            acf = pow(rels[last] / rels[last - cnt], 1.0 / cnt);
-    }
+    acf = orc_acf(rels, nrels);
     {
         double mp = 0.0;
         for (int i = 0; i < n; ++i) mp += phi[i];
@@ -1435,7 +1453,7 @@ int orc_solve(const void *hp, const double *b_in, double tol, int max_cycles, do
     stats[1] = sqrt(dot(n, r, r)) / nb;
     stats[2] = acf;
     stats[3] = S.mu_last[0];
-    if (rel > tol) rc = ORC_NOT_CONVERGED;
+    if (!(rel <= tol)) rc = ORC_NOT_CONVERGED;
 done:
     free(b);
     free(r);
@@ -1496,6 +1514,12 @@ double orc_cycles(const void *hp, double *phi, const double *f, int ncyc, long l
 
 double orc_cycle_once(const void *hp, double *phi, const double *f) {
     return orc_cycles(hp, phi, f, 1, NULL);
+}
+
+/* Exposed for the recombination pin: one coarse two-iterate recombination on caller data
+ * (e, rho updated in place from the saved pair e1, rho1). */
+void orc_recombine2(int n, double *e, double *rho, const double *e1, const double *rho1) {
+    recombine2(n, e, rho, e1, rho1);
 }
 
 /* Exposed for the recombination pin: one fine-level recombination on caller data. */

@@ -161,6 +161,64 @@ def test_recombination_minimises_residual():
     assert np.array_equal(phi3, phi) and np.array_equal(r3, r)
 
 
+def test_coarse_recombination_is_the_least_squares_step():
+    """Coarse two-iterate recombination (Sec. 2, "Cycle and acceleration"): from the current
+    pair (e, rho) and the saved pair (e1, rho1) of one visit, the step along e1 - e that
+    minimises the residual norm. The optimum is found here by a library least-squares solve
+    on L (e1 - e) formed from the dense Laplacian, not from the stored residuals."""
+    g = I.random_connected(250, 800, seed=9)
+    L = dense_L(g)
+    rng = np.random.default_rng(5)
+    f = rng.standard_normal(g.n)
+    f -= f.mean()
+    e, e1 = rng.standard_normal(g.n), rng.standard_normal(g.n)
+    rho, rho1 = f - L @ e, f - L @ e1
+    LD = L @ (e1 - e)
+    a, *_ = np.linalg.lstsq(LD[:, None], rho, rcond=None)
+    a = float(a[0])
+    assert abs(a) > 0.05  # a step whose halving or doubling is visible
+    e2, rho2 = O.recombine2(e, rho, e1, rho1)
+    np.testing.assert_allclose(e2, e + a * (e1 - e), rtol=1e-11, atol=1e-11)
+    np.testing.assert_allclose(rho2, f - L @ e2, atol=1e-9)
+    best = np.linalg.norm(rho - a * LD)
+    assert np.linalg.norm(rho2) == pytest.approx(best, rel=1e-10)
+    assert np.linalg.norm(rho2) <= min(np.linalg.norm(rho), np.linalg.norm(rho1))
+    # equal iterates carry no direction: nothing changes
+    e3, rho3 = O.recombine2(e, rho, e, rho)
+    assert np.array_equal(e3, e) and np.array_equal(rho3, rho)
+
+
+def test_acf_is_the_geometric_mean_of_the_last_five_reductions():
+    """ACF (Sec. 4.1): the geometric mean of the last five per-cycle reductions of the
+    relative residual; with fewer cycles, of all of them."""
+    for q in (0.5, 0.1, 0.013):
+        assert O.acf(q ** np.arange(12.0)) == pytest.approx(q, rel=1e-12)
+    ratios = [0.9, 0.5, 0.2, 0.3, 0.1, 0.25, 0.4]
+    hist = np.concatenate([[1.0], np.cumprod(ratios)])
+    assert O.acf(hist) == pytest.approx(float(np.prod(ratios[-5:])) ** 0.2, rel=1e-12)
+    assert O.acf([1.0, 0.5, 0.05]) == pytest.approx(np.sqrt(0.5 * 0.1), rel=1e-12)
+    assert O.acf([1.0]) == 0.0
+    assert O.acf([1.0, 0.1, 0.0]) == 0.0
+
+
+def test_solve_reports_the_acf_of_its_history():
+    g = I.grid2d(40, 33, 1.0, 1e-2)
+    _, st, hist = O.Hierarchy(g).solve(I.rhs(g.n, 1, 3)[0], 1e-8, 60)
+    assert st["converged"] and hist.size == st["cycles"] + 1 >= 7
+    assert st["acf"] == O.acf(hist)
+    assert st["acf"] == pytest.approx((hist[-1] / hist[-6]) ** 0.2, rel=1e-12)
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+def test_nonfinite_rhs_is_an_argument_error(bad):
+    """eq. (1.1) needs a finite b: a NaN or infinite entry is rejected, not solved."""
+    g = I.grid2d(16, 16)
+    b = I.rhs(g.n, 1, 0)[0]
+    b[37] = bad
+    phi, st, _ = O.Hierarchy(g).solve(b, 1e-8, 20)
+    assert st["rc"] == O.ERR_ARG and not st["converged"] and np.all(phi == 0)
+
+
 def test_zero_rhs_returns_zero():
     g = I.grid2d(20, 20)
     h = O.Hierarchy(g)
