@@ -3,26 +3,27 @@
 
 Metric: nnz(L) * RHS solved per second to ||b - L phi|| / ||b|| <= 1e-8, FP32 cycles inside
 FP64 iterative refinement (the reported `value`) beside plain FP64 cycles, with p50/p99
-solve latency. One step = one complete solve of the workload's right-hand side block
-from a zero start, hierarchy resident on the device and b already in HBM.
+solve latency. One step = one complete solve of the workload's right-hand-side block from
+a zero start, hierarchy resident on the device and b already in HBM.
 
-Default workload: the 1024 x 1024 grid-aligned anisotropic 5-point Laplacian (x-weight 1,
-y-weight 1e-3; n = 1,048,576, nnz(L) = 2m + n = 5,238,784), b ~ N(0,1) (mean removed by
-the solver), one right-hand side. Default hierarchy: low-degree elimination levels
-alternating with aggregation (--no-elimination: aggregation only).
+Default workload: the 128^3 7-point grid with lognormal(0,1) edge weights
+(n = 2,097,152, nnz(L) = 2m + n = 14,581,760) with 32 right-hand sides b ~ N(0,1) (mean
+removed by the solver) solved together: the largest nnz * RHS per solve of the measured
+configurations that fits one GPU. Other workloads behind --workload / --nrhs.
 
 The JSON line also carries
-  roofline: the FP32 Gauss-Seidel colour pass of the finest aggregation level (the largest
-            full smoothing pass, the dominant bandwidth kernel; the finest level itself is an
-            elimination level on the grids):
-            its algorithmic bytes per launch over its mean launch time, both summed over
-            every launch in a second timed FP32+IR region of the same K solves with HIP
-            events attached to every launch on the solve stream (the throughput region runs
-            without events; with --graphs it replays each cycle as a HIP graph, which needs
-            events off), against 8 TB/s HBM;
-  coarse_tail: the same timing of the coarse-level kernel (one workgroup per column), which takes the
-            largest share of the solve and is bound by dependent steps, not bytes;
-  cpu_baseline: the CPU oracle (single-threaded, FP64) solving the same system once.
+  roofline:   the dominant kernel by time (kernel kind and precision, every level) in a
+              second, evented FP32+IR region of the same solves: the library attaches a pair
+              of HIP events (the dispatch's own start and end timestamps) to every launch on
+              the solve stream; achieved = the kind's summed algorithmic bytes / its summed
+              launch durations, against 8 TB/s HBM;
+  whole_solve: algorithmic bytes of every launch of one solve (the library's count) over the
+              solve's wall time, with the working set beside it;
+  kernels:    the same in-situ figures for every kernel kind;
+  cpu_baseline: the CPU oracle (FP64, single-threaded) solving column 0 of the same block on
+              one core, setup excluded, and an aggregate leg of one oracle process per
+              available core (up to 15) solving one column each; the host CPU model and core
+              counts; the oracle's solutions of columns 0 and k-1 give err_vs_oracle.
 """
 from __future__ import annotations
 
@@ -38,41 +39,60 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MALL_BYTES = 256 << 20
 WORKLOADS = {
-    "aniso1024": "2D 5-point grid 1024x1024, weight 1 on x-edges and 1e-3 on y-edges",
     "lognormal128": "3D 7-point grid 128^3, lognormal(0,1) edge weights",
+    "aniso1024": "2D 5-point grid 1024x1024, weight 1 on x-edges and 1e-3 on y-edges",
     "chunglu2m": "Chung-Lu n=2M, degree exponent 2.1, mean degree 16, LCC, weights U[1,2]",
     "grid64": "2D 5-point grid 64x64, unit weights",
 }
+KIND_SYMBOLS = {  # kernel kinds and the kernel symbols a rocprofv3 trace shows for them
+    "gs_color": "k_csr / k_csr_mixed / k_csr_long with OP_GS (0)",
+    "residual": "k_csr / k_csr_mixed / k_csr_long with OP_RESID (1)",
+    "restrict": "k_csr / k_csr_mixed / k_csr_long with OP_SPMV (2)",
+    "prolong": "k_red_partial<T, 0> + k_prolong_mu (or k_red_final<0> + k_prolong), k_inject_add",
+    "tail": "k_tail",
+    "reduce": "k_red_partial / k_red_final / k_rc2_fused / k_rc2_update / k_rcf_update",
+    "vector": "k_copy / k_fill / k_gather_cols / k_scatter_cols / k_sub_col / k_to_f32_scaled / "
+              "k_add_scaled_f32 / k_zero_cols / k_to_cols / k_from_cols / k_fill_i64 / k_coarsest",
+    "cheb": "k_csr / k_csr_mixed / k_csr_long with OP_CHEB (3) + k_add_into",
+}
 
 
-def kernel_source_hash() -> str:
-    """Hash of the sources the cycle kernels are built from."""
-    import hashlib
-
-    h = hashlib.sha256()
-    for f in ("cycle_kernels.hip", "csr_device.h"):
-        with open(os.path.join(ROOT, "paper_2606_24791_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-def measured_traffic(workload: str, k: int, elimination: bool):
-    """HBM bytes per launch of the timed FP32 Gauss-Seidel colour pass from the committed
-    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on a copy kernel), or None
-    when it does not cover this workload and hierarchy or the kernel sources changed since
-    it was taken."""
-    path = os.path.join(ROOT, "profiles", "traffic_gs_color.json")
+def host_cpu() -> dict:
+    model = platform.processor() or platform.machine()
     try:
-        with open(path) as fh:
-            t = json.load(fh)
-    except (OSError, ValueError):
-        return None
-    if t.get("workload") != workload or t.get("nrhs") != k or \
-            bool(t.get("elimination")) != elimination or \
-            t.get("source_hash") != kernel_source_hash():
-        return None
-    return t.get("bytes_per_launch")
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(model=model, logical_cpus=os.cpu_count(),
+                usable_cpus=len(os.sched_getaffinity(0)))
+
+
+# --- the CPU oracle legs (run in spawned worker processes) ------------------------------
+
+def oracle_column(args):
+    """Worker: the oracle's hierarchy of the workload and the FP64 solve of one column.
+    Returns (column, phi, setup seconds, solve seconds, cycles)."""
+    name, k, col, tol, opts = args
+    import numpy as np  # noqa: F401
+
+    import oracle as O
+    from paper_2606_24791_amd import inputs as I
+
+    g = I.workload(name)
+    b = I.rhs(g.n, k, seed=0)[col]
+    t = time.perf_counter()
+    oh = O.Hierarchy(g, seed=1, **opts)
+    t_setup = time.perf_counter() - t
+    t = time.perf_counter()
+    phi, so, _ = oh.solve(b, tol, 300)
+    t_solve = time.perf_counter() - t
+    return col, phi, t_setup, t_solve, so["cycles"]
 
 
 def percentile(xs, q):
@@ -86,10 +106,13 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="aniso1024", choices=sorted(WORKLOADS))
-    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--workload", default="lognormal128", choices=sorted(WORKLOADS))
+    ap.add_argument("--nrhs", type=int, default=32)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-procs", type=int, default=-1,
+                    help="oracle processes of the aggregate CPU leg (-1: usable cores up to 16, "
+                         "minus one; 0: no aggregate leg)")
     ap.add_argument("--n-direct", type=int, default=0,
                     help="levels up to this size are solved directly (0: library default)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -103,14 +126,27 @@ def main() -> int:
                     help="replay each cycle as a HIP graph from the second solve on")
     ap.add_argument("--no-elimination", action="store_true",
                     help="aggregation-only hierarchy (no low-degree elimination levels)")
-    ap.add_argument("--profile-reps", type=int, default=0,
-                    help="also time the timed level's GS colour pass in isolation (back-to-back "
-                         "launches)")
+    ap.add_argument("--evented-steps", type=int, default=1,
+                    help="solves per precision in the evented (per-launch timed) region")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (the solver has no multi-GPU path); got --gpus "
+        print(f"bench.py measures one GPU only (the solver has no multi-GPU path); got --gpus "
               f"{args.gpus}", file=sys.stderr)
         return 2
+    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
+    k = args.nrhs
+
+    # Oracle worker processes are started before anything touches the GPU (a process that has
+    # initialised the GPU must not start programs); they stay idle until the GPU part is done.
+    pool, procs = None, 0
+    cpu = host_cpu()
+    if not args.no_cpu_baseline:
+        import multiprocessing as mp
+
+        usable = min(16, cpu["usable_cpus"])
+        procs = (usable - 1) if args.cpu_procs < 0 else args.cpu_procs
+        procs = max(0, min(procs, k, usable))
+        pool = mp.get_context("spawn").Pool(max(1, procs))
 
     import numpy as np
     import torch
@@ -121,7 +157,6 @@ def main() -> int:
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
 
     t = time.perf_counter()
     g = I.workload(args.workload)
@@ -139,30 +174,28 @@ def main() -> int:
     h = B.lamg_setup(g, opts)
     torch.cuda.synchronize()
     hi = B.lamg_hierarchy_info(h)
-    lt = hi["timed_level"]
     log(f"setup {hi['setup_seconds']:.2f}s levels={hi['levels']} n={hi['n']} "
-        f"elimination levels={[l for l, e in enumerate(hi['elim']) if e]} "
-        f"tail from level {hi['tail_level']}, timed level {lt}")
-    k = args.nrhs
+        f"colours={hi['ncolors']} elimination levels={[l for l, e in enumerate(hi['elim']) if e]} "
+        f"tail from level {hi['tail_level']}")
     bh = I.rhs(g.n, k, seed=0)
     b = torch.tensor(bh, device=dev)
     stream = torch.cuda.current_stream()
 
-    def run_steps(prec, phi, timed):
-        """K solves between synchronisations; with `timed`, the library brackets every launch
-        of the timed level's kernels and of the coarse tail with HIP events on `stream`."""
+    def run_steps(prec, phi, steps, evented):
+        """`steps` solves between synchronisations; with `evented`, the library brackets every
+        launch of every kernel with a pair of HIP events on `stream`."""
         torch.cuda.synchronize()
-        if timed:
-            B.lamg_timing_start(h, 65536)
+        if evented:
+            B.lamg_timing_start_all(h, 1 << 18)
         lat, stats = [], None
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             ts = time.perf_counter()
             stats = B.lamg_solve(h, b, phi, tol=args.tol, precision=prec, stream=stream)
             lat.append(time.perf_counter() - ts)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        kt = B.lamg_timing_stop(h) if timed else None
+        kt = B.lamg_timing_stop(h) if evented else None
         return wall, lat, stats, kt
 
     results = {}
@@ -170,50 +203,39 @@ def main() -> int:
         phi = torch.empty_like(b)
         for _ in range(args.warmup):
             B.lamg_solve(h, b, phi, tol=args.tol, precision=prec, stream=stream)
-        wall, lat, stats, _ = run_steps(prec, phi, False)
-        wall_ev, _, _, kt = run_steps(prec, phi, True)
+        wall, lat, stats, _ = run_steps(prec, phi, args.steps, False)
+        wall_ev, _, _, kt = run_steps(prec, phi, max(1, args.evented_steps), True)
         ms = 1e3 * wall / args.steps
         results[name] = dict(ms=ms, value=g.nnz_laplacian * k / (wall / args.steps),
                              p50_ms=1e3 * percentile(lat, 50), p99_ms=1e3 * percentile(lat, 99),
                              cycles=stats["cycles"], relres=stats["relres_max"],
                              converged=bool(stats["converged"]), phi=phi.cpu().numpy(),
-                             graph_cycles=stats["graph_cycles"],
-                             kt=kt, ms_events=1e3 * wall_ev / args.steps, wall=wall_ev)
-        log(f"{name}: {ms:.3f} ms/solve ({stats['graph_cycles']} of {stats['cycles']} cycles "
-            f"as graphs; {results[name]['ms_events']:.3f} kernel by kernel with events), "
-            f"{results[name]['value']:.3e} nnz*RHS/s, cycles={stats['cycles']} "
-            f"relres={stats['relres_max']:.2e}")
+                             graph_cycles=stats["graph_cycles"], bytes=stats["bytes"], kt=kt,
+                             ev_steps=max(1, args.evented_steps), wall_ev=wall_ev)
+        log(f"{name}: {ms:.3f} ms/solve, {results[name]['value']:.3e} nnz*RHS/s, "
+            f"cycles={stats['cycles']} relres={stats['relres_max']:.2e}, "
+            f"{stats['bytes'] / 1e9:.2f} GB algorithmic per solve "
+            f"({stats['bytes'] / (ms * 1e-3) / 1e9:.0f} GB/s); evented region "
+            f"{1e3 * wall_ev / max(1, args.evented_steps):.3f} ms/solve")
 
-    # in-situ kernel times of the FP32+IR timed region
+    # per-kind in-situ figures of the FP32+IR evented region; the dominant kind by time
     r32 = results["fp32ir"]
-    kt = r32["kt"]
-
-    def kstat(kern, prec):
-        t = kt.get((kern, prec))
-        if not t:
-            return None
-        return dict(launches=t["launches"], us_per_launch=round(1e6 * t["seconds"] / t["launches"], 3),
-                    GBs=round(t["bytes"] / t["seconds"] / 1e9, 1) if t["bytes"] else None,
-                    share=round(t["seconds"] / r32["wall"], 4))
-
-    gs = kt[(B.KERNEL_GS_COLOR, B.FP32_IR)]
-    sec = gs["seconds"] / gs["launches"]
-    byt = gs["bytes"] / gs["launches"]
-    achieved = byt / sec / 1e9
-    log(f"gs colour pass (level {lt}, fp32, in situ): {gs['launches']} launches, {sec * 1e6:.2f} us, "
-        f"{byt / 1e6:.2f} MB -> {achieved:.0f} GB/s")
-    other = {"residual": kstat(B.KERNEL_RESIDUAL, B.FP32_IR),
-             "restrict": kstat(B.KERNEL_RESTRICT, B.FP32_IR),
-             "prolong": kstat(B.KERNEL_PROLONG, B.FP32_IR),
-             "residual_fp64_outer": kstat(B.KERNEL_RESIDUAL, B.FP64),
-             "gs_color": kstat(B.KERNEL_GS_COLOR, B.FP32_IR)}
-    tail = kstat(B.KERNEL_TAIL, B.FP32_IR)
-    log(f"coarse tail (fp32, in situ): {tail}")
-    isolated = None
-    if args.profile_reps > 0:
-        s2, b2 = B.lamg_profile_kernel(h, lt, B.KERNEL_GS_COLOR, B.FP32_IR, k, args.profile_reps,
-                                       stream=stream)
-        isolated = dict(us_per_launch=s2 * 1e6, GBs=b2 / s2 / 1e9, reps=args.profile_reps)
+    kinds = {}
+    for (kern, prec), t in r32["kt"].items():
+        key = f"{B.KERNEL_NAMES[kern]}_{'fp32' if prec == B.FP32_IR else 'fp64'}"
+        kinds[key] = dict(launches=t["launches"] // r32["ev_steps"],
+                          us_per_launch=round(1e6 * t["seconds"] / t["launches"], 3),
+                          GBs=round(t["bytes"] / t["seconds"] / 1e9, 1),
+                          MB_per_launch=round(t["bytes"] / t["launches"] / 1e6, 4),
+                          share=round(t["seconds"] / r32["wall_ev"], 4))
+    (dk, dp), dt = max(r32["kt"].items(), key=lambda kv: kv[1]["seconds"])
+    dname = B.KERNEL_NAMES[dk]
+    achieved = dt["bytes"] / dt["seconds"] / 1e9
+    log(f"dominant kernel: {dname} ({'fp32' if dp == B.FP32_IR else 'fp64'}), {dt['launches']} "
+        f"launches, {1e6 * dt['seconds'] / dt['launches']:.2f} us each, "
+        f"{dt['bytes'] / dt['launches'] / 1e6:.3f} MB each -> {achieved:.0f} GB/s")
+    for key, v in sorted(kinds.items(), key=lambda kv: -kv[1]["share"]):
+        log(f"  {key}: {v}")
 
     if args.copy_probe_mb > 0:
         nel = args.copy_probe_mb * (1 << 20) // 4
@@ -225,31 +247,58 @@ def main() -> int:
         log(f"copy probe: {nel * 4} bytes read, {nel * 4} bytes written")
         del src, dst
 
-    # the FP64 oracle: error of every result against it, and the CPU baseline
-    cpu = None
-    errs = {}
-    if not args.no_cpu_baseline:
-        import oracle as O
+    hi2 = B.lamg_hierarchy_info(h)  # after the solves: hierarchy plus cached workspace
+    h.close()
 
+    # the CPU oracle: one core alone, then one process per core on separate columns
+    cpu_line, errs = None, {}
+    if pool is not None:
+        oopts = dict(n_direct=opts.n_direct, elimination=bool(opts.elimination),
+                     smoother=int(opts.smoother))
         t = time.perf_counter()
-        oh = O.Hierarchy(g, seed=1, n_direct=opts.n_direct, elimination=bool(opts.elimination),
-                         smoother=int(opts.smoother))
-        t_setup = time.perf_counter() - t
-        t = time.perf_counter()
-        ref, so, _ = oh.solve(bh[0], args.tol, 300)
-        t_solve = time.perf_counter() - t
+        col0, phi0, ts0, tv0, cyc0 = pool.apply(oracle_column,
+                                                ((args.workload, k, 0, args.tol, oopts),))
+        log(f"oracle, one core: column 0 setup {ts0:.1f}s solve {tv0:.1f}s ({cyc0} cycles)")
+        refs = {0: phi0}
+        agg = None
+        if procs > 1 or k > 1:
+            cols = sorted({k - 1} | set(range(1, max(1, procs))))[:max(1, procs)]
+            res = pool.map(oracle_column, [(args.workload, k, c, args.tol, oopts) for c in cols])
+            for c, ph, _, _, _ in res:
+                if c == k - 1:
+                    refs[c] = ph
+            rates = [g.nnz_laplacian / tv for _, _, _, tv, _ in res]
+            if len(res) > 1:
+                agg = dict(value=float(sum(rates)), unit="nnz*RHS/s", cores=len(res),
+                           kind="oracle", sample=f"{len(res)} oracle processes at once, each "
+                           f"solving one column of the same block (columns {cols[0]}..{cols[-1]}), "
+                           f"setup excluded; value = sum of the processes' rates; solve "
+                           f"{min(r[3] for r in res):.1f}-{max(r[3] for r in res):.1f}s each")
+        pool.close()
+        pool.join()
         for name in results:
-            ph = results[name]["phi"][0]
-            errs[name] = float(np.linalg.norm(ph - ref) / np.linalg.norm(ref))
-        cpu = dict(value=g.nnz_laplacian / t_solve, unit="nnz*RHS/s", cores=1, kind="oracle",
-                   sample=f"one FP64 solve of the same system (1 RHS, tol {args.tol:g}, "
-                          f"{so['cycles']} cycles, {t_solve:.2f}s; setup {t_setup:.2f}s excluded) "
-                          f"on {platform.processor() or platform.machine()}")
-        log(f"oracle: setup {t_setup:.2f}s solve {t_solve:.2f}s cycles {so['cycles']}; "
-            f"err fp32ir {errs.get('fp32ir'):.2e} fp64 {errs.get('fp64'):.2e}")
+            ph = results[name]["phi"]
+            errs[name] = {f"col{c}": float(np.linalg.norm(ph[c] - ref) / np.linalg.norm(ref))
+                          for c, ref in sorted(refs.items())}
+        log(f"oracle errors: {errs} ({time.perf_counter() - t:.0f}s of oracle work)")
+        cpu_line = dict(value=g.nnz_laplacian / tv0, unit="nnz*RHS/s", cores=1, kind="oracle",
+                        sample=f"one FP64 solve of column 0 of the same block (tol {args.tol:g}, "
+                               f"{cyc0} cycles, {tv0:.2f}s; setup {ts0:.2f}s excluded), one "
+                               f"process alone",
+                        host_cpu=cpu["model"], host_logical_cpus=cpu["logical_cpus"],
+                        host_usable_cpus=cpu["usable_cpus"], nproc_leg=agg)
 
-    traffic = measured_traffic(args.workload, k, bool(opts.elimination))
     r = results["fp32ir"]
+    sv = lambda x: 4 if "fp32" in x else 8
+    n0, e0 = hi["n"][0], hi["nnz"][0] - hi["n"][0]
+    fine_ws = {p: e0 * (4 + sv(p)) + 4 * (n0 + 1) + 2 * n0 * sv(p) + 3 * k * n0 * sv(p)
+               for p in ("fp32", "fp64")}
+    whole = {}
+    for name in results:
+        rr = results[name]
+        gbs = rr["bytes"] / (rr["ms"] * 1e-3) / 1e9
+        whole[name] = dict(bytes_per_solve=rr["bytes"], achieved_GBs=round(gbs, 1),
+                           frac=round(gbs / HBM_PEAK_GBS, 4))
     line = {
         "metric": "nnz*RHS solved/s to 1e-8 rel resid (FP32 cycles + FP64 refinement)",
         "value": r["value"],
@@ -264,10 +313,10 @@ def main() -> int:
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: {WORKLOADS[args.workload]}; b ~ N(0,1) mean-zero, "
-                        f"{k} RHS, tol {args.tol:g}",
+            "workload": f"{args.workload}: {WORKLOADS[args.workload]}; {k} RHS b ~ N(0,1) "
+                        f"mean-zero solved together, tol {args.tol:g}",
             "n": g.n, "nnz_L": g.nnz_laplacian, "nnz_2m": g.nnz, "nrhs": k,
-            "levels": hi["levels"], "op_complexity": round(hi["op_complexity"], 3),
+            "levels": hi["levels"], "level_n": hi["n"], "op_complexity": round(hi["op_complexity"], 3),
             "setup_s": round(hi["setup_seconds"], 3),
             "elimination": bool(opts.elimination), "elimination_levels": sum(hi["elim"]),
             "smoother": "chebyshev on levels with > 32 colours" if opts.smoother else "gauss-seidel",
@@ -282,28 +331,31 @@ def main() -> int:
                  "p50_ms": results["fp64"]["p50_ms"], "p99_ms": results["fp64"]["p99_ms"],
                  "cycles": results["fp64"]["cycles"], "relres": results["fp64"]["relres"],
                  "err_vs_oracle": errs.get("fp64")},
+        "fp32ir_speedup_over_fp64": results["fp64"]["ms"] / r["ms"],
         "roofline": {"bound": "hbm",
-                     "kernel": f"k_csr<float, GS> one colour pass of level {lt} (n={hi['n'][lt]}"
-                               f"{', elimination level: its eliminated rows' if hi['elim'][lt] else ''})",
+                     "kernel": f"{dname} ({'fp32' if dp == B.FP32_IR else 'fp64'}): "
+                               f"{KIND_SYMBOLS[dname]}, every level",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_launch": byt, "us_per_launch": sec * 1e6,
-                     "launches": gs["launches"], "timing": "HIP events attached to every launch "
-                     "(dispatch timestamps) in a second timed FP32+IR region of the same K solves, "
-                     "launched kernel by kernel, on the solve stream"},
-        "kernels_timed_level": dict(other, level=lt),
-        "coarse_tail": dict(tail or {}, bound="latency (dependent steps of one workgroup)",
-                            kernel="k_tail<float>"),
-        "launch_modes": {"graph_cycles_per_solve": r32["graph_cycles"],
-                         "fp32ir_ms_kernel_by_kernel_with_events": r32["ms_events"],
-                         "fp64_ms_kernel_by_kernel_with_events": results["fp64"]["ms_events"]},
-        "gs_color_isolated": isolated,
-        "cpu_baseline": cpu,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": dt["bytes"] / dt["launches"],
+                     "us_per_launch": 1e6 * dt["seconds"] / dt["launches"],
+                     "launches_per_solve": dt["launches"] // r32["ev_steps"],
+                     "share_of_solve": dt["seconds"] / r32["wall_ev"],
+                     "timing": "HIP events (dispatch timestamps) on every launch of an evented "
+                               "FP32+IR region of the same solves, on the solve stream"},
+        "whole_solve": dict(whole, unit="GB/s", peak=HBM_PEAK_GBS,
+                            bytes="algorithmic bytes of every launch of one solve "
+                                  "(compulsory traffic per launch, library count)"),
+        "working_set": {"device_bytes_hierarchy_and_workspace": hi2["bytes_device"],
+                        "finest_level_one_sweep_bytes": fine_ws,
+                        "mall_bytes": MALL_BYTES,
+                        "finest_sweep_fits_mall": {p: v <= MALL_BYTES for p, v in fine_ws.items()}},
+        "kernels": kinds,
+        "cpu_baseline": cpu_line,
         "paper_context": "0.19 us/edge median solve, 1 CPU thread Apple M5 Pro (Julia), "
                          "SuiteSparse corpus; not this workload",
     }
     print(json.dumps(line), flush=True)
-    h.close()
     return 0
 
 

@@ -148,8 +148,9 @@ typedef struct {
 } lamg_hier_info;
 
 /* Solve statistics. The caller may point the array fields at host arrays (or leave them
- * NULL): relres[nrhs], cycles[nrhs], history[max_cycles + 1] (column 0's relative residual
- * after each cycle, history[0] = 1). */
+ * NULL): relres[nrhs], cycles[nrhs], history[M + 1] with M = max_cycles if max_cycles > 0,
+ * else 300 (column 0's relative residual after each cycle, history[0] = 1; at most
+ * M + 1 entries are written, history_len of them). */
 typedef struct {
     int32_t cycles;        /* cycles (outer refinement steps for FP32_IR) run, max over columns */
     double relres_max;     /* max over columns of the final ||b - L phi|| / ||b|| (true residual) */
@@ -158,10 +159,14 @@ typedef struct {
     double seconds;        /* wall time of the call */
     double *relres;        /* optional [nrhs] */
     int32_t *col_cycles;   /* optional [nrhs] */
-    double *history;       /* optional [max_cycles + 1] */
+    double *history;       /* optional [(max_cycles > 0 ? max_cycles : 300) + 1] */
     int32_t history_len;   /* written: entries of history filled */
     int32_t graph_cycles;  /* written: cycles launched as HIP graphs (captured in this call or
                               replayed), summed over the call's 32-column chunks */
+    double bytes;          /* written: algorithmic bytes of every kernel launch of the call --
+                              compulsory traffic only (each matrix index and value, row pointer,
+                              diagonal and vector element a launch reads or writes, once), the
+                              figures lamg_timing_get reports per kernel kind */
 } lamg_solve_info;
 
 /* One level of the hierarchy copied to host buffers (parity dumps). Any pointer may be
@@ -223,7 +228,10 @@ lamg_status lamg_setup(const lamg_graph *g, const lamg_options *opt, void *strea
  * are independent: each stops at its own convergence cycle and is frozen afterwards.
  * max_cycles <= 0 selects 300. A zero column returns phi = 0. The handle caches a
  * workspace sized for the largest nrhs seen. Returns OK, NOT_CONVERGED (phi and info are
- * still written), INVALID_ARG, OOM or HIP_ERROR. */
+ * still written; also when a column's relative residual stops being a finite number, which
+ * ends that column's cycling), INVALID_ARG (also when b holds a NaN or infinite value, or a
+ * column whose norm overflows: eq. (1.1) has no solution to approach; phi is then not
+ * written), OOM or HIP_ERROR. */
 lamg_status lamg_solve(lamg_handle *h, const double *b, int32_t nrhs, double tol,
                        int32_t max_cycles, lamg_precision prec, double *phi,
                        lamg_solve_info *info, void *stream);
@@ -244,8 +252,13 @@ typedef enum {
     LAMG_KERNEL_RESIDUAL = 1, /* r = f - L x over the whole level */
     LAMG_KERNEL_RESTRICT = 2, /* f_c = P^T r from the level to the next */
     LAMG_KERNEL_PROLONG = 3,  /* x += mu P e_c from the next level */
-    LAMG_KERNEL_TAIL = 4      /* one launch of the coarse-level cycle (one workgroup per
+    LAMG_KERNEL_TAIL = 4,     /* one launch of the coarse-level cycle (one workgroup per
                                  column; in-situ timer only) */
+    LAMG_KERNEL_REDUCE = 5,   /* reductions and the updates they feed: energy-correction and
+                                 recombination sums, norms, means (in-situ timer only) */
+    LAMG_KERNEL_VECTOR = 6,   /* elementwise vector kernels: copies, fills, precision and
+                                 layout conversions, the coarsest dense solve (in-situ only) */
+    LAMG_KERNEL_CHEB = 7      /* one Chebyshev step (smoother 1; in-situ timer only) */
 } lamg_kernel;
 
 /* Measurement aid for roofline reporting: launches one cycle kernel of level `level`
@@ -272,12 +285,16 @@ lamg_status lamg_profile_kernel(lamg_handle *h, int32_t level, lamg_kernel kerne
  * the kernel's execution alone; they add no synchronisation and no stream markers. Timing
  * stops recording after `max_launches` launches (the events are created by
  * lamg_timing_start).
+ * lamg_timing_start_all does the same for EVERY kernel launch of the solve, on every level,
+ * each counted under its kind (lamg_kernel; the finest level's FP64 outer residual is an FP64
+ * residual).
  * lamg_timing_stop waits for the last recorded event, converts every pair to a duration
  * and frees the events; lamg_timing_get then returns, per kernel and precision, the number
  * of timed launches, their summed duration and their summed algorithmic bytes (the figures
- * of lamg_profile_kernel for the launch's rows; 0 for the coarse tail, which is bound by
- * dependent steps, not by bytes). Errors: INVALID_ARG (max_launches < 1, kernel out of
- * range, timing still running for lamg_timing_get), HIP_ERROR. */
+ * of lamg_profile_kernel for the launch's rows; for a coarse-tail launch the sum of those
+ * figures over every step of every level visit the launch performs, the operators counted
+ * once per launch whatever the column count). Errors: INVALID_ARG (max_launches < 1, kernel
+ * out of range, timing still running for lamg_timing_get), HIP_ERROR. */
 typedef struct {
     int64_t launches;
     double seconds;
@@ -285,6 +302,7 @@ typedef struct {
 } lamg_kernel_time;
 
 lamg_status lamg_timing_start(lamg_handle *h, int32_t max_launches);
+lamg_status lamg_timing_start_all(lamg_handle *h, int32_t max_launches);
 lamg_status lamg_timing_stop(lamg_handle *h);
 lamg_status lamg_timing_get(const lamg_handle *h, lamg_kernel kernel, lamg_precision prec,
                             lamg_kernel_time *out);

@@ -204,7 +204,15 @@ lamg_status lamg_profile_kernel(lamg_handle *h, int32_t level, lamg_kernel kerne
 lamg_status lamg_timing_start(lamg_handle *h, int32_t max_launches) {
     if (!h || max_launches < 1) return LAMG_INVALID_ARG;
     return guarded([&]() -> lamg_status {
-        h->timer.start(max_launches);
+        h->timer.start(max_launches, false);
+        return LAMG_OK;
+    });
+}
+
+lamg_status lamg_timing_start_all(lamg_handle *h, int32_t max_launches) {
+    if (!h || max_launches < 1) return LAMG_INVALID_ARG;
+    return guarded([&]() -> lamg_status {
+        h->timer.start(max_launches, true);
         return LAMG_OK;
     });
 }

@@ -352,7 +352,8 @@ __global__ void k_inject_add(int64_t nc, int k, int lkp, const int32_t *__restri
 // block combines them in block order and finishes the per-column scalar.
 // Element mapping: block of 256 threads = (256/kp) rows x kp columns.
 // ---------------------------------------------------------------------------
-enum { R_MU = 0, R_RC2 = 1, R_NORM2 = 2, R_SUM = 3, R_MAXABS = 4, R_RCF = 5, R_RES2 = 6 };
+enum { R_MU = 0, R_RC2 = 1, R_NORM2 = 2, R_SUM = 3, R_MAXABS = 4, R_RCF = 5, R_RES2 = 6,
+       R_NONFIN = 7 };
 
 template <int R>
 struct RedQ;
@@ -362,6 +363,7 @@ template <> struct RedQ<R_NORM2> { static constexpr int Q = 1; };
 template <> struct RedQ<R_SUM> { static constexpr int Q = 1; };
 template <> struct RedQ<R_MAXABS> { static constexpr int Q = 1; };
 template <> struct RedQ<R_RES2> { static constexpr int Q = 2; };  // ||r||^2 and max |r|
+template <> struct RedQ<R_NONFIN> { static constexpr int Q = 1; };  // count of NaN / inf
 // Quantities of a reduction combined by max instead of sum (bit i: quantity i).
 template <int R>
 constexpr int red_max_mask() {
@@ -388,7 +390,7 @@ struct RedElem {
         } else if (R == R_RC2) {  // a = rho, b = rho1
             a[0] = (double)((const T *)in.a)[o];
             a[1] = (double)((const T *)in.b)[o];
-        } else if (R == R_NORM2 || R == R_SUM || R == R_MAXABS || R == R_RES2) {
+        } else if (R == R_NORM2 || R == R_SUM || R == R_MAXABS || R == R_RES2 || R == R_NONFIN) {
             a[0] = (double)((const T *)in.a)[o];
         } else {  // RCF: a = r, b = history residuals (m slots; slots past m reread m - 1)
             const double *hr = (const double *)in.b;
@@ -413,6 +415,8 @@ struct RedElem {
         } else if (R == R_RES2) {
             q[0] += a[0] * a[0];
             q[1] = fmax(q[1], fabs(a[0]));
+        } else if (R == R_NONFIN) {
+            q[0] += isfinite(a[0]) ? 0.0 : 1.0;
         } else {  // RCF: G_i = r - r_i (0 past m)
             const double rv = a[0];
             double G[4];
@@ -599,7 +603,7 @@ __global__ void __launch_bounds__(kBlock)
     } else if (R == R_NORM2) {
         double v = sqrt(tot[c]);
         fin.out[c] = fin.aux ? (fin.aux[c] > 0.0 ? v / fin.aux[c] : 0.0) : v;
-    } else if (R == R_SUM) {
+    } else if (R == R_SUM || R == R_NONFIN) {
         fin.out[c] = fin.scale * tot[c];
     } else if (R == R_MAXABS) {
         fin.out[c] = tot[c];
@@ -633,9 +637,9 @@ inline int red_blocks(int64_t n, int k) {
 template <class T, int R>
 void reduce(int64_t n, int k, RedIn in, double *partial, Fin fin, hipStream_t s) {
     int nblk = red_blocks(n, k);
-    k_red_partial<T, R><<<nblk, kBlock, 0, s>>>(n, k, kp_log2(k), in, partial);
+    launch_kernel(k_red_partial<T, R>, dim3(nblk), dim3(kBlock), 0, s, n, k, kp_log2(k), in, partial);
     LAMG_LAUNCH_CHECK();
-    k_red_final<R><<<1, kBlock, 0, s>>>(nblk, k, partial, fin);
+    launch_kernel(k_red_final<R>, dim3(1), dim3(kBlock), 0, s, nblk, k, partial, fin);
     LAMG_LAUNCH_CHECK();
 }
 
@@ -953,14 +957,14 @@ void run_prolong(const SolveOp &op, const T *w0, const T *w1, const T *ec, const
 template <class T>
 void run_fill(T *x, int64_t count, T value, hipStream_t s) {
     if (count <= 0) return;
-    k_fill<T><<<blocks_for(count), kBlock, 0, s>>>(x, count, value);
+    launch_kernel(k_fill<T>, dim3(blocks_for(count)), dim3(kBlock), 0, s, x, count, value);
     LAMG_LAUNCH_CHECK();
 }
 
 template <class T>
 void run_copy(T *dst, const T *src, int64_t count, hipStream_t s) {
     if (count <= 0) return;
-    k_copy<T><<<blocks_for(count), kBlock, 0, s>>>(dst, src, count);
+    launch_kernel(k_copy<T>, dim3(blocks_for(count)), dim3(kBlock), 0, s, dst, src, count);
     LAMG_LAUNCH_CHECK();
 }
 
@@ -976,7 +980,7 @@ void run_rc2(int64_t n, T *e, T *rho, const T *e1, const T *rho1, int k, double 
              double *alpha, hipStream_t s) {
     RedIn in{rho, rho1, nullptr, nullptr, 0, 0};
     reduce<T, R_RC2>(n, k, in, partial, Fin{alpha, nullptr, 1.0, 0}, s);
-    k_rc2_update<T><<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), e, rho, const_cast<T *>(e1),
+    launch_kernel(k_rc2_update<T>, dim3(rc_blocks(n, k)), dim3(kBlock), 0, s, n, k, kp_log2(k), e, rho, const_cast<T *>(e1),
                                                        const_cast<T *>(rho1), alpha, 0);
     LAMG_LAUNCH_CHECK();
 }
@@ -987,13 +991,13 @@ void run_mu_prolong(const SolveOp &op, const T *w0, const T *w1, int64_t nc, con
                     hipStream_t s) {
     const int nblk = red_blocks(nc, k);
     RedIn in{ec, fc, rho, nullptr, 0, 0};
-    k_red_partial<T, R_MU><<<nblk, kBlock, 0, s>>>(nc, k, kp_log2(k), in, partial);
+    launch_kernel(k_red_partial<T, R_MU>, dim3(nblk), dim3(kBlock), 0, s, nc, k, kp_log2(k), in, partial);
     LAMG_LAUNCH_CHECK();
     if (fuse_totals(op.n, k, nblk)) {
         launch_kernel(k_prolong_mu<T>, dim3(rc_blocks(op.n, k)), dim3(kBlock), 0, s, op.n, k,
                       kp_log2(k), op.p0.p, op.p1.p, w0, w1, ec, nblk, (const double *)partial, x);
     } else {
-        k_red_final<R_MU><<<1, kBlock, 0, s>>>(nblk, k, partial, Fin{scal, nullptr, 1.0, 0});
+        launch_kernel(k_red_final<R_MU>, dim3(1), dim3(kBlock), 0, s, nblk, k, partial, Fin{scal, nullptr, 1.0, 0});
         launch_kernel(k_prolong<T>, dim3(rc_blocks(op.n, k)), dim3(kBlock), 0, s, op.n, k,
                       kp_log2(k), op.p0.p, op.p1.p, w0, w1, ec, (const double *)scal, x);
     }
@@ -1005,14 +1009,14 @@ void run_rc2_keep(int64_t n, T *e, T *rho, T *e1, T *rho1, int k, double *partia
                   double *scal, bool keep, hipStream_t s) {
     const int nblk = red_blocks(n, k);
     RedIn in{rho, rho1, nullptr, nullptr, 0, 0};
-    k_red_partial<T, R_RC2><<<nblk, kBlock, 0, s>>>(n, k, kp_log2(k), in, partial);
+    launch_kernel(k_red_partial<T, R_RC2>, dim3(nblk), dim3(kBlock), 0, s, n, k, kp_log2(k), in, partial);
     LAMG_LAUNCH_CHECK();
     if (fuse_totals(n, k, nblk)) {
-        k_rc2_fused<T><<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), e, rho, e1, rho1, nblk,
+        launch_kernel(k_rc2_fused<T>, dim3(rc_blocks(n, k)), dim3(kBlock), 0, s, n, k, kp_log2(k), e, rho, e1, rho1, nblk,
                                                           partial, keep ? 1 : 0);
     } else {
-        k_red_final<R_RC2><<<1, kBlock, 0, s>>>(nblk, k, partial, Fin{scal, nullptr, 1.0, 0});
-        k_rc2_update<T><<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), e, rho, e1, rho1, scal,
+        launch_kernel(k_red_final<R_RC2>, dim3(1), dim3(kBlock), 0, s, nblk, k, partial, Fin{scal, nullptr, 1.0, 0});
+        launch_kernel(k_rc2_update<T>, dim3(rc_blocks(n, k)), dim3(kBlock), 0, s, n, k, kp_log2(k), e, rho, e1, rho1, scal,
                                                            keep ? 1 : 0);
     }
     LAMG_LAUNCH_CHECK();
@@ -1021,19 +1025,19 @@ void run_rc2_keep(int64_t n, T *e, T *rho, T *e1, T *rho1, int k, double *partia
 template <class T>
 void run_coarsest(int64_t n, const double *Z, const T *f, T *y, int k, hipStream_t s) {
     if (n > 1024) throw Error(LAMG_INVALID_ARG, "coarsest level larger than 1024");
-    k_coarsest<T><<<(unsigned)((n * k + 3) / 4), kBlock, 0, s>>>(n, Z, f, y, k);
+    launch_kernel(k_coarsest<T>, dim3((unsigned)((n * k + 3) / 4)), dim3(kBlock), 0, s, n, Z, f, y, k);
     LAMG_LAUNCH_CHECK();
 }
 
 void run_gather_cols(int64_t n, int k, const int32_t *perm, const double *src, double *dst,
                      hipStream_t s) {
-    k_gather_cols<<<blocks_for(n * k), kBlock, 0, s>>>(n, k, perm, src, dst);
+    launch_kernel(k_gather_cols, dim3(blocks_for(n * k)), dim3(kBlock), 0, s, n, k, perm, src, dst);
     LAMG_LAUNCH_CHECK();
 }
 
 void run_scatter_cols(int64_t n, int k, const int32_t *perm, const double *src, const int32_t *mask,
                       double *dst, hipStream_t s) {
-    k_scatter_cols<<<blocks_for(n * k), kBlock, 0, s>>>(n, k, perm, src, mask, dst);
+    launch_kernel(k_scatter_cols, dim3(blocks_for(n * k)), dim3(kBlock), 0, s, n, k, perm, src, mask, dst);
     LAMG_LAUNCH_CHECK();
 }
 
@@ -1044,13 +1048,18 @@ void run_colsum(int64_t n, int k, const double *x, double *partial, double *out,
 }
 
 void run_sub_col(int64_t n, int k, double *x, const double *m, hipStream_t s) {
-    k_sub_col<<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), x, m);
+    launch_kernel(k_sub_col, dim3(rc_blocks(n, k)), dim3(kBlock), 0, s, n, k, kp_log2(k), x, m);
     LAMG_LAUNCH_CHECK();
 }
 
 void run_norm2(int64_t n, int k, const double *x, double *partial, double *out, hipStream_t s) {
     RedIn in{x, nullptr, nullptr, nullptr, 0, 0};
     reduce<double, R_NORM2>(n, k, in, partial, Fin{out, nullptr, 1.0, 0}, s);
+}
+
+void run_count_nonfinite(int64_t n, const double *x, double *partial, double *out, hipStream_t s) {
+    RedIn in{x, nullptr, nullptr, nullptr, 0, 0};
+    reduce<double, R_NONFIN>(n, 1, in, partial, Fin{out, nullptr, 1.0, 0}, s);
 }
 
 void run_maxabs(int64_t n, int k, const double *x, double *partial, double *out, hipStream_t s) {
@@ -1081,25 +1090,25 @@ void run_recombine_fine(int64_t n, int k, int m, double *phi, double *r, double 
     }
     RedIn in{r, hr, nullptr, nullptr, m, n * k};
     reduce<double, R_RCF>(n, k, in, partial, Fin{alpha, nullptr, 1.0, m}, s);
-    k_rcf_update<<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), m, phi, r, hphi, hr, n * k,
+    launch_kernel(k_rcf_update, dim3(rc_blocks(n, k)), dim3(kBlock), 0, s, n, k, kp_log2(k), m, phi, r, hphi, hr, n * k,
                                                      alpha, slot);
     LAMG_LAUNCH_CHECK();
 }
 
 void run_to_f32_scaled(int64_t n, int k, const double *r, const double *scale, float *dst,
                        float *zero_x, hipStream_t s) {
-    k_to_f32_scaled<<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), r, scale, dst, zero_x);
+    launch_kernel(k_to_f32_scaled, dim3(rc_blocks(n, k)), dim3(kBlock), 0, s, n, k, kp_log2(k), r, scale, dst, zero_x);
     LAMG_LAUNCH_CHECK();
 }
 
 void run_add_scaled_f32(int64_t n, int k, const float *e, const double *scale, double *phi,
                         hipStream_t s) {
-    k_add_scaled_f32<<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), e, scale, phi);
+    launch_kernel(k_add_scaled_f32, dim3(rc_blocks(n, k)), dim3(kBlock), 0, s, n, k, kp_log2(k), e, scale, phi);
     LAMG_LAUNCH_CHECK();
 }
 
 void run_zero_cols(int64_t n, int k, const int32_t *zero_mask, double *x, hipStream_t s) {
-    k_zero_cols<<<rc_blocks(n, k), kBlock, 0, s>>>(n, k, kp_log2(k), zero_mask, x);
+    launch_kernel(k_zero_cols, dim3(rc_blocks(n, k)), dim3(kBlock), 0, s, n, k, kp_log2(k), zero_mask, x);
     LAMG_LAUNCH_CHECK();
 }
 

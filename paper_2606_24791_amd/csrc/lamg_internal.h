@@ -250,7 +250,9 @@ struct Workspace {
     // counters start from zero in every solve; column freezing changes data, not launches)
     struct CycleGraph {
         hipGraphExec_t exec = nullptr;
-        std::vector<int64_t> visits_after;  // the host visit counters after the cycle
+        std::vector<int64_t> visits_after;   // the host visit counters after the cycle
+        std::vector<int64_t> tvisits_after;  // the host mirror of the tail's counters after it
+        double bytes = 0.0;                  // algorithmic bytes of the cycle's launches
     };
     struct GraphSet {
         int prec = 0, k = 0;
@@ -268,8 +270,10 @@ void clear_graphs(Workspace &w);
 // itself (hipExtLaunchKernel takes the dispatch's own start and end timestamps), so the
 // elapsed time is the kernel's execution time without stream-marker overhead.
 struct KTimer {
-    static constexpr int kKinds = 5;
+    static constexpr int kKinds = 8;
     bool on = false;
+    bool all = false;  // every launch of every level (else the timed level, the tail and the
+                       // FP64 outer residual)
     std::vector<hipEvent_t> ev;  // 2 per launch
     struct Rec {
         int kind, prec;  // prec 0: FP64, 1: FP32; kind -1: nothing was launched
@@ -280,7 +284,7 @@ struct KTimer {
     double sec[kKinds][2] = {}, bytes[kKinds][2] = {};
     // Reserves an event pair; returns its index or -1 (timer off or full).
     int open(int kind, int prec, double b);
-    void start(int max_launches);
+    void start(int max_launches, bool every_launch);
     void stop();
     void release();
 };
@@ -317,6 +321,7 @@ struct lamg_handle {
     std::vector<lamg::Level> lev;
     lamg::Workspace ws;
     lamg::KTimer timer;
+    double solve_bytes = 0.0;  // algorithmic bytes of the current solve's launches
     double setup_seconds = 0.0;
     ~lamg_handle();
 };
@@ -459,6 +464,8 @@ void run_colsum(int64_t n, int k, const double *x, double *partial, double *out,
                 hipStream_t s);  // out[c] = scale * sum_i x[i,c]
 void run_sub_col(int64_t n, int k, double *x, const double *m, hipStream_t s);  // x[:,c] -= m[c]
 void run_norm2(int64_t n, int k, const double *x, double *partial, double *out, hipStream_t s);
+// out[0] = number of entries of x[0, n) that are NaN or infinite
+void run_count_nonfinite(int64_t n, const double *x, double *partial, double *out, hipStream_t s);
 void run_maxabs(int64_t n, int k, const double *x, double *partial, double *out, hipStream_t s);
 void run_relres(int64_t n, int k, const double *r, const double *nb, double *partial, double *out,
                 hipStream_t s);

@@ -91,14 +91,34 @@ double bytes_prolong(const SolveOp &op, int k, double s) {
     return n * (8.0 + 2.0 * s) + (double)k * op.nc * s + 2.0 * k * n * s;
 }
 
-// Attaches a pair of the handle's timer events to the kernels launched during its lifetime.
+double bytes_coarsest(int64_t n, int k, double s) {
+    return 8.0 * (double)n * (double)n + 2.0 * k * (double)n * s;
+}
+// two-iterate recombination: partial sums over (rho, rho1), then e, rho updated from the
+// saved pair (and the result saved again when another visit follows)
+double bytes_rc2(int64_t n, int k, double s, bool keep) {
+    return (2.0 + 6.0 + (keep ? 2.0 : 0.0)) * k * (double)n * s;
+}
+double bytes_sweep(const SolveOp &op, int k, double s) {
+    double b = 0.0;
+    for (int c = 0; c < op.ncolors; ++c) b += bytes_gs_color(op, c, k, s);
+    return b;
+}
+
+// One launch, or a short group of launches of one kernel kind: its algorithmic bytes go
+// into the solve's total, and while the in-situ timer is on and the launch is in its scope
+// (every launch after lamg_timing_start_all; else the `narrow` ones: the timed level's
+// kernels, the coarse tail and the FP64 outer residual) a pair of the timer's events is
+// attached to the kernels launched during the object's lifetime.
 struct Timed {
     KTimer &t;
-    int idx;
+    int idx = -1;
     LaunchEvents le;
     LaunchEvents *prev = nullptr;
-    Timed(lamg_handle *h, int kind, int prec, double bytes)
-        : t(h->timer), idx(h->timer.on ? h->timer.open(kind, prec, bytes) : -1) {
+    Timed(lamg_handle *h, int kind, int prec, double bytes, bool narrow) : t(h->timer) {
+        h->solve_bytes += bytes;
+        if (!t.on || !(t.all || (narrow && kind <= LAMG_KERNEL_TAIL))) return;
+        idx = t.open(kind, prec, bytes);
         if (idx < 0) return;
         le.start = t.ev[2 * idx];
         le.stop = t.ev[2 * idx + 1];
@@ -111,6 +131,11 @@ struct Timed {
         if (!le.started) t.recs[idx].kind = -1;
     }
 };
+
+// Whether the timer takes a launch of this scope (then per-step launches are made one by one).
+inline bool timing(const lamg_handle *h, bool narrow) {
+    return h->timer.on && (h->timer.all || narrow);
+}
 
 template <class T>
 constexpr int prec_id() {
@@ -130,7 +155,42 @@ struct Cycle {
     const TailPlan *plan;   // its descriptors and LDS layout
     int64_t *d_visits;      // its visit counters (per column)
     T *cx, *cf;             // column-by-column copies of the top level's x and f (k > 1)
+    std::vector<int64_t> tvisits;  // host mirror of the tail's visit counters (byte counts)
 };
+
+// Algorithmic bytes of the visit to level l that a coarse-tail launch makes (and of every
+// visit below it), advancing the host mirror of the tail's visit counters as the kernel
+// advances its own: the same schedule, step by step, with the operators counted once per
+// launch whatever the column count.
+template <class T>
+double tail_level_bytes(Cycle<T> &C, int l) {
+    const lamg_handle *h = C.h;
+    const Level &L = h->lev[l];
+    const int k = C.k;
+    const double sz = sizeof(T);
+    if (L.coarsest) return bytes_coarsest(L.n, k, sz);
+    const SolveOp &op = L.op;
+    const Level &Lc = h->lev[l + 1];
+    const double zero_c = (double)k * Lc.n * sz;
+    if (L.elim) {
+        C.tvisits[l]++;
+        return 2.0 * bytes_gs_color(op, 0, k, sz) + bytes_gs_color(op, 1, k, sz) +
+               bytes_restrict(op, k, sz) + zero_c + 4.0 * op.nc + 3.0 * k * op.nc * sz +
+               tail_level_bytes(C, l + 1);
+    }
+    double b = 3.0 * bytes_sweep(op, k, sz) + bytes_residual(op, k, sz) +
+               bytes_restrict(op, k, sz) + zero_c;
+    const int64_t i = C.tvisits[l]++;
+    const int nvis = (int)(std::floor((double)(i + 1) * L.gamma) - std::floor((double)i * L.gamma));
+    for (int j = 1; j <= nvis; ++j) {
+        b += tail_level_bytes(C, l + 1) + bytes_residual(Lc.op, k, sz);
+        if (j >= 2)
+            b += bytes_rc2(Lc.n, k, sz, j < nvis);
+        else if (j < nvis)
+            b += 4.0 * zero_c;  // the first visit's pair saved
+    }
+    return b + 3.0 * zero_c + bytes_prolong(op, k, sz);  // energy-correction sums, prolongation
+}
 
 // First level (below the finest) whose cycle runs in the coarse-tail kernel: the first
 // level with at most tail_rows nodes, extended upwards over levels whose visit is clearly
@@ -203,22 +263,31 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
     hipStream_t s = C.s;
     Level &L = h->lev[l];
     using P = Prec<T>;
+    constexpr int pid = prec_id<T>();
+    const double sz = sizeof(T);
     if (l == C.l0) {
+        const double tb = tail_level_bytes<T>(C, l);
         if (k == 1) {
-            Timed tm(h, LAMG_KERNEL_TAIL, prec_id<T>(), 0.0);
+            Timed tm(h, LAMG_KERNEL_TAIL, pid, tb, true);
             run_tail<T>(*C.plan, l, h->nlev, k, C.d_visits, s);
             return;
         }
         // a workgroup per column, on the top level's (x, f) copied column by column
-        run_to_cols<T>(L.n, k, x, f, C.cx, C.cf, s);
         {
-            Timed tm(h, LAMG_KERNEL_TAIL, prec_id<T>(), 0.0);
+            Timed tm(h, LAMG_KERNEL_VECTOR, pid, 4.0 * k * L.n * sz, false);
+            run_to_cols<T>(L.n, k, x, f, C.cx, C.cf, s);
+        }
+        {
+            Timed tm(h, LAMG_KERNEL_TAIL, pid, tb, true);
             run_tail<T>(*C.plan, l, h->nlev, k, C.d_visits, s);
         }
+        Timed tm(h, LAMG_KERNEL_VECTOR, pid, 2.0 * k * L.n * sz, false);
         run_from_cols<T>(L.n, k, C.cx, x, s);
         return;
     }
+    const bool nar = l == C.lt;  // the timed level
     if (L.coarsest) {
+        Timed tm(h, LAMG_KERNEL_VECTOR, pid, bytes_coarsest(L.n, k, sz), false);
         run_coarsest<T>(L.n, L.Z.p, f, x, k, s);
         return;
     }
@@ -227,8 +296,7 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
     const SolveOp &cop = Lc.op;
     LevelVecs<T> &me = (*C.v)[l];
     LevelVecs<T> &cv = (*C.v)[l + 1];
-    const bool timed = l == C.lt && h->timer.on;
-    const double sz = sizeof(T);
+    const double zero_c = (double)k * Lc.n * sz;
     if (L.elim) {
         // elimination level (eq. (2.1)), cycle index 1: the eliminated rows (colour 0) are
         // set exactly from the kept ones, the coarse right-hand side is the residual of the
@@ -237,25 +305,22 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
         // eliminated rows are set exactly again. No smoothing or energy correction: the
         // interpolation is exact.
         auto relax_f = [&]() {
-            Timed tm(h, timed ? LAMG_KERNEL_GS_COLOR : -1, prec_id<T>(),
-                     bytes_gs_color(op, 0, k, sz));
+            Timed tm(h, LAMG_KERNEL_GS_COLOR, pid, bytes_gs_color(op, 0, k, sz), nar);
             run_gs_color<T>(op, 0, P::v(op), P::dinv(op), f, x, k, s, l == C.lt);
         };
         relax_f();
         {
-            Timed tm(h, timed ? LAMG_KERNEL_RESIDUAL : -1, prec_id<T>(),
-                     bytes_gs_color(op, 1, k, sz));
+            Timed tm(h, LAMG_KERNEL_RESIDUAL, pid, bytes_gs_color(op, 1, k, sz), nar);
             run_residual_color<T>(op, 1, P::v(op), P::d(op), x, f, me.r.p, k, s, l == C.lt);
         }
         {
-            Timed tm(h, timed ? LAMG_KERNEL_RESTRICT : -1, prec_id<T>(), bytes_restrict(op, k, sz));
+            Timed tm(h, LAMG_KERNEL_RESTRICT, pid, bytes_restrict(op, k, sz) + zero_c, nar);
             run_restrict<T>(op, P::rw(op), me.r.p, cv.f.p, k, s, cv.x.p);
         }
         C.visits[l]++;
         cycle<T>(C, l + 1, cv.x.p, cv.f.p);
         {
-            Timed tm(h, timed ? LAMG_KERNEL_PROLONG : -1, prec_id<T>(),
-                     4.0 * op.nc + 3.0 * k * op.nc * sz);
+            Timed tm(h, LAMG_KERNEL_PROLONG, pid, 4.0 * op.nc + 3.0 * k * op.nc * sz, nar);
             run_inject_add<T>(op, cv.x.p, x, k, s);
         }
         relax_f();
@@ -264,30 +329,31 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
     auto smooth = [&](int sweeps) {
         if (L.cheb) {  // Chebyshev sweeps (smoother option 1), in me.r as work space
             for (int sw = 0; sw < sweeps; ++sw) {
-                Timed tm(h, timed ? LAMG_KERNEL_GS_COLOR : -1, prec_id<T>(),
-                         kChebDegree * (bytes_residual(op, k, sz) + 3.0 * k * op.n * sz));
+                Timed tm(h, LAMG_KERNEL_CHEB, pid,
+                         kChebDegree * (bytes_residual(op, k, sz) + 3.0 * k * op.n * sz), nar);
                 run_cheb_sweep<T>(op, L.cheb_lmax, P::v(op), P::d(op), P::dinv(op), f, x, me.r.p,
                                   k, s, l == C.lt);
             }
             return;
         }
-        if (!timed) {
+        if (!timing(h, nar)) {
+            h->solve_bytes += sweeps * bytes_sweep(op, k, sz);
             run_gs<T>(op, P::v(op), P::dinv(op), f, x, k, sweeps, s, l == C.lt);
             return;
         }
         for (int sw = 0; sw < sweeps; ++sw)
             for (int c = 0; c < op.ncolors; ++c) {
-                Timed tm(h, LAMG_KERNEL_GS_COLOR, prec_id<T>(), bytes_gs_color(op, c, k, sz));
-                run_gs_color<T>(op, c, P::v(op), P::dinv(op), f, x, k, s, true);
+                Timed tm(h, LAMG_KERNEL_GS_COLOR, pid, bytes_gs_color(op, c, k, sz), nar);
+                run_gs_color<T>(op, c, P::v(op), P::dinv(op), f, x, k, s, l == C.lt);
             }
     };
     smooth(1);
     {
-        Timed tm(h, timed ? LAMG_KERNEL_RESIDUAL : -1, prec_id<T>(), bytes_residual(op, k, sz));
+        Timed tm(h, LAMG_KERNEL_RESIDUAL, pid, bytes_residual(op, k, sz), nar);
         run_residual<T>(op, P::v(op), P::d(op), x, f, me.r.p, k, s, l == C.lt);
     }
     {  // f_c = P^T r, and the coarse iterate starts from zero (same launch)
-        Timed tm(h, timed ? LAMG_KERNEL_RESTRICT : -1, prec_id<T>(), bytes_restrict(op, k, sz));
+        Timed tm(h, LAMG_KERNEL_RESTRICT, pid, bytes_restrict(op, k, sz) + zero_c, nar);
         run_restrict<T>(op, P::rw(op), me.r.p, cv.f.p, k, s, cv.x.p);
     }
     int64_t i = C.visits[l]++;
@@ -296,16 +362,22 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
         cycle<T>(C, l + 1, cv.x.p, cv.f.p);
         const bool again = j < nvis;
         if (j >= 2) {  // recombine with the previous visit's pair, keep it if revisiting
-            run_residual<T>(cop, P::v(cop), P::d(cop), cv.x.p, cv.f.p, cv.rho.p, k, s, false);
+            {
+                Timed tm(h, LAMG_KERNEL_RESIDUAL, pid, bytes_residual(cop, k, sz), false);
+                run_residual<T>(cop, P::v(cop), P::d(cop), cv.x.p, cv.f.p, cv.rho.p, k, s, false);
+            }
+            Timed tm(h, LAMG_KERNEL_REDUCE, pid, bytes_rc2(Lc.n, k, sz, again), false);
             run_rc2_keep<T>(Lc.n, cv.x.p, cv.rho.p, cv.x1.p, cv.rho1.p, k, C.partial, cv.alpha.p,
                             again, s);
         } else {  // first visit: the pair (x, rho) is saved by the residual launch
+            Timed tm(h, LAMG_KERNEL_RESIDUAL, pid,
+                     bytes_residual(cop, k, sz) + (again ? 2.0 * zero_c : 0.0), false);
             run_residual<T>(cop, P::v(cop), P::d(cop), cv.x.p, cv.f.p, cv.rho.p, k, s, false,
                             again ? cv.x1.p : nullptr, again ? cv.rho1.p : nullptr);
         }
     }
     {  // energy correction and prolongation
-        Timed tm(h, timed ? LAMG_KERNEL_PROLONG : -1, prec_id<T>(), bytes_prolong(op, k, sz));
+        Timed tm(h, LAMG_KERNEL_PROLONG, pid, 3.0 * zero_c + bytes_prolong(op, k, sz), nar);
         run_mu_prolong<T>(op, P::w0(op), P::w1(op), Lc.n, cv.x.p, cv.f.p, cv.rho.p, k, C.partial,
                           cv.mu.p, x, s);
     }
@@ -521,9 +593,20 @@ void emit_columns(lamg_handle *h, int k, const int32_t *d_mask, double *phi_out)
     Workspace &w = h->ws;
     hipStream_t s = h->stream;
     const int64_t n = h->lev[0].n;
-    run_copy<double>(w.tmp.p, w.phi.p, n * k, s);
-    run_colsum(n, k, w.tmp.p, w.partial.p, w.mean.p, 1.0 / (double)n, s);
-    run_sub_col(n, k, w.tmp.p, w.mean.p, s);
+    const double nk8 = 8.0 * n * k;
+    {
+        Timed tm(h, LAMG_KERNEL_VECTOR, 0, 2.0 * nk8, false);
+        run_copy<double>(w.tmp.p, w.phi.p, n * k, s);
+    }
+    {
+        Timed tm(h, LAMG_KERNEL_REDUCE, 0, nk8, false);
+        run_colsum(n, k, w.tmp.p, w.partial.p, w.mean.p, 1.0 / (double)n, s);
+    }
+    {
+        Timed tm(h, LAMG_KERNEL_VECTOR, 0, 2.0 * nk8, false);
+        run_sub_col(n, k, w.tmp.p, w.mean.p, s);
+    }
+    Timed tm(h, LAMG_KERNEL_VECTOR, 0, 2.0 * nk8 + 4.0 * n, false);
     run_scatter_cols(n, k, h->lev[0].op.perm.p, w.tmp.p, d_mask, phi_out, s);
 }
 
@@ -543,19 +626,39 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
         ensure_level_vecs<float>(h, k);
     else
         ensure_level_vecs<double>(h, k);
-    run_zero_i64(w.visits.p, (int64_t)h->nlev * kTailMaxCols, s);
-
+    const double nk8 = 8.0 * (double)nk;
+    {
+        Timed tm(h, LAMG_KERNEL_VECTOR, 0, 8.0 * h->nlev * kTailMaxCols, false);
+        run_zero_i64(w.visits.p, (int64_t)h->nlev * kTailMaxCols, s);
+    }
     // b <- P b, projected to mean zero (eq. (1.1)); ||b|| per column
-    run_gather_cols(n, k, op0.perm.p, b_user, w.b.p, s);
-    run_colsum(n, k, w.b.p, w.partial.p, w.mean.p, 1.0 / (double)n, s);
-    run_sub_col(n, k, w.b.p, w.mean.p, s);
-    run_copy<double>(w.b0.p, w.b.p, nk, s);
-    run_norm2(n, k, w.b.p, w.partial.p, w.nb.p, s);
+    {
+        Timed tm(h, LAMG_KERNEL_VECTOR, 0, 2.0 * nk8 + 4.0 * n, false);
+        run_gather_cols(n, k, op0.perm.p, b_user, w.b.p, s);
+    }
+    {
+        Timed tm(h, LAMG_KERNEL_REDUCE, 0, nk8, false);
+        run_colsum(n, k, w.b.p, w.partial.p, w.mean.p, 1.0 / (double)n, s);
+    }
+    {
+        Timed tm(h, LAMG_KERNEL_VECTOR, 0, 4.0 * nk8, false);
+        run_sub_col(n, k, w.b.p, w.mean.p, s);
+        run_copy<double>(w.b0.p, w.b.p, nk, s);
+    }
+    {
+        Timed tm(h, LAMG_KERNEL_REDUCE, 0, nk8, false);
+        run_norm2(n, k, w.b.p, w.partial.p, w.nb.p, s);
+    }
     std::vector<double> nb(k);
     w.nb.download(nb.data(), k, s);
     LAMG_HIP(hipStreamSynchronize(s));
+    // eq. (1.1) needs a finite b: a NaN or infinite entry makes the projected column's norm
+    // NaN or infinite (so does a norm that overflows); nothing has been written yet
+    for (int c = 0; c < k; ++c)
+        if (!std::isfinite(nb[c]))
+            throw Error(LAMG_INVALID_ARG, "right-hand side column is not finite");
 
-    std::vector<int32_t> active(k);
+    std::vector<int32_t> active(k), failed(k, 0);
     std::vector<std::vector<double>> hist(k);
     int n_active = 0;
     for (int c = 0; c < k; ++c) {
@@ -565,13 +668,20 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
         cycles[c] = 0;
     }
     // zero columns: phi = 0; everything else starts from phi = 0, r = b
-    run_fill<double>(w.phi.p, nk, 0.0, s);
-    run_copy<double>(w.r.p, w.b.p, nk, s);
-    if (fp32) run_maxabs(n, k, w.r.p, w.partial.p, w.scale.p, s);  // the first cycle's scale
+    {
+        Timed tm(h, LAMG_KERNEL_VECTOR, 0, 3.0 * nk8, false);
+        run_fill<double>(w.phi.p, nk, 0.0, s);
+        run_copy<double>(w.r.p, w.b.p, nk, s);
+    }
+    if (fp32) {  // the first cycle's scale
+        Timed tm(h, LAMG_KERNEL_REDUCE, 0, nk8, false);
+        run_maxabs(n, k, w.r.p, w.partial.p, w.scale.p, s);
+    }
     const bool direct = L0.coarsest;
     const int kappa = std::max(0, std::min(4, (int)h->opt.kappa));
     int hm = 0, hnext = 0;
     if (!direct && kappa > 0) {  // history starts with (0, b)
+        Timed tm(h, LAMG_KERNEL_VECTOR, 0, 3.0 * nk8, false);
         run_fill<double>(w.hphi.p, nk, 0.0, s);
         run_copy<double>(w.hr.p, w.b.p, nk, s);
         hm = 1;
@@ -580,15 +690,18 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
     if (n_active < k) {  // columns with b = 0 finish immediately with phi = 0
         for (int c = 0; c < k; ++c) w.h_mask[c] = active[c] ? 0 : 1;
         w.mask.upload(w.h_mask, k, s);
+        Timed tm(h, LAMG_KERNEL_VECTOR, 0, 2.0 * nk8 + 4.0 * n, false);
         run_scatter_cols(n, k, op0.perm.p, w.phi.p, w.mask.p, phi_out, s);
     }
 
     const int l0 = tail_level(h, k);
     const int lt = timed_level(h, k);
     Cycle<double> c64{h, k, s, &w.lv64, std::vector<int64_t>(h->nlev, 0), w.partial.p, l0, lt,
-                      &w.plan64, w.visits.p, w.tcx64.p, w.tcf64.p};
+                      &w.plan64, w.visits.p, w.tcx64.p, w.tcf64.p,
+                      std::vector<int64_t>(h->nlev, 0)};
     Cycle<float> c32{h, k, s, &w.lv32, std::vector<int64_t>(h->nlev, 0), w.partial.p, l0, lt,
-                     &w.plan32, w.visits.p, w.tcx32.p, w.tcf32.p};
+                     &w.plan32, w.visits.p, w.tcx32.p, w.tcf32.p,
+                     std::vector<int64_t>(h->nlev, 0)};
     // One cycle with its fine-level residual, recombination and relative residuals: the
     // launches depend only on the cycle's index (through the Beatty visit counters and
     // the history slots), so from the second solve of this precision and column count
@@ -602,19 +715,28 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
             // FP32 cycle on the residual equation scaled by max |r| (w.scale, formed with
             // the previous relative residuals, or before the first cycle), FP64 update
             LevelVecs<float> &v0 = w.lv32[0];
-            run_to_f32_scaled(n, k, w.r.p, w.scale.p, v0.f.p, v0.x.p, st);
+            {
+                Timed tm(h, LAMG_KERNEL_VECTOR, 0, 2.0 * nk8, false);
+                run_to_f32_scaled(n, k, w.r.p, w.scale.p, v0.f.p, v0.x.p, st);
+            }
             cycle<float>(c32, 0, v0.x.p, v0.f.p);
+            Timed tm(h, LAMG_KERNEL_VECTOR, 0, 2.5 * nk8, false);
             run_add_scaled_f32(n, k, v0.x.p, w.scale.p, w.phi.p, st);
         }
         {
-            Timed tm(h, LAMG_KERNEL_RESIDUAL, 0, bytes_residual(op0, k, 8.0));
+            Timed tm(h, LAMG_KERNEL_RESIDUAL, 0, bytes_residual(op0, k, 8.0), true);
             run_residual<double>(op0, op0.v64.p, op0.d64.p, w.phi.p, w.b.p, w.r.p, k, st, true);
         }
         if (!direct && kappa > 0) {
-            // recombination; the recombined pair goes into the next history slot
+            // recombination; the recombined pair goes into the next history slot (partial
+            // sums over r and the m saved residuals; update reading phi, r and the m pairs,
+            // writing phi, r and the slot)
+            Timed tm(h, LAMG_KERNEL_REDUCE, 0,
+                     hm > 0 ? (1.0 + hm + 2.0 + 2.0 * hm + 4.0) * nk8 : 4.0 * nk8, false);
             run_recombine_fine(n, k, hm, w.phi.p, w.r.p, w.hphi.p, w.hr.p, hnext % kappa,
                                w.partial.p, w.alpha_f.p, st);
         }
+        Timed tm(h, LAMG_KERNEL_REDUCE, 0, nk8, false);
         run_relres_maxabs(n, k, w.r.p, w.nb.p, w.partial.p, w.rel.p, w.scale.p, st);
         c64.s = s;
         c32.s = s;
@@ -627,19 +749,31 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
     int cyc = 0;
     while (n_active > 0 && cyc < max_cycles) {
         std::vector<int64_t> &vis = fp32 ? c32.visits : c64.visits;
+        std::vector<int64_t> &tvis = fp32 ? c32.tvisits : c64.tvisits;
         if (cyc >= kGraphMaxCycles) gs = nullptr;
         if (gs && cyc < (int)gs->cycles.size()) {
-            LAMG_HIP(hipGraphLaunch(gs->cycles[cyc].exec, s));
-            vis = gs->cycles[cyc].visits_after;
+            const Workspace::CycleGraph &cg = gs->cycles[cyc];
+            LAMG_HIP(hipGraphLaunch(cg.exec, s));
+            vis = cg.visits_after;
+            tvis = cg.tvisits_after;
+            h->solve_bytes += cg.bytes;
             ++graph_cycles;
         } else if (gs) {
+            // the capture runs the cycle's host side (visit counters, byte counts) without
+            // executing its kernels: if it fails, that state goes back to before it
+            const double b0 = h->solve_bytes;
+            const std::vector<int64_t> vis0 = vis, tvis0 = tvis;
             hipGraphExec_t ex = capture_and_launch(h, s, cycle_body);
             if (ex) {
-                gs->cycles.push_back(Workspace::CycleGraph{ex, vis});
+                gs->cycles.push_back(
+                    Workspace::CycleGraph{ex, vis, tvis, h->solve_bytes - b0});
                 ++graph_cycles;
             } else {
                 gs->direct = true;
                 gs = nullptr;
+                h->solve_bytes = b0;
+                vis = vis0;
+                tvis = tvis0;
                 cycle_body(s);
             }
         } else {
@@ -659,7 +793,10 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
             double rel = w.h_rel[c];
             hist[c].push_back(rel);
             cycles[c] = cyc;
+            // a column stops when it meets the tolerance, or when its relative residual is
+            // no longer a finite number (then it has failed: the solve reports it)
             if (rel <= tol || !std::isfinite(rel)) {
+                if (!(rel <= tol)) failed[c] = 1;
                 active[c] = 0;
                 --n_active;
                 w.h_mask[c] = 1;
@@ -674,6 +811,7 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
             emit_columns(h, k, w.mask.p, phi_out);
         }
         if (any_new && n_active > 0) {
+            Timed tm(h, LAMG_KERNEL_VECTOR, 0, (3.0 + 2.0 * hm) * nk8, false);
             run_zero_cols(n, k, w.mask.p, w.phi.p, s);
             run_zero_cols(n, k, w.mask.p, w.b.p, s);
             run_zero_cols(n, k, w.mask.p, w.r.p, s);
@@ -684,6 +822,8 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
         }
     }
     lamg_status st = LAMG_OK;
+    for (int c = 0; c < k; ++c)
+        if (failed[c]) st = LAMG_NOT_CONVERGED;
     if (n_active > 0) {
         for (int c = 0; c < k; ++c) w.h_mask[c] = active[c];
         w.mask.upload(w.h_mask, k, s);
@@ -691,9 +831,18 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
         st = LAMG_NOT_CONVERGED;
     }
     // true residual of the returned phi
-    run_gather_cols(n, k, op0.perm.p, phi_out, w.phi.p, s);
-    run_residual<double>(op0, op0.v64.p, op0.d64.p, w.phi.p, w.b0.p, w.r.p, k, s, true);
-    run_relres(n, k, w.r.p, w.nb.p, w.partial.p, w.rel.p, s);
+    {
+        Timed tm(h, LAMG_KERNEL_VECTOR, 0, 2.0 * nk8 + 4.0 * n, false);
+        run_gather_cols(n, k, op0.perm.p, phi_out, w.phi.p, s);
+    }
+    {
+        Timed tm(h, LAMG_KERNEL_RESIDUAL, 0, bytes_residual(op0, k, 8.0), false);
+        run_residual<double>(op0, op0.v64.p, op0.d64.p, w.phi.p, w.b0.p, w.r.p, k, s, true);
+    }
+    {
+        Timed tm(h, LAMG_KERNEL_REDUCE, 0, nk8, false);
+        run_relres(n, k, w.r.p, w.nb.p, w.partial.p, w.rel.p, s);
+    }
     w.rel.download(w.h_rel, k, s);
     LAMG_HIP(hipStreamSynchronize(s));
     for (int c = 0; c < k; ++c) {
@@ -782,8 +931,9 @@ int KTimer::open(int kind, int prec, double b) {
     return (int)recs.size() - 1;
 }
 
-void KTimer::start(int max_launches) {
+void KTimer::start(int max_launches, bool every_launch) {
     release();
+    all = every_launch;
     for (auto &c : cnt) c[0] = c[1] = 0;
     for (auto &c : sec) c[0] = c[1] = 0.0;
     for (auto &c : bytes) c[0] = c[1] = 0.0;
@@ -838,6 +988,7 @@ lamg_status run_profile(lamg_handle *h, int level, int kernel, lamg_precision pr
 lamg_status run_solve(lamg_handle *h, const double *b, int nrhs, double tol, int max_cycles,
                       lamg_precision prec, double *phi, lamg_solve_info *info) {
     auto t0 = std::chrono::steady_clock::now();
+    h->solve_bytes = 0.0;
     const bool fp32 = prec == LAMG_FP32_IR;
     if (fp32 && !h->opt.build_fp32) throw Error(LAMG_INVALID_ARG, "FP32 copies were not built");
     if (max_cycles <= 0) max_cycles = 300;
@@ -847,6 +998,17 @@ lamg_status run_solve(lamg_handle *h, const double *b, int nrhs, double tol, int
     double rel_max = 0.0, acf_max = 0.0;
     std::vector<double> hist0;
     int graph_cycles = 0;
+    if (nrhs > 32) {
+        // the columns are solved in chunks of 32 and each chunk checks its own columns before
+        // writing; with several chunks every column is checked first, so a non-finite entry
+        // in a later chunk leaves phi untouched too
+        ensure_fine(h, 32);
+        double bad = 0.0;
+        run_count_nonfinite((int64_t)n * nrhs, b, h->ws.partial.p, h->ws.rel.p, h->stream);
+        h->ws.rel.download(&bad, 1, h->stream);
+        LAMG_HIP(hipStreamSynchronize(h->stream));
+        if (bad != 0.0) throw Error(LAMG_INVALID_ARG, "right-hand side is not finite");
+    }
     for (int c0 = 0; c0 < nrhs; c0 += 32) {
         int k = std::min(32, nrhs - c0);
         std::vector<double> rel(k), acf(k), hist;
@@ -871,6 +1033,7 @@ lamg_status run_solve(lamg_handle *h, const double *b, int nrhs, double tol, int
         if (info->history)
             for (int i = 0; i < info->history_len; ++i) info->history[i] = hist0[i];
         info->graph_cycles = graph_cycles;
+        info->bytes = h->solve_bytes;
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return st;

@@ -1012,9 +1012,10 @@ int tail_lds_plan(const std::vector<Level> &lev, int l0, int k, const void *host
     lds_bytes = (size_t)off;
     jobs.resize(jv.size() * sizeof(CopyJob));
     if (!jv.empty()) std::memcpy(jobs.data(), jv.data(), jobs.size());
-    if (lds_bytes > 64 * 1024)
-        LAMG_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tail<T>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+    // the attribute is process-wide while plans of several handles coexist: always the whole
+    // budget, so that no plan lowers it below what another handle's launches request
+    LAMG_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tail<T>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget));
     return l_lds;
 }
 
@@ -1064,14 +1065,14 @@ __global__ void k_from_cols(int64_t n, int k, const T *__restrict__ cx, T *__res
 template <class T>
 void run_to_cols(int64_t n, int k, const T *x, const T *f, T *cx, T *cf, hipStream_t s) {
     if (n * k <= 0) return;
-    k_to_cols<T><<<(unsigned)((n * k + 255) / 256), 256, 0, s>>>(n, k, x, f, cx, cf);
+    launch_kernel(k_to_cols<T>, dim3((unsigned)((n * k + 255) / 256)), dim3(256), 0, s, n, k, x, f, cx, cf);
     LAMG_LAUNCH_CHECK();
 }
 
 template <class T>
 void run_from_cols(int64_t n, int k, const T *cx, T *x, hipStream_t s) {
     if (n * k <= 0) return;
-    k_from_cols<T><<<(unsigned)((n * k + 255) / 256), 256, 0, s>>>(n, k, cx, x);
+    launch_kernel(k_from_cols<T>, dim3((unsigned)((n * k + 255) / 256)), dim3(256), 0, s, n, k, cx, x);
     LAMG_LAUNCH_CHECK();
 }
 
@@ -1079,7 +1080,7 @@ size_t tail_copy_job_bytes() { return sizeof(CopyJob); }
 
 void run_zero_i64(int64_t *p, int64_t n, hipStream_t s) {
     if (n <= 0) return;
-    k_fill_i64<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n);
+    launch_kernel(k_fill_i64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
     LAMG_LAUNCH_CHECK();
 }
 

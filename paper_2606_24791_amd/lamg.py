@@ -52,7 +52,8 @@ class lamg_hier_info(C.Structure):
 class lamg_solve_info(C.Structure):
     _fields_ = [("cycles", C.c_int32), ("relres_max", C.c_double), ("acf_max", C.c_double),
                 ("seconds", C.c_double), ("relres", C.c_void_p), ("col_cycles", C.c_void_p),
-                ("history", C.c_void_p), ("history_len", C.c_int32), ("graph_cycles", C.c_int32)]
+                ("history", C.c_void_p), ("history_len", C.c_int32), ("graph_cycles", C.c_int32),
+                ("bytes", C.c_double)]
 
 
 class lamg_level_export(C.Structure):
@@ -88,7 +89,9 @@ _lib.lamg_profile_kernel.argtypes = [C.c_void_p, C.c_int32, C.c_int, C.c_int, C.
                                      C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]
 _lib.lamg_profile_kernel.restype = C.c_int
 
-KERNEL_GS_COLOR, KERNEL_RESIDUAL, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_TAIL = range(5)
+(KERNEL_GS_COLOR, KERNEL_RESIDUAL, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_TAIL, KERNEL_REDUCE,
+ KERNEL_VECTOR, KERNEL_CHEB) = range(8)
+KERNEL_NAMES = ("gs_color", "residual", "restrict", "prolong", "tail", "reduce", "vector", "cheb")
 
 
 class lamg_kernel_time(C.Structure):
@@ -97,6 +100,8 @@ class lamg_kernel_time(C.Structure):
 
 _lib.lamg_timing_start.argtypes = [C.c_void_p, C.c_int32]
 _lib.lamg_timing_start.restype = C.c_int
+_lib.lamg_timing_start_all.argtypes = [C.c_void_p, C.c_int32]
+_lib.lamg_timing_start_all.restype = C.c_int
 _lib.lamg_timing_stop.argtypes = [C.c_void_p]
 _lib.lamg_timing_stop.restype = C.c_int
 _lib.lamg_timing_get.argtypes = [C.c_void_p, C.c_int, C.c_int, C.POINTER(lamg_kernel_time)]
@@ -235,6 +240,11 @@ def lamg_solve(h: Handle, b, phi, tol: float = 1e-8, max_cycles: int = 300,
                precision: int = FP64, stream=None, history: bool = False, check: bool = True):
     """Solves for the columns of b: torch float64 device tensors of shape (k, n) (row j is
     right-hand side j) or (n,). phi receives the solutions. Returns a dict of statistics."""
+    return _solve(_lib.lamg_solve, "lamg_solve", h, b, phi, tol, max_cycles, precision, stream,
+                  history, check)
+
+
+def _solve(fn, where, h, b, phi, tol, max_cycles, precision, stream, history, check):
     import torch
 
     if b.dtype != torch.float64 or phi.dtype != torch.float64 or not b.is_cuda or not phi.is_cuda:
@@ -252,14 +262,14 @@ def lamg_solve(h: Handle, b, phi, tol: float = 1e-8, max_cycles: int = 300,
     info.relres = rel.ctypes.data
     info.col_cycles = cyc.ctypes.data
     info.history = hist.ctypes.data if hist is not None else None
-    st = _lib.lamg_solve(h.ptr, b.data_ptr(), k, float(tol), int(max_cycles), int(precision),
-                         phi.data_ptr(), C.byref(info), _stream_ptr(stream))
+    st = fn(h.ptr, b.data_ptr(), k, float(tol), int(max_cycles), int(precision), phi.data_ptr(),
+            C.byref(info), _stream_ptr(stream))
     if check and st not in (OK, NOT_CONVERGED):
-        raise LamgError(st, "lamg_solve")
+        raise LamgError(st, where)
     out = dict(status=st, converged=(st == OK), cycles=int(info.cycles),
                relres_max=float(info.relres_max), acf_max=float(info.acf_max),
                seconds=float(info.seconds), relres=rel, col_cycles=cyc,
-               graph_cycles=int(info.graph_cycles))
+               graph_cycles=int(info.graph_cycles), bytes=float(info.bytes))
     if hist is not None:
         out["history"] = hist[: info.history_len].copy()
     return out
@@ -332,6 +342,14 @@ def lamg_timing_start(h: Handle, max_launches: int = 16384) -> None:
         raise LamgError(st, "lamg_timing_start")
 
 
+def lamg_timing_start_all(h: Handle, max_launches: int = 65536) -> None:
+    """Starts in-situ event timing of every kernel launch of later solves, on every level,
+    grouped by kernel kind."""
+    st = _lib.lamg_timing_start_all(h.ptr, int(max_launches))
+    if st != OK:
+        raise LamgError(st, "lamg_timing_start_all")
+
+
 def lamg_timing_stop(h: Handle) -> dict:
     """Stops timing; returns {(kernel, precision): dict(launches, seconds, bytes)} for every
     kernel and precision with at least one timed launch."""
@@ -339,7 +357,7 @@ def lamg_timing_stop(h: Handle) -> dict:
     if st != OK:
         raise LamgError(st, "lamg_timing_stop")
     out = {}
-    for kern in range(5):
+    for kern in range(len(KERNEL_NAMES)):
         for prec in (FP64, FP32_IR):
             t = lamg_kernel_time()
             st = _lib.lamg_timing_get(h.ptr, kern, prec, C.byref(t))

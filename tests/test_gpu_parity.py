@@ -124,7 +124,10 @@ def solve_both(B, g, k, precision, seed=11, tol=TOL, elimination=True, smoother=
     return st, ph, bh, refs
 
 
-def check_solution(g, st, ph, bh, refs, tol=TOL, sol_tol=SOL_TOL):
+def check_solution(g, st, ph, bh, refs, tol=TOL, sol_tol=SOL_TOL, max_tol=None):
+    """True residual, mean zero, cycle count, and the error against the oracle in two norms:
+    relative 2-norm and max|phi - phi_oracle| / max|phi_oracle| (an error concentrated on a
+    few entries cannot hide in the second), both <= sol_tol unless max_tol is given."""
     import scipy.sparse as sp
 
     W = sp.csr_matrix((g.weight, g.col_idx, g.row_ptr), shape=(g.n, g.n))
@@ -138,6 +141,8 @@ def check_solution(g, st, ph, bh, refs, tol=TOL, sol_tol=SOL_TOL):
         assert abs(ph[c].mean()) <= 1e-12 * np.abs(ph[c]).max()
         err = np.linalg.norm(ph[c] - phi_o) / np.linalg.norm(phi_o)
         assert err <= sol_tol, (c, err)
+        emax = np.abs(ph[c] - phi_o).max() / np.abs(phi_o).max()
+        assert emax <= (sol_tol if max_tol is None else max_tol), (c, emax)
         assert abs(st["col_cycles"][c] - so["cycles"]) <= 2, (st["col_cycles"][c], so["cycles"])
 
 
@@ -170,7 +175,9 @@ def test_solve_parity_low_accuracy(B, name, prec):
     g = GRAPHS[name]()
     note(f"solve parity tol 1e-4 {name} {prec} n={g.n}")
     st, ph, bh, refs = solve_both(B, g, 1, B.FP64 if prec == "fp64" else B.FP32_IR, tol=1e-4)
-    check_solution(g, st, ph, bh, refs, tol=1e-4, sol_tol=1e-9 if prec == "fp64" else 1e-5)
+    # the max-norm error of the FP32 iterate may sit a few times above its 2-norm error
+    check_solution(g, st, ph, bh, refs, tol=1e-4, sol_tol=1e-9 if prec == "fp64" else 1e-5,
+                   max_tol=1e-9 if prec == "fp64" else 3e-5)
     assert st["cycles"] == refs[0][1]["cycles"]
 
 
@@ -521,7 +528,7 @@ def test_in_situ_timing_counts_launches_and_leaves_results_unchanged(B):
             assert kt[(B.KERNEL_RESIDUAL, B.FP32_IR)]["launches"] == cyc
             assert kt[(B.KERNEL_RESIDUAL, B.FP64)]["launches"] == cyc
         assert kt[(B.KERNEL_TAIL, prec)]["launches"] >= cyc
-        assert kt[(B.KERNEL_TAIL, prec)]["bytes"] == 0.0
+        assert kt[(B.KERNEL_TAIL, prec)]["bytes"] > 0.0
         # bytes per GS launch: whole-level sum over colours equals one residual's matrix part
         n, e = info["n"][lt], info["nnz"][lt] - info["n"][lt]
         s = 4 if prec == B.FP32_IR else 8
@@ -532,6 +539,17 @@ def test_in_situ_timing_counts_launches_and_leaves_results_unchanged(B):
         kt = B.lamg_timing_stop(h)
         assert sum(t["launches"] for t in kt.values()) == 16
         assert torch.equal(phi, ref)
+        # every launch of every level: the kinds' bytes add up to the solve's byte count,
+        # and the solve is still the untimed one bit for bit
+        B.lamg_timing_start_all(h, 1 << 17)
+        st = B.lamg_solve(h, b, phi, precision=prec)
+        kt = B.lamg_timing_stop(h)
+        assert torch.equal(phi, ref) and st["bytes"] == pytest.approx(st0["bytes"], rel=1e-12)
+        assert sum(t["bytes"] for t in kt.values()) == pytest.approx(st["bytes"], rel=1e-9)
+        assert kt[(B.KERNEL_GS_COLOR, prec)]["launches"] > 3 * ncol * cyc
+        for kern in (B.KERNEL_REDUCE, B.KERNEL_VECTOR):
+            assert kt[(kern, B.FP64)]["launches"] > 0
+        assert all(t["seconds"] > 0 for t in kt.values())
     h.close()
 
 
