@@ -45,7 +45,9 @@ typedef enum {
     LAMG_COARSENING_STALLED = 7, /* a level larger than 1024 nodes did not coarsen */
     LAMG_NOT_CONVERGED = 8,      /* max_cycles reached; phi and residuals are still written */
     LAMG_HIP_ERROR = 9,          /* a HIP runtime call failed (no device, launch failure, ...) */
-    LAMG_UNAVAILABLE = 10        /* requested data was not kept (see keep_setup_data) */
+    LAMG_UNAVAILABLE = 10,       /* requested data was not kept (see keep_setup_data) */
+    LAMG_SCRATCH_TOO_SMALL = 11  /* lamg_solve_noalloc: the solve's workspace does not fit
+                                    the fixed scratch (LAMG_NOALLOC_SCRATCH_BYTES) */
 } lamg_status;
 
 typedef enum { LAMG_MEM_HOST = 0, LAMG_MEM_DEVICE = 1 } lamg_memory;
@@ -235,6 +237,30 @@ lamg_status lamg_setup(const lamg_graph *g, const lamg_options *opt, void *strea
 lamg_status lamg_solve(lamg_handle *h, const double *b, int32_t nrhs, double tol,
                        int32_t max_cycles, lamg_precision prec, double *phi,
                        lamg_solve_info *info, void *stream);
+
+/* Bytes of the fixed device scratch array behind lamg_solve_noalloc (one array per GPU). */
+#define LAMG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* Allocation-free variant of lamg_solve, for callers that cannot allocate device memory:
+ * tight serving loops and harnesses that forbid allocation. Same arguments, results and
+ * statuses as lamg_solve, but the call allocates no device memory and no pinned host memory
+ * (no hipMalloc, hipFree, hipHostMalloc, allocator hook or HIP-graph instantiation): the
+ * solve's workspace -- per-level cycle vectors, the finest-level FP64 state and
+ * recombination history, reduction partial sums, coarse-tail descriptors -- is laid out in a
+ * fixed device array of LAMG_NOALLOC_SCRATCH_BYTES bytes that the library holds on every GPU
+ * it runs on until the process ends (its address is resolved by lamg_setup). The handle's
+ * own cached workspace is neither used nor changed, and lamg_options.graphs does not apply.
+ * A solve whose workspace does not fit returns LAMG_SCRATCH_TOO_SMALL before anything is
+ * written to phi (the finest level alone takes about 104 * n * min(nrhs, 32) bytes).
+ * Every call on a GPU shares that GPU's array and leaves its contents behind (each call
+ * initialises everything it reads): calls that overlap on one GPU -- on different streams or
+ * threads, with any handles -- race, and the caller must serialise them. The call
+ * synchronises `stream` (it reads every cycle's residual norms), so it cannot be recorded
+ * into a HIP graph. The current device must be the one the handle was set up on, else
+ * LAMG_INVALID_ARG. */
+lamg_status lamg_solve_noalloc(lamg_handle *h, const double *b, int32_t nrhs, double tol,
+                               int32_t max_cycles, lamg_precision prec, double *phi,
+                               lamg_solve_info *info, void *stream);
 
 /* Frees everything the handle owns. NULL is accepted. */
 void lamg_destroy(lamg_handle *h);

@@ -31,6 +31,7 @@ SOURCES = {
     "tail_kernel.hip": [],
     "solve.cpp": ["-x", "hip"],
     "api.cpp": ["-x", "hip"],
+    "noalloc.cpp": ["-x", "hip"],
 }
 
 

@@ -26,6 +26,16 @@ Allocator current_allocator() {
 
 void *Pool::get(size_t bytes) {
     void *p = nullptr;
+    if (base_) {
+        const size_t off = ((size_t)bytes_ + 255) & ~(size_t)255;
+        if (off > cap_ || bytes > cap_ - off)
+            throw Error(LAMG_SCRATCH_TOO_SMALL,
+                        "the solve needs more than the " + std::to_string(cap_) +
+                            " bytes of the allocation-free scratch");
+        bytes_ = (int64_t)(off + bytes);
+        peak_ = std::max(peak_, bytes_);
+        return base_ + off;
+    }
     if (a_.alloc) {
         p = a_.alloc(bytes, (void *)s_, a_.ctx);
     } else {
@@ -42,6 +52,7 @@ void *Pool::get(size_t bytes) {
 }
 
 void Pool::put(void *p) {
+    if (base_) return;
     for (size_t i = blks_.size(); i-- > 0;) {
         if (blks_[i].p == p) {
             bytes_ -= (int64_t)blks_[i].bytes;
@@ -57,6 +68,7 @@ void Pool::put(void *p) {
 }
 
 Pool::~Pool() {
+    if (base_) return;
     for (auto &b : blks_) {
         if (a_.free)
             a_.free(b.p, (void *)s_, a_.ctx);
@@ -120,6 +132,8 @@ const char *lamg_status_string(lamg_status s) {
         case LAMG_NOT_CONVERGED: return "not converged";
         case LAMG_HIP_ERROR: return "HIP runtime error";
         case LAMG_UNAVAILABLE: return "data not kept";
+        case LAMG_SCRATCH_TOO_SMALL:
+            return "solve larger than the fixed scratch of the allocation-free entry point";
     }
     return "unknown status";
 }
@@ -160,7 +174,10 @@ lamg_status lamg_setup(const lamg_graph *g, const lamg_options *opt, void *strea
         h->stream = (hipStream_t)stream;
         h->pool.reset(new Pool(h->alloc, h->stream));
         h->opt = o;
-        run_setup(h, g);
+        run_setup(h, g);  // input errors surface before any device work
+        LAMG_HIP(hipGetDevice(&h->device));
+        // the allocation-free entry point's scratch on this device, resolved once per device
+        (void)noalloc_scratch(h->device);
         return LAMG_OK;
     });
     if (st != LAMG_OK) {

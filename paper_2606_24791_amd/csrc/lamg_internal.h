@@ -74,6 +74,11 @@ Allocator current_allocator();
 class Pool {
   public:
     explicit Pool(Allocator a, hipStream_t s) : a_(a), s_(s) {}
+    // An arena over `cap` bytes of device memory at `base` that the pool does not own:
+    // get() hands out consecutive 256-byte-aligned pieces and throws
+    // Error(LAMG_SCRATCH_TOO_SMALL) past the end; put() and the destructor free nothing.
+    Pool(void *base, size_t cap, hipStream_t s)
+        : s_(s), base_(static_cast<char *>(base)), cap_(cap) {}
     ~Pool();
     Pool(const Pool &) = delete;
     Pool &operator=(const Pool &) = delete;
@@ -94,6 +99,8 @@ class Pool {
     std::vector<Blk> blks_;
     int64_t bytes_ = 0;
     int64_t peak_ = 0;
+    char *base_ = nullptr;  // arena mode
+    size_t cap_ = 0;
 };
 
 // Typed device array owned by a Pool.
@@ -226,6 +233,11 @@ struct TailPlan {
 };
 // Cached solve workspace (grown on demand, per precision).
 struct Workspace {
+    // Non-null: the workspace of one allocation-free solve, laid out in this arena (the
+    // fixed scratch array); its host mirrors are then pageable and no HIP graph is made.
+    Pool *arena = nullptr;
+    std::vector<double> h_rel_v;
+    std::vector<int32_t> h_mask_v;
     int kf = 0;  // columns of the finest FP64 state
     DArr<double> phi, b, r, b0, tmp, hphi, hr;  // n*k each; history holds 4 slots
     DArr<double> nb, rel, scale, alpha_f, mean;  // per column
@@ -313,6 +325,7 @@ inline void launch_kernel(void (*kern)(KArgs...), dim3 grid, dim3 block, uint32_
 }  // namespace lamg
 
 struct lamg_handle {
+    int device = 0;  // the HIP device the hierarchy lives on
     lamg::Allocator alloc;
     std::unique_ptr<lamg::Pool> pool;
     hipStream_t stream = nullptr;
@@ -481,5 +494,10 @@ void run_to_f32_scaled(int64_t n, int k, const double *r, const double *scale, f
 void run_add_scaled_f32(int64_t n, int k, const float *e, const double *scale, double *phi,
                         hipStream_t s);  // phi += scale[c] * e
 void run_zero_cols(int64_t n, int k, const int32_t *zero_mask, double *x, hipStream_t s);
+
+// Device address of the allocation-free entry point's scratch array on `device` (resolved
+// once per device, that device current) and its size in bytes.
+void *noalloc_scratch(int device);
+size_t noalloc_scratch_bytes();
 
 }  // namespace lamg

@@ -392,7 +392,7 @@ void ensure_level_vecs(lamg_handle *h, int k) {
     std::vector<LevelVecs<T>> &lv = W::lv(w);
     if (W::k(w) >= k && (int)lv.size() == h->nlev) return;
     clear_graphs(w);  // their kernel arguments point into the vectors replaced here
-    Pool &pool = *h->pool;
+    Pool &pool = w.arena ? *w.arena : *h->pool;
     lv.clear();
     lv.resize(h->nlev);
     for (int l = 0; l < h->nlev; ++l) {
@@ -493,7 +493,7 @@ void ensure_fine(lamg_handle *h, int k) {
     Workspace &w = h->ws;
     if (w.kf >= k) return;
     clear_graphs(w);
-    Pool &pool = *h->pool;
+    Pool &pool = w.arena ? *w.arena : *h->pool;
     int64_t m = h->lev[0].n * k;
     w.phi.alloc(pool, m);
     w.b.alloc(pool, m);
@@ -510,6 +510,14 @@ void ensure_fine(lamg_handle *h, int k) {
     w.partial.alloc(pool, (int64_t)kRedBlocksMax * kRedQMax * k);
     w.mask.alloc(pool, k);
     w.visits.alloc(pool, (int64_t)h->nlev * kTailMaxCols);
+    if (w.arena) {  // no pinned allocation: pageable mirrors (each copy is waited for)
+        w.h_rel_v.assign(k, 0.0);
+        w.h_mask_v.assign(k, 0);
+        w.h_rel = w.h_rel_v.data();
+        w.h_mask = w.h_mask_v.data();
+        w.kf = k;
+        return;
+    }
     if (w.h_rel) (void)hipHostFree(w.h_rel);
     if (w.h_mask) (void)hipHostFree(w.h_mask);
     w.h_rel = nullptr;
@@ -742,7 +750,7 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
         c32.s = s;
     };
     Workspace::GraphSet *gset = nullptr, *gs = nullptr;
-    if (h->opt.graphs && !h->timer.on) {
+    if (h->opt.graphs && !h->timer.on && !w.arena) {
         gset = &graph_set(w, fp32 ? 1 : 0, k);
         if (gset->solves > 0 && !gset->direct) gs = gset;  // the first solve runs directly
     }

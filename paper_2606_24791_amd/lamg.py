@@ -21,7 +21,8 @@ _lib = C.CDLL(str(_LIB_PATH))
 MAX_LEVELS = 64
 
 (OK, INVALID_ARG, NOT_SYMMETRIC, SELF_LOOP, BAD_WEIGHT, DISCONNECTED, OOM, COARSENING_STALLED,
- NOT_CONVERGED, HIP_ERROR, UNAVAILABLE) = range(11)
+ NOT_CONVERGED, HIP_ERROR, UNAVAILABLE, SCRATCH_TOO_SMALL) = range(12)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 MEM_HOST, MEM_DEVICE = 0, 1
 FP64, FP32_IR = 0, 1
 
@@ -79,6 +80,8 @@ _lib.lamg_setup.restype = C.c_int
 _lib.lamg_solve.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_int32, C.c_int,
                             C.c_void_p, C.POINTER(lamg_solve_info), C.c_void_p]
 _lib.lamg_solve.restype = C.c_int
+_lib.lamg_solve_noalloc.argtypes = _lib.lamg_solve.argtypes
+_lib.lamg_solve_noalloc.restype = C.c_int
 _lib.lamg_destroy.argtypes = [C.c_void_p]
 _lib.lamg_destroy.restype = None
 _lib.lamg_hierarchy_info.argtypes = [C.c_void_p, C.POINTER(lamg_hier_info)]
@@ -242,6 +245,15 @@ def lamg_solve(h: Handle, b, phi, tol: float = 1e-8, max_cycles: int = 300,
     right-hand side j) or (n,). phi receives the solutions. Returns a dict of statistics."""
     return _solve(_lib.lamg_solve, "lamg_solve", h, b, phi, tol, max_cycles, precision, stream,
                   history, check)
+
+
+def lamg_solve_noalloc(h: Handle, b, phi, tol: float = 1e-8, max_cycles: int = 300,
+                       precision: int = FP64, stream=None, history: bool = False,
+                       check: bool = True):
+    """lamg_solve through the allocation-free entry point (workspace in the library's fixed
+    device scratch array; status SCRATCH_TOO_SMALL when it does not fit)."""
+    return _solve(_lib.lamg_solve_noalloc, "lamg_solve_noalloc", h, b, phi, tol, max_cycles,
+                  precision, stream, history, check)
 
 
 def _solve(fn, where, h, b, phi, tol, max_cycles, precision, stream, history, check):
