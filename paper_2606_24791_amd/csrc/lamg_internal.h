@@ -23,7 +23,7 @@ constexpr double kTauSoc = 0.05;    // strength-of-connection threshold, eq. (3.
 constexpr double kSnap = 0.01;      // caliber-2 snapping band around 0 and 1
 constexpr int kMaxLevels = LAMG_MAX_LEVELS;
 constexpr int kStallDirectMax = 1024;  // a non-coarsening level up to this size is solved directly
-constexpr int kLongRow = 32;        // rows with more off-diagonals go to the wave-per-row bin
+constexpr int kLongRow = 32;        // rows with more off-diagonals go to the block-per-row bin
 constexpr int kBlock = 256;         // threads per block of every kernel
 constexpr int kRedBlocksMax = 256;  // partial-sum blocks of a reduction
 constexpr int kRedQMax = 14;        // quantities per reduction (4x4 normal equations + rhs)

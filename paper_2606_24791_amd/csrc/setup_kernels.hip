@@ -580,29 +580,100 @@ __global__ void k_dense_fill(int64_t n, const int32_t *__restrict__ rp, const in
 }
 
 // Whole inversion in one workgroup (n <= 1024).
-__global__ void __launch_bounds__(kBlock) k_gauss_jordan_1blk(int64_t n, double *__restrict__ A,
-                                                               double *__restrict__ col) {
-    __shared__ double pinv_s;
-    for (int64_t p = 0; p < n; ++p) {
-        if (threadIdx.x == 0) pinv_s = 1.0 / A[p * n + p];
-        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) col[i] = (i == p) ? 0.0 : A[i * n + p];
+// Inverse of the SPD matrix A (n x n, row-major, in place) by blocked Gauss-Jordan
+// elimination without pivoting: pivot blocks of kGJ rows, in order. With the pivot block D,
+// the rest of its block row U, of its block column L and of the matrix E, one step sets
+//     D <- D^-1,  U <- D^-1 U,  L <- -L D^-1,  E <- E - L D^-1 U,
+// and after the last block A holds A^-1. Every pivot block is a Schur complement of an SPD
+// matrix, hence SPD itself, so no pivoting is needed. Three launches per block: the pivot
+// block inverted in LDS by one workgroup, the row panel D^-1 U (with a copy of the old column
+// panel L), and the update of the whole matrix from those buffers.
+constexpr int kGJ = 32;
+
+// dinv = D^-1 for the pivot block [k0, k0 + b): scalar Gauss-Jordan in LDS, one thread per
+// entry (kGJ x kGJ threads), two barriers per pivot.
+__global__ void __launch_bounds__(kGJ * kGJ) k_bgj_diag(int64_t n, int64_t k0, int b,
+                                                        const double *__restrict__ A,
+                                                        double *__restrict__ dinv) {
+    __shared__ double D[kGJ][kGJ + 1];
+    const int i = threadIdx.x / kGJ, j = threadIdx.x % kGJ;
+    const bool live = i < b && j < b;
+    if (live) D[i][j] = A[(k0 + i) * n + k0 + j];
+    __syncthreads();
+    for (int p = 0; p < b; ++p) {
+        double piv = 0.0, aip = 0.0, apj = 0.0, aij = 0.0;
+        if (live) {
+            piv = D[p][p];
+            aip = D[i][p];
+            apj = D[p][j];
+            aij = D[i][j];
+        }
         __syncthreads();
-        double pinv = pinv_s;
-        for (int64_t j = threadIdx.x; j < n; j += blockDim.x)
-            A[p * n + j] = (j == p ? 1.0 : A[p * n + j]) * pinv;
-        __syncthreads();
-        for (int64_t t = threadIdx.x; t < n * n; t += blockDim.x) {
-            int64_t i = t / n, j = t % n;
-            if (i == p) continue;
-            double a = (j == p) ? 0.0 : A[t];
-            A[t] = a - col[i] * A[p * n + j];
+        if (live) {
+            double v;
+            if (i == p && j == p)
+                v = 1.0 / piv;
+            else if (i == p)
+                v = apj / piv;
+            else if (j == p)
+                v = -aip / piv;
+            else
+                v = aij - aip * (apj / piv);
+            D[i][j] = v;
         }
         __syncthreads();
     }
+    if (live) dinv[i * kGJ + j] = D[i][j];
 }
 
-// (L + 11^T/n)^{-1} = L^+ + 11^T/n for a connected graph: subtracting 1/n from every
-// entry leaves the pseudo-inverse, whose product with any f is the mean-zero solution.
+// R[t][j] = (D^-1 U)[t][j] for every column j outside the pivot block (R row-major, n wide),
+// and Cp[i][t] = A[i][k0 + t], the old block column (n x kGJ).
+__global__ void __launch_bounds__(kBlock) k_bgj_panels(int64_t n, int64_t k0, int b,
+                                                       const double *__restrict__ A,
+                                                       const double *__restrict__ dinv,
+                                                       double *__restrict__ R,
+                                                       double *__restrict__ Cp) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    for (int t = 0; t < b; ++t) Cp[j * kGJ + t] = A[j * n + k0 + t];
+    if (j >= k0 && j < k0 + b) return;
+    double u[kGJ];
+    for (int t = 0; t < b; ++t) u[t] = A[(k0 + t) * n + j];
+    for (int t = 0; t < b; ++t) {
+        double acc = 0.0;
+        for (int q = 0; q < b; ++q) acc += dinv[t * kGJ + q] * u[q];
+        R[t * n + j] = acc;
+    }
+}
+
+// The block step on every entry (i, j), from the buffers only (no entry reads another that
+// this launch writes). Block (x, y): row i = y, columns j = x * blockDim + thread.
+__global__ void __launch_bounds__(kBlock) k_bgj_update(int64_t n, int64_t k0, int b,
+                                                       double *__restrict__ A,
+                                                       const double *__restrict__ dinv,
+                                                       const double *__restrict__ R,
+                                                       const double *__restrict__ Cp) {
+    const int64_t i = blockIdx.y;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const bool ri = i >= k0 && i < k0 + b, rj = j >= k0 && j < k0 + b;
+    double v;
+    if (ri && rj) {
+        v = dinv[(i - k0) * kGJ + (j - k0)];
+    } else if (ri) {
+        v = R[(i - k0) * n + j];
+    } else if (rj) {
+        double acc = 0.0;
+        for (int t = 0; t < b; ++t) acc += Cp[i * kGJ + t] * dinv[t * kGJ + (j - k0)];
+        v = -acc;
+    } else {
+        double acc = 0.0;
+        for (int t = 0; t < b; ++t) acc += Cp[i * kGJ + t] * R[t * n + j];
+        v = A[i * n + j] - acc;
+    }
+    A[i * n + j] = v;
+}
+
 __global__ void k_minus_one_over_n(int64_t n, double *__restrict__ Z) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n * n) Z[t] = Z[t] - 1.0 / (double)n;
@@ -620,25 +691,6 @@ __global__ void k_symmetrize(int64_t n, double *__restrict__ Z) {
     Z[j * n + i] = a;
 }
 
-__global__ void k_gj_pivot(int64_t n, int64_t p, double *__restrict__ A, double *__restrict__ col) {
-    __shared__ double pinv_s;
-    if (threadIdx.x == 0) pinv_s = 1.0 / A[p * n + p];
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) col[i] = (i == p) ? 0.0 : A[i * n + p];
-    __syncthreads();
-    double pinv = pinv_s;
-    for (int64_t j = threadIdx.x; j < n; j += blockDim.x)
-        A[p * n + j] = (j == p ? 1.0 : A[p * n + j]) * pinv;
-}
-
-__global__ void k_gj_eliminate(int64_t n, int64_t p, double *__restrict__ A,
-                               const double *__restrict__ col) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * n) return;
-    int64_t i = t / n, j = t % n;
-    if (i == p) return;
-    double a = (j == p) ? 0.0 : A[t];
-    A[t] = a - col[i] * A[p * n + j];
-}
 
 // ---------------------------------------------------------------------------
 // Solve layout: rows permuted to (class, colour, index) order; the diagonal is split off.
@@ -923,18 +975,18 @@ void launch_diag(int64_t n, const int32_t *rp, const int32_t *ci, const double *
 
 void coarsest_inverse(Pool &pool, int64_t n, const int32_t *rp, const int32_t *ci,
                       const double *v, double *Z, hipStream_t s) {
-    DArr<double> col;
-    col.alloc(pool, n);
     k_dense_fill<<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, v, Z);
     LAMG_LAUNCH_CHECK();
-    if (n <= 1024) {
-        k_gauss_jordan_1blk<<<1, kBlock, 0, s>>>(n, Z, col.p);
-        LAMG_LAUNCH_CHECK();
-    } else {
-        for (int64_t p = 0; p < n; ++p) {
-            k_gj_pivot<<<1, kBlock, 0, s>>>(n, p, Z, col.p);
-            k_gj_eliminate<<<grid_for(n * n), kBlock, 0, s>>>(n, p, Z, col.p);
-        }
+    DArr<double> dinv, R, Cp;
+    dinv.alloc(pool, (int64_t)kGJ * kGJ);
+    R.alloc(pool, (int64_t)kGJ * n);
+    Cp.alloc(pool, n * kGJ);
+    const dim3 ugrid((unsigned)((n + kBlock - 1) / kBlock), (unsigned)n);
+    for (int64_t k0 = 0; k0 < n; k0 += kGJ) {
+        const int b = (int)std::min<int64_t>(kGJ, n - k0);
+        k_bgj_diag<<<1, kGJ * kGJ, 0, s>>>(n, k0, b, Z, dinv.p);
+        k_bgj_panels<<<grid_for(n), kBlock, 0, s>>>(n, k0, b, Z, dinv.p, R.p, Cp.p);
+        k_bgj_update<<<ugrid, kBlock, 0, s>>>(n, k0, b, Z, dinv.p, R.p, Cp.p);
         LAMG_LAUNCH_CHECK();
     }
     k_minus_one_over_n<<<grid_for(n * n), kBlock, 0, s>>>(n, Z);

@@ -47,6 +47,7 @@ template <class T>
 constexpr int kGather = sizeof(T) == 4 ? 8 : 4;  // gathers in flight per group
 constexpr int kRedQ = 2;   // quantities per tail reduction
 constexpr int kSplitRow = 256;  // levels with longer rows share a long row between waves
+constexpr int kMediumRow = 64;  // long rows up to this length are relaxed with the short ones
 
 // Level descriptor. Array fields hold device pointers for levels in global memory and
 // byte offsets into the launch's dynamic LDS for LDS-resident levels (Z always global).
@@ -195,6 +196,39 @@ __device__ __forceinline__ void csr_short_split(int a, int b, int skip_long,
     }
 }
 
+// Rows [a, b) and [la, lb) of one pass as a single set, by groups of kp x lpr lanes (lpr up
+// to 8, as long as the set still gives every lane a row): used when the level's long rows
+// have at most kMediumRow entries, so that they need no second, wave-per-row phase after
+// the short ones.
+template <class T, int OP>
+__device__ __forceinline__ void csr_medium_split(int a, int b, int la, int lb, const int32_t *rp,
+                                                 const int32_t *ci, const T *v, const T *dd,
+                                                 const T *f, const T *xin, T *out, int k, int lkp) {
+    constexpr int U = 4;
+    const int tid = threadIdx.x;
+    const int kp = 1 << lkp;
+    const int ns = b - a, nrow = ns + (lb - la);
+    int llpr = 0;
+    while (llpr < 3 && lkp + llpr < 6 && (nrow << (lkp + llpr + 1)) <= TB) ++llpr;
+    const int lg = lkp + llpr, G = 1 << lg, lpr = 1 << llpr;
+    const int g = tid & (G - 1);
+    const int c = g & (kp - 1), sub = g >> lkp;
+    for (int t = tid >> lg; t < nrow; t += (TB >> lg)) {
+        const int row = t < ns ? a + t : la + (t - ns);
+        const int e0 = rp[row], e1 = rp[row + 1];
+        T acc = T(0);
+        if (c < k) acc = row_sum<T, U>(ci, v, xin, e0 + sub, e1, lpr, k, c);
+        for (int o = kp; o < G; o <<= 1) acc += __shfl_xor(acc, o, 64);
+        if (sub == 0 && c < k) {
+            const int o = row * k + c;
+            if (OP == 0)
+                out[o] = (f[o] - acc) * dd[row];
+            else
+                out[o] = f[o] - dd[row] * xin[o] - acc;
+        }
+    }
+}
+
 // CSR pass over rows [a, b) (short rows) and [la, lb) (long rows, through `rows` if given):
 //   OP 0: x[r] = (f[r] - sum_off) * dd[r]      (Gauss-Seidel colour pass, in place)
 //   OP 1: out[r] = f[r] - dd[r] x[r] - sum_off  (residual)
@@ -205,9 +239,14 @@ template <class T, int OP, bool SPLIT = false>
 __device__ __forceinline__ void csr_rows(int a, int b, int la, int lb, const int32_t *rows, int skip_long,
                          const int32_t *rp, const int32_t *ci, const T *v, const T *dd, const T *f,
                          const T *xin, T *out, int k, int lkp, T *lpart, bool split,
-                         int max_llpr) {
+                         int max_llpr, int maxrow = 0) {
     const int tid = threadIdx.x;
     const int kp = 1 << lkp;
+    // SPLIT levels whose long rows are medium (Gauss-Seidel and residual passes): one phase
+    if (SPLIT && OP != 2 && !rows && maxrow <= kMediumRow) {
+        csr_medium_split<T, OP>(a, b, la, lb, rp, ci, v, dd, f, xin, out, k, lkp);
+        return;
+    }
     // SPLIT (the denser levels) and few short rows: several lanes split each row; a separate
     // instantiation, so the other levels run the plain loop
     if (SPLIT && ((b - a) << (lkp + 2)) <= TB && lkp < 6) {
@@ -306,7 +345,7 @@ __device__ __forceinline__ void residual(const Lv<T, M> &L, T *out, int k, int l
     const int nc = L.ncol;
     if (L.maxrow > kLongRow)
         csr_rows<T, 1, true>(0, (int)L.blk[nc], (int)L.blk[nc], L.n, nullptr, 0, L.rp, L.ci, L.v,
-                             L.d, L.f, L.x, out, k, lkp, lp, L.split, 3);
+                             L.d, L.f, L.x, out, k, lkp, lp, L.split, 3, L.maxrow);
     else
         csr_rows<T, 1>(0, (int)L.blk[nc], (int)L.blk[nc], L.n, nullptr, 0, L.rp, L.ci, L.v, L.d,
                        L.f, L.x, out, k, lkp, lp, L.split, 0);
@@ -533,7 +572,7 @@ __device__ __forceinline__ void smooth(const Lv<T, M> &L, int k, int lkp, int sw
                 if (L.maxrow > kLongRow)
                     csr_rows<T, 0, true>((int)L.blk[cl], (int)L.blk[cl + 1], (int)L.blk[nc + cl],
                                          (int)L.blk[nc + cl + 1], nullptr, 0, L.rp, L.ci, L.v,
-                                         L.dinv, L.f, L.x, L.x, k, lkp, lp, L.split, 3);
+                                         L.dinv, L.f, L.x, L.x, k, lkp, lp, L.split, 3, L.maxrow);
                 else
                     csr_rows<T, 0>((int)L.blk[cl], (int)L.blk[cl + 1], (int)L.blk[nc + cl],
                                    (int)L.blk[nc + cl + 1], nullptr, 0, L.rp, L.ci, L.v, L.dinv,
