@@ -122,6 +122,9 @@ def main() -> int:
                     help="coarse-tail threshold option (-1: library default)")
     ap.add_argument("--smoother", type=int, default=0,
                     help="0: multicolour Gauss-Seidel; 1: Chebyshev on levels with > 32 colours")
+    ap.add_argument("--tail-finest", type=int, default=0,
+                    help="FP32+IR cycles of a finest level up to this size run wholly in the "
+                         "coarse tail (0: library default, never)")
     ap.add_argument("--graphs", action="store_true",
                     help="replay each cycle as a HIP graph from the second solve on")
     ap.add_argument("--no-elimination", action="store_true",
@@ -170,6 +173,8 @@ def main() -> int:
         over["smoother"] = args.smoother
     if args.graphs:
         over["graphs"] = 1
+    if args.tail_finest:
+        over["tail_finest"] = args.tail_finest
     opts = B.lamg_default_options(**over)
     h = B.lamg_setup(g, opts)
     torch.cuda.synchronize()

@@ -120,6 +120,12 @@ typedef struct {
                                 launch latency dominates (systems of a few thousand rows).
                                 0 (default): never. Changes only how the cycle is launched,
                                 not what it computes. */
+    int32_t tail_finest;     /* FP32+IR solves of a graph whose finest level has at most this
+                                many nodes (and whose other levels all run in the coarse tail)
+                                run the finest level in the coarse tail too: each cycle is then
+                                one launch, and lamg_solve_group can make the launches of
+                                several such solves one. 0 (default): never; at most 65535.
+                                Changes only how the cycle is executed, not what it computes. */
 } lamg_options;
 
 /* Per-level description of a hierarchy. */
@@ -140,7 +146,8 @@ typedef struct {
     int32_t elim[LAMG_MAX_LEVELS];       /* 1: elimination level (its aggregate export holds the
                                             coarse id of each kept node and -1 on F) */
     int32_t tail_level;                  /* first level whose cycle runs in the coarse-tail
-                                            kernel in a 1-column solve (-1: none) */
+                                            kernel in a 1-column FP32+IR solve (-1: none; FP64
+                                            cycles never run the finest level there) */
     int32_t timed_level;                 /* level whose per-step kernels the in-situ timer
                                             records in a 1-column solve (the finest
                                             aggregation level unless that one runs in the
@@ -237,6 +244,24 @@ lamg_status lamg_setup(const lamg_graph *g, const lamg_options *opt, void *strea
 lamg_status lamg_solve(lamg_handle *h, const double *b, int32_t nrhs, double tol,
                        int32_t max_cycles, lamg_precision prec, double *phi,
                        lamg_solve_info *info, void *stream);
+
+/* Solves `count` independent requests together: request r is (handles[r], b[r], nrhs[r],
+ * phi[r]) with the meaning, layout and results of lamg_solve, and tol, max_cycles, prec and
+ * stream shared by all. For serving many small graphs at once, where a solve on its own is
+ * bound by its chain of dependent launches (a serving form, not part of the paper's method):
+ * requests in FP32_IR with at most 32
+ * columns whose handle runs the whole cycle in the coarse tail (lamg_options.tail_finest)
+ * advance in lockstep, and every cycle's coarse-tail work of all of them is ONE kernel launch
+ * (one workgroup per column of each request); every other request is solved by itself, in
+ * order, first. Each request computes exactly what lamg_solve computes for it (same kernels,
+ * same arithmetic, its own stopping). The handles must be distinct (each request uses its
+ * handle's workspace) and live on the current device. statuses[r] receives request r's
+ * status; infos (nullable) per-request statistics. Returns OK if every request is OK, else
+ * the first non-OK status; INVALID_ARG for bad arguments (nothing solved). */
+lamg_status lamg_solve_group(int32_t count, lamg_handle *const *handles,
+                             const double *const *b, const int32_t *nrhs, double tol,
+                             int32_t max_cycles, lamg_precision prec, double *const *phi,
+                             lamg_solve_info *infos, lamg_status *statuses, void *stream);
 
 /* Bytes of the fixed device scratch array behind lamg_solve_noalloc (one array per GPU). */
 #define LAMG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)

@@ -13,6 +13,10 @@ lamg_status run_solve(lamg_handle *h, const double *b, int nrhs, double tol, int
                       lamg_precision prec, double *phi, lamg_solve_info *info);
 lamg_status run_profile(lamg_handle *h, int level, int kernel, lamg_precision prec, int k,
                         int reps, double *sec, double *bytes);
+lamg_status run_solve_group(int count, lamg_handle *const *hs, const double *const *bs,
+                            const int32_t *nrhs, double tol, int max_cycles, lamg_precision prec,
+                            double *const *phis, lamg_solve_info *infos, lamg_status *statuses,
+                            hipStream_t stream);
 int plan_tail_level(const lamg_handle *h);
 int plan_timed_level(const lamg_handle *h);
 
@@ -153,6 +157,7 @@ void lamg_default_options(lamg_options *opt) {
     opt->elimination = 1;
     opt->smoother = 0;
     opt->graphs = 0;
+    opt->tail_finest = 0;
 }
 
 lamg_status lamg_setup(const lamg_graph *g, const lamg_options *opt, void *stream,
@@ -165,7 +170,7 @@ lamg_status lamg_setup(const lamg_graph *g, const lamg_options *opt, void *strea
     if (opt) o = *opt;
     if (o.n_direct < 1 || o.n_direct > 1024 || o.kappa < 0 || o.kappa > 4 || o.tail_rows < 0 ||
         (o.elimination != 0 && o.elimination != 1) || (o.smoother != 0 && o.smoother != 1) ||
-        (o.graphs != 0 && o.graphs != 1))
+        (o.graphs != 0 && o.graphs != 1) || o.tail_finest < 0 || o.tail_finest > 65535)
         return LAMG_INVALID_ARG;
     lamg_handle *h = nullptr;
     lamg_status st = guarded([&]() -> lamg_status {
@@ -202,6 +207,24 @@ lamg_status lamg_solve(lamg_handle *h, const double *b, int32_t nrhs, double tol
         h->stream = (hipStream_t)stream;
         h->pool->set_stream(h->stream);
         return run_solve(h, b, nrhs, tol, max_cycles, prec, phi, info);
+    });
+}
+
+lamg_status lamg_solve_group(int32_t count, lamg_handle *const *handles,
+                             const double *const *b, const int32_t *nrhs, double tol,
+                             int32_t max_cycles, lamg_precision prec, double *const *phi,
+                             lamg_solve_info *infos, lamg_status *statuses, void *stream) {
+    if (count < 1 || !handles || !b || !nrhs || !phi || !statuses || !(tol >= 0.0) ||
+        (prec != LAMG_FP64 && prec != LAMG_FP32_IR))
+        return LAMG_INVALID_ARG;
+    for (int32_t r = 0; r < count; ++r) {
+        if (!handles[r] || !b[r] || !phi[r] || nrhs[r] < 1) return LAMG_INVALID_ARG;
+        for (int32_t q = 0; q < r; ++q)
+            if (handles[q] == handles[r]) return LAMG_INVALID_ARG;  // one workspace each
+    }
+    return guarded([&]() -> lamg_status {
+        return run_solve_group(count, handles, b, nrhs, tol, max_cycles, prec, phi, infos,
+                               statuses, (hipStream_t)stream);
     });
 }
 

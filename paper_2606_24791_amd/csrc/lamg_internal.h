@@ -274,6 +274,9 @@ struct Workspace {
     };
     std::vector<GraphSet> gsets;  // least recently used first
     hipStream_t cap_stream = nullptr;
+    // grouped coarse-tail launches led by this workspace's solve: workgroup records and the
+    // launch's combined descriptors and copy jobs
+    DArr<char> grp_recs, grp_desc, grp_jobs;
 };
 // Destroys the cached cycle graphs (their kernel arguments point into the workspace).
 void clear_graphs(Workspace &w);
@@ -461,6 +464,18 @@ int tail_lds_plan(const std::vector<Level> &lev, int l0, int k, const void *host
 size_t tail_copy_job_bytes();
 template <class T>
 void run_tail(const TailPlan &tp, int l0, int nlev, int k, int64_t *d_visits, hipStream_t s);
+// Grouped launches (several requests in one launch): per-workgroup records, with offsets
+// into the launch's combined descriptor and copy-job arrays (tail_desc_bytes<T>() and
+// tail_copy_job_bytes() per entry).
+size_t tail_wg_bytes();
+template <class T>
+void tail_wg_records(const TailPlan &tp, int l0, int nlev, int k, int64_t *d_visits,
+                     std::vector<char> &recs, int64_t &ndesc, int64_t &njobs_total,
+                     std::vector<std::pair<const void *, size_t>> &desc_src,
+                     std::vector<std::pair<const void *, size_t>> &jobs_src);
+template <class T>
+void run_tail_group(const void *wgs, const void *descs, const void *jobs, int nwg,
+                    size_t lds_bytes, hipStream_t s);
 // n x k row-interleaved (x, f) -> column by column (cx, cf), and back for x.
 template <class T>
 void run_to_cols(int64_t n, int k, const T *x, const T *f, T *cx, T *cf, hipStream_t s);

@@ -205,7 +205,12 @@ double tail_level_bytes(Cycle<T> &C, int l) {
 // all columns was slower than the per-step kernels from four columns on (anisotropic
 // grid, 4 columns: 126 ms against 109 ms without the tail), one per column is faster at
 // every width measured (4 columns: 69 ms; 32 columns: 117 against 154 ms).
-int tail_level(const lamg_handle *h, int k) {
+// With `fp32` (the FP32 cycles of an FP32+IR solve), a finest level of at most
+// opt.tail_finest nodes joins the tail as well when every level below it is in the tail:
+// the whole cycle is then one launch (and the launches of several such solves can be one,
+// see solve_group). FP64 cycles keep the finest level's per-step kernels, which work on
+// the finest FP64 state directly.
+int tail_level(const lamg_handle *h, int k, bool fp32) {
     if (h->opt.tail_rows <= 0 || k > kTailMaxCols) return -1;
     int l0 = -1;
     for (int l = 1; l < h->nlev; ++l)
@@ -236,6 +241,10 @@ int tail_level(const lamg_handle *h, int k) {
         if (tail_us > 0.5 * launches * 4.0) break;
         --l0;
     }
+    const Level &F = h->lev[0];
+    if (fp32 && l0 == 1 && h->opt.tail_finest > 0 && F.n <= h->opt.tail_finest && F.n < 65536 &&
+        !F.coarsest && !F.cheb)
+        l0 = 0;
     return l0;
 }
 
@@ -243,7 +252,7 @@ int tail_level(const lamg_handle *h, int k) {
 // separate "finest" symbols: the finest aggregation level (elimination levels run no full
 // smoothing pass), or the finest level when that aggregation level runs in the coarse tail.
 int timed_level(const lamg_handle *h, int k) {
-    const int l0 = tail_level(h, k);
+    const int l0 = tail_level(h, k, false);
     for (int l = 0; l < h->nlev; ++l) {
         const Level &L = h->lev[l];
         if (L.coarsest) break;
@@ -429,7 +438,7 @@ void ensure_level_vecs(lamg_handle *h, int k) {
     // the plan serves every later solve that uses the tail (at most kTailMaxCols columns),
     // including narrower solves reusing vectors sized for a wider one, so it is built for
     // the tail level of such solves whatever k these vectors were sized for
-    const int l0 = tail_level(h, 1);
+    const int l0 = tail_level(h, 1, std::is_same<T, float>::value);
     int l_x = -1;  // one column per workgroup
     int l_lds = tail_lds_plan<T>(h->lev, l0, 1, host.data(), lds_desc, jobs, lds_bytes, l_x);
     if (l0 >= 0) {
@@ -618,118 +627,159 @@ void emit_columns(lamg_handle *h, int k, const int32_t *d_mask, double *phi_out)
     run_scatter_cols(n, k, h->lev[0].op.perm.p, w.tmp.p, d_mask, phi_out, s);
 }
 
-// One chunk of at most 32 columns.
-lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol, int max_cycles,
-                        bool fp32, double *phi_out, std::vector<double> &relres,
-                        std::vector<int32_t> &cycles, std::vector<double> &acf,
-                        std::vector<double> &hist0, int &graph_cycles) {
-    hipStream_t s = h->stream;
-    Workspace &w = h->ws;
-    Level &L0 = h->lev[0];
-    const SolveOp &op0 = L0.op;
-    const int64_t n = L0.n;
-    const int64_t nk = n * k;
-    ensure_fine(h, k);
-    if (fp32)
-        ensure_level_vecs<float>(h, k);
-    else
-        ensure_level_vecs<double>(h, k);
-    const double nk8 = 8.0 * (double)nk;
-    {
-        Timed tm(h, LAMG_KERNEL_VECTOR, 0, 8.0 * h->nlev * kTailMaxCols, false);
-        run_zero_i64(w.visits.p, (int64_t)h->nlev * kTailMaxCols, s);
-    }
-    // b <- P b, projected to mean zero (eq. (1.1)); ||b|| per column
-    {
-        Timed tm(h, LAMG_KERNEL_VECTOR, 0, 2.0 * nk8 + 4.0 * n, false);
-        run_gather_cols(n, k, op0.perm.p, b_user, w.b.p, s);
-    }
-    {
-        Timed tm(h, LAMG_KERNEL_REDUCE, 0, nk8, false);
-        run_colsum(n, k, w.b.p, w.partial.p, w.mean.p, 1.0 / (double)n, s);
-    }
-    {
-        Timed tm(h, LAMG_KERNEL_VECTOR, 0, 4.0 * nk8, false);
-        run_sub_col(n, k, w.b.p, w.mean.p, s);
-        run_copy<double>(w.b0.p, w.b.p, nk, s);
-    }
-    {
-        Timed tm(h, LAMG_KERNEL_REDUCE, 0, nk8, false);
-        run_norm2(n, k, w.b.p, w.partial.p, w.nb.p, s);
-    }
-    std::vector<double> nb(k);
-    w.nb.download(nb.data(), k, s);
-    LAMG_HIP(hipStreamSynchronize(s));
-    // eq. (1.1) needs a finite b: a NaN or infinite entry makes the projected column's norm
-    // NaN or infinite (so does a norm that overflows); nothing has been written yet
-    for (int c = 0; c < k; ++c)
-        if (!std::isfinite(nb[c]))
-            throw Error(LAMG_INVALID_ARG, "right-hand side column is not finite");
+// The state of one solve of at most 32 columns, advanced cycle by cycle: begin() prepares
+// the right-hand sides and the first iterate, each cycle launches its work (pre, the cycle,
+// post), the relative residuals come back once per cycle (host()), and finish() writes the
+// statistics. solve_chunk runs one chunk by itself; solve_group runs several in lockstep,
+// with the coarse-tail launches of all of them made as one.
+struct Chunk {
+    lamg_handle *h = nullptr;
+    int k = 0;
+    double tol = 0.0;
+    int max_cycles = 0;
+    bool fp32 = false;
+    double *phi_out = nullptr;
+    int64_t n = 0, nk = 0;
+    double nk8 = 0.0;
+    std::vector<double> nb;
+    std::vector<int32_t> active, failed, cycles;
+    std::vector<std::vector<double>> hist;
+    int n_active = 0, hm = 0, hnext = 0, kappa = 0, cyc = 0;
+    bool direct = false;
+    std::unique_ptr<Cycle<double>> c64;
+    std::unique_ptr<Cycle<float>> c32;
 
-    std::vector<int32_t> active(k), failed(k, 0);
-    std::vector<std::vector<double>> hist(k);
-    int n_active = 0;
-    for (int c = 0; c < k; ++c) {
-        active[c] = nb[c] > 0.0 ? 1 : 0;
-        n_active += active[c];
-        hist[c].push_back(1.0);
-        cycles[c] = 0;
-    }
-    // zero columns: phi = 0; everything else starts from phi = 0, r = b
-    {
-        Timed tm(h, LAMG_KERNEL_VECTOR, 0, 3.0 * nk8, false);
-        run_fill<double>(w.phi.p, nk, 0.0, s);
-        run_copy<double>(w.r.p, w.b.p, nk, s);
-    }
-    if (fp32) {  // the first cycle's scale
-        Timed tm(h, LAMG_KERNEL_REDUCE, 0, nk8, false);
-        run_maxabs(n, k, w.r.p, w.partial.p, w.scale.p, s);
-    }
-    const bool direct = L0.coarsest;
-    const int kappa = std::max(0, std::min(4, (int)h->opt.kappa));
-    int hm = 0, hnext = 0;
-    if (!direct && kappa > 0) {  // history starts with (0, b)
-        Timed tm(h, LAMG_KERNEL_VECTOR, 0, 3.0 * nk8, false);
-        run_fill<double>(w.hphi.p, nk, 0.0, s);
-        run_copy<double>(w.hr.p, w.b.p, nk, s);
-        hm = 1;
-        hnext = 1;
-    }
-    if (n_active < k) {  // columns with b = 0 finish immediately with phi = 0
-        for (int c = 0; c < k; ++c) w.h_mask[c] = active[c] ? 0 : 1;
-        w.mask.upload(w.h_mask, k, s);
-        Timed tm(h, LAMG_KERNEL_VECTOR, 0, 2.0 * nk8 + 4.0 * n, false);
-        run_scatter_cols(n, k, op0.perm.p, w.phi.p, w.mask.p, phi_out, s);
+    void begin(lamg_handle *hh, const double *b_user, int kk, double t, int mc, bool f32,
+               double *out) {
+        h = hh;
+        k = kk;
+        tol = t;
+        max_cycles = mc;
+        fp32 = f32;
+        phi_out = out;
+        hipStream_t s = h->stream;
+        Workspace &w = h->ws;
+        Level &L0 = h->lev[0];
+        const SolveOp &op0 = L0.op;
+        n = L0.n;
+        nk = n * k;
+        ensure_fine(h, k);
+        if (fp32)
+            ensure_level_vecs<float>(h, k);
+        else
+            ensure_level_vecs<double>(h, k);
+        nk8 = 8.0 * (double)nk;
+        {
+            Timed tm(h, LAMG_KERNEL_VECTOR, 0, 8.0 * h->nlev * kTailMaxCols, false);
+            run_zero_i64(w.visits.p, (int64_t)h->nlev * kTailMaxCols, s);
+        }
+        // b <- P b, projected to mean zero (eq. (1.1)); ||b|| per column
+        {
+            Timed tm(h, LAMG_KERNEL_VECTOR, 0, 2.0 * nk8 + 4.0 * n, false);
+            run_gather_cols(n, k, op0.perm.p, b_user, w.b.p, s);
+        }
+        {
+            Timed tm(h, LAMG_KERNEL_REDUCE, 0, nk8, false);
+            run_colsum(n, k, w.b.p, w.partial.p, w.mean.p, 1.0 / (double)n, s);
+        }
+        {
+            Timed tm(h, LAMG_KERNEL_VECTOR, 0, 4.0 * nk8, false);
+            run_sub_col(n, k, w.b.p, w.mean.p, s);
+            run_copy<double>(w.b0.p, w.b.p, nk, s);
+        }
+        {
+            Timed tm(h, LAMG_KERNEL_REDUCE, 0, nk8, false);
+            run_norm2(n, k, w.b.p, w.partial.p, w.nb.p, s);
+        }
+        nb.assign(k, 0.0);
+        w.nb.download(nb.data(), k, s);
+        LAMG_HIP(hipStreamSynchronize(s));
+        // eq. (1.1) needs a finite b: a NaN or infinite entry makes the projected column's
+        // norm NaN or infinite (so does a norm that overflows); nothing has been written yet
+        for (int c = 0; c < k; ++c)
+            if (!std::isfinite(nb[c]))
+                throw Error(LAMG_INVALID_ARG, "right-hand side column is not finite");
+        active.assign(k, 0);
+        failed.assign(k, 0);
+        cycles.assign(k, 0);
+        hist.assign(k, std::vector<double>());
+        n_active = 0;
+        for (int c = 0; c < k; ++c) {
+            active[c] = nb[c] > 0.0 ? 1 : 0;
+            n_active += active[c];
+            hist[c].push_back(1.0);
+        }
+        // zero columns: phi = 0; everything else starts from phi = 0, r = b
+        {
+            Timed tm(h, LAMG_KERNEL_VECTOR, 0, 3.0 * nk8, false);
+            run_fill<double>(w.phi.p, nk, 0.0, s);
+            run_copy<double>(w.r.p, w.b.p, nk, s);
+        }
+        if (fp32) {  // the first cycle's scale
+            Timed tm(h, LAMG_KERNEL_REDUCE, 0, nk8, false);
+            run_maxabs(n, k, w.r.p, w.partial.p, w.scale.p, s);
+        }
+        direct = L0.coarsest;
+        kappa = std::max(0, std::min(4, (int)h->opt.kappa));
+        hm = hnext = 0;
+        if (!direct && kappa > 0) {  // history starts with (0, b)
+            Timed tm(h, LAMG_KERNEL_VECTOR, 0, 3.0 * nk8, false);
+            run_fill<double>(w.hphi.p, nk, 0.0, s);
+            run_copy<double>(w.hr.p, w.b.p, nk, s);
+            hm = 1;
+            hnext = 1;
+        }
+        if (n_active < k) {  // columns with b = 0 finish immediately with phi = 0
+            for (int c = 0; c < k; ++c) w.h_mask[c] = active[c] ? 0 : 1;
+            w.mask.upload(w.h_mask, k, s);
+            Timed tm(h, LAMG_KERNEL_VECTOR, 0, 2.0 * nk8 + 4.0 * n, false);
+            run_scatter_cols(n, k, op0.perm.p, w.phi.p, w.mask.p, phi_out, s);
+        }
+        const int lt = timed_level(h, k);
+        c64.reset(new Cycle<double>{h, k, s, &w.lv64, std::vector<int64_t>(h->nlev, 0),
+                                    w.partial.p, tail_level(h, k, false), lt, &w.plan64,
+                                    w.visits.p, w.tcx64.p, w.tcf64.p,
+                                    std::vector<int64_t>(h->nlev, 0)});
+        c32.reset(new Cycle<float>{h, k, s, &w.lv32, std::vector<int64_t>(h->nlev, 0),
+                                   w.partial.p, tail_level(h, k, true), lt, &w.plan32,
+                                   w.visits.p, w.tcx32.p, w.tcf32.p,
+                                   std::vector<int64_t>(h->nlev, 0)});
+        cyc = 0;
     }
 
-    const int l0 = tail_level(h, k);
-    const int lt = timed_level(h, k);
-    Cycle<double> c64{h, k, s, &w.lv64, std::vector<int64_t>(h->nlev, 0), w.partial.p, l0, lt,
-                      &w.plan64, w.visits.p, w.tcx64.p, w.tcf64.p,
-                      std::vector<int64_t>(h->nlev, 0)};
-    Cycle<float> c32{h, k, s, &w.lv32, std::vector<int64_t>(h->nlev, 0), w.partial.p, l0, lt,
-                     &w.plan32, w.visits.p, w.tcx32.p, w.tcf32.p,
-                     std::vector<int64_t>(h->nlev, 0)};
-    // One cycle with its fine-level residual, recombination and relative residuals: the
-    // launches depend only on the cycle's index (through the Beatty visit counters and
-    // the history slots), so from the second solve of this precision and column count
-    // each index's launches are captured once and replayed as a graph.
-    auto cycle_body = [&](hipStream_t st) {
-        c64.s = st;
-        c32.s = st;
+    bool running() const { return n_active > 0 && cyc < max_cycles; }
+
+    // FP32 cycles: the residual equation scaled by max |r| (w.scale, formed with the previous
+    // relative residuals, or before the first cycle) as the level-0 right-hand side
+    void pre(hipStream_t st) {
+        if (!fp32) return;
+        Workspace &w = h->ws;
+        LevelVecs<float> &v0 = w.lv32[0];
+        Timed tm(h, LAMG_KERNEL_VECTOR, 0, 2.0 * nk8, false);
+        run_to_f32_scaled(n, k, w.r.p, w.scale.p, v0.f.p, v0.x.p, st);
+    }
+
+    void cycle_launches(hipStream_t st) {
+        Workspace &w = h->ws;
         if (!fp32) {
-            cycle<double>(c64, 0, w.phi.p, w.b.p);
+            c64->s = st;
+            cycle<double>(*c64, 0, w.phi.p, w.b.p);
+            c64->s = h->stream;
         } else {
-            // FP32 cycle on the residual equation scaled by max |r| (w.scale, formed with
-            // the previous relative residuals, or before the first cycle), FP64 update
             LevelVecs<float> &v0 = w.lv32[0];
-            {
-                Timed tm(h, LAMG_KERNEL_VECTOR, 0, 2.0 * nk8, false);
-                run_to_f32_scaled(n, k, w.r.p, w.scale.p, v0.f.p, v0.x.p, st);
-            }
-            cycle<float>(c32, 0, v0.x.p, v0.f.p);
+            c32->s = st;
+            cycle<float>(*c32, 0, v0.x.p, v0.f.p);
+            c32->s = h->stream;
+        }
+    }
+
+    // the FP64 update, the fine residual, recombination and the relative residuals
+    void post(hipStream_t st) {
+        Workspace &w = h->ws;
+        const SolveOp &op0 = h->lev[0].op;
+        if (fp32) {
             Timed tm(h, LAMG_KERNEL_VECTOR, 0, 2.5 * nk8, false);
-            run_add_scaled_f32(n, k, v0.x.p, w.scale.p, w.phi.p, st);
+            run_add_scaled_f32(n, k, w.lv32[0].x.p, w.scale.p, w.phi.p, st);
         }
         {
             Timed tm(h, LAMG_KERNEL_RESIDUAL, 0, bytes_residual(op0, k, 8.0), true);
@@ -746,54 +796,22 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
         }
         Timed tm(h, LAMG_KERNEL_REDUCE, 0, nk8, false);
         run_relres_maxabs(n, k, w.r.p, w.nb.p, w.partial.p, w.rel.p, w.scale.p, st);
-        c64.s = s;
-        c32.s = s;
-    };
-    Workspace::GraphSet *gset = nullptr, *gs = nullptr;
-    if (h->opt.graphs && !h->timer.on && !w.arena) {
-        gset = &graph_set(w, fp32 ? 1 : 0, k);
-        if (gset->solves > 0 && !gset->direct) gs = gset;  // the first solve runs directly
     }
-    int cyc = 0;
-    while (n_active > 0 && cyc < max_cycles) {
-        std::vector<int64_t> &vis = fp32 ? c32.visits : c64.visits;
-        std::vector<int64_t> &tvis = fp32 ? c32.tvisits : c64.tvisits;
-        if (cyc >= kGraphMaxCycles) gs = nullptr;
-        if (gs && cyc < (int)gs->cycles.size()) {
-            const Workspace::CycleGraph &cg = gs->cycles[cyc];
-            LAMG_HIP(hipGraphLaunch(cg.exec, s));
-            vis = cg.visits_after;
-            tvis = cg.tvisits_after;
-            h->solve_bytes += cg.bytes;
-            ++graph_cycles;
-        } else if (gs) {
-            // the capture runs the cycle's host side (visit counters, byte counts) without
-            // executing its kernels: if it fails, that state goes back to before it
-            const double b0 = h->solve_bytes;
-            const std::vector<int64_t> vis0 = vis, tvis0 = tvis;
-            hipGraphExec_t ex = capture_and_launch(h, s, cycle_body);
-            if (ex) {
-                gs->cycles.push_back(
-                    Workspace::CycleGraph{ex, vis, tvis, h->solve_bytes - b0});
-                ++graph_cycles;
-            } else {
-                gs->direct = true;
-                gs = nullptr;
-                h->solve_bytes = b0;
-                vis = vis0;
-                tvis = tvis0;
-                cycle_body(s);
-            }
-        } else {
-            cycle_body(s);
-        }
+
+    // after the cycle's launches: history bookkeeping and the residuals' read-back (the
+    // caller synchronises the stream before host())
+    void read_back() {
         if (!direct && kappa > 0) {
             ++hnext;
             if (hm < kappa) ++hm;
         }
         ++cyc;
-        w.rel.download(w.h_rel, k, s);
-        LAMG_HIP(hipStreamSynchronize(s));
+        h->ws.rel.download(h->ws.h_rel, k, h->stream);
+    }
+
+    void host() {
+        Workspace &w = h->ws;
+        hipStream_t s = h->stream;
         bool any_new = false;
         for (int c = 0; c < k; ++c) {
             w.h_mask[c] = 0;
@@ -829,37 +847,195 @@ lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol,
             }
         }
     }
-    lamg_status st = LAMG_OK;
-    for (int c = 0; c < k; ++c)
-        if (failed[c]) st = LAMG_NOT_CONVERGED;
-    if (n_active > 0) {
-        for (int c = 0; c < k; ++c) w.h_mask[c] = active[c];
-        w.mask.upload(w.h_mask, k, s);
-        emit_columns(h, k, w.mask.p, phi_out);
-        st = LAMG_NOT_CONVERGED;
+
+    lamg_status finish(std::vector<double> &relres, std::vector<double> &acf,
+                       std::vector<double> &hist0) {
+        Workspace &w = h->ws;
+        hipStream_t s = h->stream;
+        const SolveOp &op0 = h->lev[0].op;
+        lamg_status st = LAMG_OK;
+        for (int c = 0; c < k; ++c)
+            if (failed[c]) st = LAMG_NOT_CONVERGED;
+        if (n_active > 0) {
+            for (int c = 0; c < k; ++c) w.h_mask[c] = active[c];
+            w.mask.upload(w.h_mask, k, s);
+            emit_columns(h, k, w.mask.p, phi_out);
+            st = LAMG_NOT_CONVERGED;
+        }
+        // true residual of the returned phi
+        {
+            Timed tm(h, LAMG_KERNEL_VECTOR, 0, 2.0 * nk8 + 4.0 * n, false);
+            run_gather_cols(n, k, op0.perm.p, phi_out, w.phi.p, s);
+        }
+        {
+            Timed tm(h, LAMG_KERNEL_RESIDUAL, 0, bytes_residual(op0, k, 8.0), false);
+            run_residual<double>(op0, op0.v64.p, op0.d64.p, w.phi.p, w.b0.p, w.r.p, k, s, true);
+        }
+        {
+            Timed tm(h, LAMG_KERNEL_REDUCE, 0, nk8, false);
+            run_relres(n, k, w.r.p, w.nb.p, w.partial.p, w.rel.p, s);
+        }
+        w.rel.download(w.h_rel, k, s);
+        LAMG_HIP(hipStreamSynchronize(s));
+        relres.assign(k, 0.0);
+        acf.assign(k, 0.0);
+        for (int c = 0; c < k; ++c) {
+            relres[c] = nb[c] > 0.0 ? w.h_rel[c] : 0.0;
+            acf[c] = acf_of(hist[c]);
+        }
+        hist0 = hist[0];
+        return st;
     }
-    // true residual of the returned phi
-    {
-        Timed tm(h, LAMG_KERNEL_VECTOR, 0, 2.0 * nk8 + 4.0 * n, false);
-        run_gather_cols(n, k, op0.perm.p, phi_out, w.phi.p, s);
+};
+
+// One chunk of at most 32 columns.
+lamg_status solve_chunk(lamg_handle *h, const double *b_user, int k, double tol, int max_cycles,
+                        bool fp32, double *phi_out, std::vector<double> &relres,
+                        std::vector<int32_t> &cycles, std::vector<double> &acf,
+                        std::vector<double> &hist0, int &graph_cycles) {
+    hipStream_t s = h->stream;
+    Workspace &w = h->ws;
+    Chunk ch;
+    ch.begin(h, b_user, k, tol, max_cycles, fp32, phi_out);
+    // One cycle with its fine-level residual, recombination and relative residuals: the
+    // launches depend only on the cycle's index (through the Beatty visit counters and
+    // the history slots), so from the second solve of this precision and column count
+    // each index's launches are captured once and replayed as a graph.
+    auto cycle_body = [&](hipStream_t st) {
+        ch.pre(st);
+        ch.cycle_launches(st);
+        ch.post(st);
+    };
+    Workspace::GraphSet *gset = nullptr, *gs = nullptr;
+    if (h->opt.graphs && !h->timer.on && !w.arena) {
+        gset = &graph_set(w, fp32 ? 1 : 0, k);
+        if (gset->solves > 0 && !gset->direct) gs = gset;  // the first solve runs directly
     }
-    {
-        Timed tm(h, LAMG_KERNEL_RESIDUAL, 0, bytes_residual(op0, k, 8.0), false);
-        run_residual<double>(op0, op0.v64.p, op0.d64.p, w.phi.p, w.b0.p, w.r.p, k, s, true);
+    while (ch.running()) {
+        std::vector<int64_t> &vis = fp32 ? ch.c32->visits : ch.c64->visits;
+        std::vector<int64_t> &tvis = fp32 ? ch.c32->tvisits : ch.c64->tvisits;
+        const int cyc = ch.cyc;
+        if (cyc >= kGraphMaxCycles) gs = nullptr;
+        if (gs && cyc < (int)gs->cycles.size()) {
+            const Workspace::CycleGraph &cg = gs->cycles[cyc];
+            LAMG_HIP(hipGraphLaunch(cg.exec, s));
+            vis = cg.visits_after;
+            tvis = cg.tvisits_after;
+            h->solve_bytes += cg.bytes;
+            ++graph_cycles;
+        } else if (gs) {
+            // the capture runs the cycle's host side (visit counters, byte counts) without
+            // executing its kernels: if it fails, that state goes back to before it
+            const double b0 = h->solve_bytes;
+            const std::vector<int64_t> vis0 = vis, tvis0 = tvis;
+            hipGraphExec_t ex = capture_and_launch(h, s, cycle_body);
+            if (ex) {
+                gs->cycles.push_back(
+                    Workspace::CycleGraph{ex, vis, tvis, h->solve_bytes - b0});
+                ++graph_cycles;
+            } else {
+                gs->direct = true;
+                gs = nullptr;
+                h->solve_bytes = b0;
+                vis = vis0;
+                tvis = tvis0;
+                cycle_body(s);
+            }
+        } else {
+            cycle_body(s);
+        }
+        ch.read_back();
+        LAMG_HIP(hipStreamSynchronize(s));
+        ch.host();
     }
-    {
-        Timed tm(h, LAMG_KERNEL_REDUCE, 0, nk8, false);
-        run_relres(n, k, w.r.p, w.nb.p, w.partial.p, w.rel.p, s);
-    }
-    w.rel.download(w.h_rel, k, s);
-    LAMG_HIP(hipStreamSynchronize(s));
-    for (int c = 0; c < k; ++c) {
-        relres[c] = nb[c] > 0.0 ? w.h_rel[c] : 0.0;
-        acf[c] = acf_of(hist[c]);
-    }
-    hist0 = hist[0];
+    cycles = ch.cycles;
+    lamg_status st = ch.finish(relres, acf, hist0);
     if (gset) ++gset->solves;
     return st;
+}
+
+// Several solves in lockstep, each an FP32+IR chunk whose whole cycle runs in the coarse
+// tail (tail_level 0): per cycle, every running solve's pre-cycle launches, then ONE tail
+// launch holding every running solve's workgroups (one per column, each with its own
+// descriptors, copy jobs and visit counters), then every solve's post-cycle launches, one
+// synchronisation, and the host bookkeeping of each. Each solve computes exactly what it
+// computes alone. The launch's records, descriptors and copy jobs are gathered into
+// buffers of the first solve's workspace whenever the set of running solves changes.
+void solve_lockstep(std::vector<Chunk *> &chs, hipStream_t s) {
+    if (chs.empty()) return;
+    Workspace &g = chs[0]->h->ws;
+    Pool &gpool = g.arena ? *g.arena : *chs[0]->h->pool;
+    std::vector<int> running_prev;
+    int nwg = 0;
+    size_t lds = 0;
+    while (true) {
+        std::vector<int> running;
+        for (int i = 0; i < (int)chs.size(); ++i)
+            if (chs[i]->running()) running.push_back(i);
+        if (running.empty()) break;
+        if (running != running_prev) {
+            std::vector<char> recs;
+            int64_t ndesc = 0, njobs = 0;
+            std::vector<std::pair<const void *, size_t>> dsrc, jsrc;
+            nwg = 0;
+            lds = 0;
+            for (int i : running) {
+                Chunk &c = *chs[i];
+                Workspace &w = c.h->ws;
+                tail_wg_records<float>(w.plan32, 0, c.h->nlev, c.k, w.visits.p, recs, ndesc,
+                                       njobs, dsrc, jsrc);
+                nwg += c.k;
+                lds = std::max(lds, w.plan32.lds_bytes);
+            }
+            const int64_t db = (int64_t)ndesc * (int64_t)tail_desc_bytes<float>();
+            const int64_t jb = std::max<int64_t>(1, njobs * (int64_t)tail_copy_job_bytes());
+            if (g.grp_recs.n < (int64_t)recs.size()) g.grp_recs.alloc(gpool, (int64_t)recs.size());
+            if (g.grp_desc.n < db) g.grp_desc.alloc(gpool, db);
+            if (g.grp_jobs.n < jb) g.grp_jobs.alloc(gpool, jb);
+            g.grp_recs.upload(recs.data(), (int64_t)recs.size(), s);
+            auto gather = [&](std::vector<std::pair<const void *, size_t>> &src, char *dst) {
+                size_t off = 0;
+                for (size_t i = 0; i < src.size();) {  // contiguous pieces go as one copy
+                    const char *a = static_cast<const char *>(src[i].first);
+                    size_t len = src[i].second, j = i + 1;
+                    while (j < src.size() && static_cast<const char *>(src[j].first) == a + len) {
+                        len += src[j].second;
+                        ++j;
+                    }
+                    LAMG_HIP(hipMemcpyAsync(dst + off, a, len, hipMemcpyDeviceToDevice, s));
+                    off += len;
+                    i = j;
+                }
+            };
+            gather(dsrc, g.grp_desc.p);
+            gather(jsrc, g.grp_jobs.p);
+            running_prev = running;
+        }
+        for (int i : running) {
+            Chunk &c = *chs[i];
+            c.pre(s);
+            Cycle<float> &C = *c.c32;
+            const double sz = 4.0;
+            c.h->solve_bytes += tail_level_bytes<float>(C, 0);  // the grouped launch's share
+            if (c.k > 1) {
+                LevelVecs<float> &v0 = c.h->ws.lv32[0];
+                Timed tm(c.h, LAMG_KERNEL_VECTOR, 1, 4.0 * c.k * c.n * sz, false);
+                run_to_cols<float>(c.n, c.k, v0.x.p, v0.f.p, C.cx, C.cf, s);
+            }
+        }
+        run_tail_group<float>(g.grp_recs.p, g.grp_desc.p, g.grp_jobs.p, nwg, lds, s);
+        for (int i : running) {
+            Chunk &c = *chs[i];
+            if (c.k > 1) {
+                Timed tm(c.h, LAMG_KERNEL_VECTOR, 1, 2.0 * c.k * c.n * 4.0, false);
+                run_from_cols<float>(c.n, c.k, c.c32->cx, c.h->ws.lv32[0].x.p, s);
+            }
+            c.post(s);
+            c.read_back();
+        }
+        LAMG_HIP(hipStreamSynchronize(s));
+        for (int i : running) chs[i]->host();
+    }
 }
 
 template <class T>
@@ -1047,7 +1223,91 @@ lamg_status run_solve(lamg_handle *h, const double *b, int nrhs, double tol, int
     return st;
 }
 
-int plan_tail_level(const lamg_handle *h) { return tail_level(h, 1); }
+// Fills a request's lamg_solve_info from its chunk's results.
+static void fill_info(lamg_solve_info *info, int k, const std::vector<double> &rel,
+                      const std::vector<int32_t> &cyc, const std::vector<double> &acf,
+                      const std::vector<double> &hist0, int max_cycles, double bytes,
+                      double seconds) {
+    if (!info) return;
+    info->cycles = 0;
+    info->relres_max = 0.0;
+    info->acf_max = 0.0;
+    for (int c = 0; c < k; ++c) {
+        info->cycles = std::max(info->cycles, cyc[c]);
+        info->relres_max = std::max(info->relres_max, rel[c]);
+        info->acf_max = std::max(info->acf_max, acf[c]);
+        if (info->relres) info->relres[c] = rel[c];
+        if (info->col_cycles) info->col_cycles[c] = cyc[c];
+    }
+    info->history_len = (int32_t)std::min<size_t>(hist0.size(), (size_t)max_cycles + 1);
+    if (info->history)
+        for (int i = 0; i < info->history_len; ++i) info->history[i] = hist0[i];
+    info->graph_cycles = 0;
+    info->bytes = bytes;
+    info->seconds = seconds;
+}
+
+template <class F>
+static lamg_status status_of(F &&f) {
+    try {
+        return f();
+    } catch (const Error &e) {
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        return LAMG_OOM;
+    }
+}
+
+lamg_status run_solve_group(int count, lamg_handle *const *hs, const double *const *bs,
+                            const int32_t *nrhs, double tol, int max_cycles, lamg_precision prec,
+                            double *const *phis, lamg_solve_info *infos, lamg_status *statuses,
+                            hipStream_t stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (max_cycles <= 0) max_cycles = 300;
+    const bool fp32 = prec == LAMG_FP32_IR;
+    std::vector<int> grouped;
+    for (int r = 0; r < count; ++r) {
+        lamg_handle *h = hs[r];
+        h->stream = stream;
+        h->pool->set_stream(stream);
+        statuses[r] = LAMG_OK;
+        const bool can = fp32 && h->opt.build_fp32 && nrhs[r] <= kTailMaxCols &&
+                         tail_level(h, nrhs[r], true) == 0;
+        if (!can)  // solved on its own, in order, before the group
+            statuses[r] = status_of([&] {
+                return run_solve(h, bs[r], nrhs[r], tol, max_cycles, prec, phis[r],
+                                 infos ? &infos[r] : nullptr);
+            });
+        else
+            grouped.push_back(r);
+    }
+    std::vector<Chunk> ch(grouped.size());
+    std::vector<Chunk *> live;
+    for (size_t i = 0; i < grouped.size(); ++i) {
+        const int r = grouped[i];
+        hs[r]->solve_bytes = 0.0;
+        statuses[r] = status_of([&] {
+            ch[i].begin(hs[r], bs[r], nrhs[r], tol, max_cycles, true, phis[r]);
+            return LAMG_OK;
+        });
+        if (statuses[r] == LAMG_OK) live.push_back(&ch[i]);
+    }
+    solve_lockstep(live, stream);
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (size_t i = 0; i < grouped.size(); ++i) {
+        const int r = grouped[i];
+        if (statuses[r] != LAMG_OK) continue;
+        std::vector<double> rel, acf, hist0;
+        statuses[r] = ch[i].finish(rel, acf, hist0);
+        fill_info(infos ? &infos[r] : nullptr, ch[i].k, rel, ch[i].cycles, acf, hist0,
+                  max_cycles, hs[r]->solve_bytes, secs);
+    }
+    for (int r = 0; r < count; ++r)
+        if (statuses[r] != LAMG_OK) return statuses[r];
+    return LAMG_OK;
+}
+
+int plan_tail_level(const lamg_handle *h) { return tail_level(h, 1, true); }
 int plan_timed_level(const lamg_handle *h) { return timed_level(h, 1); }
 
 }  // namespace lamg

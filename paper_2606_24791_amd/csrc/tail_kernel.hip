@@ -82,6 +82,16 @@ struct CopyJob {
     uint32_t colb;   // top jobs: bytes per column (the level's rows x element size)
 };
 
+// One workgroup of a grouped launch (several requests' cycles in one launch): where its
+// descriptors and copy jobs start in the launch's combined arrays, its visit counters and
+// its plan (one column of one request).
+struct TailWG {
+    int64_t *visits;       // nlev visit counters of this workgroup
+    int32_t desc_off;      // first of its nlev descriptors in the launch's descriptor array
+    int32_t jobs_off;      // first of its njobs copy jobs in the launch's job array
+    int32_t njobs, l0, nlev, l_lds, l_x, pad;
+};
+
 struct TailArgs {
     const CopyJob *jobs;  // njobs per workgroup, workgroup after workgroup
     int64_t *visits;      // per workgroup and level, persistent within a solve
@@ -94,6 +104,14 @@ struct TailArgs {
 
 __device__ inline void bar() { __syncthreads(); }
 __device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// a pointer read from memory by every lane, made wave-uniform (scalar registers)
+template <class P>
+__device__ inline P *uni_ptr(P *p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return reinterpret_cast<P *>(((uint64_t)hi << 32) | lo);
+}
 
 template <bool LDS, class P>
 __device__ inline P *at(char *smem, P *p) {
@@ -795,20 +813,42 @@ __device__ __forceinline__ int visit(const TailArgs &A, const TailLvl<T> &DL, co
     return l - 1;
 }
 
-template <class T>
-__global__ void __launch_bounds__(TB) k_tail(TailArgs A, const TailLvl<T> *__restrict__ G0) {
+template <class T, bool GROUP>
+__global__ void __launch_bounds__(TB) k_tail(TailArgs A, const TailLvl<T> *__restrict__ G0,
+                                             const TailWG *__restrict__ wgs) {
     extern __shared__ __align__(16) char smem[];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    // this workgroup's column: its descriptors, copy jobs and visit counters
-    const int col = (int)blockIdx.x;
-    A.visits += (int64_t)col * A.nlev;
-    const TailLvl<T> *__restrict__ G = G0 + (int64_t)col * A.nlev;
-    const CopyJob *jobs = A.jobs + (int64_t)col * A.njobs;
-    const int l0 = A.l0, nlev = A.nlev, l_lds = A.l_lds, l_x = A.l_x;
+    // this workgroup's column: its descriptors, copy jobs and visit counters -- from its
+    // record in a grouped launch, else column blockIdx.x of the launch's one request
+    const TailLvl<T> *__restrict__ G;
+    const CopyJob *jobs;
+    int64_t *visits;
+    int njobs, l0, nlev, l_lds, l_x;
+    if constexpr (GROUP) {
+        const TailWG &W = wgs[blockIdx.x];
+        G = G0 + uni(W.desc_off);
+        jobs = A.jobs + uni(W.jobs_off);
+        visits = uni_ptr(W.visits);
+        njobs = uni(W.njobs);
+        l0 = uni(W.l0);
+        nlev = uni(W.nlev);
+        l_lds = uni(W.l_lds);
+        l_x = uni(W.l_x);
+    } else {
+        const int col = (int)blockIdx.x;
+        visits = A.visits + (int64_t)col * A.nlev;
+        G = G0 + (int64_t)col * A.nlev;
+        jobs = A.jobs + (int64_t)col * A.njobs;
+        njobs = A.njobs;
+        l0 = A.l0;
+        nlev = A.nlev;
+        l_lds = A.l_lds;
+        l_x = A.l_x;
+    }
     // bring the LDS-resident levels (and the top level's iterate and right-hand side)
     const void *top_x = nullptr;
-    for (int jb = 0; jb < A.njobs; ++jb) {
+    for (int jb = 0; jb < njobs; ++jb) {
         const CopyJob J = jobs[jb];
         const uint32_t bytes = J.top ? (uint32_t)A.k * J.colb : J.bytes;
         if (J.top == 1) top_x = J.src;
@@ -822,7 +862,7 @@ __global__ void __launch_bounds__(TB) k_tail(TailArgs A, const TailLvl<T> *__res
     }
     WaveState ws;
     ws.st = 0;
-    ws.cnt = (lane >= l0 && lane < nlev) ? (int)A.visits[lane] : 0;
+    ws.cnt = (lane >= l0 && lane < nlev) ? (int)visits[lane] : 0;
     int rbuf = 0;
     bar();
     int l = l0;
@@ -857,7 +897,7 @@ __global__ void __launch_bounds__(TB) k_tail(TailArgs A, const TailLvl<T> *__res
         T *gx = static_cast<T *>(const_cast<void *>(top_x));
         for (int t = tid; t < D.n * A.k; t += TB) gx[t] = lx[t];
     }
-    if (tid < 64 && lane >= l0 && lane < nlev) A.visits[lane] = ws.cnt;
+    if (tid < 64 && lane >= l0 && lane < nlev) visits[lane] = ws.cnt;
 }
 
 __global__ void k_fill_i64(int64_t *p, int64_t n) {
@@ -944,7 +984,7 @@ int tail_lds_plan(const std::vector<Level> &lev, int l0, int k, const void *host
     int max_lds = 0;
     LAMG_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     hipFuncAttributes fa;
-    LAMG_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_tail<T>)));
+    LAMG_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_tail<T, false>)));
     const int64_t budget = (int64_t)max_lds - (int64_t)fa.sharedSizeBytes - 256;
     auto level_bytes = [&](int l) {
         const Level &L = lev[l];
@@ -1053,8 +1093,9 @@ int tail_lds_plan(const std::vector<Level> &lev, int l0, int k, const void *host
     if (!jv.empty()) std::memcpy(jobs.data(), jv.data(), jobs.size());
     // the attribute is process-wide while plans of several handles coexist: always the whole
     // budget, so that no plan lowers it below what another handle's launches request
-    LAMG_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tail<T>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget));
+    for (const void *f : {reinterpret_cast<const void *>(&k_tail<T, false>),
+                          reinterpret_cast<const void *>(&k_tail<T, true>)})
+        LAMG_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget));
     return l_lds;
 }
 
@@ -1077,7 +1118,63 @@ void run_tail(const TailPlan &tp, int l0, int nlev, int k, int64_t *d_visits, hi
     A.l_x = tp.l_x;
     A.cpart_off = (uint32_t)(16 + ((2 * (int64_t)kRedQ * TW * 8 + 15) & ~(int64_t)15));
     const TailLvl<T> *G = static_cast<const TailLvl<T> *>(cols ? tp.lds_desc_cols : tp.lds_desc);
-    launch_kernel(k_tail<T>, dim3((unsigned)k), dim3(TB), (uint32_t)tp.lds_bytes, s, A, G);
+    launch_kernel(k_tail<T, false>, dim3((unsigned)k), dim3(TB), (uint32_t)tp.lds_bytes, s, A, G,
+                  (const TailWG *)nullptr);
+    LAMG_LAUNCH_CHECK();
+}
+
+size_t tail_wg_bytes() { return sizeof(TailWG); }
+
+// The records of one request's k columns (its workspace's plan and visit counters) for a
+// grouped launch: appended to `recs`, with that request's descriptors and copy jobs appended
+// to the launch's combined arrays as (device source, bytes) pieces to be gathered into them.
+template <class T>
+void tail_wg_records(const TailPlan &tp, int l0, int nlev, int k, int64_t *d_visits,
+                     std::vector<char> &recs, int64_t &ndesc, int64_t &njobs_total,
+                     std::vector<std::pair<const void *, size_t>> &desc_src,
+                     std::vector<std::pair<const void *, size_t>> &jobs_src) {
+    if (k < 1 || k > tp.kmax || k > kTailMaxCols || (k > 1 && !tp.lds_desc_cols))
+        throw Error(LAMG_INVALID_ARG, "coarse tail: unsupported column count");
+    const size_t db = sizeof(TailLvl<T>) * (size_t)nlev, jb = sizeof(CopyJob) * (size_t)tp.njobs;
+    for (int c = 0; c < k; ++c) {
+        TailWG W;
+        std::memset(&W, 0, sizeof(W));
+        W.visits = d_visits + (int64_t)c * nlev;
+        W.desc_off = (int32_t)ndesc;
+        W.jobs_off = (int32_t)njobs_total;
+        W.njobs = tp.njobs;
+        W.l0 = l0;
+        W.nlev = nlev;
+        W.l_lds = tp.l_lds;
+        W.l_x = tp.l_x;
+        const char *b = reinterpret_cast<const char *>(&W);
+        recs.insert(recs.end(), b, b + sizeof(W));
+        const char *dsrc = static_cast<const char *>(k > 1 ? tp.lds_desc_cols : tp.lds_desc) +
+                           (k > 1 ? (int64_t)c * db : 0);
+        const char *jsrc = static_cast<const char *>(k > 1 ? tp.jobs_cols : tp.jobs) +
+                           (k > 1 ? (int64_t)c * jb : 0);
+        desc_src.emplace_back(dsrc, db);
+        if (jb) jobs_src.emplace_back(jsrc, jb);
+        ndesc += nlev;
+        njobs_total += tp.njobs;
+    }
+}
+
+// One launch running the workgroups of `nwg` records (device array `wgs`) with `lds_bytes`
+// of dynamic LDS (the largest plan among them).
+template <class T>
+void run_tail_group(const void *wgs, const void *descs, const void *jobs, int nwg,
+                    size_t lds_bytes, hipStream_t s) {
+    if (nwg <= 0) return;
+    TailArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.k = 1;
+    A.lkp = 0;
+    A.red_off = 16;
+    A.cpart_off = (uint32_t)(16 + ((2 * (int64_t)kRedQ * TW * 8 + 15) & ~(int64_t)15));
+    A.jobs = static_cast<const CopyJob *>(jobs);
+    launch_kernel(k_tail<T, true>, dim3((unsigned)nwg), dim3(TB), (uint32_t)lds_bytes, s, A,
+                  static_cast<const TailLvl<T> *>(descs), static_cast<const TailWG *>(wgs));
     LAMG_LAUNCH_CHECK();
 }
 
@@ -1136,6 +1233,15 @@ template void tail_fill_desc<float>(void *, int, const Level &, const SolveOp &,
                                     float *, float *, float *, float *);
 template void run_tail<double>(const TailPlan &, int, int, int, int64_t *, hipStream_t);
 template void run_tail<float>(const TailPlan &, int, int, int, int64_t *, hipStream_t);
+#define LAMG_TAIL_GROUP_INST(T)                                                              \
+    template void tail_wg_records<T>(const TailPlan &, int, int, int, int64_t *,               \
+                                     std::vector<char> &, int64_t &, int64_t &,                \
+                                     std::vector<std::pair<const void *, size_t>> &,           \
+                                     std::vector<std::pair<const void *, size_t>> &);          \
+    template void run_tail_group<T>(const void *, const void *, const void *, int, size_t,     \
+                                    hipStream_t);
+LAMG_TAIL_GROUP_INST(double)
+LAMG_TAIL_GROUP_INST(float)
 template void run_to_cols<double>(int64_t, int, const double *, const double *, double *,
                                   double *, hipStream_t);
 template void run_to_cols<float>(int64_t, int, const float *, const float *, float *, float *,

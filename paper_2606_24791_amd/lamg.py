@@ -36,7 +36,8 @@ class lamg_options(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("n_direct", C.c_int32), ("enable_veto", C.c_int32),
                 ("enable_caliber2", C.c_int32), ("kappa", C.c_int32), ("build_fp32", C.c_int32),
                 ("keep_setup_data", C.c_int32), ("tail_rows", C.c_int32),
-                ("elimination", C.c_int32), ("smoother", C.c_int32), ("graphs", C.c_int32)]
+                ("elimination", C.c_int32), ("smoother", C.c_int32), ("graphs", C.c_int32),
+                ("tail_finest", C.c_int32)]
 
 
 class lamg_hier_info(C.Structure):
@@ -82,6 +83,11 @@ _lib.lamg_solve.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_i
 _lib.lamg_solve.restype = C.c_int
 _lib.lamg_solve_noalloc.argtypes = _lib.lamg_solve.argtypes
 _lib.lamg_solve_noalloc.restype = C.c_int
+_lib.lamg_solve_group.argtypes = [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                  C.POINTER(C.c_int32), C.c_double, C.c_int32, C.c_int,
+                                  C.POINTER(C.c_void_p), C.c_void_p, C.POINTER(C.c_int),
+                                  C.c_void_p]
+_lib.lamg_solve_group.restype = C.c_int
 _lib.lamg_destroy.argtypes = [C.c_void_p]
 _lib.lamg_destroy.restype = None
 _lib.lamg_hierarchy_info.argtypes = [C.c_void_p, C.POINTER(lamg_hier_info)]
@@ -284,6 +290,52 @@ def _solve(fn, where, h, b, phi, tol, max_cycles, precision, stream, history, ch
                graph_cycles=int(info.graph_cycles), bytes=float(info.bytes))
     if hist is not None:
         out["history"] = hist[: info.history_len].copy()
+    return out
+
+
+def lamg_solve_group(handles, bs, phis, tol: float = 1e-8, max_cycles: int = 300,
+                     precision: int = FP32_IR, stream=None, check: bool = True):
+    """Solves several requests together (lamg_solve_group): handles[r] with right-hand
+    sides bs[r] into phis[r] (float64 CUDA tensors of shape (k_r, n_r) or (n_r,)). Returns
+    one statistics dict per request, with its status."""
+    import torch
+
+    R = len(handles)
+    if not (len(bs) == len(phis) == R):
+        raise ValueError("one b and one phi per handle")
+    hp = (C.c_void_p * R)()
+    bp = (C.c_void_p * R)()
+    pp = (C.c_void_p * R)()
+    kk = (C.c_int32 * R)()
+    rels, cycs = [], []
+    infos = (lamg_solve_info * R)()
+    for r, (h, b, phi) in enumerate(zip(handles, bs, phis)):
+        if b.dtype != torch.float64 or phi.dtype != torch.float64 or not b.is_cuda \
+                or not phi.is_cuda or not b.is_contiguous() or not phi.is_contiguous() \
+                or b.shape != phi.shape:
+            raise TypeError("b and phi must be contiguous float64 CUDA tensors of equal shape")
+        k = 1 if b.dim() == 1 else int(b.shape[0])
+        if int(b.shape[-1]) != h.n:
+            raise ValueError(f"request {r}: right-hand side length {b.shape[-1]} != {h.n}")
+        hp[r], bp[r], pp[r], kk[r] = h.ptr, b.data_ptr(), phi.data_ptr(), k
+        rels.append(np.zeros(k))
+        cycs.append(np.zeros(k, np.int32))
+        infos[r].relres = rels[r].ctypes.data
+        infos[r].col_cycles = cycs[r].ctypes.data
+    sts = (C.c_int * R)()
+    st = _lib.lamg_solve_group(R, hp, bp, kk, float(tol), int(max_cycles), int(precision), pp,
+                               infos, sts, _stream_ptr(stream))
+    if st == INVALID_ARG and all(s == 0 for s in sts):
+        raise LamgError(st, "lamg_solve_group")
+    out = []
+    for r in range(R):
+        if check and sts[r] not in (OK, NOT_CONVERGED):
+            raise LamgError(sts[r], f"lamg_solve_group request {r}")
+        i = infos[r]
+        out.append(dict(status=int(sts[r]), converged=(sts[r] == OK), cycles=int(i.cycles),
+                        relres_max=float(i.relres_max), acf_max=float(i.acf_max),
+                        seconds=float(i.seconds), relres=rels[r], col_cycles=cycs[r],
+                        bytes=float(i.bytes)))
     return out
 
 
