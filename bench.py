@@ -130,7 +130,10 @@ def main() -> int:
     ap.add_argument("--no-elimination", action="store_true",
                     help="aggregation-only hierarchy (no low-degree elimination levels)")
     ap.add_argument("--evented-steps", type=int, default=1,
-                    help="solves per precision in the evented (per-launch timed) region")
+                    help="solves per precision in the evented (per-launch timed) region "
+                         "(0: none, no roofline or kernel table)")
+    ap.add_argument("--fp32ir-only", action="store_true",
+                    help="time only the FP32+IR solves (for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the solver has no multi-GPU path); got --gpus "
@@ -204,12 +207,17 @@ def main() -> int:
         return wall, lat, stats, kt
 
     results = {}
-    for name, prec in (("fp32ir", B.FP32_IR), ("fp64", B.FP64)):
+    precs = (("fp32ir", B.FP32_IR),) if args.fp32ir_only else (("fp32ir", B.FP32_IR),
+                                                                  ("fp64", B.FP64))
+    for name, prec in precs:
         phi = torch.empty_like(b)
         for _ in range(args.warmup):
             B.lamg_solve(h, b, phi, tol=args.tol, precision=prec, stream=stream)
         wall, lat, stats, _ = run_steps(prec, phi, args.steps, False)
-        wall_ev, _, _, kt = run_steps(prec, phi, max(1, args.evented_steps), True)
+        if args.evented_steps > 0:
+            wall_ev, _, _, kt = run_steps(prec, phi, args.evented_steps, True)
+        else:
+            wall_ev, kt = 0.0, None
         ms = 1e3 * wall / args.steps
         results[name] = dict(ms=ms, value=g.nnz_laplacian * k / (wall / args.steps),
                              p50_ms=1e3 * percentile(lat, 50), p99_ms=1e3 * percentile(lat, 99),
@@ -217,6 +225,10 @@ def main() -> int:
                              converged=bool(stats["converged"]), phi=phi.cpu().numpy(),
                              graph_cycles=stats["graph_cycles"], bytes=stats["bytes"], kt=kt,
                              ev_steps=max(1, args.evented_steps), wall_ev=wall_ev)
+        if kt is None:
+            log(f"{name}: {ms:.3f} ms/solve, {results[name]['value']:.3e} nnz*RHS/s, "
+                f"cycles={stats['cycles']}")
+            continue
         log(f"{name}: {ms:.3f} ms/solve, {results[name]['value']:.3e} nnz*RHS/s, "
             f"cycles={stats['cycles']} relres={stats['relres_max']:.2e}, "
             f"{stats['bytes'] / 1e9:.2f} GB algorithmic per solve "
@@ -226,6 +238,19 @@ def main() -> int:
     # per-kind in-situ figures of the FP32+IR evented region; the dominant kind by time
     r32 = results["fp32ir"]
     kinds = {}
+    if r32["kt"] is None:  # a hardware-counter run: the timings only
+        if args.copy_probe_mb > 0:
+            nel = args.copy_probe_mb * (1 << 20) // 4
+            src = torch.ones(nel, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            log(f"copy probe: {nel * 4} bytes read, {nel * 4} bytes written")
+        print(json.dumps(dict(ms_per_step=r32["ms"], bytes_per_solve=r32["bytes"],
+                              note="timings only (no evented region)")), flush=True)
+        h.close()
+        return 0
     for (kern, prec), t in r32["kt"].items():
         key = f"{B.KERNEL_NAMES[kern]}_{'fp32' if prec == B.FP32_IR else 'fp64'}"
         kinds[key] = dict(launches=t["launches"] // r32["ev_steps"],

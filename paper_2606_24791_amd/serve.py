@@ -72,10 +72,15 @@ class Server:
     def __init__(self, graphs: dict, hbm_budget: float = 200e9, slots: int = 4,
                  precision: int = B.FP32_IR, tol: float = 1e-8, max_columns: int = 32,
                  use_torch_allocator: bool = True, estimate=None, smoother: int = 0,
-                 hip_graphs: bool = False):
+                 hip_graphs: bool = False, group: int = 0):
         self.graphs = graphs
         self.smoother = smoother  # setup option: 1 = Chebyshev on levels with many colours
         self.hip_graphs = hip_graphs  # setup option: replay repeated cycles as HIP graphs
+        # up to this many batches on different graphs per lamg_solve_group call (0/1: none);
+        # hierarchies are then built to run the whole FP32 cycle of small graphs in the tail
+        self.group = group
+        self.groups = 0  # lamg_solve_group calls made
+        self.grouped_batches = 0
         # device bytes charged for a graph's setup before its hierarchy exists
         self.estimate = estimate or hierarchy_estimate
         self.budget = float(hbm_budget)
@@ -180,6 +185,48 @@ class Server:
             return batch, cols, extra
         return None
 
+    def _take_graph(self, gid: str, first: Request):
+        """Called with the lock held: first plus every other waiting request for gid (column
+        limit permitting), if the batch fits the budget; removes them from the queue and
+        marks gid busy. Returns (batch, cols, extra) or None."""
+        batch, cols = [first], first.b.shape[0]
+        for r in list(self.queue):
+            if r is not first and r.graph_id == gid and cols + r.b.shape[0] <= self.max_columns:
+                batch.append(r)
+                cols += r.b.shape[0]
+        ok, extra = self._admit(gid, cols)
+        if not ok:
+            return None
+        for r in batch:
+            self.queue.remove(r)
+        self.busy_graphs.add(gid)
+        self.reserved += extra
+        return batch, cols, extra
+
+    def _next_group(self, nb):
+        """Called with the lock held, after _next_batch chose nb: with grouping on and nb's
+        graph cached and groupable, more batches for other idle, cached, groupable graphs
+        (oldest request first) to be solved in the same lamg_solve_group call."""
+        if self.group <= 1:
+            return []
+        e = self.cache.get(nb[0][0].graph_id)
+        if e is None or not e.get("groupable"):
+            return []
+        extras = []
+        for req in list(self.queue):
+            if len(extras) + 1 >= self.group:
+                break
+            if req not in self.queue or req.graph_id in self.busy_graphs:
+                continue
+            e2 = self.cache.get(req.graph_id)
+            if e2 is None or not e2.get("groupable") or req.b.shape[0] > self.max_columns:
+                continue
+            got = self._take_graph(req.graph_id, req)
+            if got is None:
+                break
+            extras.append(got)
+        return extras
+
     def _reject(self, req: Request, status: int = B.OOM):
         """Called with the lock held: answers req with an error status and no solution."""
         now = time.perf_counter() - self.t0
@@ -198,8 +245,12 @@ class Server:
                         return
                     nb = self._next_batch()
                     if nb is not None:
+                        extras = self._next_group(nb)
                         break
                     self.lock.wait(0.05)
+            if extras:
+                self._run_group([nb] + extras, stream)
+                continue
             batch, cols, extra = nb
             gid = batch[0].graph_id
             resv = {"extra": extra}  # bytes this batch holds in `reserved`
@@ -226,9 +277,57 @@ class Server:
             self.cache.pop(victim)["handle"].close()
             self.evictions += 1
 
-    def _run_batch(self, batch, cols, gid, stream, resv):
+    def _build(self, gid: str, cols: int, stream, resv) -> dict:
+        """Sets up gid's hierarchy on `stream` and caches it. resv["extra"] holds the bytes
+        reserved for it (the estimate); on return it holds the workspace estimate of a
+        cols-column batch instead."""
         g = self.graphs[gid]
         fp32 = self.precision == B.FP32_IR
+        h = B.lamg_setup(g, B.lamg_default_options(
+            smoother=self.smoother, graphs=int(self.hip_graphs),
+            tail_finest=65535 if self.group > 1 else 0), stream=stream)
+        info = B.lamg_hierarchy_info(h)
+        entry = dict(handle=h, levels=info["n"], bytes=float(info["bytes_device"]), ws=0.0,
+                     groupable=info["tail_level"] == 0)
+        ws_est = float(workspace_bytes(info["n"], cols, fp32)) if cols else 0.0
+        with self.lock:
+            # the setup's high-water mark beside everything else resident
+            others = self._resident() - resv["extra"]
+            self.max_resident = max(self.max_resident, others + info["bytes_peak"])
+            # the estimate is replaced by the measured hierarchy + the workspace
+            self.reserved += ws_est - resv["extra"]
+            resv["extra"] = ws_est
+            self.cache[gid] = entry
+            self.setups += 1
+            self._make_room(gid)
+        return entry
+
+    def preload(self, gids) -> int:
+        """Builds the hierarchies of gids (in that order) before a stream starts, so that
+        their first requests are cache hits; stops at the first one the budget cannot hold.
+        Returns how many were built."""
+        stream = torch.cuda.current_stream()
+        built = 0
+        for gid in gids:
+            with self.lock:
+                if gid in self.cache:
+                    continue
+                ok, extra = self._admit(gid, 0)
+                if not ok:
+                    break
+                self.reserved += extra
+            resv = {"extra": extra}
+            try:
+                self._build(gid, 0, stream, resv)
+                built += 1
+            finally:
+                with self.lock:
+                    self.reserved -= resv["extra"]
+        stream.synchronize()
+        return built
+
+    def _run_batch(self, batch, cols, gid, stream, resv):
+        g = self.graphs[gid]
         with torch.cuda.stream(stream):
             with self.lock:
                 entry = self.cache.get(gid)
@@ -236,22 +335,7 @@ class Server:
                     self.cache.move_to_end(gid)
             hit = entry is not None
             if not hit:
-                h = B.lamg_setup(g, B.lamg_default_options(smoother=self.smoother,
-                                                           graphs=int(self.hip_graphs)),
-                                 stream=stream)
-                info = B.lamg_hierarchy_info(h)
-                entry = dict(handle=h, levels=info["n"], bytes=float(info["bytes_device"]), ws=0.0)
-                ws_est = float(workspace_bytes(info["n"], cols, fp32))
-                with self.lock:
-                    # the setup's high-water mark beside everything else resident
-                    others = self._resident() - resv["extra"]
-                    self.max_resident = max(self.max_resident, others + info["bytes_peak"])
-                    # the estimate is replaced by the measured hierarchy + the workspace
-                    self.reserved += ws_est - resv["extra"]
-                    resv["extra"] = ws_est
-                    self.cache[gid] = entry
-                    self.setups += 1
-                    self._make_room(gid)
+                entry = self._build(gid, cols, stream, resv)
             bh = np.concatenate([r.b for r in batch], axis=0)
             b = torch.tensor(bh, device="cuda")
             phi = torch.empty_like(b)
@@ -266,24 +350,68 @@ class Server:
                 print(f"[serve] batch {gid} n={g.n} cols={cols} {'hit' if hit else 'miss'} "
                       f"solve {1e3 * (time.perf_counter() - ts):.1f} ms cycles {st['cycles']}",
                       file=sys.stderr, flush=True)
-            info = B.lamg_hierarchy_info(entry["handle"])
-            now = time.perf_counter() - self.t0
+            self._answer(batch, cols, gid, entry, hit, st, ph, resv)
+
+    def _answer(self, batch, cols, gid, entry, hit, st, ph, resv):
+        """The results of one solved batch: workspace accounting, one Result per request."""
+        fp32 = self.precision == B.FP32_IR
+        info = B.lamg_hierarchy_info(entry["handle"])
+        now = time.perf_counter() - self.t0
+        with self.lock:
+            # the entry now holds its real workspace: drop the batch's reservation
+            entry["bytes"] = float(info["bytes_device"])
+            entry["ws"] = max(entry["ws"], float(workspace_bytes(entry["levels"], cols, fp32)))
+            self.max_resident = max(self.max_resident, self._resident() - resv["extra"])
+            self.reserved -= resv["extra"]
+            resv["extra"] = 0.0
+            self._make_room(gid)
+            c0 = 0
+            for r in batch:
+                k = r.b.shape[0]
+                self.results.append(Result(
+                    r.rid, gid, ph[c0:c0 + k], st["relres"][c0:c0 + k].copy(),
+                    st["col_cycles"][c0:c0 + k].copy(), now - r.arrival, hit, cols,
+                    st["status"]))
+                c0 += k
+
+    def _run_group(self, nbs, stream):
+        """Solves several batches on cached, groupable graphs with one lamg_solve_group call
+        (their coarse-tail work shares one launch per cycle)."""
+        entries, bs, phis = [], [], []
+        with self.lock:
+            for batch, _, _ in nbs:
+                gid = batch[0].graph_id
+                self.cache.move_to_end(gid)
+                entries.append(self.cache[gid])
+        try:
+            with torch.cuda.stream(stream):
+                for (batch, _, _) in nbs:
+                    b = torch.tensor(np.concatenate([r.b for r in batch], axis=0), device="cuda")
+                    bs.append(b)
+                    phis.append(torch.empty_like(b))
+                sts = B.lamg_solve_group([e["handle"] for e in entries], bs, phis, tol=self.tol,
+                                         precision=self.precision, stream=stream, check=False)
+                phs = [p.cpu().numpy() for p in phis]
+                stream.synchronize()
             with self.lock:
-                # the entry now holds its real workspace: drop the batch's reservation
-                entry["bytes"] = float(info["bytes_device"])
-                entry["ws"] = max(entry["ws"], float(workspace_bytes(entry["levels"], cols, fp32)))
-                self.max_resident = max(self.max_resident, self._resident() - resv["extra"])
-                self.reserved -= resv["extra"]
-                resv["extra"] = 0.0
-                self._make_room(gid)
-                c0 = 0
-                for r in batch:
-                    k = r.b.shape[0]
-                    self.results.append(Result(
-                        r.rid, gid, ph[c0:c0 + k], st["relres"][c0:c0 + k].copy(),
-                        st["col_cycles"][c0:c0 + k].copy(), now - r.arrival, hit, cols,
-                        st["status"]))
-                    c0 += k
+                self.groups += 1
+                self.grouped_batches += len(nbs)
+            for (batch, cols, extra), e, st, ph in zip(nbs, entries, sts, phs):
+                resv = {"extra": extra}
+                if st["status"] in (B.OK, B.NOT_CONVERGED):
+                    self._answer(batch, cols, batch[0].graph_id, e, True, st, ph, resv)
+                else:
+                    with self.lock:
+                        for r in batch:
+                            self._reject(r, st["status"])
+                with self.lock:
+                    self.reserved -= resv["extra"]
+                    resv["extra"] = 0.0
+        finally:
+            with self.lock:
+                for batch, _, _ in nbs:
+                    self.busy_graphs.discard(batch[0].graph_id)
+                self.lock.notify_all()
 
     # --- driving a stream --------------------------------------------------------------
     def run(self, requests: list[Request], stall_timeout: float = 120.0) -> dict:
@@ -343,6 +471,7 @@ class Server:
                     miss_p50_ms=pct(lat[~hit], 50) * 1e3 if (~hit).any() else None,
                     miss_p99_ms=pct(lat[~hit], 99) * 1e3 if (~hit).any() else None,
                     setups=self.setups, evictions=self.evictions, overshoots=self.overshoots,
+                    groups=self.groups, grouped_batches=self.grouped_batches,
                     mean_batch_columns=float(np.mean([r.batch_columns for r in ok]))
                     if ok else None,
                     max_relres=float(max(r.relres.max() for r in ok)) if ok else None,
@@ -453,6 +582,11 @@ def main(argv=None) -> int:
                     help="0: multicolour Gauss-Seidel; 1: Chebyshev on levels with > 32 colours")
     ap.add_argument("--hip-graphs", action="store_true",
                     help="replay each cycle of repeated (precision, columns) solves as a HIP graph")
+    ap.add_argument("--group", type=int, default=0,
+                    help="solve up to this many batches on different small graphs per "
+                         "lamg_solve_group call (0: every batch on its own)")
+    ap.add_argument("--preload", action="store_true",
+                    help="build every graph's hierarchy before each stream (a warm cache)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--seed", type=int, default=0)
     a = ap.parse_args(argv)
@@ -465,14 +599,17 @@ def main(argv=None) -> int:
     def one(rate, tag):
         reqs = request_stream(graphs, a.requests, rate, a.kmax, a.seed, shared_rhs=True)
         srv = Server(graphs, hbm_budget=a.budget_gb * 1e9, slots=a.slots, smoother=a.smoother,
-                     hip_graphs=a.hip_graphs)
+                     hip_graphs=a.hip_graphs, group=a.group)
         srv.progress_every = max(1, a.requests // 10)
         srv.log_batches = a.log_batches
+        if a.preload:
+            srv.preload(list(graphs))
+            srv.setups = 0  # count only the setups the stream itself needed
         out = srv.run(reqs)
         srv.close()
         out.update(run=tag, offered_rate=rate if rate > 0 else None, requests_total=a.requests,
                    graphs=len(graphs), slots=a.slots, kmax=a.kmax, smoother=a.smoother,
-                   hip_graphs=a.hip_graphs)
+                   hip_graphs=a.hip_graphs, group=a.group, preload=a.preload)
         out["answered_per_s"] = out["answered"] / out["wall_s"]
         print(json.dumps(out), flush=True)
         log(f"{tag}: {out['answered_per_s']:.2f} req/s p50 {out['p50_ms']:.1f} ms "

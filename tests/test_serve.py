@@ -39,6 +39,33 @@ def test_batching_coalesces_same_graph_and_respects_columns():
     assert [r.rid for r in srv.queue] == [3]
 
 
+def test_grouping_takes_other_idle_groupable_graphs():
+    """With grouping on, the batch a slot takes is joined by batches for other idle graphs
+    whose hierarchies are cached and run their whole cycle in the coarse tail (oldest
+    request first, same-graph requests coalesced), up to the group size."""
+    from paper_2606_24791_amd import serve as S
+
+    graphs = {g: I.grid2d(10 + i, 10, name=g) for i, g in enumerate("abcd")}
+    srv = S.Server(graphs, hbm_budget=1e12, slots=2, use_torch_allocator=False, group=3)
+    for gid in "abcd":
+        srv.cache[gid] = dict(handle=_FakeHandle(), levels=[graphs[gid].n], bytes=1.0, ws=0.0,
+                              groupable=gid != "c")
+    for rid, (gid, k) in enumerate([("a", 2), ("b", 1), ("c", 1), ("d", 3), ("b", 2), ("a", 1)]):
+        srv.submit(S.Request(rid, gid, np.zeros((k, graphs[gid].n))))
+    with srv.lock:
+        nb = srv._next_batch()
+        extras = srv._next_group(nb)
+    assert [r.rid for r in nb[0]] == [0, 5]
+    assert [[r.rid for r in e[0]] for e in extras] == [[1, 4], [3]]  # "c" is not groupable
+    assert srv.busy_graphs == {"a", "b", "d"} and [r.rid for r in srv.queue] == [2]
+    srv2 = S.Server(graphs, hbm_budget=1e12, slots=2, use_torch_allocator=False, group=0)
+    srv2.cache.update(srv.cache)
+    srv2.submit(S.Request(0, "a", np.zeros((1, graphs["a"].n))))
+    srv2.submit(S.Request(1, "b", np.zeros((1, graphs["b"].n))))
+    with srv2.lock:
+        assert srv2._next_group(srv2._next_batch()) == []  # grouping off
+
+
 def test_request_wider_than_a_batch_runs_alone():
     from paper_2606_24791_amd import serve as S
 
@@ -140,6 +167,55 @@ def test_stream_results_equal_solves_alone():
     assert out["evictions"] > 0 and out["overshoots"] == 0
     assert out["max_resident_bytes"] <= budget
     assert out["p50_ms"] is not None and out["p99_ms"] >= out["p50_ms"]
+    for req in reqs:
+        mix = results[req.rid].phi
+        for c in range(mix.shape[0]):
+            ref = alone[req.rid][c]
+            err = np.linalg.norm(mix[c] - ref) / np.linalg.norm(ref)
+            assert err <= 1e-6, (req.rid, c, err)
+
+
+@pytest.mark.gpu
+def test_grouped_stream_results_equal_solves_alone():
+    """Grouping on, cache preloaded: batches on different small graphs share
+    lamg_solve_group calls; every result still equals the request solved alone."""
+    import sys
+
+    import torch
+
+    from paper_2606_24791_amd import lamg as B
+    from paper_2606_24791_amd import serve as S
+
+    assert torch.cuda.is_available()
+    graphs, reqs = S.synthetic_stream(36, rate=0.0, n_graphs=8, nmin=1000, nmax=5000, kmax=4,
+                                      seed=5)
+    alone = {}
+    opts = B.lamg_default_options(tail_finest=65535)
+    for gid, g in graphs.items():
+        mine = [r for r in reqs if r.graph_id == gid]
+        if not mine:
+            continue
+        print(f"[case] alone {gid} n={g.n}", flush=True)
+        h = B.lamg_setup(g, opts)
+        for req in mine:
+            b = torch.tensor(req.b, device="cuda")
+            phi = torch.empty_like(b)
+            B.lamg_solve(h, b, phi, precision=B.FP32_IR)
+            alone[req.rid] = phi.cpu().numpy()
+        h.close()
+    srv = S.Server(graphs, hbm_budget=200e9, slots=2, group=6)
+    # a warm cache: only cached hierarchies are grouped, and a cold stream arriving at once
+    # would meet every graph uncached
+    assert srv.preload(list(graphs)) == len(graphs)
+    ngroupable = sum(e["groupable"] for e in srv.cache.values())
+    print(f"[case] grouped stream: {ngroupable} of {len(graphs)} graphs groupable", flush=True)
+    assert ngroupable >= 2
+    out = srv.run(reqs, stall_timeout=60.0)
+    results = {r.rid: r for r in srv.results}
+    srv.close()
+    print(out, file=sys.stderr, flush=True)
+    assert out["requests"] == len(reqs) and out["rejected"] == 0 and out["max_relres"] <= 1e-8
+    assert out["groups"] > 0 and out["grouped_batches"] >= 2 * out["groups"]
     for req in reqs:
         mix = results[req.rid].phi
         for c in range(mix.shape[0]):
