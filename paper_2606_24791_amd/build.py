@@ -35,8 +35,32 @@ SOURCES = {
 }
 
 
-def _compile(src: str, flags: list[str]) -> Path:
+def _deps(path: Path, seen: set) -> set:
+    """The file and the local headers it includes, transitively."""
+    if path in seen or not path.exists():
+        return seen
+    seen.add(path)
+    for line in path.read_text().splitlines():
+        line = line.strip()
+        if line.startswith("#include \""):
+            name = line.split('"')[1]
+            for d in (CSRC, INCLUDE):
+                _deps(d / name, seen)
+    return seen
+
+
+def _stale(src: str, obj: Path) -> bool:
+    """Whether obj is older than its source or a local header it includes."""
+    if not obj.exists():
+        return True
+    t = obj.stat().st_mtime
+    return any(d.stat().st_mtime > t for d in _deps(CSRC / src, set()))
+
+
+def _compile(src: str, flags: list[str], changed_only: bool = False) -> Path:
     obj = BUILD / (src + ".o")
+    if changed_only and not _stale(src, obj):
+        return obj
     cmd = [HIPCC, *COMMON, *flags, "-c", str(CSRC / src), "-o", str(obj)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -44,11 +68,12 @@ def _compile(src: str, flags: list[str]) -> Path:
     return obj
 
 
-def build(verbose: bool = False) -> Path:
-    """Compile every source and link liblamg.so in the package directory."""
+def build(verbose: bool = False, changed_only: bool = False) -> Path:
+    """Compile every source (with changed_only: those whose object is older than the source
+    or a header) and link liblamg.so in the package directory."""
     BUILD.mkdir(exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(lambda kv: _compile(*kv), SOURCES.items()))
+        objs = list(ex.map(lambda kv: _compile(*kv, changed_only), SOURCES.items()))
     tmp = LIB.with_suffix(f".so.tmp{os.getpid()}")
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", str(tmp), *map(str, objs)]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -61,4 +86,4 @@ def build(verbose: bool = False) -> Path:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, changed_only="--changed" in sys.argv)

@@ -89,19 +89,31 @@ __device__ __forceinline__ void csr_short_rows(int64_t grp, int64_t r0, int64_t 
         e = rp[row + 1];
         if (skip_long > 0 && e - b > skip_long) live = false;
     }
-    T acc = T(0);
-    if (live && col < k) acc = row_dot<T, 8>(ci, v, xin, b + sub, e, lpr, k, col);
+    const int64_t o = row * k + col;
+    // the row's own operands are loaded before its entries, so their latency overlaps the
+    // gathers' instead of following them
+    T acc = T(0), fo = T(0), dr = T(0), xo = T(0), di = T(0), oo = T(0);
+    if (live && col < k) {
+        if (OP != OP_SPMV) {
+            fo = f[o];
+            dr = dd[row];
+        }
+        if (OP == OP_RESID || OP == OP_CHEB) xo = xin[o];
+        if (OP == OP_CHEB) {
+            di = ch.dinv[row];
+            if (ch.c1 != T(0)) oo = out[o];
+        }
+        acc = row_dot<T, 8>(ci, v, xin, b + sub, e, lpr, k, col);
+    }
     if (G > (1 << lkp)) acc = group_sum(acc, lkp, G);
     if (!live || col >= k || sub != 0) return;
-    const int64_t o = row * k + col;
     if (OP == OP_GS) {
-        out[o] = (f[o] - acc) * dd[row];
+        out[o] = (fo - acc) * dr;
     } else if (OP == OP_CHEB) {
-        const T res = (f[o] - dd[row] * xin[o] - acc) * ch.dinv[row];
-        out[o] = ch.c1 == T(0) ? ch.c2 * res : ch.c1 * out[o] + ch.c2 * res;
+        const T res = (fo - dr * xo - acc) * di;
+        out[o] = ch.c1 == T(0) ? ch.c2 * res : ch.c1 * oo + ch.c2 * res;
     } else if (OP == OP_RESID) {
-        const T xo = xin[o];
-        const T res = f[o] - dd[row] * xo - acc;
+        const T res = fo - dr * xo - acc;
         out[o] = res;
         if (sx) {
             sx[o] = xo;
@@ -136,24 +148,34 @@ __device__ __forceinline__ void csr_long_row(int64_t row, const int32_t *__restr
     const int col = tid & (kp - 1);
     const int sub = tid >> lkp;
     const int32_t b = rp[row], e = rp[row + 1];
-    T acc = T(0);
+    const int64_t o = row * k + tid;
+    T acc = T(0), fo = T(0), dr = T(0), xo = T(0), di = T(0), oo = T(0);
+    if (tid < k) {  // the row's own operands, loaded before its entries
+        if (OP != OP_SPMV) {
+            fo = f[o];
+            dr = dd[row];
+        }
+        if (OP == OP_RESID || OP == OP_CHEB) xo = xin[o];
+        if (OP == OP_CHEB) {
+            di = ch.dinv[row];
+            if (ch.c1 != T(0)) oo = out[o];
+        }
+    }
     if (col < k) acc = row_dot<T, 8>(ci, v, xin, b + sub, e, NT >> lkp, k, col);
-    for (int o = kp; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
+    for (int o2 = kp; o2 < 64; o2 <<= 1) acc += __shfl_xor(acc, o2, 64);
     const int wave = tid >> 6, lane = tid & 63;
     if (lane < kp) part[wave][lane] = acc;
     __syncthreads();
     if (tid >= k) return;
     T sum = T(0);
     for (int w = 0; w < kWaves; ++w) sum += part[w][tid];
-    const int64_t o = row * k + tid;
     if (OP == OP_GS) {
-        out[o] = (f[o] - sum) * dd[row];
+        out[o] = (fo - sum) * dr;
     } else if (OP == OP_CHEB) {
-        const T res = (f[o] - dd[row] * xin[o] - sum) * ch.dinv[row];
-        out[o] = ch.c1 == T(0) ? ch.c2 * res : ch.c1 * out[o] + ch.c2 * res;
+        const T res = (fo - dr * xo - sum) * di;
+        out[o] = ch.c1 == T(0) ? ch.c2 * res : ch.c1 * oo + ch.c2 * res;
     } else if (OP == OP_RESID) {
-        const T xo = xin[o];
-        const T res = f[o] - dd[row] * xo - sum;
+        const T res = fo - dr * xo - sum;
         out[o] = res;
         if (sx) {
             sx[o] = xo;
@@ -326,16 +348,30 @@ inline unsigned rc_blocks(int64_t n, int k) {
     return (unsigned)((work + kBlock - 1) / kBlock > 0 ? (work + kBlock - 1) / kBlock : 1);
 }
 
+// (P e_c) at fine row u, column c: w0 e_c[p0] (+ w1 e_c[p1] when the row has a second
+// parent). Both gathers are issued unconditionally (a row without a second parent re-reads
+// its first) and the second term is dropped by a select, so neither load waits behind a
+// branch.
+template <class T>
+__device__ __forceinline__ T interp(int64_t u, int k, int c, const int32_t *__restrict__ p0,
+                                    const int32_t *__restrict__ p1, const T *__restrict__ w0,
+                                    const T *__restrict__ w1, const T *__restrict__ ec) {
+    const int32_t a = p0[u], q = p1[u];
+    const T wa = w0[u], wb = w1[u];
+    const T ea = ec[(int64_t)a * k + c];
+    const T eb = ec[(int64_t)(q >= 0 ? q : a) * k + c];
+    const T pe = wa * ea;
+    const T pe2 = pe + wb * eb;
+    return q >= 0 ? pe2 : pe;
+}
+
 template <class T>
 __global__ void k_prolong(int64_t n, int k, int lkp, const int32_t *__restrict__ p0,
                           const int32_t *__restrict__ p1, const T *__restrict__ w0,
                           const T *__restrict__ w1, const T *__restrict__ ec,
                           const double *__restrict__ mu, T *__restrict__ x) {
     ROWCOL(n, lkp)
-    T pe = w0[u] * ec[(int64_t)p0[u] * k + c];
-    int32_t q = p1[u];
-    if (q >= 0) pe += w1[u] * ec[(int64_t)q * k + c];
-    x[t] += (T)mu[c] * pe;
+    x[t] += (T)mu[c] * interp(u, k, c, p0, p1, w0, w1, ec);
 }
 
 // x[rows[a]] += e[a] for the kept rows of an elimination level (their interpolation is
@@ -678,20 +714,26 @@ __global__ void __launch_bounds__(kBlock)
                  T *__restrict__ x) {
     __shared__ double tot[2][32];
     __shared__ double mu_s[32];
+    // the element's operands are loaded first, so that their latency overlaps the totals'
+    const int64_t tt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t u = tt >> lkp;
+    const int c = (int)(tt & ((1 << lkp) - 1));
+    const bool live = u < n && c < k;
+    T pe = T(0), xv = T(0);
+    if (live) {
+        pe = interp(u, k, c, p0, p1, w0, w1, ec);
+        xv = x[u * k + c];
+    }
     block_totals2(nblk, k, partial, tot);
     if ((int)threadIdx.x < k) {
-        const int c = threadIdx.x;
-        const double num = tot[0][c], den = tot[1][c];
+        const int cc = threadIdx.x;
+        const double num = tot[0][cc], den = tot[1][cc];
         double mu = num / den;
         if (!(den > 0.0) || !isfinite(mu)) mu = 1.0;
-        mu_s[c] = mu;
+        mu_s[cc] = mu;
     }
     __syncthreads();
-    ROWCOL(n, lkp)
-    T pe = w0[u] * ec[(int64_t)p0[u] * k + c];
-    int32_t q = p1[u];
-    if (q >= 0) pe += w1[u] * ec[(int64_t)q * k + c];
-    x[t] += (T)mu_s[c] * pe;
+    if (live) x[u * k + c] = xv + (T)mu_s[c] * pe;
 }
 
 // Two-iterate recombination update in one launch with its coefficient: every block forms
@@ -704,18 +746,30 @@ __global__ void __launch_bounds__(kBlock)
                 int nblk, const double *__restrict__ partial, int keep) {
     __shared__ double tot[2][32];
     __shared__ double al_s[32];
+    // the element's operands are loaded first, so that their latency overlaps the totals'
+    const int64_t tt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t u = tt >> lkp;
+    const int c = (int)(tt & ((1 << lkp) - 1));
+    const bool live = u < n && c < k;
+    const int64_t t = u * k + c;
+    T ev = T(0), rv = T(0), e1v = T(0), r1v = T(0);
+    if (live) {
+        ev = e[t];
+        rv = rho[t];
+        e1v = e1[t];
+        r1v = rho1[t];
+    }
     block_totals2(nblk, k, partial, tot);
     if ((int)threadIdx.x < k) {
-        const int c = threadIdx.x;
-        const double gg = tot[0][c], gr = tot[1][c];
-        al_s[c] = (gg > 0.0) ? gr / gg : 0.0;
+        const int cc = threadIdx.x;
+        const double gg = tot[0][cc], gr = tot[1][cc];
+        al_s[cc] = (gg > 0.0) ? gr / gg : 0.0;
     }
     __syncthreads();
-    ROWCOL(n, lkp)
+    if (!live) return;
     T a = (T)al_s[c];
-    T ev = e[t], rv = rho[t];
-    const T en = ev + a * (e1[t] - ev);
-    const T rn = rv - a * (rv - rho1[t]);
+    const T en = ev + a * (e1v - ev);
+    const T rn = rv - a * (rv - r1v);
     e[t] = en;
     rho[t] = rn;
     if (keep) {
