@@ -31,7 +31,7 @@ constexpr int kRedQMax = 14;        // quantities per reduction (4x4 normal equa
 // may spend on forming its per-column scalars itself.
 constexpr int64_t kFuseTotalsMax = 1 << 15;
 constexpr int kTVShortRow = 64;     // test-vector rows longer than this get a wave each
-constexpr int kEllMaxWidth = 32;    // longest row of a level that gets an ELL copy
+constexpr int kEllMaxWidth = 64;    // longest row of a level that gets an ELL copy
 constexpr int kTailMaxCols = 32;  // workgroups (one per column) of one coarse-tail launch
 constexpr int kGraphMaxNodes = 20000;  // longer cycles are launched kernel by kernel
 constexpr int kGraphSets = 2;          // (precision, columns) pairs with cached graphs

@@ -435,8 +435,12 @@ static void build_solve_op(lamg_handle *h, int l, const std::vector<int32_t> &pe
     launch_permute_csr(n, op.perm.p, d_iperm.p, L.rp.p, L.ci.p, L.val.p, op.rp.p, op.ci.p, op.v64.p,
                        f32 ? op.v32.p : nullptr, op.d64.p, op.dinv64.p, f32 ? op.d32.p : nullptr,
                        f32 ? op.dinv32.p : nullptr, s);
-    if (!L.coarsest && n < 65536 && op.max_short_len > 0 && op.max_short_len <= kEllMaxWidth) {
-        op.ell_w = op.max_short_len;
+    // ELL copy for the coarse tail: every row (long ones too) of levels below 65536 rows
+    // whose longest row has at most kEllMaxWidth entries, when padding at most quadruples
+    // the entries
+    if (!L.coarsest && n < 65536 && op.max_len > 0 && op.max_len <= kEllMaxWidth &&
+        (int64_t)op.max_len * n <= 4 * op.nnz_off) {
+        op.ell_w = op.max_len;
         op.ell_ci.alloc(pool, n * op.ell_w);
         op.ell_v64.alloc(pool, n * op.ell_w);
         if (f32) op.ell_v32.alloc(pool, n * op.ell_w);

@@ -332,7 +332,7 @@ __device__ __forceinline__ void csr_rows(int a, int b, int la, int lb, const int
 // rows at consecutive addresses; the sum runs in entry order as in the CSR pass.
 template <class T, int M>
 __device__ __forceinline__ void residual(const Lv<T, M> &L, T *out, int k, int lkp, T *lp) {
-    if (M != kAllLds && L.ew > 0) {
+    if (M != kAllLds && L.ew > 0 && L.maxlen > 0) {  // no long rows
         const int tid = threadIdx.x;
         const int kp = 1 << lkp;
         const int c = tid & (kp - 1);
@@ -402,24 +402,51 @@ __device__ __forceinline__ void ell_gs_pass(const Lv<T, M> &L, int a, int b, int
 }
 
 template <class T>
-constexpr int kPipe = sizeof(T) == 4 ? 16 : 14;  // longest row of the pipelined path (even)
+constexpr int kPipe = sizeof(T) == 4 ? 16 : 10;  // longest row of the pipelined path
+
+// The colour block offsets of a level (2 ncolors + 1 values, each below 65536), the first
+// 192 held in the lanes of three registers for a whole smoothing call and read with
+// readlane, so that finding a pass's rows needs no memory access (the pipelined passes
+// would otherwise wait for these loads before issuing the row loads of the pass ahead).
+struct BlkRegs {
+    int b0, b1, b2;
+    const int64_t *blk;
+    template <class T, int M>
+    __device__ __forceinline__ void load(const Lv<T, M> &L) {
+        const int lane = threadIdx.x & 63, nb = 2 * L.ncol + 1;
+        blk = L.blk;
+        b0 = lane < nb ? (int)L.blk[lane] : 0;
+        b1 = lane + 64 < nb ? (int)L.blk[lane + 64] : 0;
+        b2 = lane + 128 < nb ? (int)L.blk[lane + 128] : 0;
+    }
+    __device__ __forceinline__ int operator()(int i) const {  // i: wave-uniform
+        if (i < 64) return __builtin_amdgcn_readlane(b0, i);
+        if (i < 128) return __builtin_amdgcn_readlane(b1, i - 64);
+        if (i < 192) return __builtin_amdgcn_readlane(b2, i - 128);
+        return (int)blk[i];
+    }
+};
 
 // One thread's row of one colour pass, loaded ahead of its update (stage 1: inverse
-// diagonal and right-hand side; stage 2: column indices, packed two per register, and
-// values from the level's ELL copy). Padding entries point at the row itself with weight 0.
+// diagonal and right-hand side; stage 2: column indices and values from the level's ELL
+// copy). Padding entries point at the row itself with weight 0. The loaded values go into
+// registers as they arrive and are first used by the pass that relaxes the row, so the
+// loads stay in flight across the current pass and its barrier (packing two indices into
+// one register as they were loaded made every stage wait for its loads: 1.5 us per pass).
 template <class T, int W>
 struct PipeRow {
-    uint32_t cp[W / 2];
+    int32_t ci[W];
     T vv[W];
     T dinv, fv;
     int row;
     bool live;
     template <int M>
-    __device__ __forceinline__ void stage1(const Lv<T, M> &L, int cl, int k, int lkp) {
+    __device__ __forceinline__ void stage1(const Lv<T, M> &L, const BlkRegs &bk, int cl, int k,
+                                           int lkp) {
         const int tid = threadIdx.x;
         const int c = tid & ((1 << lkp) - 1);
-        row = (int)L.blk[cl] + (tid >> lkp);
-        live = row < (int)L.blk[cl + 1] && c < k;
+        row = bk(cl) + (tid >> lkp);
+        live = row < bk(cl + 1) && c < k;
         if (live) {
             dinv = L.dinv[row];
             fv = L.f[row * k + c];
@@ -431,23 +458,13 @@ struct PipeRow {
         if (!live) return;
         const int n = L.n, ew = L.ew;
 #pragma unroll
-        for (int u = 0; u < W; u += 2) {
-            uint32_t a = (uint32_t)row, b = (uint32_t)row;
-            T va = T(0), vb = T(0);
-            if (u < ew) {
-                a = (uint32_t)L.eci[u * n + row];
-                va = L.ev[u * n + row];
-            }
-            if (u + 1 < ew) {
-                b = (uint32_t)L.eci[(u + 1) * n + row];
-                vb = L.ev[(u + 1) * n + row];
-            }
-            cp[u / 2] = a | (b << 16);
-            vv[u] = va;
-            vv[u + 1] = vb;
+        for (int u = 0; u < W; ++u) {
+            const int uu = u < ew ? u : 0;  // slots past the width re-read entry 0, weight 0
+            ci[u] = L.eci[uu * n + row];
+            vv[u] = L.ev[uu * n + row];
         }
     }
-    __device__ __forceinline__ void relax(T *x, int k, int c) const {
+    __device__ __forceinline__ void relax(T *x, int k, int c, int ew) const {
         if (!live) return;
         constexpr int G = kGather<T>;
         T acc = T(0);
@@ -456,18 +473,89 @@ struct PipeRow {
             T xx[G];
 #pragma unroll
             for (int u = 0; u < G; ++u) {
-                if (u0 + u < W) {
-                    const uint32_t j = (cp[(u0 + u) / 2] >> (16 * ((u0 + u) & 1))) & 0xffffu;
-                    xx[u] = x[(int)j * k + c];
-                }
+                if (u0 + u < W) xx[u] = x[ci[u0 + u] * k + c];
             }
 #pragma unroll
             for (int u = 0; u < G; ++u)
-                if (u0 + u < W) acc += vv[u0 + u] * xx[u];
+                if (u0 + u < W) acc = (u0 + u < ew) ? acc + vv[u0 + u] * xx[u] : acc;
         }
         x[row * k + c] = (fv - acc) * dinv;
     }
 };
+
+template <class T>
+constexpr int kPipeSplit = sizeof(T) == 4 ? 10 : 8;  // entries per lane of a split row
+
+// One row of one colour pass split over lpr = 2^llpr adjacent lane groups (rows of both
+// classes of the colour: the short ones, then the long ones), loaded ahead of its update
+// like PipeRow: lane s of the row holds entries s, s + lpr, ... (at most W) of the level's
+// full-width ELL copy, and the lanes' partial sums are added by xor shuffles (every lane
+// takes part in them, live or not).
+template <class T, int W>
+struct PipeRowS {
+    int32_t ci[W];
+    T vv[W];
+    T dinv, fv;
+    int row, sub;
+    bool live;
+    template <int M>
+    __device__ __forceinline__ void stage1(const Lv<T, M> &L, const BlkRegs &bk, int cl, int k,
+                                           int lkp, int llpr) {
+        const int tid = threadIdx.x;
+        const int c = tid & ((1 << lkp) - 1);
+        sub = (tid >> lkp) & ((1 << llpr) - 1);
+        const int t = tid >> (lkp + llpr);
+        const int a = bk(cl), ns = bk(cl + 1) - a;
+        const int la = bk(L.ncol + cl), nl = bk(L.ncol + cl + 1) - la;
+        row = t < ns ? a + t : la + (t - ns);
+        live = t < ns + nl && c < k;
+        if (live) {
+            dinv = L.dinv[row];
+            fv = L.f[row * k + c];
+        }
+    }
+    template <int M>
+    __device__ __forceinline__ void stage2(const Lv<T, M> &L, int llpr) {
+        if (!live) return;
+        const int n = L.n, ew = L.ew;
+#pragma unroll
+        for (int u = 0; u < W; ++u) {
+            const int e = (u << llpr) + sub;
+            const int ee = e < ew ? e : sub;  // slots past the width re-read entry sub, dropped
+            ci[u] = L.eci[ee * n + row];
+            vv[u] = L.ev[ee * n + row];
+        }
+    }
+    __device__ __forceinline__ void relax(T *x, int k, int c, int lkp, int llpr, int ew) const {
+        constexpr int G = kGather<T>;
+        T acc = T(0);
+        if (live) {
+#pragma unroll
+            for (int u0 = 0; u0 < W; u0 += G) {
+                T xx[G];
+#pragma unroll
+                for (int u = 0; u < G; ++u)
+                    if (u0 + u < W) xx[u] = x[ci[u0 + u] * k + c];
+#pragma unroll
+                for (int u = 0; u < G; ++u)
+                    if (u0 + u < W)
+                        acc = (((u0 + u) << llpr) + sub < ew) ? acc + vv[u0 + u] * xx[u] : acc;
+            }
+        }
+        for (int o = 1 << lkp; o < (1 << (lkp + llpr)); o <<= 1) acc += __shfl_xor(acc, o, 64);
+        if (live && sub == 0) x[row * k + c] = (fv - acc) * dinv;
+    }
+};
+
+// Lanes per row (log2) of the split pipelined pass: the fewest that leave at most
+// kPipeSplit entries per lane, if every colour then gives each lane group one row at most;
+// 0 if none does.
+template <class T, int M>
+__device__ __forceinline__ int split_llpr(const Lv<T, M> &L, int lkp) {
+    int llpr = 1;
+    while ((kPipeSplit<T> << llpr) < L.ew) ++llpr;
+    return (lkp + llpr <= 6 && (L.maxcol << (lkp + llpr)) <= TB) ? llpr : 0;
+}
 
 // `sweeps` Gauss-Seidel sweeps over the colours of level L, then (if `resid`) the residual
 // r = f - L x. On a level whose (row, column) pairs fit one per thread and whose rows have
@@ -562,23 +650,50 @@ __device__ __forceinline__ void smooth(const Lv<T, M> &L, int k, int lkp, int sw
         // pass q relaxes with the row data of stage 2 issued during pass q-1, whose
         // bounds came from stage 1 issued during pass q-2 (right after that pass's update)
         PipeRow<T, W> A, Bn;
+        BlkRegs bk;
+        bk.load(L);
         const int q_end = sweeps * nc;
         const int c = tid & (kp - 1);
-        A.stage1(L, 0, k, lkp);
-        if (1 < q_end) Bn.stage1(L, 1 % nc, k, lkp);
+        A.stage1(L, bk, 0, k, lkp);
+        if (1 < q_end) Bn.stage1(L, bk, 1 % nc, k, lkp);
         A.stage2(L);
         for (int q = 0; q < q_end; q += 2) {
-            A.relax(L.x, k, c);
-            if (q + 2 < q_end) A.stage1(L, (q + 2) % nc, k, lkp);
+            A.relax(L.x, k, c, L.ew);
+            if (q + 2 < q_end) A.stage1(L, bk, (q + 2) % nc, k, lkp);
             if (q + 1 < q_end) Bn.stage2(L);
             bar();
             if (q + 1 >= q_end) break;
-            Bn.relax(L.x, k, c);
-            if (q + 3 < q_end) Bn.stage1(L, (q + 3) % nc, k, lkp);
+            Bn.relax(L.x, k, c, L.ew);
+            if (q + 3 < q_end) Bn.stage1(L, bk, (q + 3) % nc, k, lkp);
             if (q + 2 < q_end) A.stage2(L);
             bar();
         }
-    } else if (M != kAllLds && L.ew > 0) {
+    } else if (M != kAllLds && L.ew > W && L.n < 65536 && split_llpr(L, lkp) > 0) {
+        // rows longer than the pipelined registers hold: each split over lpr lanes (at most
+        // kPipeSplit entries per lane), the next colour's rows loaded during the current pass
+        // as above; the long rows of a colour are relaxed with its short ones
+        constexpr int W2 = kPipeSplit<T>;
+        const int llpr = split_llpr(L, lkp);
+        PipeRowS<T, W2> A, Bn;
+        BlkRegs bk;
+        bk.load(L);
+        const int q_end = sweeps * nc;
+        const int c = tid & (kp - 1);
+        A.stage1(L, bk, 0, k, lkp, llpr);
+        if (1 < q_end) Bn.stage1(L, bk, 1 % nc, k, lkp, llpr);
+        A.stage2(L, llpr);
+        for (int q = 0; q < q_end; q += 2) {
+            A.relax(L.x, k, c, lkp, llpr, L.ew);
+            if (q + 2 < q_end) A.stage1(L, bk, (q + 2) % nc, k, lkp, llpr);
+            if (q + 1 < q_end) Bn.stage2(L, llpr);
+            bar();
+            if (q + 1 >= q_end) break;
+            Bn.relax(L.x, k, c, lkp, llpr, L.ew);
+            if (q + 3 < q_end) Bn.stage1(L, bk, (q + 3) % nc, k, lkp, llpr);
+            if (q + 2 < q_end) A.stage2(L, llpr);
+            bar();
+        }
+    } else if (M != kAllLds && L.ew > 0 && L.maxlen > 0) {  // no long rows
         for (int sw = 0; sw < sweeps; ++sw)
             for (int cl = 0; cl < nc; ++cl) {
                 ell_gs_pass<T, M>(L, (int)L.blk[cl], (int)L.blk[cl + 1], k, lkp);
@@ -928,8 +1043,9 @@ void tail_fill_desc(void *host_buf, int l, const Level &L, const SolveOp &op, co
     D.maxlen = op.max_short_len;
     D.maxrow = op.max_len;
     D.elim = L.elim ? 1 : 0;
-    for (int c = 0; c < op.ncolors; ++c)
-        D.maxcol = std::max(D.maxcol, (int32_t)(op.blk[c + 1] - op.blk[c]));
+    for (int c = 0; c < op.ncolors; ++c)  // rows of a colour, short and long
+        D.maxcol = std::max(D.maxcol, (int32_t)(op.blk[c + 1] - op.blk[c] + op.blk[op.ncolors + c + 1] -
+                                                op.blk[op.ncolors + c]));
     D.gamma = L.gamma;
     D.blk = d_blk;
     D.rp = op.rp.p;

@@ -40,6 +40,7 @@ GRAPHS = {
     "aniso_ragged": lambda: I.grid2d(257, 131, 1.0, 1e-3),
     "aniso_eps1e-4": lambda: I.grid2d(96, 80, 1.0, 1e-4),
     "lognormal3d": lambda: I.grid3d(23, 19, 17, "lognormal", seed=3),
+    "lognormal3d_64": lambda: I.grid3d(64, 60, 56, "lognormal", seed=3),
     "random": lambda: I.random_connected(6000, 24000, seed=4),
     "chunglu": lambda: I.chung_lu(30000, 2.1, 16, seed=5),
     "rgg": lambda: I.random_geometric(20000, 10.0, seed=6),
@@ -438,16 +439,20 @@ def test_full_size_anisotropic_1024(B):
         check_solution(g, st, ph, bh, refs)
 
 
+@pytest.mark.parametrize("name", ["aniso_ragged", "lognormal3d", "lognormal3d_64"])
 @pytest.mark.parametrize("tail_rows", [0, 400, 2500, 100000])
-def test_cycle_execution_modes_agree(B, tail_rows):
+def test_cycle_execution_modes_agree(B, tail_rows, name):
     """Every split between per-step kernels and the coarse tail (with its LDS-resident
     levels) computes the same cycle: each reaches the tolerance and the oracle's solution,
     in both precisions, for 1 to 5 right-hand sides (one tail workgroup per column, the
-    columns copied into and out of the tail's column-by-column layout from 2 on)."""
+    columns copied into and out of the tail's column-by-column layout from 2 on). The
+    coarse levels of the 3D grids have rows of 17 to 42 entries, which the tail relaxes
+    split over several lanes from an ELL copy; on the larger grid some of them are longer
+    than 32 entries (the long-row class of their colour)."""
     import torch
 
-    g = GRAPHS["aniso_ragged"]()
-    note(f"execution mode tail_rows={tail_rows}")
+    g = GRAPHS[name]()
+    note(f"execution mode {name} tail_rows={tail_rows}")
     oh = O.Hierarchy(g, seed=1)
     h = B.lamg_setup(g, B.lamg_default_options(tail_rows=tail_rows))
     bh = I.rhs(g.n, 5, seed=21)
