@@ -59,6 +59,139 @@ KIND_SYMBOLS = {  # kernel kinds and the kernel symbols a rocprofv3 trace shows 
 }
 
 
+def kernel_kind(name: str):
+    """(kind, precision) of a kernel symbol as a rocprofv3 trace shows it, in the grouping of
+    the library's in-situ timer (KIND_SYMBOLS); (None, None) for setup and library kernels."""
+    import re
+
+    base = name.replace("(anonymous namespace)", "").split("(")[0]
+    m = re.search(r"(k_csr_mixed|k_csr_long|k_csr)<(float|double), (\d)", base)
+    if m:
+        kind = {"0": "gs_color", "1": "residual", "2": "restrict", "3": "cheb"}[m.group(3)]
+        return kind, "fp32" if m.group(2) == "float" else "fp64"
+    prec = "fp32" if "<float" in base else ("fp64" if "<double" in base else None)
+    if "k_tail" in base:
+        return "tail", prec
+    for key, kind in (("k_prolong", "prolong"), ("k_inject_add", "prolong"), ("k_red_", "reduce"),
+                      ("k_rc2_", "reduce"), ("k_rcf_update", "reduce"), ("k_add_into", "cheb")):
+        if key in base:
+            return kind, prec or "fp64"
+    for key in ("k_copy", "k_fill", "k_gather_cols", "k_scatter_cols", "k_sub_col",
+                "k_to_f32_scaled", "k_add_scaled_f32", "k_zero_cols", "k_to_cols", "k_from_cols",
+                "k_fill_i64", "k_coarsest"):
+        if key in base:
+            return "vector", prec or "fp64"
+    return None, None
+
+
+KERNEL_SOURCES = ("cycle_kernels.hip", "csr_device.h", "tail_kernel.hip", "lamg_internal.h",
+                  "solve.cpp")
+
+
+def kernel_source_hash() -> str:
+    """Hash of the sources that decide the solve's kernels and launches: a traffic record
+    taken with other sources is not reported."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2606_24791_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_path(workload: str, k: int) -> str:
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}_k{k}.json")
+
+
+def summarize_profile(d: str, workload: str, k: int, copy_bytes: int, record: bool) -> int:
+    """Per kernel kind and precision: calls, total and average duration from a rocprofv3
+    --stats kernel_stats.csv; from a --pmc run, the counter's KiB per dispatch, calibrated by
+    the run's last device copy (the --copy-probe-mb probe, copy_bytes read and written).
+    With `record`, the calibrated counters go into the workload's traffic record."""
+    import csv
+    import glob
+
+    out = []
+    for path in sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)):
+        agg = {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                kind, prec = kernel_kind(r["Name"])
+                if kind is None:
+                    continue
+                a = agg.setdefault((kind, prec), [0, 0.0])
+                a[0] += int(r["Calls"])
+                a[1] += float(r["TotalDurationNs"])
+        out.append(f"kernel statistics ({os.path.relpath(path, d)}):")
+        out.append(f"  {'kind':<10} {'prec':<5} {'calls':>8} {'total ms':>10} {'avg us':>9}")
+        for (kind, prec), (c, t) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+            out.append(f"  {kind:<10} {prec:<5} {c:>8} {t / 1e6:>10.2f} {t / c / 1e3:>9.3f}")
+    rec = None
+    if record and os.path.exists(traffic_path(workload, k)):
+        with open(traffic_path(workload, k)) as fh:
+            rec = json.load(fh)
+        if rec.get("source_hash") != kernel_source_hash():
+            rec = None
+    if rec is None:
+        rec = dict(workload=workload, nrhs=k, source_hash=kernel_source_hash(), kinds={},
+                   probe={})
+    for path in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+        per = {}  # dispatch -> [name, {counter: value}]
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                e = per.setdefault(int(r["Dispatch_Id"]), [r["Kernel_Name"], {}])
+                e[1][r["Counter_Name"]] = e[1].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        counters = sorted({c for _, cv in per.values() for c in cv})
+        copies = [i for i, (name, _) in per.items() if "copyBuffer" in name or "k_copy" in name]
+        probe_id = max(copies) if copies else None
+        out.append(f"hardware counters ({os.path.relpath(path, d)}), KiB per dispatch:")
+        for cn in counters:
+            probe = per[probe_id][1].get(cn, 0.0) if probe_id is not None else 0.0
+            factor = copy_bytes / (1024.0 * probe) if probe > 0 and copy_bytes > 0 else None
+            out.append(f"  probe (last copy, {copy_bytes} bytes each way): {cn} {probe:.1f} KiB"
+                       f" -> factor {factor}")
+            agg = {}
+            for name, cv in per.values():
+                kind, prec = kernel_kind(name)
+                if kind is None or cn not in cv:
+                    continue
+                a = agg.setdefault((kind, prec), [0, 0.0])
+                a[0] += 1
+                a[1] += cv[cn]
+            for (kind, prec), (c, v) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+                out.append(f"  {cn:<11} {kind:<10} {prec:<5} dispatches {c:>7} "
+                           f"mean {v / c:>12.2f} KiB")
+                if factor is not None:
+                    e = rec["kinds"].setdefault(f"{kind}_{prec}", {})
+                    e["dispatches"] = c
+                    e[f"{cn.lower()}_kib_per_dispatch"] = v / c
+                    e[f"{cn.lower()}_bytes_per_dispatch"] = v / c * 1024.0 * factor
+            rec["probe"][cn] = dict(copy_bytes=copy_bytes, counter_kib=probe, factor=factor)
+    if record and rec["kinds"]:
+        with open(traffic_path(workload, k), "w") as fh:
+            json.dump(rec, fh, indent=1)
+        out.append(f"traffic record: {os.path.relpath(traffic_path(workload, k), ROOT)}")
+    print("\n".join(out))
+    return 0
+
+
+def traffic_of(workload: str, k: int, key: str):
+    """HBM bytes per launch of a kernel kind (FETCH_SIZE + WRITE_SIZE, calibrated) from the
+    workload's traffic record, if the record was taken with the current kernel sources."""
+    try:
+        with open(traffic_path(workload, k)) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    e = rec.get("kinds", {}).get(key, {})
+    if "fetch_size_bytes_per_dispatch" not in e or "write_size_bytes_per_dispatch" not in e:
+        return None
+    return e["fetch_size_bytes_per_dispatch"] + e["write_size_bytes_per_dispatch"]
+
+
 def host_cpu() -> dict:
     model = platform.processor() or platform.machine()
     try:
@@ -134,7 +267,16 @@ def main() -> int:
                          "(0: none, no roofline or kernel table)")
     ap.add_argument("--fp32ir-only", action="store_true",
                     help="time only the FP32+IR solves (for hardware-counter runs)")
+    ap.add_argument("--summarize-profile", metavar="DIR", default=None,
+                    help="print per-kernel-kind figures of the rocprofv3 output under DIR "
+                         "(kernel statistics, FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--record-traffic", action="store_true",
+                    help="with --summarize-profile: store the calibrated counters in "
+                         "profiles/traffic_<workload>_k<nrhs>.json")
     args = ap.parse_args()
+    if args.summarize_profile:
+        return summarize_profile(args.summarize_profile, args.workload, args.nrhs,
+                                 args.copy_probe_mb << 20, args.record_traffic)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the solver has no multi-GPU path); got --gpus "
               f"{args.gpus}", file=sys.stderr)
@@ -366,7 +508,13 @@ def main() -> int:
                      "kernel": f"{dname} ({'fp32' if dp == B.FP32_IR else 'fp64'}): "
                                f"{KIND_SYMBOLS[dname]}, every level",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_of(args.workload, k,
+                                           f"{dname}_{'fp32' if dp == B.FP32_IR else 'fp64'}"),
+                     "traffic_source": os.path.relpath(traffic_path(args.workload, k), ROOT) +
+                                       " (FETCH_SIZE + WRITE_SIZE per launch, each scaled by "
+                                       "the counter's reading of a 256 MiB device copy; null "
+                                       "unless taken with the current kernel sources)",
                      "bytes_per_launch": dt["bytes"] / dt["launches"],
                      "us_per_launch": 1e6 * dt["seconds"] / dt["launches"],
                      "launches_per_solve": dt["launches"] // r32["ev_steps"],
