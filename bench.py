@@ -490,6 +490,7 @@ def main() -> int:
             "n": g.n, "nnz_L": g.nnz_laplacian, "nnz_2m": g.nnz, "nrhs": k,
             "levels": hi["levels"], "level_n": hi["n"], "op_complexity": round(hi["op_complexity"], 3),
             "setup_s": round(hi["setup_seconds"], 3),
+            "setup_phases_ms": {k: round(1e3 * v, 1) for k, v in hi["setup_phases"].items()},
             "elimination": bool(opts.elimination), "elimination_levels": sum(hi["elim"]),
             "smoother": "chebyshev on levels with > 32 colours" if opts.smoother else "gauss-seidel",
             "chebyshev_levels": sum(hi["cheb"]),

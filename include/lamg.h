@@ -128,8 +128,25 @@ typedef struct {
                                 Changes only how the cycle is executed, not what it computes. */
 } lamg_options;
 
-/* Per-level description of a hierarchy. */
 #define LAMG_MAX_LEVELS 64
+#define LAMG_SETUP_PHASES 9
+
+/* Phases of lamg_setup timed in lamg_hier_info.setup_phase_seconds (host wall time; each
+ * phase ends with its device work complete). */
+typedef enum {
+    LAMG_SETUP_INPUT = 0,       /* input checks, the Laplacian of level 0 */
+    LAMG_SETUP_COLOR = 1,       /* greedy colourings (Sec. 2 "Relaxation" reading) */
+    LAMG_SETUP_LEVEL = 2,       /* veto, test vectors, affinities, moments (and their copies
+                                   to the host for aggregation) */
+    LAMG_SETUP_AGGREGATE = 3,   /* the greedy aggregation pass (host) */
+    LAMG_SETUP_INTERP = 4,      /* caliber-1/caliber-2 interpolation weights */
+    LAMG_SETUP_ELIMINATE = 5,   /* elimination sets and Schur complements */
+    LAMG_SETUP_GALERKIN = 6,    /* Galerkin coarse operators (and their copy to the host) */
+    LAMG_SETUP_COARSEST = 7,    /* pseudo-inverse of the directly solved level */
+    LAMG_SETUP_LAYOUT = 8       /* solve layout: colour-permuted operators, transfers, ELL */
+} lamg_setup_phase;
+
+/* Per-level description of a hierarchy. */
 typedef struct {
     int32_t levels;                      /* number of levels; the last is solved directly */
     int64_t n[LAMG_MAX_LEVELS];          /* nodes per level */
@@ -154,6 +171,8 @@ typedef struct {
                                             coarse tail; then 0) */
     int32_t cheb[LAMG_MAX_LEVELS];       /* 1: smoothed by Chebyshev polynomials (smoother 1) */
     double cheb_lmax[LAMG_MAX_LEVELS];   /* their Gershgorin bound of D^{-1} L (0 otherwise) */
+    double setup_phase_seconds[LAMG_SETUP_PHASES]; /* wall time of lamg_setup by phase, summed
+                                                       over the levels (lamg_setup_phase) */
 } lamg_hier_info;
 
 /* Solve statistics. The caller may point the array fields at host arrays (or leave them

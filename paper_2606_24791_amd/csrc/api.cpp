@@ -304,6 +304,7 @@ lamg_status lamg_hierarchy_info(const lamg_handle *h, lamg_hier_info *info) {
     info->bytes_device = h->pool->bytes();
     info->op_complexity = tot / nnz0;
     info->setup_seconds = h->setup_seconds;
+    for (int i = 0; i < LAMG_SETUP_PHASES; ++i) info->setup_phase_seconds[i] = h->setup_phase[i];
     info->bytes_peak = h->pool->peak();
     info->tail_level = plan_tail_level(h);
     info->timed_level = plan_timed_level(h);

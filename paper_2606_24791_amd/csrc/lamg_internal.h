@@ -339,6 +339,7 @@ struct lamg_handle {
     lamg::KTimer timer;
     double solve_bytes = 0.0;  // algorithmic bytes of the current solve's launches
     double setup_seconds = 0.0;
+    double setup_phase[LAMG_SETUP_PHASES] = {};  // seconds per lamg_setup_phase
     ~lamg_handle();
 };
 

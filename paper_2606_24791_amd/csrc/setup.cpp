@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <optional>
 #include <cmath>
 #include <system_error>
 #include <thread>
@@ -118,6 +119,17 @@ static HostGraph read_graph(const lamg_graph *g, hipStream_t s) {
     if ((int64_t)q.size() != h.n) throw Error(LAMG_DISCONNECTED, "graph: not connected");
     return h;
 }
+
+// Adds the wall time of its scope to one of the handle's setup phases; each scope ends with
+// its device work complete (the stream is synchronised before it closes).
+struct PhaseClock {
+    double &acc;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    PhaseClock(lamg_handle *h, lamg_setup_phase p) : acc(h->setup_phase[p]) {}
+    ~PhaseClock() {
+        acc += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Natural-order greedy colouring: colour(u) = smallest colour unused by neighbours v < u.
@@ -273,7 +285,11 @@ static void setup_level(lamg_handle *h, int l) {
     Level &L = h->lev[l];
     const int64_t n = L.n, nnz = L.nnz;
 
-    L.ncolors = greedy_color(n, L.h_rp, L.h_ci, L.h_color);
+    {
+        PhaseClock pc(h, LAMG_SETUP_COLOR);
+        L.ncolors = greedy_color(n, L.h_rp, L.h_ci, L.h_color);
+    }
+    std::optional<PhaseClock> pc_level(std::in_place, h, LAMG_SETUP_LEVEL);
     // rows of each colour: those with at most kTVShortRow stored entries ascending, then the
     // longer ones ascending (rows of one colour are independent, so the order only decides
     // which kernel relaxes them)
@@ -325,9 +341,14 @@ static void setup_level(lamg_handle *h, int l) {
     L.X.download(hx.data(), n * kTV, s);
     L.mom.download(hm.data(), n * 9, s);
     LAMG_HIP(hipStreamSynchronize(s));
+    pc_level.reset();
 
-    L.nc = greedy_aggregate(n, L.h_rp, L.h_ci, hs, ha, hx, hm, L.h_seed, L.h_agg);
+    {
+        PhaseClock pc(h, LAMG_SETUP_AGGREGATE);
+        L.nc = greedy_aggregate(n, L.h_rp, L.h_ci, hs, ha, hx, hm, L.h_seed, L.h_agg);
+    }
     if (L.nc >= n || l + 1 >= kMaxLevels) return;  // caller decides (stall)
+    PhaseClock pc_interp(h, LAMG_SETUP_INTERP);
 
     std::vector<int32_t> aggseed(L.nc);
     for (int64_t u = 0; u < n; ++u)
@@ -560,8 +581,10 @@ static void build_solve_op(lamg_handle *h, int l, const std::vector<int32_t> &pe
 // ---------------------------------------------------------------------------
 void run_setup(lamg_handle *h, const lamg_graph *g) {
     auto t0 = std::chrono::steady_clock::now();
+    for (double &t : h->setup_phase) t = 0.0;
     Pool &pool = *h->pool;
     hipStream_t s = h->stream;
+    std::optional<PhaseClock> pc_input(std::in_place, h, LAMG_SETUP_INPUT);
     HostGraph hg = read_graph(g, s);
     const int64_t n = hg.n;
 
@@ -603,6 +626,7 @@ void run_setup(lamg_handle *h, const lamg_graph *g) {
         launch_laplacian(n, arp.p, aci.p, aw.p, L.rp.p, L.ci.p, L.val.p, s);
         LAMG_HIP(hipStreamSynchronize(s));
     }
+    pc_input.reset();
     const int64_t n_direct = h->opt.n_direct;
     for (int l = 0;; ++l) {
         Level &L = h->lev[l];
@@ -612,12 +636,16 @@ void run_setup(lamg_handle *h, const lamg_graph *g) {
         }
         // elimination and aggregation alternate: an elimination level comes before each
         // aggregation step (when it removes enough nodes), never after another one
-        if (h->opt.elimination && !(l > 0 && h->lev[l - 1].elim) && l + 1 < kMaxLevels &&
-            try_elimination(h, l))
-            continue;
+        bool eliminated = false;
+        if (h->opt.elimination && !(l > 0 && h->lev[l - 1].elim) && l + 1 < kMaxLevels) {
+            PhaseClock pc(h, LAMG_SETUP_ELIMINATE);
+            eliminated = try_elimination(h, l);
+        }
+        if (eliminated) continue;
         setup_level(h, l);
         if (h->opt.smoother == 1 && L.ncolors > kChebColors) {
             // Chebyshev smoothing on this dense level: the Gershgorin bound of D^{-1} L
+            PhaseClock pc(h, LAMG_SETUP_LEVEL);
             std::vector<double> q(L.n);
             DArr<double> dq;
             dq.alloc(*h->pool, L.n);
@@ -637,6 +665,7 @@ void run_setup(lamg_handle *h, const lamg_graph *g) {
             }
             throw Error(LAMG_COARSENING_STALLED, "coarsening stalled");
         }
+        PhaseClock pc(h, LAMG_SETUP_GALERKIN);
         h->lev.emplace_back();
         Level &C = h->lev[l + 1];
         Level &F = h->lev[l];  // re-bind after emplace_back (reserve keeps it valid)
@@ -676,15 +705,21 @@ void run_setup(lamg_handle *h, const lamg_graph *g) {
     // coarsest inverse
     {
         Level &C = h->lev[h->nlev - 1];
+        PhaseClock pc(h, LAMG_SETUP_COARSEST);
         C.Z.alloc(pool, C.n * C.n);
         coarsest_inverse(pool, C.n, C.rp.p, C.ci.p, C.val.p, C.Z.p, s);
+        LAMG_HIP(hipStreamSynchronize(s));
     }
 
     // solve layout, all levels
-    std::vector<std::vector<int32_t>> perm(h->nlev), iperm(h->nlev);
-    for (int l = 0; l < h->nlev; ++l) compute_perm(h->lev[l], perm[l], iperm[l]);
-    for (int l = 0; l < h->nlev; ++l)
-        build_solve_op(h, l, perm[l], iperm[l], l + 1 < h->nlev ? &iperm[l + 1] : nullptr);
+    {
+        PhaseClock pc(h, LAMG_SETUP_LAYOUT);
+        std::vector<std::vector<int32_t>> perm(h->nlev), iperm(h->nlev);
+        for (int l = 0; l < h->nlev; ++l) compute_perm(h->lev[l], perm[l], iperm[l]);
+        for (int l = 0; l < h->nlev; ++l)
+            build_solve_op(h, l, perm[l], iperm[l], l + 1 < h->nlev ? &iperm[l + 1] : nullptr);
+        LAMG_HIP(hipStreamSynchronize(s));
+    }
 
     if (!h->opt.keep_setup_data) {
         for (int l = 0; l < h->nlev; ++l) {

@@ -19,6 +19,9 @@ if not _LIB_PATH.exists():
 _lib = C.CDLL(str(_LIB_PATH))
 
 MAX_LEVELS = 64
+SETUP_PHASES = 9
+SETUP_PHASE_NAMES = ("input", "color", "level", "aggregate", "interp", "eliminate", "galerkin",
+                     "coarsest", "layout")
 
 (OK, INVALID_ARG, NOT_SYMMETRIC, SELF_LOOP, BAD_WEIGHT, DISCONNECTED, OOM, COARSENING_STALLED,
  NOT_CONVERGED, HIP_ERROR, UNAVAILABLE, SCRATCH_TOO_SMALL) = range(12)
@@ -48,7 +51,8 @@ class lamg_hier_info(C.Structure):
                 ("op_complexity", C.c_double), ("setup_seconds", C.c_double),
                 ("bytes_peak", C.c_int64), ("elim", C.c_int32 * MAX_LEVELS),
                 ("tail_level", C.c_int32), ("timed_level", C.c_int32),
-                ("cheb", C.c_int32 * MAX_LEVELS), ("cheb_lmax", C.c_double * MAX_LEVELS)]
+                ("cheb", C.c_int32 * MAX_LEVELS), ("cheb_lmax", C.c_double * MAX_LEVELS),
+                ("setup_phase_seconds", C.c_double * SETUP_PHASES)]
 
 
 class lamg_solve_info(C.Structure):
@@ -356,7 +360,8 @@ def lamg_hierarchy_info(h: Handle) -> dict:
                 setup_seconds=float(info.setup_seconds), bytes_peak=int(info.bytes_peak),
                 elim=[bool(e) for e in info.elim[:L]], tail_level=int(info.tail_level),
                 timed_level=int(info.timed_level), cheb=[bool(c) for c in info.cheb[:L]],
-                cheb_lmax=list(info.cheb_lmax[:L]))
+                cheb_lmax=list(info.cheb_lmax[:L]),
+                setup_phases=dict(zip(SETUP_PHASE_NAMES, info.setup_phase_seconds)))
 
 
 def lamg_export_level(h: Handle, level: int) -> dict:

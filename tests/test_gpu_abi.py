@@ -77,3 +77,22 @@ def test_history_buffer_of_the_default_cycle_cap(B):
     assert buf[0] == 1.0 and np.all(buf[1:info.history_len] > 0)
     assert np.all(buf[301:] == -5.0)
     h.close()
+
+
+def test_setup_phase_times(B):
+    """lamg_hier_info.setup_phase_seconds: every phase non-negative, their sum within the
+    setup's wall time, and the phases a hierarchy with aggregation and elimination levels
+    runs (colouring, level kernels, aggregation, interpolation, elimination, Galerkin,
+    coarsest inverse, layout, input) all positive."""
+    g = I.grid2d(120, 90, 1.0, 1e-2)
+    note("setup phase times")
+    h = B.lamg_setup(g)
+    hi = B.lamg_hierarchy_info(h)
+    h.close()
+    ph = hi["setup_phases"]
+    assert set(ph) == set(B.SETUP_PHASE_NAMES)
+    assert all(v >= 0.0 for v in ph.values()), ph
+    assert sum(ph.values()) <= hi["setup_seconds"] * (1 + 1e-9) + 1e-6, (ph, hi["setup_seconds"])
+    assert any(hi["elim"]) and hi["levels"] >= 3
+    for name in B.SETUP_PHASE_NAMES:
+        assert ph[name] > 0.0, (name, ph)
