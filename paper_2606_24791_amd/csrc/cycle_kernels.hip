@@ -125,6 +125,135 @@ __device__ __forceinline__ void csr_short_rows(int64_t grp, int64_t r0, int64_t 
     }
 }
 
+// Vector of V consecutive columns of one row (16 bytes: 4 FP32 or 2 FP64 columns).
+template <class T, int V>
+struct alignas(16) ColVec {
+    T c[V];
+};
+
+// Short-row body with V consecutive columns per lane (k a multiple of V, vectors 16-byte
+// aligned): a group of (kp / V) column lanes x lpr entry lanes handles one row, every gather
+// and every own-operand access a 16-byte load or store. A row's index/value loads are shared
+// by a quarter (FP32) or half (FP64) as many lanes as in the one-column form, and each
+// gather instruction moves four (two) times the bytes, so more of the row's neighbours are
+// in flight per wave. Sums per column run in entry order per lane, then across the lpr
+// lanes by the same xor tree as the one-column form.
+template <class T, int OP, int V>
+__device__ __forceinline__ void csr_short_rows_vec(int64_t grp, int64_t r0, int64_t nrows,
+                                                   const int32_t *__restrict__ rows,
+                                                   const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci,
+                                                   const T *__restrict__ v,
+                                                   const T *__restrict__ dd,
+                                                   const T *__restrict__ f, const T *xin, T *out,
+                                                   int k, int lkv, int llpr, T *sx, T *sr,
+                                                   ChebArgs<T> ch) {
+    using CV = ColVec<T, V>;
+    constexpr int U = 8;
+    const int lg = lkv + llpr;
+    const int G = 1 << lg;
+    const int g = threadIdx.x & (G - 1);
+    const int cv = g & ((1 << lkv) - 1);
+    const int sub = g >> lkv;
+    const int lpr = 1 << llpr;
+    const int kv = k / V;
+    const bool live = grp < nrows && cv < kv;
+    int64_t row = 0;
+    int32_t b = 0, e = 0;
+    if (grp < nrows) {
+        row = rows ? (int64_t)rows[grp] : r0 + grp;
+        b = rp[row];
+        e = rp[row + 1];
+    }
+    const int64_t o = row * k + (int64_t)cv * V;
+    T acc[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) acc[q] = T(0);
+    CV fo{}, xo{}, oo{};
+    T dr = T(0), di = T(0);
+    if (live) {
+        if (OP != OP_SPMV) {
+            fo = *reinterpret_cast<const CV *>(f + o);
+            dr = dd[row];
+        }
+        if (OP == OP_RESID || OP == OP_CHEB) xo = *reinterpret_cast<const CV *>(xin + o);
+        if (OP == OP_CHEB) {
+            di = ch.dinv[row];
+            if (ch.c1 != T(0)) oo = *reinterpret_cast<const CV *>(out + o);
+        }
+        for (int32_t j = b + sub; j < e; j += U * lpr) {
+            int32_t cc[U];
+            T vv[U];
+            CV xx[U];
+            // FP32: every slot loaded (past the end: the group's first entry, dropped by a
+            // select), as in row_dot; FP64: slots past the end load nothing
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t jj = j + u * lpr;
+                const bool ok = jj < e;
+                if constexpr (sizeof(T) == 4) {
+                    const int32_t js = ok ? jj : j;
+                    cc[u] = ci[js];
+                    vv[u] = v[js];
+                } else {
+                    cc[u] = ok ? ci[jj] : -1;
+                    vv[u] = ok ? v[jj] : T(0);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if constexpr (sizeof(T) == 4) {
+                    xx[u] = *reinterpret_cast<const CV *>(xin + (int64_t)cc[u] * k + cv * V);
+                } else if (cc[u] >= 0) {
+                    xx[u] = *reinterpret_cast<const CV *>(xin + (int64_t)cc[u] * k + cv * V);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < V; ++q) xx[u].c[q] = T(0);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool ok = j + u * lpr < e;
+#pragma unroll
+                for (int q = 0; q < V; ++q) {
+                    const T term = vv[u] * xx[u].c[q];
+                    if constexpr (sizeof(T) == 4)
+                        acc[q] = ok ? acc[q] + term : acc[q];
+                    else
+                        acc[q] += term;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < V; ++q)
+        for (int sh = 1 << lkv; sh < G; sh <<= 1) acc[q] += __shfl_xor(acc[q], sh, 64);
+    if (!live || sub != 0) return;
+    CV res;
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+        if (OP == OP_GS) {
+            res.c[q] = (fo.c[q] - acc[q]) * dr;
+        } else if (OP == OP_CHEB) {
+            const T rr = (fo.c[q] - dr * xo.c[q] - acc[q]) * di;
+            res.c[q] = ch.c1 == T(0) ? ch.c2 * rr : ch.c1 * oo.c[q] + ch.c2 * rr;
+        } else if (OP == OP_RESID) {
+            res.c[q] = fo.c[q] - dr * xo.c[q] - acc[q];
+        } else {
+            res.c[q] = acc[q];
+        }
+    }
+    *reinterpret_cast<CV *>(out + o) = res;
+    if (OP == OP_RESID && sx) {
+        *reinterpret_cast<CV *>(sx + o) = xo;
+        *reinterpret_cast<CV *>(sr + o) = res;
+    }
+    if (OP == OP_SPMV && sx) {
+        CV z{};
+        *reinterpret_cast<CV *>(sx + o) = z;
+    }
+}
+
 // Long rows (more than kLongRow off-diagonals: the hubs of power-law graphs and of their
 // dense coarse levels): one block of NT threads per row, kp column lanes times NT/kp entry
 // lanes, each with 8 loads in flight; the entry lanes' partial sums are combined by a wave
@@ -205,6 +334,18 @@ __global__ void __launch_bounds__(kBlock)
                           llpr, sx, sr, ch);
 }
 
+template <class T, int OP, int FINE, int V>
+__global__ void __launch_bounds__(kBlock)
+    k_csr_vec(int64_t r0, int64_t nrows, const int32_t *__restrict__ rows,
+              const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+              const T *__restrict__ v, const T *__restrict__ dd, const T *__restrict__ f,
+              const T *xin, T *out, int k, int lkv, int llpr, T *sx, T *sr, ChebArgs<T> ch) {
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t grp = blk * (kBlock >> (lkv + llpr)) + (threadIdx.x >> (lkv + llpr));
+    csr_short_rows_vec<T, OP, V>(grp, r0, nrows, rows, rp, ci, v, dd, f, xin, out, k, lkv, llpr,
+                                 sx, sr, ch);
+}
+
 template <class T, int OP, int FINE, int NT>
 __global__ void __launch_bounds__(NT)
     k_csr_long(int64_t r0, const int32_t *__restrict__ rows, const int32_t *__restrict__ rp,
@@ -255,6 +396,14 @@ inline int short_llpr(int lkp, int lpr, int64_t nrows) {
     return llpr;
 }
 
+// Whether every per-row vector of a launch is 16-byte aligned (the vector-column form).
+inline bool vec_aligned(const void *a, const void *b, const void *c, const void *d,
+                        const void *e) {
+    for (const void *p : {a, b, c, d, e})
+        if (p && (reinterpret_cast<uintptr_t>(p) & 15)) return false;
+    return true;
+}
+
 // FINE = 1 marks launches on the timed level: the code is identical, the separate
 // symbol lets a kernel trace attribute that level's time on its own.
 template <class T, int OP, int FINE = 0>
@@ -265,6 +414,19 @@ void launch_csr(int64_t r0, int64_t nrows, const int32_t *rows, int skip_long, c
     if (nrows <= 0) return;
     int lkp = kp_log2(k);
     int llpr = short_llpr(lkp, lpr, nrows);
+    constexpr int V = 16 / sizeof(T);
+    if (skip_long == 0 && k % V == 0 && k >= 2 * V && vec_aligned(f, xin, out, sx, sr)) {
+        // V columns per lane on kp / V column lanes; the row's entries split over as many
+        // lanes as the level asks for (none where the one-column form splits none)
+        const int lkv = kp_log2(k / V);
+        const int llv = llpr == 0 ? 0 : std::min(ilog2(lpr), 6 - lkv);
+        const int64_t gpb = kBlock >> (lkv + llv);
+        launch_kernel(k_csr_vec<T, OP, FINE, V>, dim3((unsigned)((nrows + gpb - 1) / gpb)),
+                      dim3(kBlock), 0, s, r0, nrows, rows, rp, ci, v, dd, f, xin, out, k, lkv, llv,
+                      sx, sr, ch);
+        LAMG_LAUNCH_CHECK();
+        return;
+    }
     int lg = lkp + llpr;
     int64_t groups_per_block = kBlock >> lg;
     unsigned grid = (unsigned)((nrows + groups_per_block - 1) / groups_per_block);
