@@ -47,15 +47,15 @@ WORKLOADS = {
     "grid64": "2D 5-point grid 64x64, unit weights",
 }
 KIND_SYMBOLS = {  # kernel kinds and the kernel symbols a rocprofv3 trace shows for them
-    "gs_color": "k_csr / k_csr_vec / k_csr_mixed / k_csr_long with OP_GS (0)",
-    "residual": "k_csr / k_csr_vec / k_csr_mixed / k_csr_long with OP_RESID (1)",
-    "restrict": "k_csr / k_csr_vec / k_csr_mixed / k_csr_long with OP_SPMV (2)",
+    "gs_color": "k_csr / k_csr_vec / k_csr_mixed / k_csr_mixed_vec / k_csr_long with OP_GS (0)",
+    "residual": "k_csr / k_csr_vec / k_csr_mixed / k_csr_mixed_vec / k_csr_long with OP_RESID (1)",
+    "restrict": "k_csr / k_csr_vec / k_csr_mixed / k_csr_mixed_vec / k_csr_long with OP_SPMV (2)",
     "prolong": "k_red_partial<T, 0> + k_prolong_mu (or k_red_final<0> + k_prolong), k_inject_add",
     "tail": "k_tail",
     "reduce": "k_red_partial / k_red_final / k_rc2_fused / k_rc2_update / k_rcf_update",
     "vector": "k_copy / k_fill / k_gather_cols / k_scatter_cols / k_sub_col / k_to_f32_scaled / "
               "k_add_scaled_f32 / k_zero_cols / k_to_cols / k_from_cols / k_fill_i64 / k_coarsest",
-    "cheb": "k_csr / k_csr_vec / k_csr_mixed / k_csr_long with OP_CHEB (3) + k_add_into",
+    "cheb": "k_csr / k_csr_vec / k_csr_mixed / k_csr_mixed_vec / k_csr_long with OP_CHEB (3) + k_add_into",
 }
 
 
@@ -65,7 +65,7 @@ def kernel_kind(name: str):
     import re
 
     base = name.replace("(anonymous namespace)", "").split("(")[0]
-    m = re.search(r"(k_csr_mixed|k_csr_long|k_csr_vec|k_csr)<(float|double), (\d)", base)
+    m = re.search(r"(k_csr_mixed_vec|k_csr_mixed|k_csr_long|k_csr_vec|k_csr)<(float|double), (\d)", base)
     if m:
         kind = {"0": "gs_color", "1": "residual", "2": "restrict", "3": "cheb"}[m.group(3)]
         return kind, "fp32" if m.group(2) == "float" else "fp64"

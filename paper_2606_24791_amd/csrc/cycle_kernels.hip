@@ -381,6 +381,28 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
+// k_csr_mixed with the short rows in the vector-column form (k_csr_vec's conditions).
+template <class T, int OP, int FINE, int V>
+__global__ void __launch_bounds__(kBlock)
+    k_csr_mixed_vec(int64_t sblocks, int64_t r0, int64_t nrows, const int32_t *__restrict__ rows,
+                    int64_t lr0, const int32_t *__restrict__ lrows,
+                    const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                    const T *__restrict__ v, const T *__restrict__ dd, const T *__restrict__ f,
+                    const T *xin, T *out, int k, int lkp, int lkv, int llv, T *sx, T *sr,
+                    ChebArgs<T> ch) {
+    const int64_t bid = blockIdx.x;
+    if (bid < sblocks) {
+        const int64_t grp = xcd_block(bid, sblocks) * (kBlock >> (lkv + llv)) +
+                            (threadIdx.x >> (lkv + llv));
+        csr_short_rows_vec<T, OP, V>(grp, r0, nrows, rows, rp, ci, v, dd, f, xin, out, k, lkv,
+                                     llv, sx, sr, ch);
+    } else {
+        const int64_t j = bid - sblocks;
+        const int64_t row = lrows ? (int64_t)lrows[j] : lr0 + j;
+        csr_long_row<T, OP>(row, rp, ci, v, dd, f, xin, out, k, lkp, sx, sr, ch);
+    }
+}
+
 // Lane split of a short-row launch: log2 of the lanes per row, at most a wave per row.
 // With 16 or more columns a row's column lanes alone hold half a wave or more; when the
 // launch has rows enough for at least 4096 such waves (rows x column lanes >= 2^18) they
@@ -470,6 +492,18 @@ void launch_csr_both(int64_t r0, int64_t nrows, const int32_t *rows, int skip_lo
     }
     int lkp = kp_log2(k);
     int llpr = short_llpr(lkp, lpr, nrows);
+    constexpr int V = 16 / sizeof(T);
+    if (skip_long == 0 && k % V == 0 && k >= 2 * V && vec_aligned(f, xin, out, sx, sr)) {
+        const int lkv = kp_log2(k / V);
+        const int llv = llpr == 0 ? 0 : std::min(ilog2(lpr), 6 - lkv);
+        const int64_t gpb = kBlock >> (lkv + llv);
+        const int64_t sb = (nrows + gpb - 1) / gpb;
+        launch_kernel(k_csr_mixed_vec<T, OP, FINE, V>, dim3((unsigned)(sb + nlong)), dim3(kBlock),
+                      0, s, sb, r0, nrows, rows, lr0, lrows, rp, ci, v, dd, f, xin, out, k, lkp,
+                      lkv, llv, sx, sr, ch);
+        LAMG_LAUNCH_CHECK();
+        return;
+    }
     int64_t groups_per_block = kBlock >> (lkp + llpr);
     int64_t sblocks = (nrows + groups_per_block - 1) / groups_per_block;
     launch_kernel(k_csr_mixed<T, OP, FINE>, dim3((unsigned)(sblocks + nlong)), dim3(kBlock), 0, s,
