@@ -437,7 +437,7 @@ void launch_csr(int64_t r0, int64_t nrows, const int32_t *rows, int skip_long, c
     int lkp = kp_log2(k);
     int llpr = short_llpr(lkp, lpr, nrows);
     constexpr int V = 16 / sizeof(T);
-    if (skip_long == 0 && k % V == 0 && k >= 2 * V && vec_aligned(f, xin, out, sx, sr)) {
+    if (skip_long == 0 && k % V == 0 && k >= V && vec_aligned(f, xin, out, sx, sr)) {
         // V columns per lane on kp / V column lanes; the row's entries split over as many
         // lanes as the level asks for (none where the one-column form splits none)
         const int lkv = kp_log2(k / V);
@@ -493,7 +493,7 @@ void launch_csr_both(int64_t r0, int64_t nrows, const int32_t *rows, int skip_lo
     int lkp = kp_log2(k);
     int llpr = short_llpr(lkp, lpr, nrows);
     constexpr int V = 16 / sizeof(T);
-    if (skip_long == 0 && k % V == 0 && k >= 2 * V && vec_aligned(f, xin, out, sx, sr)) {
+    if (skip_long == 0 && k % V == 0 && k >= V && vec_aligned(f, xin, out, sx, sr)) {
         const int lkv = kp_log2(k / V);
         const int llv = llpr == 0 ? 0 : std::min(ilog2(lpr), 6 - lkv);
         const int64_t gpb = kBlock >> (lkv + llv);
