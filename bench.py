@@ -168,6 +168,23 @@ def summarize_profile(d: str, workload: str, k: int, copy_bytes: int, record: bo
                     e[f"{cn.lower()}_kib_per_dispatch"] = v / c
                     e[f"{cn.lower()}_bytes_per_dispatch"] = v / c * 1024.0 * factor
             rec["probe"][cn] = dict(copy_bytes=copy_bytes, counter_kib=probe, factor=factor)
+            # the largest kernel symbols on their own (the timed level's passes carry
+            # separate symbols)
+            sym = {}
+            for name, cv in per.values():
+                if kernel_kind(name)[0] is None or cn not in cv:
+                    continue
+                short = name.replace("(anonymous namespace)::", "").replace("void ", "")
+                short = short.replace("lamg::", "").split("(")[0]
+                a = sym.setdefault(short, [0, 0.0])
+                a[0] += 1
+                a[1] += cv[cn]
+            for short, (c, v) in sorted(sym.items(), key=lambda kv: -kv[1][1])[:8]:
+                out.append(f"  {cn:<11} {short:<40} dispatches {c:>7} mean {v / c:>12.2f} KiB")
+                if factor is not None:
+                    e = rec.setdefault("symbols", {}).setdefault(short, {})
+                    e["dispatches"] = c
+                    e[f"{cn.lower()}_bytes_per_dispatch"] = v / c * 1024.0 * factor
     if record and rec["kinds"]:
         with open(traffic_path(workload, k), "w") as fh:
             json.dump(rec, fh, indent=1)
