@@ -19,14 +19,17 @@ namespace lamg {
 //    form costs more than it saves here: on the Chung-Lu graph with 4 columns a plain FP64
 //    solve took 1028 ms with it against 854 ms without, on the 128^3 grid with 32 columns
 //    419 against 406 ms (the FP32 cycles of the same solves: 633 and 311 ms either way).
-template <class T, int U>
+//  - Rows spread over many lanes (the long-row blocks) load predicated in both precisions:
+//    there most lanes hold one or two entries, and unconditional slots would issue U loads
+//    for each (Chung-Lu with one column: 463 against 386 ms).
+template <class T, int U, bool UNCOND = (sizeof(T) == 4)>
 __device__ inline T row_dot(const int32_t *__restrict__ ci, const T *__restrict__ v, const T *x,
                             int32_t j0, int32_t e, int32_t stride, int k, int col) {
     T acc = T(0);
     for (int32_t j = j0; j < e; j += U * stride) {
         int32_t cc[U];
         T vv[U], xx[U];
-        if constexpr (sizeof(T) == 4) {
+        if constexpr (UNCOND) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int32_t jj = j + u * stride;

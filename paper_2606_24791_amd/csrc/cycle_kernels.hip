@@ -290,7 +290,7 @@ __device__ __forceinline__ void csr_long_row(int64_t row, const int32_t *__restr
             if (ch.c1 != T(0)) oo = out[o];
         }
     }
-    if (col < k) acc = row_dot<T, 8>(ci, v, xin, b + sub, e, NT >> lkp, k, col);
+    if (col < k) acc = row_dot<T, 8, false>(ci, v, xin, b + sub, e, NT >> lkp, k, col);
     for (int o2 = kp; o2 < 64; o2 <<= 1) acc += __shfl_xor(acc, o2, 64);
     const int wave = tid >> 6, lane = tid & 63;
     if (lane < kp) part[wave][lane] = acc;
