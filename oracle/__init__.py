@@ -76,6 +76,9 @@ def lib():
         L.orc_gershgorin.argtypes = [C.c_int, _i32p, _i32p, _f64p]
         L.orc_cheb_sweep.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_double, C.c_double, C.c_int,
                                      C.c_void_p, _f64p, _f64p, _f64p]
+        L.orc_bjgs_sweep.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, C.c_void_p, _f64p,
+                                     _f64p]
+        L.orc_set_bj_block.argtypes = [C.c_void_p, C.c_int]
         L.orc_free.argtypes = [C.c_void_p]
         L.orc_nlevels.argtypes = [C.c_void_p]
         L.orc_level_info.argtypes = [C.c_void_p, C.c_int, np.ctypeslib.ndpointer(np.int64),
@@ -248,6 +251,16 @@ def cheb_sweep(rp, ci, v, lmax, f, x, ratio=30.0, degree=2):
     return x
 
 
+def bjgs_sweep(rp, ci, v, bs, f, x):
+    """One block-Jacobi Gauss-Seidel sweep (blocks of bs rows) in place on x (f may be None
+    for L x = 0)."""
+    n = rp.size - 1
+    x = np.ascontiguousarray(x, np.float64)
+    fp = None if f is None else np.ascontiguousarray(f, np.float64)
+    lib().orc_bjgs_sweep(n, rp, ci, v, int(bs), _p(fp), x, np.empty(n))
+    return x
+
+
 def recombine(phi, r, hphi, hr):
     """One fine-level recombination (in place on phi, r) over saved pairs."""
     m = len(hphi)
@@ -307,13 +320,19 @@ class Hierarchy:
         return lib().orc_nlevels(self._h)
 
     def level_info(self, l: int) -> dict:
-        s = np.zeros(8, np.int64)
+        s = np.zeros(9, np.int64)
         d = np.zeros(3)
         if lib().orc_level_info(self._h, l, s, d) != OK:
             raise IndexError(l)
         return dict(n=int(s[0]), nnz=int(s[1]), ncolors=int(s[2]), nc=int(s[3]),
                     n_cal2=int(s[4]), coarsest=bool(s[5]), elim=bool(s[6]), cheb=bool(s[7]),
-                    gamma=float(d[0]), tau=float(d[1]), cheb_lmax=float(d[2]))
+                    bjgs=bool(s[8]), gamma=float(d[0]), tau=float(d[1]),
+                    cheb_lmax=float(d[2]))
+
+    def set_bj_block(self, bs: int) -> None:
+        """Rows per block of the block-Jacobi Gauss-Seidel smoother (smoother 2)."""
+        if lib().orc_set_bj_block(self._h, int(bs)) != OK:
+            raise ValueError(bs)
 
     def export(self, l: int) -> dict:
         info = self.level_info(l)

@@ -26,6 +26,7 @@
 
 #define ORC_K 4 /* test vectors per level: LAMG+ fixes K = 4 (Sec. 3.3) */
 #define ORC_MAX_LEVELS 64
+#define ORC_BJ_BLOCK 256 /* rows per block of the block-Jacobi Gauss-Seidel smoother */
 
 enum {
     ORC_OK = 0,
@@ -63,6 +64,7 @@ typedef struct {
     int elim;         /* 1: low-degree elimination level (agg = coarse id, -1 on F) */
     int cheb;         /* 1: smoothed by Chebyshev polynomials instead of Gauss-Seidel */
     double cheb_lmax; /* Gershgorin bound of the spectrum of D^{-1} L */
+    int bjgs;         /* 1: smoothed by block-Jacobi Gauss-Seidel instead */
     int nc;           /* size of the next level */
     int n_cal2;       /* rows with two parents */
     double gamma, tau;
@@ -76,8 +78,10 @@ typedef struct {
     uint64_t seed;
     int n_direct;
     int enable_veto, enable_caliber2, enable_elim;
-    int smoother;       /* 0: multicolour GS; 1: Chebyshev on levels with many colours */
+    int smoother;       /* 0: multicolour GS; 1: Chebyshev on levels with many colours;
+                           2: block-Jacobi Gauss-Seidel on those levels */
     int cheb_colors;    /* ... more than this many colours */
+    int bj_block;       /* rows per block of the block-Jacobi Gauss-Seidel sweep */
     int cheb_degree;    /* residual evaluations per Chebyshev sweep */
     double cheb_ratio;  /* smoothed interval [lmax / ratio, lmax] */
     double q_guard, tau_soc, snap, elim_min;
@@ -829,6 +833,47 @@ void orc_cheb_sweep(int n, const int *rp, const int *ci, const double *v, double
 }
 
 /* ------------------------------------------------------------------------- */
+/* S14: block-Jacobi Gauss-Seidel, the other parallel substitute for Gauss-Seidel  */
+/* that Sec. 5 ("On the feasibility of a parallel LAMG+") names: the coupling     */
+/* between blocks is frozen                                                       */
+/* ------------------------------------------------------------------------- */
+
+/* One sweep on L x = f (f may be NULL for f = 0). The rows are cut into consecutive
+ * blocks of `bs` in their natural order; each block is relaxed by a Gauss-Seidel sweep in
+ * row order, x_u = (f_u - sum_{j != u} L_uj x_j) / L_uu with the sum in CSR order from
+ * +0.0, where x_j is the value just computed for j in u's block and the value at the
+ * start of the sweep for j in any other block. x0: scratch of n.
+ * Pinned: bs >= n is the natural-order forward Gauss-Seidel sweep (the lower-triangular
+ * solve (D + L_lower) x' = f - L_upper x), bs = 1 a Jacobi sweep, and any bs the
+ * triangular solve with the block-lower part of L. */
+void orc_bjgs_sweep(int n, const int *rp, const int *ci, const double *v, int bs,
+                    const double *f, double *x, double *x0) {
+    for (int u = 0; u < n; ++u) x0[u] = x[u];
+    for (int b0 = 0; b0 < n; b0 += bs) {
+        const int b1 = n - b0 > bs ? b0 + bs : n;
+        for (int u = b0; u < b1; ++u) {
+            double acc = 0.0, dg = 0.0;
+            for (int j = rp[u]; j < rp[u + 1]; ++j) {
+                const int c = ci[j];
+                if (c == u) {
+                    dg = v[j];
+                    continue;
+                }
+                acc = acc + v[j] * ((c >= b0 && c < b1) ? x[c] : x0[c]);
+            }
+            x[u] = ((f ? f[u] : 0.0) - acc) / dg;
+        }
+    }
+}
+
+/* Block size of the block-Jacobi Gauss-Seidel smoother (smoother 2) of a hierarchy. */
+int orc_set_bj_block(void *hp, int bs) {
+    if (!hp || bs < 1) return ORC_ERR_ARG;
+    ((ohier *)hp)->bj_block = bs;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
 /* S12: coarsest level, dense solve of (L + 11^T/n) y = f                       */
 /* ------------------------------------------------------------------------- */
 
@@ -950,6 +995,7 @@ int orc_setup(int n, const int *rp, const int *ci, const double *w, uint64_t see
     h->cheb_colors = 32;
     h->cheb_degree = 3;
     h->cheb_ratio = 5.0;
+    h->bj_block = ORC_BJ_BLOCK;
     int rc = ORC_OK;
     /* level 0 */
     olevel *l0 = &h->lev[0];
@@ -1009,6 +1055,7 @@ int orc_setup(int n, const int *rp, const int *ci, const double *w, uint64_t see
         }
         rc = build_level_data(h, l);
         if (rc) goto fail;
+        if (h->smoother == 2 && lv->ncolors > h->cheb_colors) lv->bjgs = 1;
         if (h->smoother == 1 && lv->ncolors > h->cheb_colors) {
             lv->cheb = 1;
             lv->cheb_lmax = orc_gershgorin(lv->L.n, lv->L.rp, lv->L.ci, lv->L.v);
@@ -1081,8 +1128,8 @@ void orc_free(void *hp) {
 
 int orc_nlevels(const void *hp) { return ((const ohier *)hp)->nlev; }
 
-/* sizes[0..7] = n, nnz, ncolors, nc, n_cal2, coarsest, elim, cheb; sched = gamma, tau,
- * Chebyshev spectral bound */
+/* sizes[0..8] = n, nnz, ncolors, nc, n_cal2, coarsest, elim, cheb, bjgs; sched = gamma,
+ * tau, Chebyshev spectral bound */
 int orc_level_info(const void *hp, int l, long long *sizes, double *sched) {
     const ohier *h = (const ohier *)hp;
     if (l < 0 || l >= h->nlev) return ORC_ERR_ARG;
@@ -1095,6 +1142,7 @@ int orc_level_info(const void *hp, int l, long long *sizes, double *sched) {
     sizes[5] = lv->coarsest;
     sizes[6] = lv->elim;
     sizes[7] = lv->cheb;
+    sizes[8] = lv->bjgs;
     sched[0] = lv->gamma;
     sched[1] = lv->tau;
     sched[2] = lv->cheb_lmax;
@@ -1184,13 +1232,16 @@ static void recombine2(int n, double *e, double *rho, const double *e1, const do
     }
 }
 
-/* One relaxation sweep of a level: multicolour Gauss-Seidel, or a Chebyshev sweep on
- * the levels marked for it (work vectors r, d of the level's size). */
+/* One relaxation sweep of a level: multicolour Gauss-Seidel, or a Chebyshev or
+ * block-Jacobi Gauss-Seidel sweep on the levels marked for it (work vectors r, d of the
+ * level's size). */
 static void smooth_level(const ohier *h, const olevel *lv, double *r, double *d, const double *f,
                          double *phi) {
     if (lv->cheb)
         orc_cheb_sweep(lv->L.n, lv->L.rp, lv->L.ci, lv->L.v, lv->cheb_lmax, h->cheb_ratio,
                        h->cheb_degree, f, phi, r, d);
+    else if (lv->bjgs)
+        orc_bjgs_sweep(lv->L.n, lv->L.rp, lv->L.ci, lv->L.v, h->bj_block, f, phi, r);
     else
         orc_gs_sweep_multi(lv->L.n, lv->L.rp, lv->L.ci, lv->L.v, lv->color, lv->ncolors, 1, f,
                            phi);
