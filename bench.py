@@ -56,6 +56,7 @@ KIND_SYMBOLS = {  # kernel kinds and the kernel symbols a rocprofv3 trace shows 
     "vector": "k_copy / k_fill / k_gather_cols / k_scatter_cols / k_sub_col / k_to_f32_scaled / "
               "k_add_scaled_f32 / k_zero_cols / k_to_cols / k_from_cols / k_fill_i64 / k_coarsest",
     "cheb": "k_csr / k_csr_vec / k_csr_mixed / k_csr_mixed_vec / k_csr_long with OP_CHEB (3) + k_add_into",
+    "bjgs": "k_bjgs (+ the residual launch before it, which a trace counts as residual)",
 }
 
 
@@ -72,6 +73,8 @@ def kernel_kind(name: str):
     prec = "fp32" if "<float" in base else ("fp64" if "<double" in base else None)
     if "k_tail" in base:
         return "tail", prec
+    if "k_bjgs" in base:
+        return "bjgs", prec
     for key, kind in (("k_prolong", "prolong"), ("k_inject_add", "prolong"), ("k_red_", "reduce"),
                       ("k_rc2_", "reduce"), ("k_rcf_update", "reduce"), ("k_add_into", "cheb")):
         if key in base:
@@ -271,7 +274,8 @@ def main() -> int:
     ap.add_argument("--tail-rows", type=int, default=-1,
                     help="coarse-tail threshold option (-1: library default)")
     ap.add_argument("--smoother", type=int, default=0,
-                    help="0: multicolour Gauss-Seidel; 1: Chebyshev on levels with > 32 colours")
+                    help="0: multicolour Gauss-Seidel; 1: Chebyshev on levels with > 32 colours; "
+                         "2: block-Jacobi Gauss-Seidel on those levels")
     ap.add_argument("--tail-finest", type=int, default=0,
                     help="FP32+IR cycles of a finest level up to this size run wholly in the "
                          "coarse tail (0: library default, never)")
@@ -509,8 +513,10 @@ def main() -> int:
             "setup_s": round(hi["setup_seconds"], 3),
             "setup_phases_ms": {k: round(1e3 * v, 1) for k, v in hi["setup_phases"].items()},
             "elimination": bool(opts.elimination), "elimination_levels": sum(hi["elim"]),
-            "smoother": "chebyshev on levels with > 32 colours" if opts.smoother else "gauss-seidel",
+            "smoother": {0: "gauss-seidel", 1: "chebyshev on levels with > 32 colours",
+                         2: "block-jacobi gauss-seidel on levels with > 32 colours"}[opts.smoother],
             "chebyshev_levels": sum(hi["cheb"]),
+            "block_jacobi_levels": sum(hi["bjgs"]),
             "tail_level": hi["tail_level"],
         },
         "latency_ms": {"p50": r["p50_ms"], "p99": r["p99_ms"]},

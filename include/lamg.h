@@ -108,7 +108,13 @@ typedef struct {
                                 the Jacobi-scaled operator D^{-1} L -- the polynomial substitute
                                 for Gauss-Seidel named in Sec. 5 -- of degree 3 on
                                 [lmax / 5, lmax], lmax = the Gershgorin bound of D^{-1} L; one
-                                polynomial per Gauss-Seidel sweep it replaces. */
+                                polynomial per Gauss-Seidel sweep it replaces. 2: the same
+                                levels are smoothed instead by block-Jacobi Gauss-Seidel, the
+                                other substitute Sec. 5 names: the rows in blocks of 256 in
+                                their natural order, a Gauss-Seidel sweep in row order inside
+                                each block, the entries of other blocks read at their values
+                                from the start of the sweep; one such sweep per Gauss-Seidel
+                                sweep it replaces. */
     int32_t graphs;          /* 1: from the second solve with the same precision and column
                                 count, each cycle's launch sequence (which depends only on the
                                 cycle's index within the solve) is captured once as a HIP graph
@@ -173,6 +179,7 @@ typedef struct {
     double cheb_lmax[LAMG_MAX_LEVELS];   /* their Gershgorin bound of D^{-1} L (0 otherwise) */
     double setup_phase_seconds[LAMG_SETUP_PHASES]; /* wall time of lamg_setup by phase, summed
                                                        over the levels (lamg_setup_phase) */
+    int32_t bjgs[LAMG_MAX_LEVELS];       /* 1: smoothed by block-Jacobi Gauss-Seidel (smoother 2) */
 } lamg_hier_info;
 
 /* Solve statistics. The caller may point the array fields at host arrays (or leave them
@@ -328,7 +335,9 @@ typedef enum {
                                  recombination sums, norms, means (in-situ timer only) */
     LAMG_KERNEL_VECTOR = 6,   /* elementwise vector kernels: copies, fills, precision and
                                  layout conversions, the coarsest dense solve (in-situ only) */
-    LAMG_KERNEL_CHEB = 7      /* one Chebyshev step (smoother 1; in-situ timer only) */
+    LAMG_KERNEL_CHEB = 7,     /* one Chebyshev step (smoother 1; in-situ timer only) */
+    LAMG_KERNEL_BJGS = 8      /* one block-Jacobi Gauss-Seidel sweep: the snapshot copy and the
+                                 sweep (smoother 2; in-situ timer only) */
 } lamg_kernel;
 
 /* Measurement aid for roofline reporting: launches one cycle kernel of level `level`

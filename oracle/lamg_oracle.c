@@ -26,7 +26,7 @@
 
 #define ORC_K 4 /* test vectors per level: LAMG+ fixes K = 4 (Sec. 3.3) */
 #define ORC_MAX_LEVELS 64
-#define ORC_BJ_BLOCK 256 /* rows per block of the block-Jacobi Gauss-Seidel smoother */
+#define ORC_BJ_BLOCK 64 /* rows per block of the block-Jacobi Gauss-Seidel smoother */
 
 enum {
     ORC_OK = 0,

@@ -169,7 +169,7 @@ lamg_status lamg_setup(const lamg_graph *g, const lamg_options *opt, void *strea
     lamg_default_options(&o);
     if (opt) o = *opt;
     if (o.n_direct < 1 || o.n_direct > 1024 || o.kappa < 0 || o.kappa > 4 || o.tail_rows < 0 ||
-        (o.elimination != 0 && o.elimination != 1) || (o.smoother != 0 && o.smoother != 1) ||
+        (o.elimination != 0 && o.elimination != 1) || (o.smoother < 0 || o.smoother > 2) ||
         (o.graphs != 0 && o.graphs != 1) || o.tail_finest < 0 || o.tail_finest > 65535)
         return LAMG_INVALID_ARG;
     lamg_handle *h = nullptr;
@@ -296,6 +296,7 @@ lamg_status lamg_hierarchy_info(const lamg_handle *h, lamg_hier_info *info) {
         info->elim[l] = L.elim ? 1 : 0;
         info->cheb[l] = L.cheb ? 1 : 0;
         info->cheb_lmax[l] = L.cheb ? L.cheb_lmax : 0.0;
+        info->bjgs[l] = L.bjgs ? 1 : 0;
         info->n_caliber2[l] = L.coarsest ? 0 : L.n_cal2;
         info->gamma[l] = L.coarsest ? 0.0 : L.gamma;
         info->tau[l] = L.coarsest ? 0.0 : L.tau;

@@ -1180,6 +1180,124 @@ void run_cheb_sweep(const SolveOp &op, double lmax, const T *v, const T *d, cons
     }
 }
 
+// Block-Jacobi Gauss-Seidel sweep (smoother 2) on L x = f, blocks of kBjBlock rows in their
+// natural order, after r = f - L x at the sweep's start: a row's right-hand side minus its
+// entries in other blocks is r + d x + (its in-block entries times x), all at the start
+// values, so the cross-block sums -- the hub rows' thousands of entries among them -- come
+// from the residual kernel, and this kernel keeps to one block per wave:
+//  - the block's start values, diagonals and in-block entries (the first kBjStage of them;
+//    blocks of hub rows read the rest from global memory) go to LDS, and every row's
+//    right-hand side for the block's sweep is formed from them, rows side by side;
+//  - then the rows in order (kp column lanes x 64/kp entry lanes per row) gather their
+//    in-block entries from the LDS copy of the block's values, which holds the new value of
+//    every row already relaxed and the start value of the others; the new value goes to
+//    LDS and to x. The wave's LDS accesses complete in program order, so each row sees the
+//    rows before it.
+constexpr int kBjStage = 1024;
+
+template <class T>
+struct BjArgs {
+    const int32_t *rows, *irp;
+    const uint8_t *iloc;
+    const T *iv, *d, *dinv, *r;
+    T *x;
+};
+
+namespace {
+template <class T>
+__global__ void __launch_bounds__(64) k_bjgs(int64_t n, int k, int lkp, BjArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char bj_smem[];
+    __shared__ T dv[kBjBlock], dg[kBjBlock], ivs[kBjStage];
+    __shared__ int32_t rs[kBjBlock], ir[kBjBlock + 1];
+    __shared__ uint8_t ils[kBjStage];
+    const int kp = 1 << lkp;
+    T *xs = reinterpret_cast<T *>(bj_smem);  // [kBjBlock][kp]: the block's current values
+    T *fs = xs + kBjBlock * kp;              // [kBjBlock][kp]: right-hand sides of the block
+    const int lane = threadIdx.x;
+    const int64_t b0 = (int64_t)blockIdx.x * kBjBlock;
+    const int nb = (int)min((int64_t)kBjBlock, n - b0);
+    const int ib = a.irp[b0];
+    for (int t = lane; t <= nb; t += 64) ir[t] = a.irp[b0 + t] - ib;
+    const int ni = a.irp[b0 + nb] - ib;
+    const int ns = min(ni, kBjStage);
+    for (int e = lane; e < ns; e += 64) {
+        ils[e] = a.iloc[ib + e];
+        ivs[e] = a.iv[ib + e];
+    }
+    for (int t = lane; t < nb; t += 64) {
+        const int i = a.rows[b0 + t];
+        rs[t] = i;
+        dv[t] = a.dinv[i];
+        dg[t] = a.d[i];
+    }
+    __syncthreads();
+    for (int q = lane; q < (nb << lkp); q += 64) {
+        const int t = q >> lkp, c = q & (kp - 1);
+        if (c < k) xs[q] = a.x[(int64_t)rs[t] * k + c];
+    }
+    __syncthreads();
+    for (int q = lane; q < (nb << lkp); q += 64) {
+        const int t = q >> lkp, c = q & (kp - 1);
+        if (c >= k) continue;
+        T s = a.r[(int64_t)rs[t] * k + c] + dg[t] * xs[q];
+        for (int j = ir[t]; j < ir[t + 1]; ++j)
+            s += (j < ns ? ivs[j] : a.iv[ib + j]) * xs[(j < ns ? ils[j] : a.iloc[ib + j]) * kp + c];
+        fs[q] = s;
+    }
+    __syncthreads();
+    const int c = lane & (kp - 1);
+    const int s2 = lane >> lkp, g2 = 64 >> lkp;
+    for (int t = 0; t < nb; ++t) {
+        const int j1 = ir[t + 1];
+        T acc = T(0);
+        if (c < k)
+            for (int j = ir[t] + s2; j < j1; j += g2) {
+                int lc;
+                T vv;
+                if (j < ns) {
+                    lc = ils[j];
+                    vv = ivs[j];
+                } else {
+                    lc = a.iloc[ib + j];
+                    vv = a.iv[ib + j];
+                }
+                acc += vv * xs[lc * kp + c];
+            }
+        for (int o = kp; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
+        if (s2 == 0 && c < k) {
+            const T xn = (fs[t * kp + c] - acc) * dv[t];
+            xs[t * kp + c] = xn;
+            a.x[(int64_t)rs[t] * k + c] = xn;
+        }
+    }
+}
+}  // namespace
+
+template <class T>
+void run_bjgs_sweep(const SolveOp &op, const T *v, const T *d, const T *dinv, const T *f, T *x,
+                    T *r, int k, hipStream_t s, bool fine) {
+    if (op.n <= 0) return;
+    if (k < 1 || k > 32) throw Error(LAMG_INVALID_ARG, "block-Jacobi sweep: column count");
+    run_residual<T>(op, v, d, x, f, r, k, s, fine);
+    const int lkp = kp_log2(k);
+    BjArgs<T> a;
+    a.rows = op.bj_rows.p;
+    a.irp = op.bj_irp.p;
+    a.iloc = op.bj_iloc.p;
+    if constexpr (sizeof(T) == 8)
+        a.iv = op.bj_iv64.p;
+    else
+        a.iv = op.bj_iv32.p;
+    a.d = d;
+    a.dinv = dinv;
+    a.r = r;
+    a.x = x;
+    const uint32_t lds = (uint32_t)(2 * (size_t)kBjBlock * ((size_t)1 << lkp) * sizeof(T));
+    launch_kernel(k_bjgs<T>, dim3((unsigned)((op.n + kBjBlock - 1) / kBjBlock)), dim3(64), lds, s,
+                  op.n, k, lkp, a);
+    LAMG_LAUNCH_CHECK();
+}
+
 template <class T>
 void run_inject_add(const SolveOp &op, const T *ec, T *x, int k, hipStream_t s) {
     if (op.nc <= 0) return;
@@ -1376,6 +1494,8 @@ void run_zero_cols(int64_t n, int k, const int32_t *zero_mask, double *x, hipStr
     template void run_inject_add<T>(const SolveOp &, const T *, T *, int, hipStream_t);           \
     template void run_cheb_sweep<T>(const SolveOp &, double, const T *, const T *, const T *,     \
                                     const T *, T *, T *, int, hipStream_t, bool);                 \
+    template void run_bjgs_sweep<T>(const SolveOp &, const T *, const T *, const T *, const T *,  \
+                                    T *, T *, int, hipStream_t, bool);                            \
     template void run_mu_prolong<T>(const SolveOp &, const T *, const T *, int64_t, const T *,    \
                                     const T *, const T *, int, double *, double *, T *,           \
                                     hipStream_t);                                                 \

@@ -38,7 +38,8 @@ constexpr int kGraphSets = 2;          // (precision, columns) pairs with cached
 constexpr int kGraphMaxCycles = 64;    // later cycles of a solve are launched kernel by kernel
 constexpr int kChebColors = 32;      // smoother 1: levels with more colours use Chebyshev
 constexpr int kChebDegree = 3;       // residual evaluations per Chebyshev sweep
-constexpr double kChebRatio = 5.0;   // smoothed interval [lmax / kChebRatio, lmax]     // solves with more columns run every step as its own kernel
+constexpr double kChebRatio = 5.0;   // smoothed interval [lmax / kChebRatio, lmax]
+constexpr int kBjBlock = 64;         // smoother 2: rows per block-Jacobi Gauss-Seidel block
 constexpr int kElimMaxDegree = 4;   // eliminated nodes have at most this many neighbours
 constexpr double kElimMinFrac = 0.1;  // an elimination level removes at least this share
 
@@ -184,6 +185,14 @@ struct SolveOp {
     DArr<int32_t> ell_ci;
     DArr<double> ell_v64;
     DArr<float> ell_v32;
+    // block-Jacobi Gauss-Seidel (smoother 2), in the level's natural row order (block b =
+    // rows [b kBjBlock, (b + 1) kBjBlock)): each row's solve index and its off-diagonal
+    // entries whose column lies in its block (column as the position in the block, CSR order)
+    int64_t bj_ni = 0;  // in-block entries
+    DArr<int32_t> bj_rows, bj_irp;
+    DArr<uint8_t> bj_iloc;
+    DArr<double> bj_iv64;
+    DArr<float> bj_iv32;
 };
 
 struct Level {
@@ -191,6 +200,7 @@ struct Level {
     bool coarsest = false;
     bool elim = false;  // elimination level: h_agg = coarse id of kept nodes, -1 on F
     bool cheb = false;        // smoothed by Chebyshev polynomials (smoother option 1)
+    bool bjgs = false;        // smoothed by block-Jacobi Gauss-Seidel (smoother option 2)
     double cheb_lmax = 0.0;   // Gershgorin bound of the spectrum of D^{-1} L
     std::vector<int32_t> h_rp, h_ci;  // canonical pattern on the host
     DArr<int32_t> rp, ci;             // canonical CSR on the device
@@ -285,7 +295,7 @@ void clear_graphs(Workspace &w);
 // itself (hipExtLaunchKernel takes the dispatch's own start and end timestamps), so the
 // elapsed time is the kernel's execution time without stream-marker overhead.
 struct KTimer {
-    static constexpr int kKinds = 8;
+    static constexpr int kKinds = 9;
     bool on = false;
     bool all = false;  // every launch of every level (else the timed level, the tail and the
                        // FP64 outer residual)
@@ -416,6 +426,11 @@ void run_residual_color(const SolveOp &op, int c, const T *v, const T *d, const 
 template <class T>
 void run_cheb_sweep(const SolveOp &op, double lmax, const T *v, const T *d, const T *dinv,
                     const T *f, T *x, T *dvec, int k, hipStream_t s, bool fine);
+// One block-Jacobi Gauss-Seidel sweep on L x = f (blocks of kBjBlock rows in the natural
+// order); r (n*k) is work space, the residual at the sweep's start.
+template <class T>
+void run_bjgs_sweep(const SolveOp &op, const T *v, const T *d, const T *dinv, const T *f, T *x,
+                    T *r, int k, hipStream_t s, bool fine);
 // x += e_c on the kept rows of an elimination level (its one-entry-per-row P^T).
 template <class T>
 void run_inject_add(const SolveOp &op, const T *ec, T *x, int k, hipStream_t s);

@@ -456,6 +456,45 @@ static void build_solve_op(lamg_handle *h, int l, const std::vector<int32_t> &pe
     launch_permute_csr(n, op.perm.p, d_iperm.p, L.rp.p, L.ci.p, L.val.p, op.rp.p, op.ci.p, op.v64.p,
                        f32 ? op.v32.p : nullptr, op.d64.p, op.dinv64.p, f32 ? op.d32.p : nullptr,
                        f32 ? op.dinv32.p : nullptr, s);
+    if (L.bjgs) {
+        // block-Jacobi Gauss-Seidel: rows in natural order and, per row, its entries inside
+        // its block (canonical entry order kept)
+        std::vector<double> hv((size_t)L.nnz);
+        L.val.download(hv.data(), L.nnz, s);
+        LAMG_HIP(hipStreamSynchronize(s));
+        std::vector<int32_t> irp(n + 1, 0);
+        std::vector<uint8_t> iloc;
+        std::vector<double> iv;
+        for (int64_t u = 0; u < n; ++u) {
+            const int64_t b0 = (u / kBjBlock) * kBjBlock;
+            for (int32_t j = L.h_rp[u]; j < L.h_rp[u + 1]; ++j) {
+                const int32_t c = L.h_ci[j];
+                if (c != u && c >= b0 && c < b0 + kBjBlock) {
+                    iloc.push_back((uint8_t)(c - b0));
+                    iv.push_back(hv[j]);
+                }
+            }
+            irp[u + 1] = (int32_t)iloc.size();
+        }
+        const int64_t ni = (int64_t)iloc.size();
+        op.bj_ni = ni;
+        op.bj_rows.alloc(pool, n);
+        op.bj_irp.alloc(pool, n + 1);
+        op.bj_iloc.alloc(pool, std::max<int64_t>(ni, 1));
+        op.bj_iv64.alloc(pool, std::max<int64_t>(ni, 1));
+        op.bj_rows.upload(iperm.data(), n, s);
+        op.bj_irp.upload(irp.data(), n + 1, s);
+        op.bj_iloc.upload(iloc.data(), ni, s);
+        op.bj_iv64.upload(iv.data(), ni, s);
+        std::vector<float> iv32;
+        if (f32) {
+            iv32.assign(iv.begin(), iv.end());
+            op.bj_iv32.alloc(pool, std::max<int64_t>(ni, 1));
+            op.bj_iv32.upload(iv32.data(), ni, s);
+        }
+        // the uploads read host vectors that end with this block
+        LAMG_HIP(hipStreamSynchronize(s));
+    }
     // ELL copy for the coarse tail: every row (long ones too) of levels below 65536 rows
     // whose longest row has at most kEllMaxWidth entries, when padding at most quadruples
     // the entries
@@ -643,6 +682,7 @@ void run_setup(lamg_handle *h, const lamg_graph *g) {
         }
         if (eliminated) continue;
         setup_level(h, l);
+        if (h->opt.smoother == 2 && L.ncolors > kChebColors) L.bjgs = true;
         if (h->opt.smoother == 1 && L.ncolors > kChebColors) {
             // Chebyshev smoothing on this dense level: the Gershgorin bound of D^{-1} L
             PhaseClock pc(h, LAMG_SETUP_LEVEL);

@@ -104,6 +104,13 @@ double bytes_sweep(const SolveOp &op, int k, double s) {
     for (int c = 0; c < op.ncolors; ++c) b += bytes_gs_color(op, c, k, s);
     return b;
 }
+// block-Jacobi Gauss-Seidel sweep after the residual: each in-block entry once (1-byte
+// position and value), the two row arrays, the diagonal and its inverse, and per column the
+// residual and x read and x written
+double bytes_bjgs(const SolveOp &op, int k, double s) {
+    const double n = (double)op.n;
+    return (double)op.bj_ni * (1.0 + s) + 4.0 * (2.0 * n + 1.0) + 2.0 * n * s + 3.0 * k * n * s;
+}
 
 // One launch, or a short group of launches of one kernel kind: its algorithmic bytes go
 // into the solve's total, and while the in-situ timer is on and the launch is in its scope
@@ -219,15 +226,16 @@ int tail_level(const lamg_handle *h, int k, bool fp32) {
             break;
         }
     if (l0 < 0) return -1;
-    // levels smoothed by Chebyshev polynomials stay with the per-step kernels
+    // levels smoothed by Chebyshev polynomials or block-Jacobi Gauss-Seidel stay with the
+    // per-step kernels
     for (int l = h->nlev - 1; l >= 0; --l)
-        if (h->lev[l].cheb) {
+        if (h->lev[l].cheb || h->lev[l].bjgs) {
             if (l0 <= l) l0 = l + 1;
             break;
         }
     if (l0 >= h->nlev) return -1;
     while (l0 > 1) {
-        if (h->lev[l0 - 1].cheb) break;
+        if (h->lev[l0 - 1].cheb || h->lev[l0 - 1].bjgs) break;
         const Level &L = h->lev[l0 - 1];
         const SolveOp &op = L.op;
         if (L.coarsest || L.n >= 65536) break;
@@ -243,7 +251,7 @@ int tail_level(const lamg_handle *h, int k, bool fp32) {
     }
     const Level &F = h->lev[0];
     if (fp32 && l0 == 1 && h->opt.tail_finest > 0 && F.n <= h->opt.tail_finest && F.n < 65536 &&
-        !F.coarsest && !F.cheb)
+        !F.coarsest && !F.cheb && !F.bjgs)
         l0 = 0;
     return l0;
 }
@@ -342,6 +350,15 @@ void cycle(Cycle<T> &C, int l, T *x, const T *f) {
                          kChebDegree * (bytes_residual(op, k, sz) + 3.0 * k * op.n * sz), nar);
                 run_cheb_sweep<T>(op, L.cheb_lmax, P::v(op), P::d(op), P::dinv(op), f, x, me.r.p,
                                   k, s, l == C.lt);
+            }
+            return;
+        }
+        if (L.bjgs) {  // block-Jacobi Gauss-Seidel sweeps (smoother option 2), in me.r as work space
+            for (int sw = 0; sw < sweeps; ++sw) {
+                Timed tm(h, LAMG_KERNEL_BJGS, pid, bytes_residual(op, k, sz) + bytes_bjgs(op, k, sz),
+                         nar);
+                run_bjgs_sweep<T>(op, P::v(op), P::d(op), P::dinv(op), f, x, me.r.p, k, s,
+                                  l == C.lt);
             }
             return;
         }

@@ -52,7 +52,8 @@ class lamg_hier_info(C.Structure):
                 ("bytes_peak", C.c_int64), ("elim", C.c_int32 * MAX_LEVELS),
                 ("tail_level", C.c_int32), ("timed_level", C.c_int32),
                 ("cheb", C.c_int32 * MAX_LEVELS), ("cheb_lmax", C.c_double * MAX_LEVELS),
-                ("setup_phase_seconds", C.c_double * SETUP_PHASES)]
+                ("setup_phase_seconds", C.c_double * SETUP_PHASES),
+                ("bjgs", C.c_int32 * MAX_LEVELS)]
 
 
 class lamg_solve_info(C.Structure):
@@ -103,8 +104,9 @@ _lib.lamg_profile_kernel.argtypes = [C.c_void_p, C.c_int32, C.c_int, C.c_int, C.
 _lib.lamg_profile_kernel.restype = C.c_int
 
 (KERNEL_GS_COLOR, KERNEL_RESIDUAL, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_TAIL, KERNEL_REDUCE,
- KERNEL_VECTOR, KERNEL_CHEB) = range(8)
-KERNEL_NAMES = ("gs_color", "residual", "restrict", "prolong", "tail", "reduce", "vector", "cheb")
+ KERNEL_VECTOR, KERNEL_CHEB, KERNEL_BJGS) = range(9)
+KERNEL_NAMES = ("gs_color", "residual", "restrict", "prolong", "tail", "reduce", "vector", "cheb",
+                "bjgs")
 
 
 class lamg_kernel_time(C.Structure):
@@ -360,7 +362,7 @@ def lamg_hierarchy_info(h: Handle) -> dict:
                 setup_seconds=float(info.setup_seconds), bytes_peak=int(info.bytes_peak),
                 elim=[bool(e) for e in info.elim[:L]], tail_level=int(info.tail_level),
                 timed_level=int(info.timed_level), cheb=[bool(c) for c in info.cheb[:L]],
-                cheb_lmax=list(info.cheb_lmax[:L]),
+                cheb_lmax=list(info.cheb_lmax[:L]), bjgs=[bool(c) for c in info.bjgs[:L]],
                 setup_phases=dict(zip(SETUP_PHASE_NAMES, info.setup_phase_seconds)))
 
 

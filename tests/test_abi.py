@@ -88,7 +88,7 @@ def test_input_errors_are_reported_without_device():
     assert B.lamg_setup_status(good, B.lamg_default_options(n_direct=0)) == B.INVALID_ARG
     assert B.lamg_setup_status(good, B.lamg_default_options(kappa=5)) == B.INVALID_ARG
     assert B.lamg_setup_status(good, B.lamg_default_options(elimination=2)) == B.INVALID_ARG
-    assert B.lamg_setup_status(good, B.lamg_default_options(smoother=2)) == B.INVALID_ARG
+    assert B.lamg_setup_status(good, B.lamg_default_options(smoother=3)) == B.INVALID_ARG
     assert B.lamg_setup_status(good, B.lamg_default_options(graphs=-1)) == B.INVALID_ARG
     assert B.lamg_setup_status(good, B.lamg_default_options(tail_rows=-1)) == B.INVALID_ARG
     assert B.lamg_setup_status(good, B.lamg_default_options(n_direct=1025)) == B.INVALID_ARG

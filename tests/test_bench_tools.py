@@ -21,6 +21,8 @@ import bench
     ("lamg::k_rcf_update(long, int)", ("reduce", "fp64")),
     ("k_prolong_mu<float>(long)", ("prolong", "fp32")),
     ("void lamg::k_from_cols<float>", ("vector", "fp32")),
+    ("void lamg::(anonymous namespace)::k_bjgs<double>(long, int, int, lamg::BjArgs<double>)",
+     ("bjgs", "fp64")),
     ("__amd_rocclr_copyBuffer", (None, None)),
     ("k_tv_sweep_long(long, int const*)", (None, None)),
 ])

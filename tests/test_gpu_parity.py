@@ -660,3 +660,55 @@ def test_solve_parity_chebyshev(B, name, prec):
     p = B.FP64 if prec == "fp64" else B.FP32_IR
     st, ph, bh, refs = solve_both(B, g, k, p, smoother=1)
     check_solution(g, st, ph, bh, refs)
+
+
+# --- Block-Jacobi Gauss-Seidel on the dense levels (smoother option 2) ----------------------
+
+
+@pytest.mark.parametrize("name", list(CHEB_GRAPHS))
+def test_block_jacobi_levels_match(B, name):
+    g = CHEB_GRAPHS[name]()
+    note(f"block-Jacobi setup {name}")
+    oh = O.Hierarchy(g, seed=1, smoother=2)
+    h = B.lamg_setup(g, B.lamg_default_options(smoother=2))
+    info = B.lamg_hierarchy_info(h)
+    assert info["levels"] == oh.nlevels
+    for l in range(oh.nlevels):
+        assert info["bjgs"][l] == oh.level_info(l)["bjgs"], l
+        assert not info["cheb"][l]
+    assert any(info["bjgs"])
+    assert info["tail_level"] < 0 or info["tail_level"] > max(
+        l for l in range(info["levels"]) if info["bjgs"][l])
+    h.close()
+
+
+@pytest.mark.parametrize("name,k", [("chunglu", 3), ("chunglu_dense", 1), ("chunglu", 9)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32ir"])
+def test_solve_parity_block_jacobi(B, name, k, prec):
+    """k = 1, 3 and 9 take the kernel's three lane layouts (8, 2 and 1 entry lanes per row
+    beside the column lanes while the cross-block sums are formed)."""
+    g = CHEB_GRAPHS[name]()
+    note(f"block-Jacobi solve parity {name} {prec} k={k}")
+    p = B.FP64 if prec == "fp64" else B.FP32_IR
+    st, ph, bh, refs = solve_both(B, g, k, p, smoother=2)
+    check_solution(g, st, ph, bh, refs)
+
+
+def test_block_jacobi_first_cycle_matches_oracle(B):
+    """The relative residual after the first FP64 cycle (every block-Jacobi level smoothed
+    once per visit) agrees with the oracle's to rounding."""
+    import torch
+
+    g = CHEB_GRAPHS["chunglu"]()
+    note("block-Jacobi first cycle")
+    oh = O.Hierarchy(g, seed=1, smoother=2)
+    h = B.lamg_setup(g, B.lamg_default_options(smoother=2))
+    bh = I.rhs(g.n, 1, seed=4)
+    b = torch.tensor(bh, device="cuda")
+    phi = torch.empty_like(b)
+    st = B.lamg_solve(h, b, phi, tol=TOL, max_cycles=100, precision=B.FP64, history=True)
+    _, so, hist = oh.solve(bh[0], TOL, 100)
+    assert st["history"][0] == 1.0 and hist[0] == 1.0
+    assert abs(st["history"][1] - hist[1]) <= 1e-6 * hist[1], (st["history"][1], hist[1])
+    assert st["cycles"] == so["cycles"]
+    h.close()
