@@ -74,7 +74,8 @@ class Server:
                  use_torch_allocator: bool = True, estimate=None, smoother: int = 0,
                  hip_graphs: bool = False, group: int = 0):
         self.graphs = graphs
-        self.smoother = smoother  # setup option: 1 = Chebyshev on levels with many colours
+        # setup option: 1 = Chebyshev, 2 = block-Jacobi Gauss-Seidel, on levels with many colours
+        self.smoother = smoother
         self.hip_graphs = hip_graphs  # setup option: replay repeated cycles as HIP graphs
         # up to this many batches on different graphs per lamg_solve_group call (0/1: none);
         # hierarchies are then built to run the whole FP32 cycle of small graphs in the tail
@@ -579,7 +580,8 @@ def main(argv=None) -> int:
                     help="run one stream at this offered rate (requests/s) instead")
     ap.add_argument("--log-batches", action="store_true")
     ap.add_argument("--smoother", type=int, default=0,
-                    help="0: multicolour Gauss-Seidel; 1: Chebyshev on levels with > 32 colours")
+                    help="0: multicolour Gauss-Seidel; 1: Chebyshev on levels with > 32 colours; "
+                         "2: block-Jacobi Gauss-Seidel on those levels")
     ap.add_argument("--hip-graphs", action="store_true",
                     help="replay each cycle of repeated (precision, columns) solves as a HIP graph")
     ap.add_argument("--group", type=int, default=0,
