@@ -79,6 +79,8 @@ def lib():
         L.orc_bjgs_sweep.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, C.c_void_p, _f64p,
                                      _f64p]
         L.orc_set_bj_block.argtypes = [C.c_void_p, C.c_int]
+        L.orc_rcm.restype = C.c_int
+        L.orc_rcm.argtypes = [C.c_int, _i32p, _i32p, _i32p]
         L.orc_free.argtypes = [C.c_void_p]
         L.orc_nlevels.argtypes = [C.c_void_p]
         L.orc_level_info.argtypes = [C.c_void_p, C.c_int, np.ctypeslib.ndpointer(np.int64),
@@ -261,6 +263,35 @@ def bjgs_sweep(rp, ci, v, bs, f, x):
     return x
 
 
+def rcm(rp, ci):
+    """Self-gated reverse Cuthill-McKee order of an adjacency CSR: (perm, kept) with
+    perm[new] = old (the identity when the gate rejects the renumbering)."""
+    n = rp.size - 1
+    perm = np.empty(n, np.int32)
+    rc = lib().orc_rcm(n, np.ascontiguousarray(rp, np.int32), np.ascontiguousarray(ci, np.int32),
+                       perm)
+    if rc < 0:
+        raise MemoryError("orc_rcm")
+    return perm, bool(rc)
+
+
+def renumbered(g, perm):
+    """The graph with node perm[p] renamed p (columns ascending again in every row)."""
+    from paper_2606_24791_amd.inputs import Graph
+
+    n = g.n
+    iperm = np.empty(n, np.int64)
+    iperm[perm] = np.arange(n)
+    deg = np.diff(g.row_ptr)
+    rows = np.repeat(np.arange(n), deg)
+    nr, nc = iperm[rows], iperm[g.col_idx]
+    order = np.lexsort((nc, nr))
+    row_ptr = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(nr, minlength=n), out=row_ptr[1:])
+    return Graph(n, row_ptr.astype(np.int32), nc[order].astype(np.int32),
+                 np.asarray(g.weight, np.float64)[order], g.name)
+
+
 def recombine(phi, r, hphi, hr):
     """One fine-level recombination (in place on phi, r) over saved pairs."""
     m = len(hphi)
@@ -300,7 +331,16 @@ class Hierarchy:
 
     def __init__(self, g, seed: int = 1, n_direct: int = 512, enable_veto: bool = True,
                  enable_caliber2: bool = True, kappa: int = 4, elimination: bool = True,
-                 smoother: int = 0):
+                 smoother: int = 0, reorder: int = 0):
+        # reorder = 1: the hierarchy is built on the graph renumbered by the self-gated
+        # reverse Cuthill-McKee order (perm[new] = old, or None when not renumbered); levels,
+        # cycles and exports are in that numbering, solve() takes and returns the caller's
+        self.perm = None
+        if reorder:
+            perm, kept = rcm(g.row_ptr, g.col_idx)
+            if kept:
+                self.perm = perm
+                g = renumbered(g, perm)
         h = C.c_void_p()
         rc = lib().orc_setup(g.n, g.row_ptr, g.col_idx, np.ascontiguousarray(g.weight, np.float64),
                              seed, n_direct, int(enable_veto), int(enable_caliber2), kappa,
@@ -361,10 +401,16 @@ class Hierarchy:
     def solve(self, b, tol: float = 1e-8, max_cycles: int = 300):
         """Solve for one right-hand side; returns (phi, stats, history)."""
         b = np.ascontiguousarray(b, np.float64)
+        if self.perm is not None:
+            b = np.ascontiguousarray(b[self.perm])
         phi = np.empty(self.n)
         hist = np.zeros(max_cycles + 1)
         stats = np.zeros(4)
         rc = lib().orc_solve(self._h, b, tol, max_cycles, phi, _p(hist), stats)
+        if self.perm is not None:
+            out = np.empty_like(phi)
+            out[self.perm] = phi
+            phi = out
         cyc = int(stats[0])
         return phi, dict(rc=rc, cycles=cyc, relres=float(stats[1]), acf=float(stats[2]),
                          mu=float(stats[3]), converged=(rc == OK)), hist[: cyc + 1].copy()

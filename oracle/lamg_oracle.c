@@ -866,6 +866,140 @@ void orc_bjgs_sweep(int n, const int *rp, const int *ci, const double *v, int bs
     }
 }
 
+/* ------------------------------------------------------------------------- */
+/* S15: self-gated reverse Cuthill-McKee renumbering of the input graph, the     */
+/* reordering for cache locality that Sec. 4.2 lists among the implementation's  */
+/* constant-lowering features                                                    */
+/* ------------------------------------------------------------------------- */
+
+/* Breadth-first search from r over r's component: order[0..*cnt) in visiting order, the
+ * neighbours of each node taken in CSR order; level[u] = distance from r. Returns the
+ * eccentricity of r (the last level). mark[] holds `stamp` for visited nodes. */
+static int bfs_levels(const int *rp, const int *ci, int r, int *mark, int stamp, int *order,
+                      int *level, int *cnt) {
+    int head = 0, tail = 0;
+    order[tail++] = r;
+    mark[r] = stamp;
+    level[r] = 0;
+    while (head < tail) {
+        int u = order[head++];
+        for (int j = rp[u]; j < rp[u + 1]; ++j) {
+            int v = ci[j];
+            if (mark[v] == stamp) continue;
+            mark[v] = stamp;
+            level[v] = level[u] + 1;
+            order[tail++] = v;
+        }
+    }
+    *cnt = tail;
+    return level[order[tail - 1]];
+}
+
+/* The reverse Cuthill-McKee order of a graph given as a CSR without self-loops
+ * (perm[new] = old). Degree = number of stored neighbours. Components are taken in the
+ * order of their smallest node. A component starts at a pseudo-peripheral node (the
+ * George-Liu iteration): r = its node of least degree (ties: smallest index); breadth-first
+ * levels from r; x = the node of least degree (ties: smallest index) in the last level; if
+ * x's eccentricity exceeds r's, r = x and again, else r is the start. Cuthill-McKee from r:
+ * breadth first, each node's not yet numbered neighbours appended in order of increasing
+ * degree (ties: smallest index). The whole sequence is then reversed. Self-gate: the
+ * renumbering is kept only if it at least halves the mean index distance |u - v| over the
+ * entries (the sum, compared exactly in integers); returns 1 then, else 0 with perm the
+ * identity. */
+int orc_rcm(int n, const int *rp, const int *ci, int *perm) {
+    int *mark = (int *)calloc((size_t)n, sizeof(int));
+    int *order = (int *)malloc(sizeof(int) * (size_t)n);
+    int *level = (int *)malloc(sizeof(int) * (size_t)n);
+    int *done = (int *)calloc((size_t)n, sizeof(int));
+    int *nb = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    if (!mark || !order || !level || !done || !nb) {
+        free(mark);
+        free(order);
+        free(level);
+        free(done);
+        free(nb);
+        return -ORC_ERR_ALLOC;
+    }
+    int stamp = 0, pos = 0;
+    for (int s0 = 0; s0 < n; ++s0) {
+        if (done[s0]) continue;
+        int cnt = 0;
+        bfs_levels(rp, ci, s0, mark, ++stamp, order, level, &cnt);
+        int r = order[0];
+        for (int i = 1; i < cnt; ++i) {
+            int u = order[i], du = rp[u + 1] - rp[u], dr = rp[r + 1] - rp[r];
+            if (du < dr || (du == dr && u < r)) r = u;
+        }
+        int ecc = bfs_levels(rp, ci, r, mark, ++stamp, order, level, &cnt);
+        for (;;) {
+            int x = -1;
+            for (int i = 0; i < cnt; ++i) {
+                int u = order[i];
+                if (level[u] != ecc) continue;
+                if (x < 0) {
+                    x = u;
+                    continue;
+                }
+                int du = rp[u + 1] - rp[u], dx = rp[x + 1] - rp[x];
+                if (du < dx || (du == dx && u < x)) x = u;
+            }
+            int ecc_x = bfs_levels(rp, ci, x, mark, ++stamp, order, level, &cnt);
+            if (ecc_x > ecc) {
+                r = x;
+                ecc = ecc_x;
+            } else {
+                break;
+            }
+        }
+        /* Cuthill-McKee from r */
+        int head = pos;
+        perm[pos++] = r;
+        done[r] = 1;
+        while (head < pos) {
+            int u = perm[head++], m = 0;
+            for (int j = rp[u]; j < rp[u + 1]; ++j)
+                if (!done[ci[j]]) {
+                    done[ci[j]] = 1;
+                    nb[m++] = ci[j];
+                }
+            for (int a = 1; a < m; ++a) { /* insertion sort by (degree, index) */
+                int v = nb[a], dv = rp[v + 1] - rp[v], b = a - 1;
+                while (b >= 0) {
+                    int w = nb[b], dw = rp[w + 1] - rp[w];
+                    if (dw < dv || (dw == dv && w < v)) break;
+                    nb[b + 1] = w;
+                    --b;
+                }
+                nb[b + 1] = v;
+            }
+            for (int a = 0; a < m; ++a) perm[pos++] = nb[a];
+        }
+    }
+    for (int i = 0; i < n / 2; ++i) {
+        int t = perm[i];
+        perm[i] = perm[n - 1 - i];
+        perm[n - 1 - i] = t;
+    }
+    /* gate: summed index distance before and after (inverse of perm in `order`) */
+    for (int i = 0; i < n; ++i) order[perm[i]] = i;
+    long long sum0 = 0, sum1 = 0;
+    for (int u = 0; u < n; ++u)
+        for (int j = rp[u]; j < rp[u + 1]; ++j) {
+            long long d0 = (long long)u - ci[j], d1 = (long long)order[u] - order[ci[j]];
+            sum0 += d0 < 0 ? -d0 : d0;
+            sum1 += d1 < 0 ? -d1 : d1;
+        }
+    int keep = 2 * sum1 <= sum0;
+    if (!keep)
+        for (int i = 0; i < n; ++i) perm[i] = i;
+    free(mark);
+    free(order);
+    free(level);
+    free(done);
+    free(nb);
+    return keep;
+}
+
 /* Block size of the block-Jacobi Gauss-Seidel smoother (smoother 2) of a hierarchy. */
 int orc_set_bj_block(void *hp, int bs) {
     if (!hp || bs < 1) return ORC_ERR_ARG;
