@@ -45,6 +45,8 @@ WORKLOADS = {
     "aniso1024": "2D 5-point grid 1024x1024, weight 1 on x-edges and 1e-3 on y-edges",
     "chunglu2m": "Chung-Lu n=2M, degree exponent 2.1, mean degree 16, LCC, weights U[1,2]",
     "grid64": "2D 5-point grid 64x64, unit weights",
+    "rgg1m": "random geometric graph, 1M points in the unit square, mean degree 10, LCC, unit "
+             "weights, numbered in the points' random draw order",
 }
 KIND_SYMBOLS = {  # kernel kinds and the kernel symbols a rocprofv3 trace shows for them
     "gs_color": "k_csr / k_csr_vec / k_csr_mixed / k_csr_mixed_vec / k_csr_long with OP_GS (0)",
@@ -273,6 +275,9 @@ def main() -> int:
                          "the HBM byte counters of a profiler run)")
     ap.add_argument("--tail-rows", type=int, default=-1,
                     help="coarse-tail threshold option (-1: library default)")
+    ap.add_argument("--reorder", action="store_true",
+                    help="renumber the input by the self-gated reverse Cuthill-McKee order "
+                         "(option reorder)")
     ap.add_argument("--no-setup-warmup", action="store_true",
                     help="skip the untimed setup and solve of a small grid that precedes the "
                          "workload's setup (profiler runs: its kernels would enter their "
@@ -341,6 +346,8 @@ def main() -> int:
         over["tail_rows"] = args.tail_rows
     if args.smoother:
         over["smoother"] = args.smoother
+    if args.reorder:
+        over["reorder"] = 1
     if args.graphs:
         over["graphs"] = 1
     if args.tail_finest:
@@ -464,7 +471,7 @@ def main() -> int:
     cpu_line, errs = None, {}
     if pool is not None:
         oopts = dict(n_direct=opts.n_direct, elimination=bool(opts.elimination),
-                     smoother=int(opts.smoother))
+                     smoother=int(opts.smoother), reorder=int(opts.reorder))
         t = time.perf_counter()
         col0, phi0, ts0, tv0, cyc0 = pool.apply(oracle_column,
                                                 ((args.workload, k, 0, args.tol, oopts),))
@@ -536,6 +543,7 @@ def main() -> int:
                          2: "block-jacobi gauss-seidel on levels with > 32 colours"}[opts.smoother],
             "chebyshev_levels": sum(hi["cheb"]),
             "block_jacobi_levels": sum(hi["bjgs"]),
+            "reordered": hi["reordered"],
             "tail_level": hi["tail_level"],
         },
         "latency_ms": {"p50": r["p50_ms"], "p99": r["p99_ms"]},

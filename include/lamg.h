@@ -110,7 +110,7 @@ typedef struct {
                                 [lmax / 5, lmax], lmax = the Gershgorin bound of D^{-1} L; one
                                 polynomial per Gauss-Seidel sweep it replaces. 2: the same
                                 levels are smoothed instead by block-Jacobi Gauss-Seidel, the
-                                other substitute Sec. 5 names: the rows in blocks of 256 in
+                                other substitute Sec. 5 names: the rows in blocks of 64 in
                                 their natural order, a Gauss-Seidel sweep in row order inside
                                 each block, the entries of other blocks read at their values
                                 from the start of the sweep; one such sweep per Gauss-Seidel
@@ -132,6 +132,16 @@ typedef struct {
                                 one launch, and lamg_solve_group can make the launches of
                                 several such solves one. 0 (default): never; at most 65535.
                                 Changes only how the cycle is executed, not what it computes. */
+    int32_t reorder;         /* 1: the input graph is renumbered before the setup by the reverse
+                                Cuthill-McKee order (the reordering for cache locality of
+                                Sec. 4.2), self-gated: only if it at least halves the mean index
+                                distance |u - v| over the edges. Start node of each component
+                                (taken in the order of their smallest node) by the George-Liu
+                                iteration from its node of least degree, neighbours appended by
+                                increasing degree, ties by smallest index; the sequence then
+                                reversed. Levels, colourings and exports are in the renumbered
+                                order; solves take b and return phi in the caller's. 0
+                                (default): no renumbering. */
 } lamg_options;
 
 #define LAMG_MAX_LEVELS 64
@@ -180,6 +190,7 @@ typedef struct {
     double setup_phase_seconds[LAMG_SETUP_PHASES]; /* wall time of lamg_setup by phase, summed
                                                        over the levels (lamg_setup_phase) */
     int32_t bjgs[LAMG_MAX_LEVELS];       /* 1: smoothed by block-Jacobi Gauss-Seidel (smoother 2) */
+    int32_t reordered;                   /* 1: the input was renumbered (option reorder) */
 } lamg_hier_info;
 
 /* Solve statistics. The caller may point the array fields at host arrays (or leave them

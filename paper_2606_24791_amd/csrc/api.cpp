@@ -158,6 +158,7 @@ void lamg_default_options(lamg_options *opt) {
     opt->smoother = 0;
     opt->graphs = 0;
     opt->tail_finest = 0;
+    opt->reorder = 0;
 }
 
 lamg_status lamg_setup(const lamg_graph *g, const lamg_options *opt, void *stream,
@@ -169,7 +170,7 @@ lamg_status lamg_setup(const lamg_graph *g, const lamg_options *opt, void *strea
     lamg_default_options(&o);
     if (opt) o = *opt;
     if (o.n_direct < 1 || o.n_direct > 1024 || o.kappa < 0 || o.kappa > 4 || o.tail_rows < 0 ||
-        (o.elimination != 0 && o.elimination != 1) || (o.smoother < 0 || o.smoother > 2) ||
+        (o.elimination != 0 && o.elimination != 1) || (o.smoother < 0 || o.smoother > 2) || (o.reorder != 0 && o.reorder != 1) ||
         (o.graphs != 0 && o.graphs != 1) || o.tail_finest < 0 || o.tail_finest > 65535)
         return LAMG_INVALID_ARG;
     lamg_handle *h = nullptr;
@@ -287,6 +288,7 @@ lamg_status lamg_hierarchy_info(const lamg_handle *h, lamg_hier_info *info) {
     if (!h || !info) return LAMG_INVALID_ARG;
     std::memset(info, 0, sizeof(*info));
     info->levels = h->nlev;
+    info->reordered = h->reordered ? 1 : 0;
     double nnz0 = (double)h->lev[0].nnz, tot = 0.0;
     for (int l = 0; l < h->nlev && l < LAMG_MAX_LEVELS; ++l) {
         const Level &L = h->lev[l];

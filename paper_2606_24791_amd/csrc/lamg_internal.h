@@ -164,6 +164,8 @@ struct SolveOp {
     int max_short_len = 0;     // longest off-diagonal row; 0 if any row is in the long bin
     int max_len = 0;           // longest off-diagonal row
     DArr<int32_t> perm;        // solve index -> canonical index
+    DArr<int32_t> io_perm;     // level 0: solve index -> the caller's node index (perm, composed
+                               // with the input's renumbering when there is one)
     DArr<int32_t> rp, ci;      // off-diagonal CSR in solve numbering
     DArr<double> v64, d64, dinv64;
     DArr<float> v32, d32, dinv32;
@@ -350,6 +352,7 @@ struct lamg_handle {
     double solve_bytes = 0.0;  // algorithmic bytes of the current solve's launches
     double setup_seconds = 0.0;
     double setup_phase[LAMG_SETUP_PHASES] = {};  // seconds per lamg_setup_phase
+    bool reordered = false;                      // the input was renumbered (option reorder)
     ~lamg_handle();
 };
 

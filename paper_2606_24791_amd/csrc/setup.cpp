@@ -10,6 +10,7 @@
 #include <chrono>
 #include <optional>
 #include <cmath>
+#include <cstdlib>
 #include <system_error>
 #include <thread>
 
@@ -118,6 +119,113 @@ static HostGraph read_graph(const lamg_graph *g, hipStream_t s) {
     }
     if ((int64_t)q.size() != h.n) throw Error(LAMG_DISCONNECTED, "graph: not connected");
     return h;
+}
+
+// Self-gated reverse Cuthill-McKee renumbering of the input (the reordering for cache
+// locality that Sec. 4.2 lists among the implementation's constant-lowering features):
+// order[new] = old. Components are taken in the order of their smallest node; each starts
+// at a pseudo-peripheral node (George-Liu: from the component's node of least degree, ties
+// to the smallest index, move to the least-degree node of the farthest breadth-first level
+// while that lengthens the eccentricity); Cuthill-McKee numbers breadth first, each node's
+// not yet numbered neighbours by increasing degree (ties: smallest index); the whole
+// sequence is reversed. Kept only if it at least halves the summed index distance |u - v|
+// over the entries; returns whether it is kept.
+static bool rcm_order(const HostGraph &g, std::vector<int32_t> &order) {
+    const int64_t n = g.n;
+    auto deg = [&](int32_t u) { return g.rp[u + 1] - g.rp[u]; };
+    auto less = [&](int32_t a, int32_t b) { return deg(a) < deg(b) || (deg(a) == deg(b) && a < b); };
+    std::vector<int32_t> dist(n, -1), queue;
+    queue.reserve(n);
+    std::vector<char> numbered(n, 0);
+    // breadth-first distances from r over its component (the component's nodes in queue);
+    // returns r's eccentricity
+    auto bfs = [&](int32_t r) {
+        for (int32_t u : queue) dist[u] = -1;
+        queue.clear();
+        queue.push_back(r);
+        dist[r] = 0;
+        for (size_t q = 0; q < queue.size(); ++q) {
+            const int32_t u = queue[q];
+            for (int32_t j = g.rp[u]; j < g.rp[u + 1]; ++j) {
+                const int32_t v = g.ci[j];
+                if (dist[v] < 0) {
+                    dist[v] = dist[u] + 1;
+                    queue.push_back(v);
+                }
+            }
+        }
+        return dist[queue.back()];
+    };
+    order.clear();
+    order.reserve(n);
+    std::vector<int32_t> nb;
+    for (int32_t s0 = 0; s0 < n; ++s0) {
+        if (numbered[s0]) continue;
+        bfs(s0);
+        int32_t r = queue[0];
+        for (int32_t u : queue)
+            if (less(u, r)) r = u;
+        int32_t ecc = bfs(r);
+        for (;;) {
+            int32_t x = -1;
+            for (int32_t u : queue)
+                if (dist[u] == ecc && (x < 0 || less(u, x))) x = u;
+            const int32_t ex = bfs(x);
+            if (ex <= ecc) break;
+            r = x;
+            ecc = ex;
+        }
+        size_t head = order.size();
+        order.push_back(r);
+        numbered[r] = 1;
+        for (; head < order.size(); ++head) {
+            const int32_t u = order[head];
+            nb.clear();
+            for (int32_t j = g.rp[u]; j < g.rp[u + 1]; ++j) {
+                const int32_t v = g.ci[j];
+                if (!numbered[v]) {
+                    numbered[v] = 1;
+                    nb.push_back(v);
+                }
+            }
+            std::sort(nb.begin(), nb.end(), less);
+            order.insert(order.end(), nb.begin(), nb.end());
+        }
+    }
+    std::reverse(order.begin(), order.end());
+    std::vector<int32_t> inv(n);
+    for (int64_t i = 0; i < n; ++i) inv[order[i]] = (int32_t)i;
+    int64_t d0 = 0, d1 = 0;
+    for (int64_t u = 0; u < n; ++u)
+        for (int32_t j = g.rp[u]; j < g.rp[u + 1]; ++j) {
+            d0 += std::llabs(u - (int64_t)g.ci[j]);
+            d1 += std::llabs((int64_t)inv[u] - (int64_t)inv[g.ci[j]]);
+        }
+    return 2 * d1 <= d0;
+}
+
+// The graph with node order[p] renamed p, columns ascending again in every row.
+static void renumber(HostGraph &g, const std::vector<int32_t> &order) {
+    const int64_t n = g.n;
+    std::vector<int32_t> inv(n), rp(n + 1, 0), ci(g.nnz);
+    std::vector<double> w(g.nnz);
+    for (int64_t i = 0; i < n; ++i) inv[order[i]] = (int32_t)i;
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t p = 0; p < n; ++p) {
+        const int32_t u = order[p];
+        row.clear();
+        for (int32_t j = g.rp[u]; j < g.rp[u + 1]; ++j) row.emplace_back(inv[g.ci[j]], g.w[j]);
+        std::sort(row.begin(), row.end(),
+                  [](const auto &a, const auto &b) { return a.first < b.first; });
+        rp[p + 1] = rp[p] + (int32_t)row.size();
+        for (size_t e = 0; e < row.size(); ++e) {
+            ci[rp[p] + e] = row[e].first;
+            w[rp[p] + e] = row[e].second;
+        }
+    }
+    g.rp.swap(rp);
+    g.ci.swap(ci);
+    g.w.swap(w);
 }
 
 // Adds the wall time of its scope to one of the handle's setup phases; each scope ends with
@@ -626,6 +734,12 @@ void run_setup(lamg_handle *h, const lamg_graph *g) {
     std::optional<PhaseClock> pc_input(std::in_place, h, LAMG_SETUP_INPUT);
     HostGraph hg = read_graph(g, s);
     const int64_t n = hg.n;
+    std::vector<int32_t> rcm;  // order[new] = the caller's node, when renumbered
+    h->reordered = false;
+    if (h->opt.reorder && rcm_order(hg, rcm)) {
+        renumber(hg, rcm);
+        h->reordered = true;
+    }
 
     // level 0: L = D - W
     h->lev.clear();
@@ -758,6 +872,13 @@ void run_setup(lamg_handle *h, const lamg_graph *g) {
         for (int l = 0; l < h->nlev; ++l) compute_perm(h->lev[l], perm[l], iperm[l]);
         for (int l = 0; l < h->nlev; ++l)
             build_solve_op(h, l, perm[l], iperm[l], l + 1 < h->nlev ? &iperm[l + 1] : nullptr);
+        // right-hand sides come in, and solutions go out, in the caller's numbering
+        std::vector<int32_t> io(perm[0]);
+        if (h->reordered)
+            for (auto &u : io) u = rcm[u];
+        SolveOp &op0 = h->lev[0].op;
+        op0.io_perm.alloc(*h->pool, h->lev[0].n);
+        op0.io_perm.upload(io.data(), h->lev[0].n, s);
         LAMG_HIP(hipStreamSynchronize(s));
     }
 

@@ -641,7 +641,7 @@ void emit_columns(lamg_handle *h, int k, const int32_t *d_mask, double *phi_out)
         run_sub_col(n, k, w.tmp.p, w.mean.p, s);
     }
     Timed tm(h, LAMG_KERNEL_VECTOR, 0, 2.0 * nk8 + 4.0 * n, false);
-    run_scatter_cols(n, k, h->lev[0].op.perm.p, w.tmp.p, d_mask, phi_out, s);
+    run_scatter_cols(n, k, h->lev[0].op.io_perm.p, w.tmp.p, d_mask, phi_out, s);
 }
 
 // The state of one solve of at most 32 columns, advanced cycle by cycle: begin() prepares
@@ -693,7 +693,7 @@ struct Chunk {
         // b <- P b, projected to mean zero (eq. (1.1)); ||b|| per column
         {
             Timed tm(h, LAMG_KERNEL_VECTOR, 0, 2.0 * nk8 + 4.0 * n, false);
-            run_gather_cols(n, k, op0.perm.p, b_user, w.b.p, s);
+            run_gather_cols(n, k, op0.io_perm.p, b_user, w.b.p, s);
         }
         {
             Timed tm(h, LAMG_KERNEL_REDUCE, 0, nk8, false);
@@ -750,7 +750,7 @@ struct Chunk {
             for (int c = 0; c < k; ++c) w.h_mask[c] = active[c] ? 0 : 1;
             w.mask.upload(w.h_mask, k, s);
             Timed tm(h, LAMG_KERNEL_VECTOR, 0, 2.0 * nk8 + 4.0 * n, false);
-            run_scatter_cols(n, k, op0.perm.p, w.phi.p, w.mask.p, phi_out, s);
+            run_scatter_cols(n, k, op0.io_perm.p, w.phi.p, w.mask.p, phi_out, s);
         }
         const int lt = timed_level(h, k);
         c64.reset(new Cycle<double>{h, k, s, &w.lv64, std::vector<int64_t>(h->nlev, 0),
@@ -882,7 +882,7 @@ struct Chunk {
         // true residual of the returned phi
         {
             Timed tm(h, LAMG_KERNEL_VECTOR, 0, 2.0 * nk8 + 4.0 * n, false);
-            run_gather_cols(n, k, op0.perm.p, phi_out, w.phi.p, s);
+            run_gather_cols(n, k, op0.io_perm.p, phi_out, w.phi.p, s);
         }
         {
             Timed tm(h, LAMG_KERNEL_RESIDUAL, 0, bytes_residual(op0, k, 8.0), false);

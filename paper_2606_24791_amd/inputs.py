@@ -209,4 +209,7 @@ def workload(name: str) -> Graph:
         return grid3d(128, 128, 128, "lognormal", seed=0, name=name)
     if name == "chunglu2m":  # Chung-Lu n = 2M, beta 2.1, mean degree 16, LCC
         return chung_lu(2_000_000, 2.1, 16.0, seed=0, name=name)
+    if name == "rgg1m":  # random geometric, 1M points, mean degree 10, LCC; numbered in the
+        # points' draw order, which is random in space
+        return random_geometric(1_000_000, 10.0, seed=0, name=name)
     raise KeyError(name)

@@ -40,7 +40,7 @@ class lamg_options(C.Structure):
                 ("enable_caliber2", C.c_int32), ("kappa", C.c_int32), ("build_fp32", C.c_int32),
                 ("keep_setup_data", C.c_int32), ("tail_rows", C.c_int32),
                 ("elimination", C.c_int32), ("smoother", C.c_int32), ("graphs", C.c_int32),
-                ("tail_finest", C.c_int32)]
+                ("tail_finest", C.c_int32), ("reorder", C.c_int32)]
 
 
 class lamg_hier_info(C.Structure):
@@ -53,7 +53,7 @@ class lamg_hier_info(C.Structure):
                 ("tail_level", C.c_int32), ("timed_level", C.c_int32),
                 ("cheb", C.c_int32 * MAX_LEVELS), ("cheb_lmax", C.c_double * MAX_LEVELS),
                 ("setup_phase_seconds", C.c_double * SETUP_PHASES),
-                ("bjgs", C.c_int32 * MAX_LEVELS)]
+                ("bjgs", C.c_int32 * MAX_LEVELS), ("reordered", C.c_int32)]
 
 
 class lamg_solve_info(C.Structure):
@@ -363,6 +363,7 @@ def lamg_hierarchy_info(h: Handle) -> dict:
                 elim=[bool(e) for e in info.elim[:L]], tail_level=int(info.tail_level),
                 timed_level=int(info.timed_level), cheb=[bool(c) for c in info.cheb[:L]],
                 cheb_lmax=list(info.cheb_lmax[:L]), bjgs=[bool(c) for c in info.bjgs[:L]],
+                reordered=bool(info.reordered),
                 setup_phases=dict(zip(SETUP_PHASE_NAMES, info.setup_phase_seconds)))
 
 

@@ -39,7 +39,8 @@ def test_host_only_entry_points():
     assert "gfx950" in B.lamg_version()
     o = B.lamg_default_options()
     assert (o.seed, o.n_direct, o.enable_veto, o.enable_caliber2, o.kappa) == (1, 512, 1, 1, 4)
-    assert (o.elimination, o.smoother, o.tail_rows, o.build_fp32, o.graphs) == (1, 0, 2500, 1, 0)
+    assert (o.elimination, o.smoother, o.tail_rows, o.build_fp32, o.graphs, o.reorder) == \
+        (1, 0, 2500, 1, 0, 0)
     assert o.tail_finest == 0
 
 
@@ -89,6 +90,7 @@ def test_input_errors_are_reported_without_device():
     assert B.lamg_setup_status(good, B.lamg_default_options(kappa=5)) == B.INVALID_ARG
     assert B.lamg_setup_status(good, B.lamg_default_options(elimination=2)) == B.INVALID_ARG
     assert B.lamg_setup_status(good, B.lamg_default_options(smoother=3)) == B.INVALID_ARG
+    assert B.lamg_setup_status(good, B.lamg_default_options(reorder=2)) == B.INVALID_ARG
     assert B.lamg_setup_status(good, B.lamg_default_options(graphs=-1)) == B.INVALID_ARG
     assert B.lamg_setup_status(good, B.lamg_default_options(tail_rows=-1)) == B.INVALID_ARG
     assert B.lamg_setup_status(good, B.lamg_default_options(n_direct=1025)) == B.INVALID_ARG

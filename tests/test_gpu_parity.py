@@ -110,11 +110,12 @@ def test_setup_bit_exact(B, name, elimination):
     h.close()
 
 
-def solve_both(B, g, k, precision, seed=11, tol=TOL, elimination=True, smoother=0):
+def solve_both(B, g, k, precision, seed=11, tol=TOL, elimination=True, smoother=0, reorder=0):
     import torch
 
-    oh = O.Hierarchy(g, seed=1, elimination=elimination, smoother=smoother)
-    h = B.lamg_setup(g, B.lamg_default_options(elimination=int(elimination), smoother=smoother))
+    oh = O.Hierarchy(g, seed=1, elimination=elimination, smoother=smoother, reorder=reorder)
+    h = B.lamg_setup(g, B.lamg_default_options(elimination=int(elimination), smoother=smoother,
+                                               reorder=reorder))
     bh = I.rhs(g.n, k, seed=seed)
     b = torch.tensor(bh, device="cuda")
     phi = torch.empty_like(b)
@@ -408,6 +409,37 @@ def test_graph_replay_matches_kernel_by_kernel_launches(B, name):
         assert sg["cycles"] == sd["cycles"] and np.array_equal(sg["relres"], sd["relres"])
     hg.close()
     hd.close()
+
+
+# --- Self-gated reverse Cuthill-McKee renumbering of the input (option reorder) ------------
+
+
+def scrambled_rgg():
+    g = I.random_geometric(20000, seed=3)
+    return O.renumbered(g, np.random.default_rng(4).permutation(g.n).astype(np.int32))
+
+
+@pytest.mark.parametrize("name", ["rgg_scrambled", "grid"])
+def test_reorder_setup_bit_exact(B, name):
+    """A geometric graph numbered at random is renumbered (identically on both sides); a grid
+    in its own numbering is left as it is by the gate."""
+    g = scrambled_rgg() if name == "rgg_scrambled" else I.grid2d(60, 45)
+    note(f"reorder setup {name} n={g.n}")
+    oh = O.Hierarchy(g, seed=1, reorder=1)
+    h = B.lamg_setup(g, B.lamg_default_options(keep_setup_data=1, reorder=1))
+    info = B.lamg_hierarchy_info(h)
+    assert info["reordered"] == (oh.perm is not None) == (name == "rgg_scrambled")
+    compare_hierarchies(B, h, oh)
+    h.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32ir"])
+def test_solve_parity_reorder(B, prec):
+    """Right-hand sides in and solutions out in the caller's numbering."""
+    g = scrambled_rgg()
+    note(f"reorder solve parity {prec}")
+    st, ph, bh, refs = solve_both(B, g, 3, B.FP64 if prec == "fp64" else B.FP32_IR, reorder=1)
+    check_solution(g, st, ph, bh, refs)
 
 
 def test_not_converged_still_returns_iterate(B):
