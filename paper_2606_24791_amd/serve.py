@@ -72,11 +72,12 @@ class Server:
     def __init__(self, graphs: dict, hbm_budget: float = 200e9, slots: int = 4,
                  precision: int = B.FP32_IR, tol: float = 1e-8, max_columns: int = 32,
                  use_torch_allocator: bool = True, estimate=None, smoother: int = 0,
-                 hip_graphs: bool = False, group: int = 0):
+                 hip_graphs: bool = False, group: int = 0, reorder: int = 0):
         self.graphs = graphs
         # setup option: 1 = Chebyshev, 2 = block-Jacobi Gauss-Seidel, on levels with many colours
         self.smoother = smoother
         self.hip_graphs = hip_graphs  # setup option: replay repeated cycles as HIP graphs
+        self.reorder = reorder  # setup option: self-gated RCM renumbering of each graph
         # up to this many batches on different graphs per lamg_solve_group call (0/1: none);
         # hierarchies are then built to run the whole FP32 cycle of small graphs in the tail
         self.group = group
@@ -285,7 +286,7 @@ class Server:
         g = self.graphs[gid]
         fp32 = self.precision == B.FP32_IR
         h = B.lamg_setup(g, B.lamg_default_options(
-            smoother=self.smoother, graphs=int(self.hip_graphs),
+            smoother=self.smoother, graphs=int(self.hip_graphs), reorder=int(self.reorder),
             tail_finest=65535 if self.group > 1 else 0), stream=stream)
         info = B.lamg_hierarchy_info(h)
         entry = dict(handle=h, levels=info["n"], bytes=float(info["bytes_device"]), ws=0.0,
@@ -579,6 +580,8 @@ def main(argv=None) -> int:
     ap.add_argument("--rate", type=float, default=None,
                     help="run one stream at this offered rate (requests/s) instead")
     ap.add_argument("--log-batches", action="store_true")
+    ap.add_argument("--reorder", action="store_true",
+                    help="renumber each graph by the self-gated reverse Cuthill-McKee order")
     ap.add_argument("--smoother", type=int, default=0,
                     help="0: multicolour Gauss-Seidel; 1: Chebyshev on levels with > 32 colours; "
                          "2: block-Jacobi Gauss-Seidel on those levels")
@@ -601,7 +604,7 @@ def main(argv=None) -> int:
     def one(rate, tag):
         reqs = request_stream(graphs, a.requests, rate, a.kmax, a.seed, shared_rhs=True)
         srv = Server(graphs, hbm_budget=a.budget_gb * 1e9, slots=a.slots, smoother=a.smoother,
-                     hip_graphs=a.hip_graphs, group=a.group)
+                     hip_graphs=a.hip_graphs, group=a.group, reorder=int(a.reorder))
         srv.progress_every = max(1, a.requests // 10)
         srv.log_batches = a.log_batches
         if a.preload:
@@ -611,7 +614,7 @@ def main(argv=None) -> int:
         srv.close()
         out.update(run=tag, offered_rate=rate if rate > 0 else None, requests_total=a.requests,
                    graphs=len(graphs), slots=a.slots, kmax=a.kmax, smoother=a.smoother,
-                   hip_graphs=a.hip_graphs, group=a.group, preload=a.preload)
+                   hip_graphs=a.hip_graphs, group=a.group, preload=a.preload, reorder=a.reorder)
         out["answered_per_s"] = out["answered"] / out["wall_s"]
         print(json.dumps(out), flush=True)
         log(f"{tag}: {out['answered_per_s']:.2f} req/s p50 {out['p50_ms']:.1f} ms "
