@@ -99,3 +99,59 @@ def test_noalloc_solve_matches_lamg_solve(B):
         for h in handles:
             h.close()
         B.lamg_set_allocator()
+
+
+def test_noalloc_with_smoother_and_renumbering_options(B):
+    """Hierarchies built with the block-Jacobi smoother (its sweeps use the level's residual
+    vector as work space) and with the input renumbered (right-hand sides and solutions go
+    through the composed permutation): the allocation-free solve still equals lamg_solve."""
+    import torch
+
+    dev = torch.cuda.current_device()
+    counts = {"alloc": 0}
+
+    def alloc(nbytes, stream, ctx):
+        counts["alloc"] += 1
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream or 0)
+        except Exception:
+            return None
+
+    def free(ptr, stream, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    B.lamg_set_allocator(alloc, free)
+    handles = []
+    try:
+        cases = [  # (name, graph, options, columns, precision, rhs seed)
+            ("Chung-Lu n=10000, block-Jacobi", I.chung_lu(10000, 2.1, 24, seed=3),
+             dict(smoother=2), 2, B.FP32_IR, 41),
+            ("random geometric n=5000, renumbered", I.random_geometric(5000, seed=5),
+             dict(reorder=1), 3, B.FP64, 42),
+        ]
+        for name, g, opts, k, prec, seed in cases:
+            note(f"noalloc with options: {name} n={g.n} k={k} precision={prec}")
+            h = B.lamg_setup(g, B.lamg_default_options(**opts))
+            handles.append(h)
+            info = B.lamg_hierarchy_info(h)
+            assert any(info["bjgs"]) if "smoother" in opts else info["reordered"]
+            b = torch.tensor(I.rhs(g.n, k, seed=seed), device="cuda")
+            ref = torch.empty_like(b)
+            st_ref = B.lamg_solve(h, b, ref, precision=prec)
+            torch.cuda.synchronize()
+            phi = torch.full_like(b, 3.0)
+            a0 = counts["alloc"]
+            st = B.lamg_solve_noalloc(h, b, phi, precision=prec)
+            torch.cuda.synchronize()
+            assert counts["alloc"] == a0, "device allocation in noalloc"
+            assert st["status"] == B.OK and st["relres_max"] <= 1e-8, st
+            assert st["cycles"] == st_ref["cycles"]
+            p, r = phi.cpu().numpy(), ref.cpu().numpy()
+            for c in range(k):
+                err = np.linalg.norm(p[c] - r[c]) / np.linalg.norm(r[c])
+                emax = np.abs(p[c] - r[c]).max() / np.abs(r[c]).max()
+                assert err <= SOL_TOL and emax <= SOL_TOL, (c, err, emax)
+    finally:
+        for h in handles:
+            h.close()
+        B.lamg_set_allocator()
